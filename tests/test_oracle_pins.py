@@ -1,0 +1,274 @@
+"""Pins of the CPU oracle against facts fixed outside it: published
+known-answer values, hand-evaluated formulas from the paper, library
+routines (numpy sort, bisect, Python's bytes ordering), closed forms of the
+input distributions, and brute force on tiny inputs."""
+import bisect
+import itertools
+import math
+import os
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lines(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def test_splitmix64_known_answers():
+    for row in _lines("splitmix64_kat.txt"):
+        state, outs = int(row[0], 0), [int(x, 16) for x in row[1:]]
+        assert oracle.splitmix64(state, len(outs)) == outs
+        # the input generators implement the same published generator separately
+        assert [int(x) for x in synth.stream(state, len(outs))] == outs
+
+
+def test_mulhi64_exact():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        a, b = int(rng.integers(0, 2**63)) * 2 + 1, int(rng.integers(0, 2**63))
+        assert oracle.mulhi64(a, b) == (a * b) >> 64
+
+
+def test_task_rules_hand_values():
+    for name, n, v in _lines("task_rules.txt"):
+        n, v = int(n), int(v)
+        if name == "alpha":
+            assert oracle.alpha(n) == v, n
+        else:
+            assert oracle.adaptive_k(n, 256, 16) == v, n
+
+
+def test_adaptive_k_against_real_valued_formula():
+    # The printed formula evaluated in floating point at sizes where no
+    # rounding decision is close to an integer boundary.
+    rng = np.random.default_rng(2)
+    k, n0 = 256, 16
+    for n in rng.integers(17, 1 << 22, size=3000).tolist():
+        x = math.log2(n / n0)
+        if k * n0 < n < k * k * n0:
+            t = (x + 1) / 2
+            if abs(t - round(t)) < 1e-9:
+                continue
+            want = 2 ** math.ceil(t)
+        elif n0 < n <= k * n0:
+            if abs(x - round(x)) < 1e-9:
+                continue
+            want = 2 ** math.ceil(x)
+        else:
+            want = k
+        assert oracle.adaptive_k(n, k, n0) == max(2, min(k, want)), n
+
+
+KINDS = ["u32", "u64", "f64", "pair", "rec100"]
+
+
+def _keys(a, kind):
+    """Sort keys as Python objects whose natural order is the key order."""
+    if kind == "u32" or kind == "u64":
+        return [int(x) for x in a]
+    if kind == "f64":
+        return [float(x) for x in a]
+    if kind == "pair":
+        return [int(x) for x in a[:, 0]]
+    return [bytes(r[:10]) for r in a]
+
+
+def _multiset(a, kind):
+    if a.ndim == 1:
+        return Counter(a.tobytes()[i * a.itemsize:(i + 1) * a.itemsize] for i in range(a.shape[0]))
+    return Counter(bytes(r.tobytes()) for r in a)
+
+
+def _gen(kind, dist, n, seed):
+    if kind == "f64":
+        return synth.gen_f64("uniform" if dist not in ("exponential",) else dist, n, seed)
+    if kind == "rec100":
+        return synth.gen_rec100("rootdup" if dist == "rootdup" else "uniform", n, seed)
+    if kind == "u32" and dist == "twodup" or kind == "u32" and dist == "eightdup":
+        return synth.gen_u32(dist, n, seed)
+    return synth.generate(kind, dist, n, seed)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", [0, 1, 2, 17, 1000, 65536])
+def test_sort_matches_library_sort(kind, n):
+    for dist in ("uniform", "rootdup", "twodup"):
+        a = _gen(kind, dist, n, 11 + n)
+        s = oracle.sort(a, kind)
+        k = _keys(s, kind)
+        assert k == sorted(_keys(a, kind))          # library sort of the keys
+        assert _multiset(s, kind) == _multiset(a, kind)
+        if kind in ("u32", "u64", "f64"):
+            assert np.array_equal(s, np.sort(a, kind="stable"))
+
+
+def test_sort_brute_force_tiny():
+    # Every permutation of distinct keys and every sequence over {0,1,2} for
+    # n <= 6: the sorted output is the unique non-decreasing arrangement.
+    for n in range(0, 7):
+        base = np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 >> 3)
+        for perm in itertools.permutations(range(n)):
+            a = base[list(perm)]
+            assert np.array_equal(oracle.sort(a, "u64"), np.sort(base))
+        for seq in itertools.product(range(3), repeat=n):
+            a = np.array(seq, dtype=np.uint32)
+            s = oracle.sort(a, "u32")
+            assert all(s[i] <= s[i + 1] for i in range(n - 1))
+            assert Counter(s.tolist()) == Counter(seq)
+
+
+def test_pair_sort_values_are_indices():
+    a = synth.gen_pair("rootdup", 5000, 3)
+    s = oracle.sort(a, "pair")
+    assert sorted(s[:, 1].tolist()) == list(range(5000))
+    assert np.array_equal(a[s[:, 1].astype(np.int64), 0], s[:, 0])
+
+
+def test_rec100_order_is_unsigned_bytes():
+    a = synth.gen_rec100("uniform", 3000, 5)
+    a[::7, 0] = 0xFF      # bytes >= 0x80 must sort after small ones
+    a[1::7, 0:10] = a[0, 0:10]
+    s = oracle.sort(a, "rec100")
+    assert [bytes(r[:10]) for r in s] == sorted(bytes(r[:10]) for r in a)
+    assert _multiset(s, "rec100") == _multiset(a, "rec100")
+
+
+def test_f64_total_order_golden():
+    want = [int(r[0], 16) for r in _lines("f64_total_order.txt")]
+    bits = np.array(want, dtype=np.uint64)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        shuffled = bits[rng.permutation(bits.size)].view(np.float64)
+        s = oracle.sort(shuffled.copy(), "f64")
+        assert s.view(np.uint64).tolist() == want
+
+
+@pytest.mark.parametrize("n", [1000, 4096, 65536])
+def test_closed_forms_of_distributions(n):
+    assert np.array_equal(oracle.sort(synth.gen_u64("almostsorted", n, 9), "u64"),
+                          np.arange(n, dtype=np.uint64))
+    assert not oracle.sort(synth.gen_u64("zero", n, 9), "u64").any()
+    m = math.isqrt(n)
+    rd = oracle.sort(synth.gen_u64("rootdup", n, 9), "u64")
+    want = np.repeat(np.arange(m, dtype=np.uint64), [(n - 1 - v) // m + 1 for v in range(m)])
+    assert np.array_equal(rd, want)
+    for dist in ("twodup", "eightdup", "exponential"):
+        a = synth.gen_u64(dist, n, 9)
+        cnt = np.bincount(a.astype(np.int64))                    # counting sort
+        assert np.array_equal(oracle.sort(a, "u64"),
+                              np.repeat(np.arange(cnt.size, dtype=np.uint64), cnt))
+    s = synth.gen_u64("sorted", n, 9)
+    assert np.array_equal(oracle.sort(s[::-1].copy(), "u64"), s)
+
+
+def _classify_pins(keys, spl, K, kind):
+    """Pin oracle_classify with bisect (library) and the equality-bucket
+    properties: odd bucket 2i+1 holds exactly the keys equal to s_i, even
+    bucket 2i the keys strictly between s_{i-1} and s_i, bucket 2K-1 the keys
+    above every splitter, bucket 2K-2 nothing."""
+    sk = [int(x) for x in spl[:K - 1]]
+    for e in keys:
+        e_arr = np.array([e], dtype=spl.dtype)
+        i = bisect.bisect_left(sk, int(e))
+        assert oracle.classify(e_arr, kind, spl, K, False) == i
+        b = oracle.classify(e_arr, kind, spl, K, True)
+        if b % 2 == 1 and b < 2 * K - 1:
+            assert int(e) == sk[b // 2]
+        elif b == 2 * K - 1:
+            assert int(e) > sk[-1]
+        else:
+            assert b != 2 * K - 2
+            j = b // 2
+            assert (j == 0 or sk[j - 1] < int(e)) and int(e) < sk[j]
+
+
+def test_classify_exhaustive_small_domain():
+    rng = np.random.default_rng(5)
+    for K in (2, 4, 8):
+        for _ in range(60):
+            u = int(rng.integers(1, K))              # distinct splitters, padded
+            vals = np.sort(rng.choice(16, size=u, replace=False)).astype(np.uint32)
+            spl = np.concatenate([vals, np.full(K - u, vals[-1], dtype=np.uint32)])
+            _classify_pins(range(16), spl, K, "u32")
+
+
+def test_classify_monotone_and_histogram():
+    a = synth.gen_u64("twodup", 1 << 14, 2)
+    st = oracle.sample_step(a, "u64", seed=7, k=64)
+    spl, K = st["splitters"], st["K"]
+    for eq in (False, True):
+        h = oracle.histogram(a, "u64", spl, K, eq)
+        keys = np.sort(a)
+        bk = [oracle.classify(np.array([x], dtype=np.uint64), "u64", spl, K, eq) for x in keys[::37]]
+        assert bk == sorted(bk)
+        if not eq:
+            idx = np.searchsorted(spl[:K - 1], a, side="left")      # library
+            assert np.array_equal(h, np.bincount(idx, minlength=K).astype(np.uint64))
+        assert int(h.sum()) == a.size
+
+
+@pytest.mark.parametrize("dist", ["uniform", "rootdup", "eightdup", "zero"])
+def test_sample_step_definition(dist):
+    n, seed, l = 1 << 16, 99, 0
+    a = synth.gen_u64(dist, n, 4)
+    st = oracle.sample_step(a, "u64", l=l, n=n, seed=seed)
+    alpha, kp = st["alpha"], st["k_prime"]
+    assert (alpha, kp) == (3, 128)                # hand values: 16/5 -> 3; 2^16 -> 128
+    assert st["m"] == alpha * kp
+    # Sample positions recomputed with the generator module's own SplitMix64
+    # and Python big integers.
+    ts_state = (seed ^ ((l * 0x9E3779B97F4A7C15) & (2**64 - 1)) ^ (0 << 56))
+    _, tseed = synth.splitmix64_scalar(ts_state)
+    assert oracle.task_seed(seed, l, 0) == tseed
+    xs = synth.stream(tseed, st["m"])
+    pos = [l + ((int(x) * n) >> 64) for x in xs]
+    assert np.array_equal(st["sample"], np.sort(a[pos]))
+    pick = [st["sample"][(i + 1) * alpha - 1] for i in range(kp - 1)]
+    distinct = sorted(set(int(x) for x in pick))
+    assert st["u"] == len(distinct)
+    assert st["eq"] == (len(distinct) < kp - 1)
+    K = st["K"]
+    assert K >= st["u"] + 1 and K // 2 < st["u"] + 1 and K & (K - 1) == 0
+    assert [int(x) for x in st["splitters"]] == distinct + [distinct[-1]] * (K - len(distinct))
+
+
+def test_check_partition_detects_planted_mistake():
+    a = synth.gen_u64("uniform", 1 << 12, 8)
+    st = oracle.sample_step(a, "u64", seed=1, k=16)
+    spl, K = st["splitters"], st["K"]
+    b = np.array([oracle.classify(np.array([x], dtype=np.uint64), "u64", spl, K, False) for x in a])
+    order = np.argsort(b, kind="stable")
+    part = a[order]
+    starts = np.concatenate([[0], np.cumsum(np.bincount(b, minlength=K))]).astype(np.uint64)
+    assert oracle.check_partition(part, "u64", spl, K, False, starts) is None
+    bad = part.copy()
+    i, j = int(starts[1]) - 1, int(starts[2])       # swap across a boundary
+    bad[i], bad[j] = bad[j], bad[i]
+    assert oracle.check_partition(bad, "u64", spl, K, False, starts) in (i, j)
+
+
+def test_radix_digit_info_hand_values():
+    a = np.array([0x1234, 0x1200, 0x1210], dtype=np.uint64)       # xor 0x34: h = 5
+    assert oracle.radix_digit_info(a, "u64") == {"shift": 0, "width": 6, "all_equal": False}
+    rd = synth.gen_u64("rootdup", 1 << 20, 0)                     # 0..1023: h = 9
+    assert oracle.radix_digit_info(rd, "u64") == {"shift": 2, "width": 8, "all_equal": False}
+    assert oracle.radix_digit_info(np.full(5, 7, dtype=np.uint32), "u32")["all_equal"]
+    h = oracle.radix_histogram(rd, "u64", 2, 8)
+    assert np.array_equal(h, np.full(256, 4096, dtype=np.uint64))
+
+
+def test_count_less_matches_searchsorted():
+    a = synth.gen_u64("rootdup", 10000, 1)
+    s = np.sort(a)
+    for v in (0, 5, 50, 99, 1000):
+        x = np.array([v], dtype=np.uint64)
+        assert oracle.count_less(a, "u64", x) == int(np.searchsorted(s, v, "left"))
+        assert oracle.count_less(a, "u64", x, True) == int(np.searchsorted(s, v, "right"))
