@@ -1,0 +1,187 @@
+/* ips.h - C ABI of an MI355X (gfx950) in-place parallel samplesort and
+ * radix sort.
+ *
+ * The operation is the sorting problem stated in Section 2 ("Definitions
+ * and Preliminaries") of Axtmann, Witt, Ferizovic, Sanders, "Engineering
+ * In-place (Shared-memory) Sorting Algorithms" (arXiv 2009.13569): the n
+ * elements of an array are rearranged in that same array so that their
+ * keys are non-decreasing.  The method is the paper's recursive in-place
+ * partitioning step (Section 4.1: sampling with a branchless decision tree,
+ * classification through buffer blocks, block permutation with per-bucket
+ * read/write pointers, cleanup; equality buckets for duplicate keys) and,
+ * for IPS_RADIX, the radix variant IPS2Ra of Section 6 that replaces the
+ * decision tree by an 8-bit digit of unsigned integer keys.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers refer to memory of the device the context was created
+ *    on.  The caller owns all of it.  The library never allocates or frees
+ *    device memory while sorting; extra memory comes from the caller's
+ *    workspace, sized by ips_workspace_bytes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; the sort entry points also synchronize with it
+ *    between recursion levels (the host plans each level from the bucket
+ *    sizes of the previous one), so they return only when the data is
+ *    sorted.
+ *  - Return values are IPS_OK (0) or a negative IPS_E_* code; arguments are
+ *    validated before any HIP call.  ips_status_string names every code.
+ *  - The sort is unstable: records with equal keys may end in any order.
+ *  - One context must not be used by two host threads at once.
+ */
+#ifndef IPS_H
+#define IPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPS_ABI_VERSION 1
+
+/* Status codes. */
+#define IPS_OK 0
+#define IPS_E_INVALID_ARG (-1)     /* null pointer with n > 0, bad enum, bad params */
+#define IPS_E_UNSUPPORTED (-2)     /* e.g. IPS_RADIX on 100-byte records */
+#define IPS_E_WORKSPACE (-3)       /* workspace smaller than ips_workspace_bytes */
+#define IPS_E_MISALIGNED (-4)      /* data not naturally aligned (4 B for u32 and
+                                      100-byte records, 8 B otherwise), or the
+                                      workspace not 256-byte aligned */
+#define IPS_E_TOO_LARGE (-5)       /* n beyond what the block pointers can index */
+#define IPS_E_HIP (-6)             /* a HIP runtime call failed; see ips_last_hip_error */
+#define IPS_E_DEVICE (-7)          /* a kernel reported an internal consistency error;
+                                      see ips_last_device_error */
+#define IPS_E_NO_DEVICE (-8)       /* no usable gfx950 device */
+
+/* Element types.  Keys: u32, u64, f64 (ordered by IEEE 754 totalOrder, so
+ * -0.0 < +0.0 and NaNs sort to the ends by sign).  Records (Section 7 of the
+ * paper): IPS_PAIR_U64_U64 is 16 bytes, a u64 key at byte 0 and a u64 value
+ * at byte 8; IPS_REC100 is 100 bytes whose key is bytes 0..9 compared
+ * lexicographically as unsigned bytes (memcmp order, Algorithm 4). */
+typedef enum { IPS_U32 = 1, IPS_U64 = 2, IPS_F64 = 3 } ips_key_type;
+typedef enum { IPS_PAIR_U64_U64 = 4, IPS_REC100 = 5 } ips_rec_type;
+
+/* IPS_SAMPLESORT: IPS4o.  IPS_RADIX: IPS2Ra (unsigned integer keys; the
+ * f64 key is mapped to its order-preserving unsigned image; not available
+ * for IPS_REC100). */
+typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
+
+/* Flags of ips_params. */
+#define IPS_FLAG_NO_SORTED_CHECK 0x1u  /* skip the sorted / reverse-sorted detection
+                                          (Section 6) */
+#define IPS_FLAG_EQ_ON 0x2u           /* force equality buckets on every step */
+#define IPS_FLAG_EQ_OFF 0x4u          /* no equality buckets on the root step (later
+                                          steps still enable them when a step would
+                                          otherwise make no progress) */
+#define IPS_FLAG_LEVEL1_ONLY 0x8u     /* stop after the root partitioning step: the
+                                          array is then partitioned, not sorted; see
+                                          ips_get_root_info */
+#define IPS_FLAG_GLOBAL_BUFFERS 0x10u /* keep the classification buffer blocks in the
+                                          workspace instead of LDS, so that block_bytes
+                                          may exceed the LDS budget (e.g. 2 KiB blocks
+                                          with 256 buckets) */
+
+/* Tuning and test parameters.  A zero field selects the default.
+ *  k            maximum number of buckets per step (power of two, 2..256;
+ *               default 256, Section 6)
+ *  block_bytes  requested block size in bytes; the block holds
+ *               max(1, block_bytes / element size) elements.  Default: the
+ *               largest block for which one buffer block per bucket fits the
+ *               LDS budget.  Larger requests need IPS_FLAG_GLOBAL_BUFFERS.
+ *  n0           base-case size of the adaptive-k rule (default 16, Section 6)
+ *  lds_task_max tasks with at most this many elements are sorted inside one
+ *               workgroup's LDS (default: per type, 1..16384); 1 forces every
+ *               task of two or more elements through a partitioning step
+ *  piece_blocks maximum blocks per pointer piece of the block permutation
+ *               (default 256)
+ *  seed         seed of the sampling stream (default 0)
+ */
+typedef struct {
+  uint32_t k;
+  uint32_t block_bytes;
+  uint32_t n0;
+  uint32_t lds_task_max;
+  uint32_t piece_blocks;
+  uint32_t flags;
+  uint64_t seed;
+  uint32_t reserved[4];
+} ips_params;
+
+typedef struct ips_ctx ips_ctx;
+
+/* Create a context on HIP device `device` (the "sorter object" of
+ * Section 7.6: it keeps host-side state and pinned staging buffers between
+ * calls; it holds no device memory).  Errors: IPS_E_INVALID_ARG for a null
+ * `out`, IPS_E_NO_DEVICE, IPS_E_HIP. */
+int ips_ctx_create(ips_ctx** out, int device);
+
+/* Destroy a context (NULL is accepted). */
+int ips_ctx_destroy(ips_ctx* ctx);
+
+/* Workspace bytes needed to sort n elements of `elem_type` (1..5) with
+ * `algo` and `params` (nullable).  Pure host computation, no HIP call.
+ * The size is O(k * b) per workgroup of the largest batch plus O(n / b)
+ * words of block flags.  Errors: IPS_E_INVALID_ARG, IPS_E_UNSUPPORTED,
+ * IPS_E_TOO_LARGE. */
+int ips_workspace_bytes(uint64_t n, int elem_type, int algo,
+                        const ips_params* params, size_t* out_bytes);
+
+/* Sort n keys in place at device pointer d_keys.  d_ws: device workspace of
+ * ws_bytes >= ips_workspace_bytes(...) bytes, 256-byte aligned; its
+ * contents need no initialization and are garbage afterwards.  n in {0, 1}
+ * is a successful no-op. */
+int ips_sort_keys(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type,
+                  int algo, void* d_ws, size_t ws_bytes,
+                  const ips_params* params, void* stream);
+
+/* Sort n records in place at device pointer d_recs (array of structures).
+ * Records move as whole records; only the key is compared. */
+int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type,
+                   int algo, void* d_ws, size_t ws_bytes,
+                   const ips_params* params, void* stream);
+
+/* Description of the root partitioning step of the last sort on `ctx`
+ * (Section 4.1).  For IPS_SAMPLESORT: alpha, k_prime (adaptive k), m (sample
+ * size), u (distinct splitters), K (power of two >= u+1), eq (equality
+ * buckets), nb (buckets: K, or 2K with equality buckets), splitters[0..K-1]
+ * stored as keys (u32 keys widened to u64; f64 as the raw double bits; the
+ * 100-byte record key as bytes 0..9 in the first ten bytes of the 16-byte
+ * slot).  For IPS_RADIX: radix_shift and radix_width of the root digit.
+ * bucket_start[0..nb] are the bucket boundaries (elements) after the step.
+ * valid is 0 when the last sort had no root partitioning step (n small,
+ * sorted input). */
+typedef struct {
+  uint32_t valid, algo, alpha, k_prime, m, u, K, eq, nb;
+  uint32_t radix_shift, radix_width, block_elems, stripes, pad;
+  uint64_t n;
+  uint8_t splitters[256][16];
+  uint64_t bucket_start[513];
+} ips_root_info;
+
+int ips_get_root_info(ips_ctx* ctx, ips_root_info* out);
+
+/* Counters of the last sort: partitioning levels, steps, elements moved
+ * through partitioning steps and through the LDS tier, whether the input
+ * was detected as sorted (1) or reverse sorted (2). */
+typedef struct {
+  uint32_t levels, steps, batches, lds_tasks;
+  uint32_t detected, pad0;
+  uint64_t partitioned_elems, lds_elems;
+  uint64_t max_step_elems;
+} ips_stats;
+
+int ips_get_stats(ips_ctx* ctx, ips_stats* out);
+
+/* Last HIP error code seen by the context (hipError_t as int) and the
+ * last kernel-reported consistency error (0 = none; bits 0-7 the error
+ * code, bits 8-19 and 20-31 the low bits of its two arguments). */
+int ips_last_hip_error(ips_ctx* ctx);
+int ips_last_device_error(ips_ctx* ctx);
+
+const char* ips_status_string(int status);
+int ips_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPS_H */

@@ -1,0 +1,199 @@
+"""Python binding of libips.so: in-place samplesort (IPS4o) and radix sort
+(IPS2Ra) of device arrays on an MI355X.
+
+Argument marshalling only: every step of the sort runs in the HIP library;
+PyTorch supplies device memory and the stream.  Importing fails loudly if
+the library has not been built (``python -m paper_2009_13569_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libips.so")
+
+# PyTorch's HIP runtime is loaded first so that libips.so binds to the same
+# runtime (its dependency is recorded as plain libamdhip64.so).
+import torch  # noqa: E402,F401
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2009_13569_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+IPS_OK = 0
+STATUS = {0: "IPS_OK", -1: "IPS_E_INVALID_ARG", -2: "IPS_E_UNSUPPORTED", -3: "IPS_E_WORKSPACE",
+          -4: "IPS_E_MISALIGNED", -5: "IPS_E_TOO_LARGE", -6: "IPS_E_HIP", -7: "IPS_E_DEVICE",
+          -8: "IPS_E_NO_DEVICE"}
+TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5}
+ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100}
+ALGOS = {"samplesort": 0, "radix": 1}
+FLAG_NO_SORTED_CHECK = 0x1
+FLAG_EQ_ON = 0x2
+FLAG_EQ_OFF = 0x4
+FLAG_LEVEL1_ONLY = 0x8
+FLAG_GLOBAL_BUFFERS = 0x10
+
+EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
+           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_last_hip_error",
+           "ips_last_device_error", "ips_status_string", "ips_abi_version"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32),
+                ("lds_task_max", ctypes.c_uint32), ("piece_blocks", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class RootInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("valid", "algo", "alpha", "k_prime", "m", "u", "K", "eq", "nb", "radix_shift",
+                 "radix_width", "block_elems", "stripes", "pad")] + [
+        ("n", ctypes.c_uint64), ("splitters", (ctypes.c_uint8 * 16) * 256),
+        ("bucket_start", ctypes.c_uint64 * 513)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("steps", ctypes.c_uint32), ("batches", ctypes.c_uint32),
+                ("lds_tasks", ctypes.c_uint32), ("detected", ctypes.c_uint32), ("pad0", ctypes.c_uint32),
+                ("partitioned_elems", ctypes.c_uint64), ("lds_elems", ctypes.c_uint64),
+                ("max_step_elems", ctypes.c_uint64)]
+
+
+_vp, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+_lib.ips_ctx_create.argtypes = [ctypes.POINTER(_vp), _i32]
+_lib.ips_ctx_destroy.argtypes = [_vp]
+_lib.ips_workspace_bytes.argtypes = [_u64, _i32, _i32, ctypes.POINTER(Params), ctypes.POINTER(_sz)]
+_lib.ips_sort_keys.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_sort_pairs.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_get_root_info.argtypes = [_vp, ctypes.POINTER(RootInfo)]
+_lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+_lib.ips_last_hip_error.argtypes = [_vp]
+_lib.ips_last_device_error.argtypes = [_vp]
+_lib.ips_status_string.argtypes = [_i32]
+_lib.ips_status_string.restype = ctypes.c_char_p
+for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
+           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_last_hip_error",
+           "ips_last_device_error", "ips_abi_version"):
+    getattr(_lib, _f).restype = _i32
+
+
+class IpsError(RuntimeError):
+    def __init__(self, code: int, what: str = "", detail: str = ""):
+        self.code = code
+        msg = _lib.ips_status_string(code).decode()
+        super().__init__(f"{what}: {msg}{(' ' + detail) if detail else ''}")
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0) -> Params:
+    p = Params()
+    p.k, p.block_bytes, p.n0, p.lds_task_max, p.piece_blocks = k, block_bytes, n0, lds_task_max, piece_blocks
+    p.flags, p.seed = flags, seed
+    return p
+
+
+def workspace_bytes(n: int, kind: str, algo: str = "samplesort", params: Params | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    rc = _lib.ips_workspace_bytes(n, TYPES[kind], ALGOS[algo],
+                                  ctypes.byref(params) if params is not None else None, ctypes.byref(out))
+    if rc != IPS_OK:
+        raise IpsError(rc, "ips_workspace_bytes")
+    return int(out.value)
+
+
+def kind_of(t) -> str:
+    """Element kind of a torch tensor: 1-D uint32/uint64/float64 keys, (n, 2)
+    64-bit pairs, or (n, 100) uint8 records."""
+    import torch
+    if t.dim() == 1:
+        return {torch.uint32: "u32", torch.int32: "u32", torch.uint64: "u64", torch.int64: "u64",
+                torch.float64: "f64"}[t.dtype]
+    if t.dim() == 2 and t.shape[1] == 2 and t.dtype in (torch.uint64, torch.int64):
+        return "pair"
+    if t.dim() == 2 and t.shape[1] == 100 and t.dtype == torch.uint8:
+        return "rec100"
+    raise TypeError(f"unsupported tensor {tuple(t.shape)} {t.dtype}")
+
+
+class Sorter:
+    """A context on one device plus a cached workspace tensor."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = _lib.ips_ctx_create(ctypes.byref(h), device)
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_ctx_create")
+        self._h = h
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            _lib.ips_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int):
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def sort_(self, t, algo: str = "samplesort", params: Params | None = None, kind: str | None = None,
+              stream=None, ws=None):
+        """Sort tensor `t` in place on its device; returns t."""
+        import torch
+        if not t.is_cuda:
+            raise ValueError("tensor must be on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        kind = kind or kind_of(t)
+        n = t.shape[0]
+        need = workspace_bytes(n, kind, algo, params)
+        ws = ws if ws is not None else self.workspace(need)
+        if stream is None:
+            stream = torch.cuda.current_stream(t.device)
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        pp = ctypes.byref(params) if params is not None else None
+        fn = _lib.ips_sort_keys if kind in ("u32", "u64", "f64") else _lib.ips_sort_pairs
+        rc = fn(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ALGOS[algo],
+                ctypes.c_void_p(ws.data_ptr()), ws.numel(), pp, sp)
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_sort", f"(hip={_lib.ips_last_hip_error(self._h)}, "
+                                           f"device={hex(_lib.ips_last_device_error(self._h))})")
+        return t
+
+    def root_info(self) -> RootInfo:
+        ri = RootInfo()
+        _lib.ips_get_root_info(self._h, ctypes.byref(ri))
+        return ri
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _lib.ips_get_stats(self._h, ctypes.byref(s))
+        return s
+
+
+_default = {}
+
+
+def sorter(device: int = 0) -> Sorter:
+    if device not in _default:
+        _default[device] = Sorter(device)
+    return _default[device]
+
+
+def sort_(t, algo: str = "samplesort", params: Params | None = None, kind: str | None = None):
+    """Sort a device tensor in place with the default sorter of its device."""
+    return sorter(t.device.index or 0).sort_(t, algo=algo, params=params, kind=kind)

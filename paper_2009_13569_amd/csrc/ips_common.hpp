@@ -1,0 +1,120 @@
+// Definitions shared by the host orchestrator and the gfx950 kernels of the
+// in-place samplesort (IPS4o) / radix sort (IPS2Ra) hot path of
+// arXiv 2009.13569.
+#pragma once
+#include <stdint.h>
+
+namespace ips {
+
+// Limits.  MAX_K is the largest number of buckets of a step without
+// equality buckets (k <= 256, Section 6); with equality buckets a step has
+// 2K buckets (Definitions and Preliminaries), so at most MAX_NB.
+constexpr uint32_t MAX_K = 256;
+constexpr uint32_t MAX_NB = 512;
+constexpr uint32_t MAX_BLOCK_BYTES = 2048;   // 64 lanes x 8 dwords
+constexpr uint32_t BUF_LDS_BYTES = 128u * 1024u;   // buffer blocks in LDS
+constexpr uint32_t CLS_THREADS = 1024;
+constexpr uint32_t PERM_THREADS = 256;
+constexpr uint32_t SMP_THREADS = 1024;
+constexpr uint32_t CLN_THREADS = 256;
+constexpr uint32_t LDST_THREADS = 512;
+constexpr uint32_t MAX_SAMPLE = 4096;        // padded sample of one step
+constexpr uint32_t PTR_BIAS = 0x80000000u;   // bias of the read pointer half
+
+// Control block at the start of the workspace.
+enum CtrlSlot : uint32_t {
+  CTRL_ERR = 0,        // first consistency error code (0 = none)
+  CTRL_ERR_A = 1,
+  CTRL_ERR_B = 2,
+  CTRL_DESC = 4,       // sorted check: a descent was found
+  CTRL_ASC = 5,        // sorted check: an ascent was found
+  CTRL_MINMAX = 8,     // two u64: min and max radix key (dword index 8..11)
+  CTRL_WORDS = 64
+};
+
+// Device error codes.
+enum DevErr : uint32_t {
+  DE_NONE = 0,
+  DE_CLS_INPLACE = 1,     // classification write past the consumed region
+  DE_PIECES = 2,          // more pointer pieces than planned
+  DE_PLACE = 3,           // no free slot found for a block
+  DE_WAIT = 4,            // reader flag never set
+  DE_CLEANUP_COUNT = 5,   // elements to place != free positions
+  DE_SAMPLE = 6,          // sample too large
+  DE_PERM_RANGE = 7,      // block position outside the task
+  DE_CLN_RANGE = 8,
+  DE_LDST = 9,            // task too large for the LDS tier
+  DE_BLOCK = 10,          // block larger than the group can hold
+};
+
+// Result of the sampling phase of one step (Section 4.1) or the digit of a
+// radix step.  Keys live in 16-byte slots so that every key type fits.
+struct StepRec {
+  uint32_t K, logK, eq, nb, u, alpha, kp, m;
+  uint32_t shift, width, radix, pad;
+  uint64_t tree[MAX_K][2];   // tree[1..K-1], breadth-first order
+  uint64_t spl[MAX_K][2];    // sorted splitters s_0..s_{K-1}, s_{K-1} = s_{K-2}
+};
+
+// One partitioning task of a batch (a subarray A[l, l+n) of the input).
+struct PTask {
+  uint64_t l, n;             // element offset and size
+  uint64_t slot_off;         // byte offset of stripe 0's buffer slot (slots contiguous)
+  uint64_t spill_off;        // byte offset of the per-bucket spill area
+  uint64_t flag_off;         // index of the first u32 block flag
+  uint32_t level, tflags;    // recursion depth; TF_* bits
+  uint32_t b, NB, W, wg_base;        // block elements, blocks, stripes, first WG
+  uint32_t nb, K, logK, eq;          // buckets of the step
+  uint32_t slot_bytes;               // bytes of one stripe's buffer slot
+  uint32_t piece_base, piece_cap;    // pointer pieces of the permutation
+  uint32_t ngrp, pwg_base, glanes;   // permutation groups
+  uint32_t bucket_base;              // first entry in the batch bucket tables
+  uint32_t shift, width;             // radix digit
+  uint32_t pad0, pad1;
+};
+
+enum TaskFlags : uint32_t { TF_EQ_ON = 1u, TF_EQ_OFF = 2u, TF_RADIX = 4u };
+
+// A task of the LDS tier: sorted entirely inside one workgroup's LDS.
+struct LTask {
+  uint64_t l;
+  uint32_t n, pad;
+};
+
+// Arguments shared by the kernels of one batch.
+struct BatchArgs {
+  uint32_t* data;             // the array (as dwords)
+  uint32_t* ctrl;             // control block
+  const PTask* tasks;
+  StepRec* recs;
+  const uint32_t* cls_task;   // classification WG -> task
+  const uint32_t* perm_task;  // permutation WG -> task
+  const uint32_t* cln_map;    // cleanup WG -> (task << 10) | bucket
+  uint32_t* wg_nfull;         // [WG][MAX_NB] full blocks flushed per bucket
+  uint32_t* wg_left;          // [WG][MAX_NB] elements left in the buffer
+  uint32_t* wg_F;             // [WG] full blocks at the stripe front
+  uint64_t* wg_min;           // [WG][MAX_K] radix: min key per bucket
+  uint64_t* wg_max;
+  uint8_t* slots;             // stripe buffer slots
+  uint8_t* spill;             // spill areas
+  uint32_t* ovf;              // [task][MAX_BLOCK_BYTES/4] overflow blocks
+  uint32_t* flags;            // block read flags
+  uint64_t* b_start;          // [bucket_base + j], j = 0..nb (task-relative)
+  uint32_t* b_count;          // blocks of bucket j
+  uint32_t* b_d;              // first block of bucket j
+  uint32_t* b_plb;            // placement pieces [plb, ple) of bucket j
+  uint32_t* b_ple;
+  uint64_t* b_min;            // radix: min/max key of bucket j
+  uint64_t* b_max;
+  uint64_t* p_word;           // pieces: packed (w << 32) | (r + PTR_BIAS)
+  uint32_t* p_a;              // first block of the piece
+  uint32_t* p_c;              // end block (exclusive) of the piece
+  int32_t* p_rinit;           // last unprocessed block at the start (a-1: none)
+  uint32_t* p_cum;            // unprocessed blocks of the earlier pieces
+  uint32_t* t_npieces;        // [task] number of pieces
+  uint32_t* t_unproc;         // [task] unprocessed blocks in total
+  uint32_t gbuf;              // buffer blocks in the slots instead of LDS
+  uint32_t ntasks;
+};
+
+}  // namespace ips

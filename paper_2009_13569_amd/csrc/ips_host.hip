@@ -1,0 +1,755 @@
+// Host side of the C ABI (include/ips.h): argument validation, workspace
+// planning, and the level-by-level orchestration of partitioning steps
+// (arXiv 2009.13569, Sections 4.1-4.2 and 6) on one MI355X.
+//
+// The recursion is breadth first.  All partitioning tasks of one recursion
+// level are grouped into batches; one batch runs each phase of the
+// partitioning step as one kernel launch over all of its tasks.  Bucket
+// sizes come back to the host after each batch, which turns large buckets
+// into next-level tasks and launches the LDS-tier sort for small ones.
+// Equality buckets are final (Section 4.1, "Sampling").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ips.h"
+#include "ips_common.hpp"
+#include "ips_launch.hpp"
+
+using namespace ips;
+
+namespace {
+
+constexpr uint32_t WG_TARGET = 512;       // classification workgroups per level
+constexpr uint32_t GRP_TARGET = 32768;    // permutation groups per batch
+constexpr uint32_t TB_MAX = 512;          // tasks per batch
+constexpr uint32_t WB_MAX = 1024;         // classification workgroups per batch
+
+struct Cfg {
+  const Launchers* L;
+  int type;
+  uint32_t D, DW;
+  bool radix, gbuf;
+  uint32_t k, n0, cap, cmax, flags;
+  uint64_t seed;
+  uint32_t b_req;   // requested block elements (0 = automatic)
+};
+
+uint32_t elem_bytes(int t) {
+  switch (t) {
+    case 1: return 4;
+    case 2: return 8;
+    case 3: return 8;
+    case 4: return 16;
+    case 5: return 100;
+    default: return 0;
+  }
+}
+
+const Launchers* launchers_for(int t) {
+  switch (t) {
+    case 1: return launchers_u32();
+    case 2: return launchers_u64();
+    case 3: return launchers_f64();
+    case 4: return launchers_pair();
+    case 5: return launchers_rec100();
+    default: return nullptr;
+  }
+}
+
+uint32_t default_cap(int t) {
+  switch (t) {
+    case 1: return 16384;
+    case 2: case 3: return 8192;
+    case 4: return 4096;
+    case 5: return 1024;
+    default: return 0;
+  }
+}
+
+// Paper's block size max(1, 2^floor(11 - log2 D)) elements (Section 6).
+uint32_t paper_block(uint32_t D) {
+  uint32_t b = 1;
+  while ((uint64_t)b * 2 * D <= 2048) b *= 2;
+  return b;
+}
+
+int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
+  (void)n;
+  const uint32_t D = elem_bytes(type);
+  if (!D) return IPS_E_INVALID_ARG;
+  if (algo != IPS_SAMPLESORT && algo != IPS_RADIX) return IPS_E_INVALID_ARG;
+  if (algo == IPS_RADIX && type == 5) return IPS_E_UNSUPPORTED;
+  ips_params z;
+  std::memset(&z, 0, sizeof(z));
+  if (!p) p = &z;
+  c->type = type;
+  c->D = D;
+  c->DW = D / 4;
+  c->radix = algo == IPS_RADIX;
+  c->flags = p->flags;
+  c->gbuf = (p->flags & IPS_FLAG_GLOBAL_BUFFERS) != 0;
+  c->k = p->k ? p->k : MAX_K;
+  if (c->k < 2 || c->k > MAX_K || (c->k & (c->k - 1))) return IPS_E_INVALID_ARG;
+  c->n0 = p->n0 ? p->n0 : 16;
+  const uint32_t dcap = default_cap(type);
+  c->cap = p->lds_task_max ? p->lds_task_max : dcap;
+  if (c->cap > dcap) return IPS_E_INVALID_ARG;
+  c->cmax = p->piece_blocks ? p->piece_blocks : 256;
+  c->seed = p->seed;
+  c->b_req = 0;
+  if (p->block_bytes) {
+    c->b_req = std::max<uint32_t>(1, p->block_bytes / D);
+    if ((uint64_t)c->b_req * D > MAX_BLOCK_BYTES) return IPS_E_INVALID_ARG;
+  } else if (c->gbuf) {
+    c->b_req = paper_block(D);
+  }
+  if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0x1Fu) return IPS_E_INVALID_ARG;
+  c->L = nullptr;
+  return IPS_OK;
+}
+
+// Block elements of a step with nb buckets: in LDS mode one buffer block per
+// bucket must fit the LDS budget; a block never exceeds MAX_BLOCK_BYTES.
+uint32_t block_elems(const Cfg& c, uint32_t nb) {
+  const uint32_t bmax = std::max<uint32_t>(1, MAX_BLOCK_BYTES / c.D);
+  if (c.gbuf) return std::min(bmax, std::max<uint32_t>(1, c.b_req));
+  uint32_t b = std::max<uint32_t>(1, BUF_LDS_BYTES / (nb * c.D));
+  b = std::min(b, bmax);
+  if (c.b_req) b = std::min(b, c.b_req);
+  return b;
+}
+
+uint32_t max_nb(const Cfg& c) { return c.radix ? MAX_K : 2 * c.k; }
+
+struct Layout {
+  uint32_t TB, WB, PWB, LTB, NBE;   // tasks, cls WGs, perm WGs, LDS tasks, bucket entries
+  uint64_t SB, SPB, FB, PB;         // slot bytes, spill bytes, flag words, pieces
+  uint64_t slot_max;
+  size_t off[40];
+  size_t total;
+};
+
+enum Region {
+  R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
+  R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
+  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_COUNT
+};
+
+void plan(uint64_t n, const Cfg& c, Layout* L) {
+  const uint64_t nbm = max_nb(c);
+  const uint32_t bmin = block_elems(c, (uint32_t)nbm);
+  uint64_t slot_max = 0;
+  for (uint32_t nb = 2; nb <= nbm; nb *= 2)
+    slot_max = std::max<uint64_t>(slot_max, ((uint64_t)nb * block_elems(c, nb) * c.D + 255) & ~255ull);
+  const uint64_t tasks_ub = n / ((uint64_t)c.cap + 1) + 1;
+  L->TB = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(TB_MAX, tasks_ub),
+                                       std::max<uint64_t>(64, n * c.D / (256 * 1024)));
+  L->WB = (uint32_t)std::min<uint64_t>(std::min<uint32_t>(WB_MAX, WG_TARGET + L->TB),
+                                       L->TB + n * c.D / 65536 + 16);
+  L->slot_max = slot_max;
+  // Budgets scale with the data: a batch holds as many tasks as fit, and any
+  // single task fits (its slots need at most max(slot, n D / 2 + W * 256)).
+  const uint64_t data_budget = n * c.D / 4 + 4 * slot_max + (uint64_t)WG_TARGET * 256;
+  L->SB = std::min<uint64_t>((uint64_t)WG_TARGET * slot_max, data_budget);
+  L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, std::max<uint64_t>(slot_max, data_budget));
+  L->FB = n / bmin + L->TB + 1;
+  L->PB = (uint64_t)L->TB * (2 * nbm + 2) + L->WB + L->FB / c.cmax + 16;
+  L->PWB = GRP_TARGET / 4 + 2 * L->TB + 16;
+  L->NBE = L->TB * (uint32_t)(nbm + 1);
+  L->LTB = L->TB * (uint32_t)nbm + 1;
+  size_t sz[R_COUNT];
+  sz[R_CTRL] = CTRL_WORDS * 4;
+  sz[R_TASKS] = (size_t)L->TB * sizeof(PTask);
+  sz[R_RECS] = (size_t)L->TB * sizeof(StepRec);
+  sz[R_CLS] = (size_t)L->WB * 4;
+  sz[R_PERM] = (size_t)L->PWB * 4;
+  sz[R_CLN] = (size_t)L->TB * nbm * 4;
+  sz[R_NFULL] = (size_t)L->WB * MAX_NB * 4;
+  sz[R_LEFT] = (size_t)L->WB * MAX_NB * 4;
+  sz[R_F] = (size_t)L->WB * 4;
+  sz[R_WMIN] = c.radix ? (size_t)L->WB * MAX_K * 8 : 0;
+  sz[R_WMAX] = sz[R_WMIN];
+  sz[R_SLOTS] = L->SB;
+  sz[R_SPILL] = L->SPB;
+  sz[R_OVF] = (size_t)L->TB * MAX_BLOCK_BYTES;
+  sz[R_FLAGS] = L->FB * 4;
+  sz[R_BSTART] = (size_t)L->NBE * 8;
+  sz[R_BCOUNT] = (size_t)L->NBE * 4;
+  sz[R_BD] = (size_t)L->NBE * 4;
+  sz[R_BPLB] = (size_t)L->NBE * 4;
+  sz[R_BPLE] = (size_t)L->NBE * 4;
+  sz[R_BMIN] = c.radix ? (size_t)L->NBE * 8 : 0;
+  sz[R_BMAX] = sz[R_BMIN];
+  sz[R_PWORD] = L->PB * 8;
+  sz[R_PA] = L->PB * 4;
+  sz[R_PC] = L->PB * 4;
+  sz[R_PR] = L->PB * 4;
+  sz[R_PCUM] = L->PB * 4;
+  sz[R_TNP] = (size_t)L->TB * 4;
+  sz[R_TUP] = (size_t)L->TB * 4;
+  sz[R_LT] = (size_t)L->LTB * sizeof(LTask);
+  size_t off = 0;
+  for (int r = 0; r < R_COUNT; ++r) {
+    L->off[r] = off;
+    off += (sz[r] + 255) & ~(size_t)255;
+  }
+  L->total = off;
+}
+
+struct HTask {
+  uint64_t l, n;
+  uint32_t level, tflags, shift, width;
+};
+
+}  // namespace
+
+struct ips_ctx {
+  int device = 0;
+  int last_hip = 0;
+  int last_dev = 0;
+  ips_root_info root;
+  ips_stats stats;
+  uint8_t* pin = nullptr;   // pinned staging
+  size_t pin_bytes = 0;
+};
+
+namespace {
+
+#define HIPCHK(ctx, expr)                        \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) {                      \
+      (ctx)->last_hip = (int)e_;                 \
+      return IPS_E_HIP;                          \
+    }                                            \
+  } while (0)
+
+int ensure_pinned(ips_ctx* ctx, size_t bytes) {
+  if (ctx->pin_bytes >= bytes) return IPS_OK;
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  ctx->pin = nullptr;
+  ctx->pin_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 20);
+  HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->pin), want, hipHostMallocDefault));
+  ctx->pin_bytes = want;
+  return IPS_OK;
+}
+
+struct Run {
+  ips_ctx* ctx;
+  Cfg c;
+  Layout L;
+  uint8_t* ws;
+  uint32_t* data;
+  uint64_t n;
+  hipStream_t st;
+  BatchArgs a;
+  // pinned staging areas
+  PTask* h_tasks;
+  uint32_t* h_maps;   // cls | perm | cln
+  LTask* h_lt;
+  uint8_t* h_rb;      // readback
+  size_t rb_bytes;
+  uint32_t* h_ctrl;
+};
+
+template <class P>
+P* wsp(Run& r, Region reg) { return reinterpret_cast<P*>(r.ws + r.L.off[reg]); }
+
+int check_dev_error(Run& r) {
+  uint32_t err = r.h_ctrl[CTRL_ERR];
+  if (err) {
+    r.ctx->last_dev = (int)((err & 0xFFu) | ((r.h_ctrl[CTRL_ERR_A] & 0xFFFu) << 8) |
+                            ((r.h_ctrl[CTRL_ERR_B] & 0xFFFu) << 20));
+    return IPS_E_DEVICE;
+  }
+  return IPS_OK;
+}
+
+int read_ctrl(Run& r) {
+  HIPCHK(r.ctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st));
+  HIPCHK(r.ctx, hipStreamSynchronize(r.st));
+  return check_dev_error(r);
+}
+
+int launch_lds_tasks(Run& r, const std::vector<LTask>& lt) {
+  size_t done = 0;
+  while (done < lt.size()) {
+    const size_t cnt = std::min<size_t>(lt.size() - done, r.L.LTB);
+    std::memcpy(r.h_lt, lt.data() + done, cnt * sizeof(LTask));
+    LTask* d_lt = wsp<LTask>(r, R_LT);
+    HIPCHK(r.ctx, hipMemcpyAsync(d_lt, r.h_lt, cnt * sizeof(LTask), hipMemcpyHostToDevice, r.st));
+    HIPCHK(r.ctx, r.c.L->lds_sort(d_lt, (uint32_t)cnt, r.data, r.c.cap, r.a.ctrl, r.st));
+    done += cnt;
+    r.ctx->stats.lds_tasks += (uint32_t)cnt;
+    if (done < lt.size()) {   // the staging buffer is reused: wait for the copy
+      HIPCHK(r.ctx, hipStreamSynchronize(r.st));
+    }
+  }
+  return IPS_OK;
+}
+
+// Upper bounds of one task's resources before its step is sampled.
+struct Need {
+  uint64_t wg, slot, spill, flags, pieces;
+};
+
+Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
+  Need nd;
+  const uint64_t wub = std::max<uint64_t>(1, (uint64_t)WG_TARGET * t.n / std::max<uint64_t>(1, level_elems));
+  nd.wg = std::min<uint64_t>(std::min<uint64_t>(wub, WG_TARGET), r.L.WB);
+  nd.slot = std::min<uint64_t>(nd.wg * r.L.slot_max,
+                               std::max<uint64_t>(r.L.slot_max, t.n * r.c.D / 4 + nd.wg * 256));
+  nd.spill = r.L.slot_max;
+  const uint32_t bmin = block_elems(r.c, max_nb(r.c));
+  nd.flags = t.n / bmin + 1;
+  nd.pieces = 2 * (uint64_t)max_nb(r.c) + 2 + nd.wg + nd.flags / r.c.cmax + 1;
+  return nd;
+}
+
+int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::vector<HTask>& next,
+              bool root_level) {
+  ips_ctx* ctx = r.ctx;
+  const Cfg& c = r.c;
+  const uint32_t T = (uint32_t)bt.size();
+  // 1. Tasks and, for samplesort, the sampling phase.
+  for (uint32_t t = 0; t < T; ++t) {
+    PTask& p = r.h_tasks[t];
+    std::memset(&p, 0, sizeof(p));
+    p.l = bt[t].l;
+    p.n = bt[t].n;
+    p.level = bt[t].level;
+    p.tflags = bt[t].tflags | (c.radix ? TF_RADIX : 0u);
+    p.shift = bt[t].shift;
+    p.width = bt[t].width;
+  }
+  PTask* d_tasks = wsp<PTask>(r, R_TASKS);
+  StepRec* d_recs = wsp<StepRec>(r, R_RECS);
+  struct Hdr { uint32_t K, logK, eq, nb, u, alpha, kp, m; };
+  std::vector<Hdr> hdr(T);
+  if (!c.radix) {
+    HIPCHK(ctx, hipMemcpyAsync(d_tasks, r.h_tasks, T * sizeof(PTask), hipMemcpyHostToDevice, r.st));
+    HIPCHK(ctx, c.L->sample(r.a, T, c.seed, c.k, c.n0, r.st));
+    HIPCHK(ctx, hipMemcpy2DAsync(r.h_rb, sizeof(Hdr), d_recs, sizeof(StepRec), sizeof(Hdr), T,
+                                 hipMemcpyDeviceToHost, r.st));
+    HIPCHK(ctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st));
+    HIPCHK(ctx, hipStreamSynchronize(r.st));
+    if (int e = check_dev_error(r)) return e;
+    std::memcpy(hdr.data(), r.h_rb, T * sizeof(Hdr));
+  } else {
+    for (uint32_t t = 0; t < T; ++t) {
+      Hdr& h = hdr[t];
+      std::memset(&h, 0, sizeof(h));
+      h.K = 1u << bt[t].width;
+      h.logK = bt[t].width;
+      h.nb = h.K;
+    }
+  }
+  // 2. Geometry of every task.
+  uint64_t nb_sum = 0, blocks_sum = 0;
+  std::vector<uint32_t> bvec(T), NBv(T), nbv(T);
+  for (uint32_t t = 0; t < T; ++t) {
+    nbv[t] = hdr[t].nb;
+    bvec[t] = block_elems(c, nbv[t]);
+    NBv[t] = (uint32_t)((bt[t].n + bvec[t] - 1) / bvec[t]);
+    nb_sum += nbv[t];
+    blocks_sum += NBv[t];
+  }
+  uint32_t wg = 0, pwg = 0, maxW = 1, cln = 0;
+  uint64_t slot_off = 0, spill_off = 0, flag_off = 0;
+  uint32_t piece = 0, bucket = 0;
+  uint32_t* h_cls = r.h_maps;
+  uint32_t* h_perm = h_cls + r.L.WB;
+  uint32_t* h_cln = h_perm + r.L.PWB;
+  size_t max_dyn = 0;
+  for (uint32_t t = 0; t < T; ++t) {
+    PTask& p = r.h_tasks[t];
+    const uint32_t b = bvec[t], nb = nbv[t], NB = NBv[t];
+    p.nb = nb;
+    p.K = hdr[t].K;
+    p.logK = hdr[t].logK;
+    p.eq = hdr[t].eq;
+    p.b = b;
+    p.NB = NB;
+    uint64_t W = std::max<uint64_t>(1, (uint64_t)WG_TARGET * p.n / std::max<uint64_t>(1, level_elems));
+    W = std::min<uint64_t>(W, std::max<uint64_t>(1, p.n / (4ull * nb * b)));
+    W = std::min<uint64_t>(W, NB);
+    W = std::min<uint64_t>(W, WG_TARGET);
+    W = std::min<uint64_t>(W, r.L.WB);
+    p.W = (uint32_t)W;
+    p.wg_base = wg;
+    for (uint32_t s = 0; s < p.W; ++s) h_cls[wg + s] = t;
+    wg += p.W;
+    maxW = std::max(maxW, p.W);
+    p.slot_bytes = (uint32_t)(((uint64_t)nb * b * c.D + 255) & ~255ull);
+    p.slot_off = slot_off;
+    slot_off += (uint64_t)p.W * p.slot_bytes;
+    p.spill_off = spill_off;
+    spill_off += p.slot_bytes;
+    p.flag_off = flag_off;
+    flag_off += NB;
+    p.piece_base = piece;
+    p.piece_cap = 2 * nb + 2 + p.W + NB / c.cmax + 1;
+    piece += p.piece_cap;
+    p.bucket_base = bucket;
+    bucket += nb + 1;
+    const uint32_t bdw = b * c.DW;
+    uint32_t gl = 4;
+    while (gl * 8 < bdw) gl *= 2;
+    p.glanes = gl;
+    uint64_t ng = std::max<uint64_t>(1, std::min<uint64_t>(NB / 4, (uint64_t)GRP_TARGET * NB / std::max<uint64_t>(1, blocks_sum)));
+    p.ngrp = (uint32_t)ng;
+    const uint32_t gpw = PERM_THREADS / gl;
+    const uint32_t nwg = (uint32_t)((ng + gpw - 1) / gpw);
+    p.pwg_base = pwg;
+    for (uint32_t x = 0; x < nwg; ++x) h_perm[pwg + x] = t;
+    pwg += nwg;
+    for (uint32_t j = 0; j < nb; ++j) h_cln[cln++] = (t << 10) | j;
+    if (!c.gbuf) max_dyn = std::max<size_t>(max_dyn, (size_t)nb * b * c.D);
+  }
+  if (wg > r.L.WB || pwg > r.L.PWB || slot_off > r.L.SB || spill_off > r.L.SPB || flag_off > r.L.FB ||
+      piece > r.L.PB || bucket > r.L.NBE || cln > r.L.TB * max_nb(c)) {
+    ctx->last_dev = 0x100;
+    return IPS_E_DEVICE;
+  }
+  // 3. Upload and run the phases.
+  HIPCHK(ctx, hipMemcpyAsync(d_tasks, r.h_tasks, T * sizeof(PTask), hipMemcpyHostToDevice, r.st));
+  HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_CLS), h_cls, wg * 4, hipMemcpyHostToDevice, r.st));
+  HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_PERM), h_perm, pwg * 4, hipMemcpyHostToDevice, r.st));
+  HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_CLN), h_cln, cln * 4, hipMemcpyHostToDevice, r.st));
+  HIPCHK(ctx, c.L->classify(r.a, wg, (uint32_t)max_dyn, c.gbuf, r.st));
+  HIPCHK(ctx, launch_boundaries(r.a, T, c.cmax, r.st));
+  HIPCHK(ctx, launch_fill32(r.a.flags, flag_off, 0u, r.st));
+  HIPCHK(ctx, c.L->permute(r.a, pwg, r.st));
+  HIPCHK(ctx, c.L->cleanup_a(r.a, T, r.st));
+  HIPCHK(ctx, c.L->cleanup_b(r.a, cln, maxW, r.st));
+  // 4. Bucket boundaries back to the host.
+  const size_t sb_bytes = (size_t)bucket * 8;
+  const size_t mm_bytes = c.radix ? (size_t)bucket * 8 : 0;
+  if (sb_bytes + 2 * mm_bytes > r.rb_bytes) { ctx->last_dev = 0x101; return IPS_E_DEVICE; }
+  HIPCHK(ctx, hipMemcpyAsync(r.h_rb, r.a.b_start, sb_bytes, hipMemcpyDeviceToHost, r.st));
+  if (c.radix) {
+    HIPCHK(ctx, hipMemcpyAsync(r.h_rb + sb_bytes, r.a.b_min, mm_bytes, hipMemcpyDeviceToHost, r.st));
+    HIPCHK(ctx, hipMemcpyAsync(r.h_rb + sb_bytes + mm_bytes, r.a.b_max, mm_bytes, hipMemcpyDeviceToHost, r.st));
+  }
+  if (int e = read_ctrl(r)) return e;
+  const uint64_t* hstart = reinterpret_cast<const uint64_t*>(r.h_rb);
+  const uint64_t* hmin = reinterpret_cast<const uint64_t*>(r.h_rb + sb_bytes);
+  const uint64_t* hmax = reinterpret_cast<const uint64_t*>(r.h_rb + sb_bytes + mm_bytes);
+  ctx->stats.steps += T;
+  ctx->stats.batches += 1;
+  // Root-step description for ips_get_root_info.
+  if (root_level && T == 1) {
+    ips_root_info& ri = ctx->root;
+    const PTask& p = r.h_tasks[0];
+    ri.valid = 1;
+    ri.algo = c.radix ? 1 : 0;
+    ri.alpha = hdr[0].alpha;
+    ri.k_prime = hdr[0].kp;
+    ri.m = hdr[0].m;
+    ri.u = hdr[0].u;
+    ri.K = p.K;
+    ri.eq = p.eq;
+    ri.nb = p.nb;
+    ri.radix_shift = p.shift;
+    ri.radix_width = p.width;
+    ri.block_elems = p.b;
+    ri.stripes = p.W;
+    ri.n = p.n;
+    for (uint32_t j = 0; j <= p.nb && j < 513; ++j) ri.bucket_start[j] = hstart[p.bucket_base + j];
+    if (!c.radix) {
+      std::vector<uint64_t> spl((size_t)p.K * 2);
+      HIPCHK(ctx, hipMemcpy(spl.data(), &d_recs[0].spl[0][0], spl.size() * 8, hipMemcpyDeviceToHost));
+      for (uint32_t i = 0; i < p.K && i < 256; ++i) {
+        uint64_t k0 = spl[2 * i], k1 = spl[2 * i + 1];
+        if (c.type == 3) k0 = (k0 >> 63) ? (k0 & ~(1ull << 63)) : ~k0;   // ordered image -> bits
+        if (c.type == 5) {
+          uint8_t* d = ri.splitters[i];
+          for (int q = 0; q < 8; ++q) d[q] = (uint8_t)(k0 >> (56 - 8 * q));
+          d[8] = (uint8_t)(k1 >> 8);
+          d[9] = (uint8_t)k1;
+        } else {
+          std::memcpy(ri.splitters[i], &k0, 8);
+        }
+      }
+    }
+  }
+  if (c.flags & IPS_FLAG_LEVEL1_ONLY) return IPS_OK;
+  // 5. Children: next-level tasks and LDS-tier tasks.
+  std::vector<LTask> lt;
+  for (uint32_t t = 0; t < T; ++t) {
+    const PTask& p = r.h_tasks[t];
+    ctx->stats.partitioned_elems += p.n;
+    ctx->stats.max_step_elems = std::max<uint64_t>(ctx->stats.max_step_elems, p.n);
+    for (uint32_t j = 0; j < p.nb; ++j) {
+      const uint64_t s0 = hstart[p.bucket_base + j], s1 = hstart[p.bucket_base + j + 1];
+      const uint64_t sz = s1 - s0;
+      if (sz <= 1) continue;
+      if (!c.radix && p.eq && (j & 1u) && j != 2 * p.K - 1) continue;   // equality bucket
+      HTask ch;
+      ch.l = p.l + s0;
+      ch.n = sz;
+      ch.level = p.level + 1;
+      ch.tflags = 0;
+      ch.shift = 0;
+      ch.width = 0;
+      if (c.radix) {
+        const uint64_t mn = hmin[p.bucket_base + j], mx = hmax[p.bucket_base + j];
+        if (mn == mx) continue;
+        const uint32_t h = 63u - (uint32_t)__builtin_clzll(mn ^ mx);
+        ch.shift = h >= 7 ? h - 7 : 0;
+        ch.width = h - ch.shift + 1;
+      } else if (sz == p.n) {
+        ch.tflags = TF_EQ_ON;   // no progress without equality buckets
+      }
+      if (sz <= c.cap) {
+        LTask q;
+        q.l = ch.l;
+        q.n = (uint32_t)sz;
+        q.pad = 0;
+        lt.push_back(q);
+        ctx->stats.lds_elems += sz;
+      } else {
+        next.push_back(ch);
+      }
+    }
+  }
+  return launch_lds_tasks(r, lt);
+}
+
+int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
+              const ips_params* params, void* stream) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  Run r;
+  std::memset(&r.a, 0, sizeof(r.a));
+  int rc = make_cfg(n, type, algo, params, &r.c);
+  if (rc) return rc;
+  if (n > 0 && !d) return IPS_E_INVALID_ARG;
+  const uint32_t align = (type == 1 || type == 5) ? 4 : 8;
+  if (reinterpret_cast<uintptr_t>(d) % align) return IPS_E_MISALIGNED;
+  if (n >= (1ull << 31) * (uint64_t)block_elems(r.c, max_nb(r.c))) return IPS_E_TOO_LARGE;
+  std::memset(&ctx->root, 0, sizeof(ctx->root));
+  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  ctx->last_dev = 0;
+  if (n < 2) return IPS_OK;
+  plan(n, r.c, &r.L);
+  if (!ws) return IPS_E_INVALID_ARG;
+  if (ws_bytes < r.L.total) return IPS_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return IPS_E_MISALIGNED;
+  r.c.L = launchers_for(type);
+  r.ctx = ctx;
+  r.ws = static_cast<uint8_t*>(ws);
+  r.data = static_cast<uint32_t*>(d);
+  r.n = n;
+  r.st = static_cast<hipStream_t>(stream);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  // Pinned staging: tasks | maps | LDS tasks | readback | ctrl.
+  const size_t b_tasks = (size_t)r.L.TB * sizeof(PTask);
+  const size_t b_maps = ((size_t)r.L.WB + r.L.PWB + (size_t)r.L.TB * max_nb(r.c)) * 4;
+  const size_t b_lt = (size_t)r.L.LTB * sizeof(LTask);
+  const size_t b_rb = std::max<size_t>((size_t)r.L.NBE * 24, (size_t)r.L.TB * 64) + 4096;
+  const size_t b_ctrl = CTRL_WORDS * 4;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  if (int e = ensure_pinned(ctx, al(b_tasks) + al(b_maps) + al(b_lt) + al(b_rb) + al(b_ctrl))) return e;
+  uint8_t* pp = ctx->pin;
+  r.h_tasks = reinterpret_cast<PTask*>(pp); pp += al(b_tasks);
+  r.h_maps = reinterpret_cast<uint32_t*>(pp); pp += al(b_maps);
+  r.h_lt = reinterpret_cast<LTask*>(pp); pp += al(b_lt);
+  r.h_rb = pp; r.rb_bytes = b_rb; pp += al(b_rb);
+  r.h_ctrl = reinterpret_cast<uint32_t*>(pp);
+  // Device views of the workspace.
+  BatchArgs& a = r.a;
+  a.data = r.data;
+  a.ctrl = wsp<uint32_t>(r, R_CTRL);
+  a.tasks = wsp<PTask>(r, R_TASKS);
+  a.recs = wsp<StepRec>(r, R_RECS);
+  a.cls_task = wsp<uint32_t>(r, R_CLS);
+  a.perm_task = wsp<uint32_t>(r, R_PERM);
+  a.cln_map = wsp<uint32_t>(r, R_CLN);
+  a.wg_nfull = wsp<uint32_t>(r, R_NFULL);
+  a.wg_left = wsp<uint32_t>(r, R_LEFT);
+  a.wg_F = wsp<uint32_t>(r, R_F);
+  a.wg_min = wsp<uint64_t>(r, R_WMIN);
+  a.wg_max = wsp<uint64_t>(r, R_WMAX);
+  a.slots = wsp<uint8_t>(r, R_SLOTS);
+  a.spill = wsp<uint8_t>(r, R_SPILL);
+  a.ovf = wsp<uint32_t>(r, R_OVF);
+  a.flags = wsp<uint32_t>(r, R_FLAGS);
+  a.b_start = wsp<uint64_t>(r, R_BSTART);
+  a.b_count = wsp<uint32_t>(r, R_BCOUNT);
+  a.b_d = wsp<uint32_t>(r, R_BD);
+  a.b_plb = wsp<uint32_t>(r, R_BPLB);
+  a.b_ple = wsp<uint32_t>(r, R_BPLE);
+  a.b_min = wsp<uint64_t>(r, R_BMIN);
+  a.b_max = wsp<uint64_t>(r, R_BMAX);
+  a.p_word = wsp<uint64_t>(r, R_PWORD);
+  a.p_a = wsp<uint32_t>(r, R_PA);
+  a.p_c = wsp<uint32_t>(r, R_PC);
+  a.p_rinit = wsp<int32_t>(r, R_PR);
+  a.p_cum = wsp<uint32_t>(r, R_PCUM);
+  a.t_npieces = wsp<uint32_t>(r, R_TNP);
+  a.t_unproc = wsp<uint32_t>(r, R_TUP);
+  a.gbuf = r.c.gbuf ? 1 : 0;
+  // Control block: errors and flags cleared; min = all ones, max = 0.
+  HIPCHK(ctx, launch_fill32(a.ctrl, CTRL_WORDS, 0u, r.st));
+  HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_MINMAX, 2, 0xFFFFFFFFu, r.st));
+  // Sorted and reverse-sorted inputs (Section 6).
+  if (!(r.c.flags & (IPS_FLAG_NO_SORTED_CHECK | IPS_FLAG_LEVEL1_ONLY))) {
+    HIPCHK(ctx, r.c.L->sorted_check(r.data, n, a.ctrl, r.st));
+    if (int e = read_ctrl(r)) return e;
+    if (!r.h_ctrl[CTRL_DESC]) { ctx->stats.detected = 1; return IPS_OK; }
+    if (!r.h_ctrl[CTRL_ASC]) {
+      ctx->stats.detected = 2;
+      HIPCHK(ctx, r.c.L->reverse(r.data, n, r.st));
+      HIPCHK(ctx, hipStreamSynchronize(r.st));
+      return IPS_OK;
+    }
+  }
+  HTask root;
+  root.l = 0;
+  root.n = n;
+  root.level = 0;
+  root.tflags = 0;
+  root.shift = 0;
+  root.width = 0;
+  if (r.c.flags & IPS_FLAG_EQ_ON) root.tflags |= TF_EQ_ON;
+  if (r.c.flags & IPS_FLAG_EQ_OFF) root.tflags |= TF_EQ_OFF;
+  if (r.c.radix) {
+    HIPCHK(ctx, r.c.L->minmax(r.data, n, a.ctrl, r.st));
+    if (int e = read_ctrl(r)) return e;
+    const uint64_t mn = (uint64_t)r.h_ctrl[CTRL_MINMAX] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 1] << 32);
+    const uint64_t mx = (uint64_t)r.h_ctrl[CTRL_MINMAX + 2] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 3] << 32);
+    if (mn == mx) return IPS_OK;
+    const uint32_t h = 63u - (uint32_t)__builtin_clzll(mn ^ mx);
+    root.shift = h >= 7 ? h - 7 : 0;
+    root.width = h - root.shift + 1;
+  }
+  if (n <= r.c.cap && !(r.c.flags & IPS_FLAG_LEVEL1_ONLY)) {
+    std::vector<LTask> lt(1);
+    lt[0].l = 0;
+    lt[0].n = (uint32_t)n;
+    lt[0].pad = 0;
+    ctx->stats.lds_elems += n;
+    if (int e = launch_lds_tasks(r, lt)) return e;
+    return read_ctrl(r);
+  }
+  std::vector<HTask> cur(1, root), next;
+  uint32_t level = 0;
+  while (!cur.empty()) {
+    uint64_t level_elems = 0;
+    for (const HTask& t : cur) level_elems += t.n;
+    next.clear();
+    size_t i = 0;
+    while (i < cur.size()) {
+      std::vector<HTask> bt;
+      Need tot{0, 0, 0, 0, 0};
+      while (i < cur.size() && bt.size() < r.L.TB) {
+        Need nd = task_need(r, cur[i], level_elems);
+        if (!bt.empty() && (tot.wg + nd.wg > r.L.WB || tot.slot + nd.slot > r.L.SB ||
+                            tot.spill + nd.spill > r.L.SPB || tot.flags + nd.flags > r.L.FB ||
+                            tot.pieces + nd.pieces > r.L.PB))
+          break;
+        tot.wg += nd.wg; tot.slot += nd.slot; tot.spill += nd.spill;
+        tot.flags += nd.flags; tot.pieces += nd.pieces;
+        bt.push_back(cur[i++]);
+      }
+      if (int e = run_batch(r, bt, level_elems, next, level == 0)) return e;
+      if (r.c.flags & IPS_FLAG_LEVEL1_ONLY) return IPS_OK;
+    }
+    ctx->stats.levels = ++level;
+    std::swap(cur, next);
+  }
+  return read_ctrl(r);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ips_abi_version(void) { return IPS_ABI_VERSION; }
+
+const char* ips_status_string(int s) {
+  switch (s) {
+    case IPS_OK: return "IPS_OK";
+    case IPS_E_INVALID_ARG: return "IPS_E_INVALID_ARG: invalid argument";
+    case IPS_E_UNSUPPORTED: return "IPS_E_UNSUPPORTED: unsupported type/algorithm combination";
+    case IPS_E_WORKSPACE: return "IPS_E_WORKSPACE: workspace too small";
+    case IPS_E_MISALIGNED: return "IPS_E_MISALIGNED: pointer not aligned";
+    case IPS_E_TOO_LARGE: return "IPS_E_TOO_LARGE: too many elements";
+    case IPS_E_HIP: return "IPS_E_HIP: HIP runtime error";
+    case IPS_E_DEVICE: return "IPS_E_DEVICE: kernel consistency error";
+    case IPS_E_NO_DEVICE: return "IPS_E_NO_DEVICE: no usable device";
+    default: return "unknown status";
+  }
+}
+
+int ips_ctx_create(ips_ctx** out, int device) {
+  if (!out) return IPS_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return IPS_E_NO_DEVICE;
+  ips_ctx* c = new (std::nothrow) ips_ctx();
+  if (!c) return IPS_E_INVALID_ARG;
+  c->device = device;
+  std::memset(&c->root, 0, sizeof(c->root));
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  *out = c;
+  return IPS_OK;
+}
+
+int ips_ctx_destroy(ips_ctx* ctx) {
+  if (!ctx) return IPS_OK;
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  delete ctx;
+  return IPS_OK;
+}
+
+int ips_workspace_bytes(uint64_t n, int elem_type, int algo, const ips_params* params,
+                        size_t* out_bytes) {
+  if (!out_bytes) return IPS_E_INVALID_ARG;
+  *out_bytes = 0;
+  Cfg c;
+  int rc = make_cfg(n, elem_type, algo, params, &c);
+  if (rc) return rc;
+  if (n >= (1ull << 31) * (uint64_t)block_elems(c, max_nb(c))) return IPS_E_TOO_LARGE;
+  if (n < 2) return IPS_OK;
+  Layout L;
+  plan(n, c, &L);
+  *out_bytes = L.total;
+  return IPS_OK;
+}
+
+int ips_sort_keys(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, int algo, void* d_ws,
+                  size_t ws_bytes, const ips_params* params, void* stream) {
+  if (key_type != IPS_U32 && key_type != IPS_U64 && key_type != IPS_F64) return IPS_E_INVALID_ARG;
+  return sort_impl(ctx, d_keys, n, key_type, algo, d_ws, ws_bytes, params, stream);
+}
+
+int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type, int algo, void* d_ws,
+                   size_t ws_bytes, const ips_params* params, void* stream) {
+  if (rec_type != IPS_PAIR_U64_U64 && rec_type != IPS_REC100) return IPS_E_INVALID_ARG;
+  return sort_impl(ctx, d_recs, n, rec_type, algo, d_ws, ws_bytes, params, stream);
+}
+
+int ips_get_root_info(ips_ctx* ctx, ips_root_info* out) {
+  if (!ctx || !out) return IPS_E_INVALID_ARG;
+  *out = ctx->root;
+  return IPS_OK;
+}
+
+int ips_get_stats(ips_ctx* ctx, ips_stats* out) {
+  if (!ctx || !out) return IPS_E_INVALID_ARG;
+  *out = ctx->stats;
+  return IPS_OK;
+}
+
+int ips_last_hip_error(ips_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+int ips_last_device_error(ips_ctx* ctx) { return ctx ? ctx->last_dev : 0; }
+
+}  // extern "C"

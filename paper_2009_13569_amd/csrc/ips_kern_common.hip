@@ -1,0 +1,21 @@
+// Kernels that do not depend on the element type.
+#define IPS_COMMON_KERNELS 1
+#include "ips_kernels.hpp"
+#include "ips_launch.hpp"
+
+namespace ips {
+
+hipError_t launch_boundaries(const BatchArgs& a, uint32_t nt, uint32_t cmax, hipStream_t st) {
+  if (!nt) return hipSuccess;
+  hipLaunchKernelGGL(k_boundaries, dim3(nt), dim3(512), 0, st, a, cmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  uint32_t g = (uint32_t)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill32, dim3(g), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace ips

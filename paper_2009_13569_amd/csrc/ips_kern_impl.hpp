@@ -1,0 +1,99 @@
+// Launcher table for one element type.  Included once per type by the
+// ips_kern_<type>.hip translation units.
+#pragma once
+#include "ips_kernels.hpp"
+#include "ips_launch.hpp"
+
+namespace ips {
+
+template <class T>
+struct LaunchImpl {
+  static size_t lds_bytes(uint32_t cap) {
+    uint32_t P = 2;
+    while (P < cap) P <<= 1;
+    size_t bytes = (size_t)P * sizeof(typename T::Key);
+    if (!T::KEYS_ONLY) bytes += (size_t)P * 4 + (size_t)cap * T::DW * 4;
+    return bytes;
+  }
+  static hipError_t sample_(const BatchArgs& a, uint32_t nt, uint64_t seed, uint32_t k, uint32_t n0,
+                           hipStream_t st) {
+    if (!nt) return hipSuccess;
+    hipLaunchKernelGGL((k_sample<T>), dim3(nt), dim3(SMP_THREADS), 0, st, a, seed, k, n0);
+    return hipGetLastError();
+  }
+  static hipError_t classify(const BatchArgs& a, uint32_t nwg, uint32_t dyn, bool gbuf, hipStream_t st) {
+    if (!nwg) return hipSuccess;
+    static bool attr_done = false;
+    if (!attr_done) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_classify<T, false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)BUF_LDS_BYTES);
+      attr_done = true;
+    }
+    if (gbuf)
+      hipLaunchKernelGGL((k_classify<T, true>), dim3(nwg), dim3(CLS_THREADS), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_classify<T, false>), dim3(nwg), dim3(CLS_THREADS), dyn, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t permute(const BatchArgs& a, uint32_t nwg, hipStream_t st) {
+    if (!nwg) return hipSuccess;
+    hipLaunchKernelGGL((k_permute<T>), dim3(nwg), dim3(PERM_THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t cleanup_a(const BatchArgs& a, uint32_t nt, hipStream_t st) {
+    if (!nt) return hipSuccess;
+    hipLaunchKernelGGL((k_cleanup_a<T>), dim3(nt), dim3(CLN_THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t cleanup_b(const BatchArgs& a, uint32_t nwg, uint32_t max_w, hipStream_t st) {
+    if (!nwg) return hipSuccess;
+    const size_t dyn = (size_t)(max_w + 3) * sizeof(uint64_t);
+    hipLaunchKernelGGL((k_cleanup_b<T>), dim3(nwg), dim3(CLN_THREADS), dyn, st, a, max_w);
+    return hipGetLastError();
+  }
+  static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t cap, uint32_t* ctrl,
+                             hipStream_t st) {
+    if (!nt) return hipSuccess;
+    static bool attr_done = false;
+    const size_t dyn = lds_bytes(cap);
+    if (!attr_done) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_sort<T>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr_done = true;
+    }
+    hipLaunchKernelGGL((k_lds_sort<T>), dim3(nt), dim3(LDST_THREADS), dyn, st, lt, data, cap, ctrl);
+    return hipGetLastError();
+  }
+  static hipError_t sorted_check(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
+    uint64_t chunks = (n + 4095) / 4096;
+    uint32_t g = (uint32_t)(chunks < 2048 ? (chunks ? chunks : 1) : 2048);
+    hipLaunchKernelGGL((k_sorted_check<T>), dim3(g), dim3(256), 0, st, data, n, ctrl);
+    return hipGetLastError();
+  }
+  static hipError_t reverse(uint32_t* data, uint64_t n, hipStream_t st) {
+    uint64_t half = n / 2;
+    uint32_t g = (uint32_t)((half + 255) / 256 < 4096 ? (half + 255) / 256 : 4096);
+    if (!g) return hipSuccess;
+    hipLaunchKernelGGL((k_reverse<T::DW>), dim3(g), dim3(256), 0, st, data, n);
+    return hipGetLastError();
+  }
+  static hipError_t minmax(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
+    if constexpr (T::RADIX_OK) {
+      uint32_t g = (uint32_t)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+      if (!g) g = 1;
+      hipLaunchKernelGGL((k_minmax<T>), dim3(g), dim3(256), 0, st, data, n, ctrl);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  static const Launchers* table() {
+    static const Launchers t = {
+        T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
+        0, &lds_bytes, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
+        &sorted_check, &reverse, &minmax};
+    return &t;
+  }
+};
+
+}  // namespace ips

@@ -1,0 +1,1040 @@
+// gfx950 kernels of the in-place partitioning step of IPS4o / IPS2Ra
+// (arXiv 2009.13569, Section 4.1) and the LDS-resident base case.
+//
+// One partitioning step on a batch of tasks runs as:
+//   k_sample      sampling, splitter selection, decision tree   (Sec. 4.1)
+//   k_classify    classification into per-bucket buffer blocks; full blocks
+//                 are flushed to the front of the workgroup's stripe
+//   k_boundaries  bucket sizes, delimiters, read/write pointer pieces
+//   k_permute     block permutation with atomic read/write pointers
+//   k_cleanup_a/b cleanup of bucket heads/tails (Section 4.1 "Cleanup")
+// Tasks small enough for one workgroup's LDS are sorted by k_lds_sort.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ips_common.hpp"
+#include "ips_traits.hpp"
+
+namespace ips {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint64_t at_load64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t at_add64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t at_load32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void at_store32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void dev_error(uint32_t* ctrl, uint32_t code, uint32_t x,
+                                          uint32_t y) {
+  if (atomicCAS(&ctrl[CTRL_ERR], 0u, code) == 0u) {
+    ctrl[CTRL_ERR_A] = x;
+    ctrl[CTRL_ERR_B] = y;
+  }
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output j of the generator seeded
+// with s is mix(s + (j+1) * gamma).
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm64_at(uint64_t s, uint64_t j) {
+  return sm64_mix(s + (j + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+__device__ __forceinline__ uint32_t ilog2_u64(uint64_t x) { return 63u - __clzll(x); }
+
+// Oversampling factor floor(0.2 log2 n), at least 1 (Section 6).
+__device__ __forceinline__ uint32_t step_alpha(uint64_t n) {
+  uint32_t a = ilog2_u64(n > 0 ? n : 1) / 5;
+  return a ? a : 1;
+}
+
+// Adaptive number of buckets (Section 4.2): 2^ceil((log2(n/n0)+1)/2) for
+// k n0 < n < k^2 n0, 2^ceil(log2(n/n0)) for n0 < n <= k n0, otherwise k;
+// decided exactly in integers and clamped to [2, k].
+__device__ __forceinline__ uint32_t step_kprime(uint64_t n, uint32_t k, uint32_t n0) {
+  const uint64_t kn0 = (uint64_t)k * n0, kkn0 = kn0 * k;
+  uint64_t r = k;
+  if (n > kn0 && n < kkn0) {
+    uint32_t c = 1;
+    while (((uint64_t)n0 << (2 * c - 1)) < n) ++c;
+    r = 1ull << c;
+  } else if (n > n0 && n <= kn0) {
+    uint32_t c = 0;
+    while (((uint64_t)n0 << c) < n) ++c;
+    r = 1ull << c;
+  }
+  if (r > k) r = k;
+  if (r < 2) r = 2;
+  return (uint32_t)r;
+}
+
+__device__ __forceinline__ uint64_t step_task_seed(uint64_t seed, uint64_t l, uint32_t level) {
+  return sm64_mix((seed ^ (l * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)level << 56)) +
+                  0x9E3779B97F4A7C15ull);
+}
+
+template <int DW>
+__device__ __forceinline__ void ld_elem(const uint32_t* p, uint32_t (&w)[DW]) {
+  if constexpr (DW == 2) {
+    uint2 v = *reinterpret_cast<const uint2*>(p);
+    w[0] = v.x; w[1] = v.y;
+  } else if constexpr (DW == 4) {
+    uint2 v0 = *reinterpret_cast<const uint2*>(p);
+    uint2 v1 = *reinterpret_cast<const uint2*>(p + 2);
+    w[0] = v0.x; w[1] = v0.y; w[2] = v1.x; w[3] = v1.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < DW; ++i) w[i] = p[i];
+  }
+}
+template <int DW>
+__device__ __forceinline__ void st_elem(uint32_t* p, const uint32_t (&w)[DW]) {
+  if constexpr (DW == 2) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+  } else if constexpr (DW == 4) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+    *reinterpret_cast<uint2*>(p + 2) = make_uint2(w[2], w[3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < DW; ++i) p[i] = w[i];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ typename T::Key key_of(const uint32_t (&w)[T::DW]) {
+  constexpr int D = T::DW;
+  return T::key(w[0], w[D > 1 ? 1 : 0], w[D > 2 ? 2 : 0]);
+}
+
+// Branchless decision tree (Definitions and Preliminaries, Algorithm 1):
+// from node 1, i <- 2i + [tree_i < e] for log2 K levels; the leaf gives the
+// bucket i with s_{i-1} < e <= s_i.  With equality buckets the bucket
+// becomes 2i + 1 - [e < s_i], using s_{K-1} = s_{K-2}.
+template <class Key>
+__device__ __forceinline__ uint32_t tree_bucket(const Key* __restrict__ tree,
+                                                const Key* __restrict__ spl,
+                                                uint32_t logK, uint32_t eq, const Key& e) {
+  uint32_t i = 1;
+  for (uint32_t l = 0; l < logK; ++l) i = 2 * i + (kless(tree[i], e) ? 1u : 0u);
+  i -= (1u << logK);
+  if (eq) i = 2 * i + (kless(e, spl[i]) ? 0u : 1u);
+  return i;
+}
+
+template <class T>
+__device__ __forceinline__ uint32_t bucket_of(const typename T::Key& k, const typename T::Key* tree,
+                                              const typename T::Key* spl, uint32_t logK,
+                                              uint32_t eq, bool radix, uint32_t shift,
+                                              uint64_t rmask) {
+  if constexpr (T::RADIX_OK) {
+    if (radix) return (uint32_t)((T::rkey(k) >> shift) & rmask);
+  }
+  return tree_bucket(tree, spl, logK, eq, k);
+}
+
+// --------------------------------------------------------------- sampling
+
+// Bitonic sort of n2 (power of two) keys in LDS by all threads of the block.
+template <class Key>
+__device__ void lds_bitonic_keys(Key* a, uint32_t n2) {
+  for (uint32_t k = 2; k <= n2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < n2 / 2; i += blockDim.x) {
+        uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
+        bool up = (lo & k) == 0;
+        Key x = a[lo], y = a[hi];
+        if (kless(y, x) == up) { a[lo] = y; a[hi] = x; }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Sampling phase (Section 4.1) of every task of the batch: alpha k' samples
+// drawn with replacement at positions l + floor(n x_j / 2^64), sorted;
+// k'-1 equidistant splitters (the i-th at sorted position (i+1) alpha - 1);
+// duplicates removed; equality buckets iff a duplicate was removed; K the
+// next power of two >= u+1 with the splitters padded by the largest; tree
+// in breadth-first order.
+template <class T>
+__global__ void __launch_bounds__(SMP_THREADS)
+k_sample(BatchArgs a, uint64_t seed, uint32_t k, uint32_t n0) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  __shared__ Key s_smp[MAX_SAMPLE];
+  __shared__ Key s_spl[MAX_K];
+  __shared__ uint32_t s_u;
+  const uint32_t tix = blockIdx.x;
+  const PTask& tk = a.tasks[tix];
+  const uint64_t n = tk.n, l = tk.l;
+  StepRec* rec = a.recs + tix;
+  const uint32_t alpha = step_alpha(n);
+  const uint32_t kp = step_kprime(n, k, n0);
+  const uint32_t m = alpha * kp;
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  if (P > MAX_SAMPLE) {
+    if (threadIdx.x == 0) dev_error(a.ctrl, DE_SAMPLE, tix, m);
+    return;
+  }
+  const uint64_t ts = step_task_seed(seed, l, tk.level);
+  const uint32_t* gd = a.data + l * DW;
+  for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) {
+    if (j < m) {
+      uint64_t pos = __umul64hi(sm64_at(ts, j), n);
+      uint32_t w[DW];
+      ld_elem<DW>(gd + pos * DW, w);
+      s_smp[j] = key_of<T>(w);
+    } else {
+      s_smp[j] = T::kmax();
+    }
+  }
+  __syncthreads();
+  lds_bitonic_keys(s_smp, P);
+  if (threadIdx.x == 0) {
+    uint32_t u = 0;
+    for (uint32_t i = 0; i + 1 < kp; ++i) {
+      Key s = s_smp[(i + 1) * alpha - 1];
+      if (u > 0 && keq(s, s_spl[u - 1])) continue;
+      s_spl[u++] = s;
+    }
+    s_u = u;
+  }
+  __syncthreads();
+  const uint32_t u = s_u;
+  uint32_t eq = (u < kp - 1) ? 1u : 0u;
+  if (tk.tflags & TF_EQ_ON) eq = 1;
+  if (tk.tflags & TF_EQ_OFF) eq = 0;
+  uint32_t K = 1, logK = 0;
+  while (K < u + 1) { K <<= 1; ++logK; }
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+    Key v = s_spl[i < u ? i : u - 1];
+    T::to_slot(v, rec->spl[i]);
+  }
+  for (uint32_t i = threadIdx.x; i < MAX_K; i += blockDim.x) {
+    if (i >= 1 && i < K) {
+      uint32_t d = 31u - __clz(i);
+      uint32_t p = i - (1u << d);
+      uint32_t idx = ((2 * p + 1) << (logK - d - 1)) - 1;
+      Key v = s_spl[idx < u ? idx : u - 1];
+      T::to_slot(v, rec->tree[i]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    rec->K = K; rec->logK = logK; rec->eq = eq; rec->nb = eq ? 2 * K : K;
+    rec->u = u; rec->alpha = alpha; rec->kp = kp; rec->m = m;
+    rec->shift = 0; rec->width = 0; rec->radix = 0;
+  }
+}
+
+// --------------------------------------------------------- classification
+
+// Classification phase (Section 4.1): the workgroup scans its stripe of
+// blocks tile by tile, classifies each element, and appends it to the
+// buffer block of its bucket.  A full buffer block is written back to the
+// stripe at the front (the write position never passes the read position);
+// blocks that a single tile fills completely are written directly.  At the
+// end the partial buffers are saved in the stripe's slot and the per-bucket
+// counts are published.
+template <class T, bool GBUF>
+__global__ void __launch_bounds__(CLS_THREADS)
+k_classify(BatchArgs a) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  constexpr int EPT = T::EPT;
+  constexpr uint32_t NT = CLS_THREADS;
+  constexpr uint32_t TILE = NT * EPT;
+  __shared__ Key s_tree[MAX_K];
+  __shared__ Key s_spl[MAX_K];
+  __shared__ uint32_t s_cnt[MAX_NB], s_nfull[MAX_NB], s_oldf[MAX_NB];
+  __shared__ int32_t s_base[MAX_NB];
+  __shared__ uint64_t s_mn[MAX_K], s_mx[MAX_K];
+  __shared__ uint32_t s_wpos;
+  extern __shared__ __align__(16) uint32_t s_buf[];
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wg = blockIdx.x;
+  const uint32_t tix = a.cls_task[wg];
+  const PTask& tk = a.tasks[tix];
+  const uint64_t tn = tk.n;
+  const uint32_t b = tk.b, nb = tk.nb, NB = tk.NB, W = tk.W;
+  const uint32_t s = wg - tk.wg_base;
+  const bool radix = (tk.tflags & TF_RADIX) != 0;
+  const uint32_t logK = tk.logK, eq = tk.eq, shift = tk.shift;
+  const uint64_t rmask = (tk.width >= 64) ? ~0ull : ((1ull << tk.width) - 1);
+  const StepRec* rec = a.recs + tix;
+  if (!radix) {
+    for (uint32_t i = tid; i < tk.K; i += NT) {
+      s_tree[i] = T::from_slot(rec->tree[i]);
+      s_spl[i] = T::from_slot(rec->spl[i]);
+    }
+  }
+  for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_nfull[j] = 0; s_oldf[j] = 0; s_base[j] = 0; }
+  for (uint32_t j = tid; j < MAX_K; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
+  if (tid == 0) s_wpos = 0;
+  uint32_t* buf = GBUF ? reinterpret_cast<uint32_t*>(a.slots + tk.slot_off + (uint64_t)s * tk.slot_bytes)
+                       : s_buf;
+  __syncthreads();
+
+  const uint32_t blo = (uint32_t)(((uint64_t)s * NB) / W);
+  const uint32_t bhi = (uint32_t)(((uint64_t)(s + 1) * NB) / W);
+  const uint64_t elo = (uint64_t)blo * b;
+  const uint64_t ehi = ((uint64_t)bhi * b < tn) ? (uint64_t)bhi * b : tn;
+  uint32_t* gd = a.data + tk.l * DW;
+
+  uint32_t cur[EPT][DW];
+  uint32_t nxt[EPT][DW];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const uint64_t idx = elo + (uint64_t)i * NT + tid;
+    if (idx < ehi) ld_elem<DW>(gd + idx * DW, cur[i]);
+  }
+  for (uint64_t ts = elo; ts < ehi; ts += TILE) {
+    uint32_t bk[EPT], sl[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint64_t idx = ts + (uint64_t)i * NT + tid;
+      bk[i] = 0; sl[i] = 0;
+      if (idx < ehi) {
+        const Key key = key_of<T>(cur[i]);
+        bk[i] = bucket_of<T>(key, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        if constexpr (T::RADIX_OK) {
+          if (radix) {
+            atomicMin((unsigned long long*)&s_mn[bk[i]], (unsigned long long)T::rkey(key));
+            atomicMax((unsigned long long*)&s_mx[bk[i]], (unsigned long long)T::rkey(key));
+          }
+        }
+        sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
+      }
+    }
+    // Prefetch the next tile; it is never written while this tile is processed.
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint64_t idx = ts + TILE + (uint64_t)i * NT + tid;
+      if (idx < ehi) ld_elem<DW>(gd + idx * DW, nxt[i]);
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < nb; j += NT) {
+      const uint32_t fo = s_nfull[j];
+      const uint32_t nf = s_cnt[j] / b;
+      s_oldf[j] = fo;
+      if (nf > fo) {
+        const uint32_t p = atomicAdd(&s_wpos, nf - fo);
+        s_base[j] = (int32_t)p - (int32_t)fo;
+        s_nfull[j] = nf;
+      }
+    }
+    __syncthreads();
+    const uint64_t consumed = ((ts + TILE < ehi) ? ts + TILE : ehi) - elo;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint64_t idx = ts + (uint64_t)i * NT + tid;
+      if (idx < ehi) {
+        const uint32_t j = bk[i];
+        const uint32_t blk = sl[i] / b, o = sl[i] - blk * b;
+        if (blk == s_oldf[j]) {
+          st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
+        } else if (blk < s_nfull[j]) {
+          const uint64_t pos = (uint64_t)(s_base[j] + (int32_t)blk) * b + o;
+          if (pos >= consumed) dev_error(a.ctrl, DE_CLS_INPLACE, wg, (uint32_t)pos);
+          else st_elem<DW>(gd + (elo + pos) * DW, cur[i]);
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const uint32_t wave = tid >> 6, lane = tid & 63;
+      const uint32_t bdw = b * DW;
+      for (uint32_t j = wave; j < nb; j += NT / 64) {
+        const uint32_t fo = s_oldf[j];
+        if (s_nfull[j] > fo) {
+          const uint64_t pos = (uint64_t)(s_base[j] + (int32_t)fo) * b;
+          if (pos + b > consumed) {
+            if (lane == 0) dev_error(a.ctrl, DE_CLS_INPLACE, wg, (uint32_t)pos);
+          } else {
+            uint32_t* dst = gd + (elo + pos) * DW;
+            const uint32_t* src = buf + (uint64_t)j * bdw;
+            for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint64_t idx = ts + (uint64_t)i * NT + tid;
+      if (idx < ehi) {
+        const uint32_t j = bk[i];
+        const uint32_t blk = sl[i] / b, o = sl[i] - blk * b;
+        if (blk == s_nfull[j] && blk > s_oldf[j])
+          st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+#pragma unroll
+      for (int d = 0; d < DW; ++d) cur[i][d] = nxt[i][d];
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < nb; j += NT) {
+    a.wg_nfull[(uint64_t)wg * MAX_NB + j] = s_nfull[j];
+    a.wg_left[(uint64_t)wg * MAX_NB + j] = s_cnt[j] - s_nfull[j] * b;
+    if (radix && j < MAX_K) {
+      a.wg_min[(uint64_t)wg * MAX_K + j] = s_mn[j];
+      a.wg_max[(uint64_t)wg * MAX_K + j] = s_mx[j];
+    }
+  }
+  if (tid == 0) a.wg_F[wg] = s_wpos;
+  if (!GBUF) {
+    uint32_t* slot = reinterpret_cast<uint32_t*>(a.slots + tk.slot_off + (uint64_t)s * tk.slot_bytes);
+    const uint32_t wave = tid >> 6, lane = tid & 63;
+    for (uint32_t j = wave; j < nb; j += NT / 64) {
+      const uint32_t fill = (s_cnt[j] - s_nfull[j] * b) * DW;
+      const uint32_t* src = buf + (uint64_t)j * b * DW;
+      uint32_t* dst = slot + (uint64_t)j * b * DW;
+      for (uint32_t x = lane; x < fill; x += 64) dst[x] = src[x];
+    }
+  }
+}
+
+// -------------------------------------------------------------- boundaries
+
+__device__ __forceinline__ uint32_t stripe_of(uint32_t p, uint32_t W, uint32_t NB) {
+  return (uint32_t)((((uint64_t)p + 1) * W - 1) / NB);
+}
+__device__ __forceinline__ uint32_t stripe_begin(uint32_t s, uint32_t W, uint32_t NB) {
+  return (uint32_t)(((uint64_t)s * NB) / W);
+}
+
+// Walks the pieces of bucket range [d, dend): split at stripe ends, at the
+// end e of the bucket's own blocks, and every cmax blocks.  A piece is a
+// placement piece if it lies before e; pieces after e only hold blocks of
+// other buckets that must be read out.  Inside one stripe the full blocks
+// are a prefix, so each piece is "unprocessed blocks, then empty blocks",
+// the invariant of the block permutation (Section 4.1).
+template <class F>
+__device__ void for_each_piece(uint32_t d, uint32_t dend, uint32_t e, uint32_t cmax, uint32_t W,
+                               uint32_t NB, const uint32_t* stripeF, F&& f) {
+  uint32_t cur = d;
+  while (cur < dend) {
+    const uint32_t s = stripe_of(cur, W, NB);
+    const uint32_t snext = stripe_begin(s + 1, W, NB);
+    const uint32_t fend = stripe_begin(s, W, NB) + stripeF[s];
+    uint32_t end = dend < snext ? dend : snext;
+    if (cur + cmax < end) end = cur + cmax;
+    if (cur < e && end > e) end = e;
+    const uint32_t uend = fend < end ? fend : end;
+    const int32_t rinit = (uend > cur) ? (int32_t)uend - 1 : (int32_t)cur - 1;
+    const bool place = end <= e;
+    if (place || uend > cur) f(cur, end, rinit, place);
+    cur = end;
+  }
+}
+
+#ifdef IPS_COMMON_KERNELS
+// Bucket boundaries (Section 4.1): per-bucket totals over the stripes, the
+// exclusive prefix sum, delimiters rounded up to blocks, and the pieces with
+// their packed (write, read) pointers.
+__global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) {
+  constexpr uint32_t NT = 512;
+  __shared__ uint64_t s_size[MAX_NB];
+  __shared__ uint64_t s_start[MAX_NB + 1];
+  __shared__ uint32_t s_cntb[MAX_NB];
+  __shared__ uint32_t s_np[MAX_NB + 1], s_up[MAX_NB + 1];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tix = blockIdx.x;
+  const PTask& tk = a.tasks[tix];
+  const uint32_t nb = tk.nb, b = tk.b, NB = tk.NB, W = tk.W, wg0 = tk.wg_base;
+  const uint32_t bb = tk.bucket_base;
+  const bool radix = (tk.tflags & TF_RADIX) != 0;
+  const uint32_t* stripeF = a.wg_F + wg0;
+  for (uint32_t j = tid; j < nb; j += NT) {
+    uint64_t full = 0, left = 0;
+    uint64_t mn = ~0ull, mx = 0;
+    for (uint32_t s = 0; s < W; ++s) {
+      const uint64_t o = (uint64_t)(wg0 + s) * MAX_NB + j;
+      full += a.wg_nfull[o];
+      left += a.wg_left[o];
+      if (radix) {
+        const uint64_t om = (uint64_t)(wg0 + s) * MAX_K + j;
+        const uint64_t x = a.wg_min[om], y = a.wg_max[om];
+        mn = x < mn ? x : mn;
+        mx = y > mx ? y : mx;
+      }
+    }
+    s_cntb[j] = (uint32_t)full;
+    s_size[j] = full * b + left;
+    if (radix) { a.b_min[bb + j] = mn; a.b_max[bb + j] = mx; }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < nb; ++j) { s_start[j] = acc; acc += s_size[j]; }
+    s_start[nb] = acc;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < nb; j += NT) {
+    const uint64_t st = s_start[j];
+    const uint32_t d = (uint32_t)((st + b - 1) / b);
+    const uint32_t dend = (j + 1 < nb) ? (uint32_t)((s_start[j + 1] + b - 1) / b) : NB;
+    const uint32_t e = d + s_cntb[j];
+    uint32_t np = 0, up = 0;
+    for_each_piece(d, dend, e, cmax, W, NB, stripeF,
+                   [&](uint32_t c0, uint32_t, int32_t ri, bool) {
+                     ++np;
+                     up += (uint32_t)(ri - (int32_t)c0 + 1);
+                   });
+    s_np[j] = np;
+    s_up[j] = up;
+    a.b_start[bb + j] = st;
+    a.b_count[bb + j] = s_cntb[j];
+    a.b_d[bb + j] = d;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t accp = 0, accu = 0;
+    for (uint32_t j = 0; j < nb; ++j) {
+      const uint32_t x = s_np[j], y = s_up[j];
+      s_np[j] = accp; s_up[j] = accu;
+      accp += x; accu += y;
+    }
+    s_np[nb] = accp;
+    s_up[nb] = accu;
+    a.b_start[bb + nb] = s_start[nb];
+    a.t_npieces[tix] = accp;
+    a.t_unproc[tix] = accu;
+    if (accp > tk.piece_cap) dev_error(a.ctrl, DE_PIECES, tix, accp);
+    if (s_start[nb] != tk.n) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, 0xFFFFFFFFu);
+  }
+  __syncthreads();
+  if (s_np[nb] > tk.piece_cap) return;
+  const uint32_t pb = tk.piece_base;
+  for (uint32_t j = tid; j < nb; j += NT) {
+    const uint64_t st = s_start[j];
+    const uint32_t d = (uint32_t)((st + b - 1) / b);
+    const uint32_t dend = (j + 1 < nb) ? (uint32_t)((s_start[j + 1] + b - 1) / b) : NB;
+    const uint32_t e = d + s_cntb[j];
+    uint32_t p = pb + s_np[j];
+    uint32_t cu = s_up[j];
+    uint32_t plb = p, ple = p;
+    for_each_piece(d, dend, e, cmax, W, NB, stripeF,
+                   [&](uint32_t c0, uint32_t c1, int32_t ri, bool place) {
+                     a.p_a[p] = c0;
+                     a.p_c[p] = place ? c1 : c0;
+                     a.p_rinit[p] = ri;
+                     a.p_cum[p] = cu;
+                     a.p_word[p] = ((uint64_t)c0 << 32) | (uint64_t)((uint32_t)ri + PTR_BIAS);
+                     cu += (uint32_t)(ri - (int32_t)c0 + 1);
+                     ++p;
+                     if (place) ple = p;
+                   });
+    a.b_plb[bb + j] = plb;
+    a.b_ple[bb + j] = ple;
+  }
+}
+
+#endif  // IPS_COMMON_KERNELS
+
+// ------------------------------------------------------------ permutation
+
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t lane) {
+  return (uint32_t)__shfl((int)v, (int)lane, 64);
+}
+
+template <class T>
+__device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[8], uint32_t lbase,
+                                                 const typename T::Key* tree,
+                                                 const typename T::Key* spl, uint32_t logK,
+                                                 uint32_t eq, bool radix, uint32_t shift,
+                                                 uint64_t rmask) {
+  const uint32_t w0 = shfl32(dat[0], lbase);
+  const uint32_t w1 = (T::KDW > 1) ? shfl32(dat[0], lbase + 1) : 0u;
+  const uint32_t w2 = (T::KDW > 2) ? shfl32(dat[0], lbase + 2) : 0u;
+  return bucket_of<T>(T::key(w0, w1, w2), tree, spl, logK, eq, radix, shift, rmask);
+}
+
+// Waits until every load into `v` has returned (an opaque use of each
+// register), so that a later store or flag cannot overtake them.
+__device__ __forceinline__ void wait_regs(const uint32_t (&v)[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) asm volatile("" ::"v"(v[r]) : "memory");
+}
+
+// Block permutation (Section 4.1).  A group of `glanes` lanes plays the
+// role of one thread of the paper: it holds one block in registers (its
+// swap buffer).  Each bucket's final block range is split into pieces, each
+// with a packed (w, r) pointer word: blocks [a, w) are correct, [w, r]
+// unprocessed, the rest empty.  A group claims an unprocessed block by
+// decrementing r of a piece of its assigned source range, classifies its
+// first element, and reserves the next slot w of a piece of the destination
+// bucket: an unprocessed block there is swapped out (or skipped if it is
+// already correct), an empty slot is written.  A slot that another group
+// is still reading (w > r but w <= the piece's initial r) is written only
+// after that reader has set the block's flag (the paper's reader guard).
+template <class T>
+__global__ void __launch_bounds__(PERM_THREADS)
+k_permute(BatchArgs a) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  __shared__ Key s_tree[MAX_K];
+  __shared__ Key s_spl[MAX_K];
+  const uint32_t tix = a.perm_task[blockIdx.x];
+  const PTask& tk = a.tasks[tix];
+  const bool radix = (tk.tflags & TF_RADIX) != 0;
+  const uint32_t logK = tk.logK, eq = tk.eq, shift = tk.shift;
+  const uint64_t rmask = (tk.width >= 64) ? ~0ull : ((1ull << tk.width) - 1);
+  if (!radix) {
+    const StepRec* rec = a.recs + tix;
+    for (uint32_t i = threadIdx.x; i < tk.K; i += PERM_THREADS) {
+      s_tree[i] = T::from_slot(rec->tree[i]);
+      s_spl[i] = T::from_slot(rec->spl[i]);
+    }
+  }
+  __syncthreads();
+  const uint32_t GL = tk.glanes;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t gl = lane & (GL - 1);
+  const uint32_t lbase = lane - gl;
+  const uint32_t gid = (blockIdx.x - tk.pwg_base) * (PERM_THREADS / GL) + threadIdx.x / GL;
+  const uint32_t b = tk.b, NB = tk.NB;
+  const uint32_t BDW = b * DW;
+  uint32_t* gd = a.data + tk.l * DW;
+  const uint32_t pb = tk.piece_base;
+  const uint32_t np = a.t_npieces[tix];
+  const uint32_t U = a.t_unproc[tix];
+  uint64_t* word = a.p_word + pb;
+  const uint32_t* pa = a.p_a + pb;
+  const uint32_t* pc = a.p_c + pb;
+  const int32_t* pr = a.p_rinit + pb;
+  const uint32_t* pcum = a.p_cum + pb;
+  uint32_t* flags = a.flags + tk.flag_off;
+  const uint32_t bb = tk.bucket_base;
+  const bool partial = (tk.n % b) != 0;
+  uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
+  if (BDW > 8 * GL) {
+    if (threadIdx.x == 0) dev_error(a.ctrl, DE_BLOCK, tix, BDW);
+    return;
+  }
+
+  enum : uint32_t { CLAIM = 0, PLACE = 1, WAIT = 2, DONE = 3 };
+  uint32_t mode = (gid < tk.ngrp && U > 0) ? CLAIM : DONE;
+  uint32_t src = 0, src_end = 0;
+  if (mode == CLAIM) {
+    const uint64_t ulo = (uint64_t)gid * U / tk.ngrp;
+    const uint64_t uhi = (uint64_t)(gid + 1) * U / tk.ngrp;
+    if (ulo == uhi) {
+      mode = DONE;
+    } else {
+      uint32_t lo = 0, hi = np;            // first p with cum + unproc > ulo
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        const uint64_t ce = (uint64_t)pcum[mid] + (uint32_t)(pr[mid] - (int32_t)pa[mid] + 1);
+        if (ce > ulo) hi = mid; else lo = mid + 1;
+      }
+      src = lo;
+      lo = src; hi = np;                   // first p with cum >= uhi
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if ((uint64_t)pcum[mid] >= uhi) hi = mid; else lo = mid + 1;
+      }
+      src_end = lo;
+    }
+  }
+  uint32_t dat[8], tmp[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) { dat[r] = 0; tmp[r] = 0; }
+  uint32_t dest = 0, probe = 0, wpos = 0, spin = 0;
+
+  while (true) {
+    if (__all(mode == DONE)) break;
+    if (mode == CLAIM) {
+      uint32_t P = 0xFFFFFFFFu;
+      if (gl == 0) {
+        while (src < src_end) {
+          uint64_t wv = at_load64(&word[src]);
+          int32_t w = (int32_t)(wv >> 32), r = (int32_t)((uint32_t)wv - PTR_BIAS);
+          if (r < w) { ++src; continue; }
+          wv = at_add64(&word[src], ~0ull);
+          w = (int32_t)(wv >> 32);
+          r = (int32_t)((uint32_t)wv - PTR_BIAS);
+          if (r >= w) { P = (uint32_t)r; break; }
+          ++src;
+        }
+      }
+      P = shfl32(P, lbase);
+      if (P == 0xFFFFFFFFu) {
+        mode = DONE;
+      } else if (P >= NB || (P == NB - 1 && partial)) {
+        if (gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, P);
+        mode = DONE;
+      } else {
+        const uint32_t* sp = gd + (uint64_t)P * BDW;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const uint32_t x = gl + GL * r;
+          if (x < BDW) dat[r] = sp[x];
+        }
+        wait_regs(dat);
+        if (gl == 0) at_store32(&flags[P], 1u);
+        dest = block_bucket<T>(dat, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
+        mode = PLACE;
+      }
+    } else if (mode == PLACE) {
+      uint32_t w = 0, ok = 0, sr = 0;
+      int32_t r = 0;
+      if (gl == 0) {
+        const uint32_t plb = a.b_plb[bb + dest] - pb, ple = a.b_ple[bb + dest] - pb;
+        const uint32_t npl = ple - plb;
+        uint32_t tries = 0;
+        while (npl > 0 && tries < 4 * npl + 64) {
+          sr = plb + (probe % npl);
+          uint64_t wv = at_load64(&word[sr]);
+          if ((uint32_t)(wv >> 32) < pc[sr]) {
+            wv = at_add64(&word[sr], 1ull << 32);
+            w = (uint32_t)(wv >> 32);
+            r = (int32_t)((uint32_t)wv - PTR_BIAS);
+            if (w < pc[sr]) { ok = 1; break; }
+          }
+          ++probe;
+          ++tries;
+        }
+        if (!ok) dev_error(a.ctrl, DE_PLACE, tix, dest);
+      }
+      ok = shfl32(ok, lbase);
+      w = shfl32(w, lbase);
+      r = (int32_t)shfl32((uint32_t)r, lbase);
+      sr = shfl32(sr, lbase);
+      if (!ok || w >= NB || ((int32_t)w <= r && w == NB - 1 && partial)) {
+        if (ok && gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, w);
+        mode = DONE;
+      } else if ((int32_t)w <= r) {
+        uint32_t* wp = gd + (uint64_t)w * BDW;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t x = gl + GL * q;
+          if (x < BDW) tmp[q] = wp[x];
+        }
+        wait_regs(tmp);
+        const uint32_t d2 = block_bucket<T>(tmp, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        if (d2 != dest) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const uint32_t x = gl + GL * q;
+            if (x < BDW) wp[x] = dat[q];
+            dat[q] = tmp[q];
+          }
+          dest = d2;
+          probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
+        }
+      } else if ((int32_t)w <= pr[sr]) {
+        wpos = w;
+        spin = 0;
+        mode = WAIT;
+      } else {
+        uint32_t* wp = (w == NB - 1 && partial) ? ovf : gd + (uint64_t)w * BDW;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t x = gl + GL * q;
+          if (x < BDW) wp[x] = dat[q];
+        }
+        mode = CLAIM;
+      }
+    } else if (mode == WAIT) {
+      uint32_t f = 0;
+      if (gl == 0) f = at_load32(&flags[wpos]);
+      f = shfl32(f, lbase);
+      if (f) {
+        uint32_t* wp = gd + (uint64_t)wpos * BDW;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t x = gl + GL * q;
+          if (x < BDW) wp[x] = dat[q];
+        }
+        mode = CLAIM;
+      } else if (++spin > (1u << 22)) {
+        if (gl == 0) dev_error(a.ctrl, DE_WAIT, tix, wpos);
+        mode = DONE;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- cleanup
+
+struct BucketGeo {
+  uint64_t start, end, F;   // F: end of the bucket's blocks inside the array
+  uint32_t d, count;
+  bool ovf;                 // the bucket's last block sits in the overflow block
+};
+
+__device__ __forceinline__ BucketGeo bucket_geo(const BatchArgs& a, const PTask& tk, uint32_t j) {
+  BucketGeo g;
+  const uint32_t bb = tk.bucket_base;
+  g.start = a.b_start[bb + j];
+  g.end = a.b_start[bb + j + 1];
+  g.d = a.b_d[bb + j];
+  g.count = a.b_count[bb + j];
+  const uint32_t e = g.d + g.count;
+  g.ovf = g.count > 0 && e == tk.NB && (tk.n % tk.b) != 0;
+  g.F = (uint64_t)(g.ovf ? e - 1 : e) * tk.b;
+  return g;
+}
+
+// Cleanup, first part: the last block of a bucket may reach into the head of
+// the next bucket; those elements are saved before any head is rewritten.
+template <class T>
+__global__ void __launch_bounds__(CLN_THREADS) k_cleanup_a(BatchArgs a) {
+  constexpr int DW = T::DW;
+  const uint32_t tix = blockIdx.x;
+  const PTask& tk = a.tasks[tix];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t* gd = a.data + tk.l * DW;
+  uint32_t* spill = reinterpret_cast<uint32_t*>(a.spill + tk.spill_off);
+  for (uint32_t j = wave; j < tk.nb; j += CLN_THREADS / 64) {
+    const BucketGeo g = bucket_geo(a, tk, j);
+    if (g.count > 0 && !g.ovf && g.F > g.end) {
+      const uint64_t len = (g.F - g.end) * DW;
+      if (g.F - g.end >= tk.b || g.F > (uint64_t)tk.NB * tk.b) {
+        if (lane == 0) dev_error(a.ctrl, DE_CLN_RANGE, tix, j);
+        continue;
+      }
+      const uint32_t* src = gd + g.end * DW;
+      uint32_t* dst = spill + (uint64_t)j * tk.b * DW;
+      for (uint64_t x = lane; x < len; x += 64) dst[x] = src[x];
+    }
+  }
+}
+
+// Cleanup, second part (Section 4.1 "Cleanup"): the elements of bucket j
+// that are not yet inside [start_j, end_j) - the saved spill, the overflow
+// block, and the partial buffer blocks of every stripe - fill the bucket's
+// free positions: its head [start_j, d_j b) and its tail after its blocks.
+template <class T>
+__global__ void __launch_bounds__(CLN_THREADS) k_cleanup_b(BatchArgs a, uint32_t max_w) {
+  constexpr int DW = T::DW;
+  extern __shared__ uint64_t s_off[];   // max_w + 3 entries
+  const uint32_t m = a.cln_map[blockIdx.x];
+  const uint32_t tix = m >> 10, j = m & 1023u;
+  const PTask& tk = a.tasks[tix];
+  const BucketGeo g = bucket_geo(a, tk, j);
+  const uint32_t b = tk.b, W = tk.W;
+  if (W > max_w) {
+    if (threadIdx.x == 0) dev_error(a.ctrl, DE_CLN_RANGE, tix, W);
+    return;
+  }
+  const uint64_t hend = ((uint64_t)g.d * b < g.end) ? (uint64_t)g.d * b : g.end;
+  const uint64_t hlen = hend - g.start;
+  const uint64_t tlen = (g.F < g.end) ? g.end - g.F : 0;
+  const uint64_t sp = (g.count > 0 && !g.ovf && g.F > g.end) ? g.F - g.end : 0;
+  if (threadIdx.x == 0) {
+    uint64_t acc = 0;
+    s_off[0] = 0;
+    acc += sp;
+    s_off[1] = acc;
+    acc += g.ovf ? b : 0;
+    s_off[2] = acc;
+    for (uint32_t s = 0; s < W; ++s) {
+      acc += a.wg_left[(uint64_t)(tk.wg_base + s) * MAX_NB + j];
+      s_off[3 + s] = acc;
+    }
+  }
+  __syncthreads();
+  const uint64_t total = s_off[2 + W];
+  if (total != hlen + tlen) {
+    if (threadIdx.x == 0) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, j);
+    return;
+  }
+  uint32_t* gd = a.data + tk.l * DW;
+  const uint32_t* spill = reinterpret_cast<const uint32_t*>(a.spill + tk.spill_off) + (uint64_t)j * b * DW;
+  const uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
+  const uint8_t* slot0 = a.slots + tk.slot_off;
+  for (uint64_t e = threadIdx.x; e < total; e += CLN_THREADS) {
+    uint32_t lo = 0, hi = W + 2;     // segment: largest i with s_off[i] <= e
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) / 2;
+      if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t k = e - s_off[lo];
+    const uint32_t* src;
+    if (lo == 0) src = spill + k * DW;
+    else if (lo == 1) src = ovf + k * DW;
+    else src = reinterpret_cast<const uint32_t*>(slot0 + (uint64_t)(lo - 2) * tk.slot_bytes) +
+               ((uint64_t)j * b + k) * DW;
+    const uint64_t dst = (e < hlen) ? g.start + e : g.F + (e - hlen);
+    if (dst < g.start || dst >= g.end) {
+      dev_error(a.ctrl, DE_CLN_RANGE, tix, j);
+      continue;
+    }
+    uint32_t w[DW];
+    ld_elem<DW>(src, w);
+    st_elem<DW>(gd + dst * DW, w);
+  }
+}
+
+// ---------------------------------------------------------------- LDS tier
+
+// Sorts a task of at most `cap` elements inside one workgroup's LDS:
+// one coalesced load, a bitonic sort of (key, index) pairs, one store.
+template <class T>
+__global__ void __launch_bounds__(LDST_THREADS)
+k_lds_sort(const LTask* lt, uint32_t* data, uint32_t cap, uint32_t* ctrl) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  constexpr uint32_t NT = LDST_THREADS;
+  extern __shared__ __align__(16) uint32_t s_dyn[];
+  const LTask t = lt[blockIdx.x];
+  const uint32_t n = t.n;
+  if (n > cap) {
+    if (threadIdx.x == 0) dev_error(ctrl, DE_LDST, blockIdx.x, n);
+    return;
+  }
+  if (n < 2) return;
+  uint32_t P = 2;
+  while (P < n) P <<= 1;
+  Key* keys = reinterpret_cast<Key*>(s_dyn);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(keys + P);
+  uint32_t* stage = idx + P;
+  uint32_t* gd = data + t.l * DW;
+  if constexpr (T::KEYS_ONLY) {
+    for (uint32_t i = threadIdx.x; i < P; i += NT) {
+      if (i < n) {
+        uint32_t w[DW];
+        ld_elem<DW>(gd + (uint64_t)i * DW, w);
+        keys[i] = key_of<T>(w);
+      } else {
+        keys[i] = T::kmax();
+      }
+    }
+    __syncthreads();
+    lds_bitonic_keys(keys, P);
+    for (uint32_t i = threadIdx.x; i < n; i += NT) {
+      uint32_t w[DW];
+      T::from_key(keys[i], w);
+      st_elem<DW>(gd + (uint64_t)i * DW, w);
+    }
+  } else {
+    for (uint32_t x = threadIdx.x; x < n * DW; x += NT) stage[x] = gd[x];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P; i += NT) {
+      if (i < n) {
+        const uint32_t* e = stage + (uint64_t)i * DW;
+        keys[i] = T::key(e[0], e[DW > 1 ? 1 : 0], e[DW > 2 ? 2 : 0]);
+      } else {
+        keys[i] = T::kmax();
+      }
+      idx[i] = i;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = threadIdx.x; i < P / 2; i += NT) {
+          const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
+          const bool up = (lo & k) == 0;
+          const Key x = keys[lo], y = keys[hi];
+          const uint32_t ix = idx[lo], iy = idx[hi];
+          const bool ylt = kless(y, x) || (keq(x, y) && iy < ix);
+          if (ylt == up) { keys[lo] = y; keys[hi] = x; idx[lo] = iy; idx[hi] = ix; }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t x = threadIdx.x; x < n * DW; x += NT) {
+      const uint32_t i = x / DW, d = x - i * DW;
+      gd[x] = stage[(uint64_t)idx[i] * DW + d];
+    }
+  }
+}
+
+// -------------------------------------------------- sorted check, radix root
+
+// Sorted / reverse-sorted detection (Section 6): records whether any
+// adjacent pair descends or ascends; workgroups stop early once both have
+// been seen.
+template <class T>
+__global__ void __launch_bounds__(256) k_sorted_check(const uint32_t* data, uint64_t n, uint32_t* ctrl) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  constexpr uint64_t CH = 256 * 16;
+  __shared__ uint32_t s_f[2];
+  for (uint64_t c0 = (uint64_t)blockIdx.x * CH; c0 + 1 < n; c0 += (uint64_t)gridDim.x * CH) {
+    if (threadIdx.x == 0) { s_f[0] = at_load32(&ctrl[CTRL_DESC]); s_f[1] = at_load32(&ctrl[CTRL_ASC]); }
+    __syncthreads();
+    const bool stop = s_f[0] && s_f[1];
+    __syncthreads();
+    if (stop) return;
+    uint32_t desc = 0, asc = 0;
+    for (uint32_t q = 0; q < 16; ++q) {
+      const uint64_t i = c0 + (uint64_t)q * 256 + threadIdx.x;
+      if (i + 1 < n) {
+        uint32_t w0[DW], w1[DW];
+        ld_elem<DW>(data + i * DW, w0);
+        ld_elem<DW>(data + (i + 1) * DW, w1);
+        const Key x = key_of<T>(w0), y = key_of<T>(w1);
+        desc |= kless(y, x) ? 1u : 0u;
+        asc |= kless(x, y) ? 1u : 0u;
+      }
+    }
+    if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_DESC], 1u);
+    if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_ASC], 1u);
+  }
+}
+
+template <int DW>
+__global__ void __launch_bounds__(256) k_reverse(uint32_t* data, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n / 2; i += (uint64_t)gridDim.x * 256) {
+    uint32_t x[DW], y[DW];
+    ld_elem<DW>(data + i * DW, x);
+    ld_elem<DW>(data + (n - 1 - i) * DW, y);
+    st_elem<DW>(data + i * DW, y);
+    st_elem<DW>(data + (n - 1 - i) * DW, x);
+  }
+}
+
+// Minimum and maximum radix key of the whole input (significant-bit
+// detection of the radix variant).
+template <class T>
+__global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n, uint32_t* ctrl) {
+  constexpr int DW = T::DW;
+  uint64_t mn = ~0ull, mx = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    uint32_t w[DW];
+    ld_elem<DW>(data + i * DW, w);
+    const uint64_t k = T::rkey(key_of<T>(w));
+    mn = k < mn ? k : mn;
+    mx = k > mx ? k : mx;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = (uint64_t)__shfl_xor((long long)mn, o, 64);
+    const uint64_t b = (uint64_t)__shfl_xor((long long)mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    uint64_t* mm = reinterpret_cast<uint64_t*>(ctrl + CTRL_MINMAX);
+    atomicMin((unsigned long long*)&mm[0], (unsigned long long)mn);
+    atomicMax((unsigned long long*)&mm[1], (unsigned long long)mx);
+  }
+}
+
+#ifdef IPS_COMMON_KERNELS
+__global__ void __launch_bounds__(256) k_fill32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = v;
+}
+#endif  // IPS_COMMON_KERNELS
+
+}  // namespace ips

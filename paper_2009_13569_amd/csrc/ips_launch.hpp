@@ -1,0 +1,40 @@
+// Per-element-type kernel launchers (one table per type, defined in the
+// per-type translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ips_common.hpp"
+
+namespace ips {
+
+struct Launchers {
+  int code;
+  uint32_t dw;            // dwords per element
+  uint32_t key_slot;      // bytes of a key in StepRec slots actually used
+  bool keys_only, radix_ok;
+  uint32_t lds_cap;       // default LDS-tier capacity (elements)
+  size_t (*lds_bytes)(uint32_t cap);
+  hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, uint32_t k, uint32_t n0,
+                       hipStream_t);
+  hipError_t (*classify)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, bool gbuf, hipStream_t);
+  hipError_t (*permute)(const BatchArgs&, uint32_t nwg, hipStream_t);
+  hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);
+  hipError_t (*cleanup_b)(const BatchArgs&, uint32_t nwg, uint32_t max_w, hipStream_t);
+  hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, uint32_t cap, uint32_t* ctrl,
+                         hipStream_t);
+  hipError_t (*sorted_check)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
+  hipError_t (*reverse)(uint32_t* data, uint64_t n, hipStream_t);
+  hipError_t (*minmax)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
+};
+
+const Launchers* launchers_u32();
+const Launchers* launchers_u64();
+const Launchers* launchers_f64();
+const Launchers* launchers_pair();
+const Launchers* launchers_rec100();
+
+hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t cmax, hipStream_t);
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t);
+
+}  // namespace ips

@@ -1,0 +1,115 @@
+// Element types and key orders for the gfx950 kernels.
+//
+// Every element is handled as DW dwords; its key is extracted from the first
+// KDW dwords.  u32/u64 compare as unsigned integers; f64 keys are mapped to
+// unsigned integers by the order-preserving image of IEEE 754 totalOrder
+// (negative: all bits flipped; positive: sign bit set); Pair compares its
+// u64 key at byte 0; the 100-byte record compares bytes 0..9 as unsigned
+// bytes (Algorithm 4 of the paper with unsigned char), i.e. as a big-endian
+// 80-bit integer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ips {
+
+struct K80 {
+  uint64_t hi;
+  uint32_t lo;
+  uint32_t pad;
+};
+
+__device__ __forceinline__ bool kless(uint32_t a, uint32_t b) { return a < b; }
+__device__ __forceinline__ bool kless(uint64_t a, uint64_t b) { return a < b; }
+__device__ __forceinline__ bool kless(const K80& a, const K80& b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+__device__ __forceinline__ bool keq(uint32_t a, uint32_t b) { return a == b; }
+__device__ __forceinline__ bool keq(uint64_t a, uint64_t b) { return a == b; }
+__device__ __forceinline__ bool keq(const K80& a, const K80& b) {
+  return a.hi == b.hi && a.lo == b.lo;
+}
+
+__device__ __forceinline__ uint64_t f64_to_ord(uint64_t b) {
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+__device__ __forceinline__ uint64_t ord_to_f64(uint64_t k) {
+  return (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+}
+
+struct TU32 {
+  static constexpr int DW = 1, KDW = 1, CODE = 1, EPT = 16;
+  static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  using Key = uint32_t;
+  __device__ static Key key(uint32_t w0, uint32_t, uint32_t) { return w0; }
+  __device__ static Key kmax() { return 0xFFFFFFFFu; }
+  __device__ static uint64_t rkey(Key k) { return k; }
+  __device__ static void from_key(Key k, uint32_t* w) { w[0] = k; }
+  __device__ static Key from_slot(const uint64_t* s) { return (uint32_t)s[0]; }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+};
+
+struct TU64 {
+  static constexpr int DW = 2, KDW = 2, CODE = 2, EPT = 8;
+  static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  using Key = uint64_t;
+  __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
+    return (uint64_t)w0 | ((uint64_t)w1 << 32);
+  }
+  __device__ static Key kmax() { return ~0ull; }
+  __device__ static uint64_t rkey(Key k) { return k; }
+  __device__ static void from_key(Key k, uint32_t* w) { w[0] = (uint32_t)k; w[1] = (uint32_t)(k >> 32); }
+  __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+};
+
+struct TF64 {
+  static constexpr int DW = 2, KDW = 2, CODE = 3, EPT = 8;
+  static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  using Key = uint64_t;
+  __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
+    return f64_to_ord((uint64_t)w0 | ((uint64_t)w1 << 32));
+  }
+  __device__ static Key kmax() { return ~0ull; }
+  __device__ static uint64_t rkey(Key k) { return k; }
+  __device__ static void from_key(Key k, uint32_t* w) {
+    uint64_t b = ord_to_f64(k);
+    w[0] = (uint32_t)b; w[1] = (uint32_t)(b >> 32);
+  }
+  __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+};
+
+struct TPair {
+  static constexpr int DW = 4, KDW = 2, CODE = 4, EPT = 4;
+  static constexpr bool KEYS_ONLY = false, RADIX_OK = true;
+  using Key = uint64_t;
+  __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
+    return (uint64_t)w0 | ((uint64_t)w1 << 32);
+  }
+  __device__ static Key kmax() { return ~0ull; }
+  __device__ static uint64_t rkey(Key k) { return k; }
+  __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+};
+
+struct TRec100 {
+  static constexpr int DW = 25, KDW = 3, CODE = 5, EPT = 1;
+  static constexpr bool KEYS_ONLY = false, RADIX_OK = false;
+  using Key = K80;
+  __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t w2) {
+    K80 k;
+    k.hi = ((uint64_t)__builtin_bswap32(w0) << 32) | (uint64_t)__builtin_bswap32(w1);
+    k.lo = ((w2 & 0xFFu) << 8) | ((w2 >> 8) & 0xFFu);
+    k.pad = 0;
+    return k;
+  }
+  __device__ static Key kmax() { K80 k; k.hi = ~0ull; k.lo = 0xFFFFu; k.pad = 0; return k; }
+  __device__ static uint64_t rkey(Key) { return 0; }
+  __device__ static Key from_slot(const uint64_t* s) {
+    K80 k; k.hi = s[0]; k.lo = (uint32_t)s[1]; k.pad = 0; return k;
+  }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k.hi; s[1] = k.lo; }
+};
+
+}  // namespace ips

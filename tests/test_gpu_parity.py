@@ -1,0 +1,191 @@
+"""Parity of the HIP sort (called through the C ABI) with the CPU oracle.
+
+Keys must be bit-identical to the oracle's sorted keys; records must also
+keep their multiset.  Sizes span several blocks, stripes and a ragged tail.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2009_13569_amd as ips
+import synth
+from gpu_util import assert_parity, generate, gpu_sort, log
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["u32", "u64", "f64", "pair", "rec100"]
+
+
+@pytest.fixture(scope="module")
+def sorter():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ips.Sorter(0)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_lds_tier(sorter, kind):
+    cap = {"u32": 16384, "u64": 8192, "f64": 8192, "pair": 4096, "rec100": 1024}[kind]
+    for n in (2, 3, 17, 1000, cap - 1, cap):
+        a = generate(kind, "uniform", n, 100 + n)
+        log(f"lds {kind} n={n}")
+        assert_parity(gpu_sort(sorter, a, kind), a, kind)
+
+
+DISTS = {
+    "u32": ["uniform", "exponential", "rootdup", "twodup", "eightdup", "almostsorted", "zipf"],
+    "u64": ["uniform", "exponential", "rootdup", "twodup", "eightdup", "almostsorted", "zipf"],
+    "f64": ["uniform", "exponential"],
+    "pair": ["uniform", "rootdup"],
+    "rec100": ["uniform", "rootdup"],
+}
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_samplesort_parity(sorter, kind):
+    nbig = {"rec100": 40_000}.get(kind, 300_001)
+    for dist in DISTS[kind]:
+        for n in (20_011, nbig):
+            a = generate(kind, dist, n, 7)
+            log(f"samplesort {kind} {dist} n={n}")
+            p = ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)
+            assert_parity(gpu_sort(sorter, a, kind, params=p), a, kind)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
+def test_radix_parity(sorter, kind):
+    for dist in DISTS[kind]:
+        for n in (20_011, 300_001):
+            a = generate(kind, dist, n, 9)
+            log(f"radix {kind} {dist} n={n}")
+            assert_parity(gpu_sort(sorter, a, kind, algo="radix"), a, kind)
+
+
+def test_config1_full(sorter):
+    """n = 2^20 uniform u64, k = 256, 2 KiB blocks, n0 = 16."""
+    a = synth.gen_u64("uniform", 1 << 20, synth.seed_for(1))
+    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
+    log("config1 gbuf")
+    assert_parity(gpu_sort(sorter, a, "u64", params=p), a, "u64")
+    log("config1 lds")
+    assert_parity(gpu_sort(sorter, a, "u64"), a, "u64")
+
+
+def _level1(sorter, a, kind, params, algo="samplesort"):
+    out = gpu_sort(sorter, a, kind, algo=algo, params=params)
+    ri = sorter.root_info()
+    assert ri.valid == 1
+    return out, ri
+
+
+@pytest.mark.parametrize("kind,n,gbuf", [("u64", 1 << 20, True), ("u64", 1 << 20, False),
+                                         ("u32", 300_001, False), ("f64", 200_003, False),
+                                         ("pair", 100_003, False), ("rec100", 30_011, False)])
+def test_level1_exact(sorter, kind, n, gbuf):
+    """The root step's sample, splitters, equality-bucket flag and bucket
+    boundaries equal the oracle's, and every element lies in its bucket."""
+    for dist in ("uniform", "rootdup"):
+        a = generate(kind, dist, n, 3)
+        flags = ips.FLAG_LEVEL1_ONLY | (ips.FLAG_GLOBAL_BUFFERS if gbuf else 0)
+        p = ips.make_params(block_bytes=2048 if gbuf else 0, flags=flags, seed=12345)
+        log(f"level1 {kind} {dist} n={n} gbuf={gbuf}")
+        out, ri = _level1(sorter, a, kind, p)
+        st = oracle.sample_step(a, kind, seed=12345)
+        assert (ri.alpha, ri.k_prime, ri.m, ri.u, ri.K, bool(ri.eq), ri.nb) == \
+            (st["alpha"], st["k_prime"], st["m"], st["u"], st["K"], st["eq"], st["nb"])
+        spl = st["splitters"]
+        for i in range(st["K"]):
+            got = bytes(ri.splitters[i])
+            if kind == "rec100":
+                assert got[:10] == bytes(spl[i][:10]), i
+            elif kind == "u32":
+                assert int.from_bytes(got[:8], "little") == int(spl[i]), i
+            else:
+                assert got[:8] == np.ascontiguousarray(spl[i]).tobytes()[:8], i
+        hist = oracle.histogram(a, kind, spl, st["K"], st["eq"])
+        starts = np.concatenate([[0], np.cumsum(hist)]).astype(np.uint64)
+        assert np.array_equal(np.array(ri.bucket_start[:st["nb"] + 1], dtype=np.uint64), starts)
+        assert oracle.check_partition(out, kind, spl, st["K"], st["eq"], starts) is None
+        assert_parity(oracle.sort(out, kind), a, kind)     # multiset kept
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "pair"])
+def test_level1_radix_exact(sorter, kind):
+    for dist in ("uniform", "rootdup", "exponential"):
+        a = generate(kind, dist, 200_003, 5)
+        log(f"level1 radix {kind} {dist}")
+        out, ri = _level1(sorter, a, kind, ips.make_params(flags=ips.FLAG_LEVEL1_ONLY), "radix")
+        d = oracle.radix_digit_info(a, kind)
+        assert (ri.radix_shift, ri.radix_width) == (d["shift"], d["width"])
+        h = oracle.radix_histogram(a, kind, d["shift"], d["width"])
+        starts = np.concatenate([[0], np.cumsum(h)]).astype(np.uint64)
+        assert np.array_equal(np.array(ri.bucket_start[:ri.nb + 1], dtype=np.uint64), starts)
+        keys = out if kind != "pair" else out[:, 0]
+        dig = (keys.astype(np.uint64) >> np.uint64(d["shift"])) & np.uint64((1 << d["width"]) - 1)
+        assert np.all(np.diff(dig.astype(np.int64)) >= 0)
+
+
+@pytest.mark.parametrize("k,bb", [(2, 8), (4, 8), (2, 16), (4, 16)])
+def test_brute_force_tiny(sorter, k, bb):
+    """Every permutation of distinct keys and every sequence over {0,1,2}
+    (n <= 6), through the partitioning path (LDS tier off)."""
+    base = dict(k=k, block_bytes=bb, n0=1, lds_task_max=1, flags=ips.FLAG_NO_SORTED_CHECK)
+    for eqflag in (0, ips.FLAG_EQ_ON, ips.FLAG_EQ_OFF):
+        p = ips.make_params(**{**base, "flags": base["flags"] | eqflag})
+        for n in range(2, 7):
+            log(f"brute k={k} bb={bb} eq={eqflag} n={n}")
+            vals = np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 >> 3)
+            for perm in itertools.permutations(range(n)):
+                a = vals[list(perm)]
+                assert np.array_equal(gpu_sort(sorter, a, "u64", params=p), np.sort(vals)), perm
+            if n <= 5:
+                for seq in itertools.product(range(3), repeat=n):
+                    a = np.array(seq, dtype=np.uint64)
+                    assert np.array_equal(gpu_sort(sorter, a, "u64", params=p), np.sort(a)), seq
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100"])
+def test_edge_cases(sorter, kind):
+    rng = np.random.default_rng(11)
+    p1 = ips.make_params(lds_task_max=1, flags=ips.FLAG_NO_SORTED_CHECK)
+    for n in (0, 1, 2, 63, 64, 65, 127, 128, 129, 193, 1000, 4097):
+        a = generate(kind, "uniform", n, 200 + n)
+        log(f"edge {kind} n={n}")
+        assert_parity(gpu_sort(sorter, a, kind, params=p1), a, kind)
+        assert_parity(gpu_sort(sorter, a, kind), a, kind)
+    n = 70_001
+    base = generate(kind, "uniform", n, 1)
+    cases = {"all_equal": np.repeat(base[:1], n, axis=0),
+             "two_values": base[rng.integers(0, 2, n)],
+             "one_outlier": np.concatenate([np.repeat(base[:1], n - 1, axis=0), base[1:2]])}
+    s = oracle.sort(base, kind)
+    cases["sorted"] = s
+    cases["reverse"] = s[::-1].copy()
+    for name, a in cases.items():
+        for params in (None, ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)):
+            log(f"edge {kind} {name} check={params is None}")
+            assert_parity(gpu_sort(sorter, np.ascontiguousarray(a), kind, params=params), a, kind)
+
+
+def test_extreme_keys(sorter):
+    n = 50_000
+    rng = np.random.default_rng(3)
+    u = rng.choice(np.array([0, 1, 2**63, 2**64 - 2, 2**64 - 1], dtype=np.uint64), n)
+    for algo in ("samplesort", "radix"):
+        log(f"extreme u64 {algo}")
+        assert_parity(gpu_sort(sorter, u, "u64", algo=algo), u, "u64")
+    specials = np.array([0x0, 0x8000000000000000, 0x1, 0x8000000000000001, 0x7FF0000000000000,
+                         0xFFF0000000000000, 0x3FF0000000000000, 0xBFF0000000000000,
+                         0x7FF8000000000000, 0xFFF8000000000000], dtype=np.uint64)
+    f = specials[rng.integers(0, specials.size, n)].view(np.float64)
+    for algo in ("samplesort", "radix"):
+        log(f"extreme f64 {algo}")
+        out = gpu_sort(sorter, f, "f64", algo=algo)
+        assert np.array_equal(out.view(np.uint64), oracle.sort(f, "f64").view(np.uint64))
+    r = synth.gen_rec100("uniform", 20_000, 4)
+    r[::3, 0] = 0xFF
+    r[1::3, 0] = 0x80
+    log("extreme rec100")
+    assert_parity(gpu_sort(sorter, r, "rec100"), r, "rec100")
