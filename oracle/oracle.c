@@ -2,9 +2,9 @@
  *
  * Paper references are to arXiv 2009.13569: "Definitions and
  * Preliminaries" (problem statement, super scalar samplesort, branchless
- * decision tree with equality buckets, Algorithm 1), Section 3.1 "Sampling",
- * Section 3.2 "Task Scheduling" (adaptive k), Section 5 "Implementation
- * Details" (parameters, IPS2Ra) and Section 6 (data types, comparators
+ * decision tree with equality buckets, Algorithm 1), Section 4.1 (partitioning step, "Sampling"),
+ * Section 4.2 "Task Scheduling" (adaptive k), Section 6 "Implementation
+ * Details" (parameters, IPS2Ra) and Section 7 (data types, comparators
  * Algorithms 3-4).
  */
 #include "oracle.h"
@@ -51,7 +51,7 @@ static int f64_total_less(uint64_t a, uint64_t b) {
 }
 
 /* Strict key order of the element types.  Pair compares only its key
- * (value is payload, Section 6); rec100 compares the first ten bytes
+ * (value is payload, Section 7); rec100 compares the first ten bytes
  * lexicographically as unsigned bytes (Algorithm 4 read with unsigned
  * char, the memcmp order). */
 int oracle_key_less(int type, const void* a, const void* b) {
@@ -131,7 +131,7 @@ static uint32_t floor_log2_u64(uint64_t x) {
   return r;
 }
 
-/* Oversampling factor alpha = 0.2 log2 n (Section 5), floored and at least
+/* Oversampling factor alpha = 0.2 log2 n (Section 6), floored and at least
  * one.  floor(log2(n)/5) equals floor(floor(log2 n)/5), so the integer form
  * is exact. */
 uint32_t oracle_alpha(uint64_t n) {
@@ -139,7 +139,7 @@ uint32_t oracle_alpha(uint64_t n) {
   return a ? a : 1;
 }
 
-/* Adaptive number of buckets (Section 3.2): for k n0 < n < k^2 n0 use
+/* Adaptive number of buckets (Section 4.2): for k n0 < n < k^2 n0 use
  * 2^ceil((log2(n/n0)+1)/2); for n0 < n <= k n0 use 2^ceil(log2(n/n0));
  * otherwise k.  Evaluated exactly with integers: the smallest c with
  * n0 * 2^(2c-1) >= n, resp. n0 * 2^c >= n.  Clamped to [2, k]. */
@@ -170,7 +170,7 @@ uint64_t oracle_task_seed(uint64_t seed, uint64_t l, uint32_t level) {
   return oracle_splitmix64_next(&st);
 }
 
-/* Sampling phase of one partitioning step (Section 3.1) on the task
+/* Sampling phase of one partitioning step (Section 4.1) on the task
  * data[l, l+n):
  *   alpha = oracle_alpha(n), k' = oracle_adaptive_k(n, k, n0), m = alpha k';
  *   sample j (0 <= j < m) is the element at l + floor(n * x_j / 2^64) where
@@ -260,7 +260,7 @@ int oracle_histogram(const void* data, uint64_t n, int type,
   return 0;
 }
 
-/* Unsigned integer key used by the radix variant (Section 5: IPS2Ra takes
+/* Unsigned integer key used by the radix variant (Section 6: IPS2Ra takes
  * unsigned integer keys).  Doubles use the order-preserving bit map of
  * totalOrder: flip all bits of negatives, set the sign bit of positives. */
 static uint64_t radix_key(int type, const void* e) {
@@ -275,7 +275,7 @@ static uint64_t radix_key(int type, const void* e) {
 
 /* Digit of the radix variant on one task: the task's minimum and maximum
  * key are scanned, h is the highest bit in which they differ (significant
- * bit detection, Section 6.1), and the digit is bits [max(0,h-7), h].
+ * bit detection, Section 7.2), and the digit is bits [max(0,h-7), h].
  * info = {shift, width, all_equal}. */
 int oracle_radix_digit_info(const void* data, uint64_t n, int type,
                             uint32_t* info) {
