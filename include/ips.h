@@ -76,6 +76,8 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
 #define IPS_FLAG_LEVEL1_ONLY 0x8u     /* stop after the root partitioning step: the
                                           array is then partitioned, not sorted; see
                                           ips_get_root_info */
+#define IPS_FLAG_PROFILE 0x20u        /* time every kernel launch with HIP events on
+                                          `stream`; see ips_get_profile */
 #define IPS_FLAG_GLOBAL_BUFFERS 0x10u /* keep the classification buffer blocks in the
                                           workspace instead of LDS, so that block_bytes
                                           may exceed the LDS budget (e.g. 2 KiB blocks
@@ -171,6 +173,29 @@ typedef struct {
 } ips_stats;
 
 int ips_get_stats(ips_ctx* ctx, ips_stats* out);
+
+/* Per-kernel timing of the last sort made with IPS_FLAG_PROFILE.  Row L <
+ * IPS_MAX_LEVELS covers the partitioning steps of recursion level L and the
+ * LDS-tier sorts of the buckets they produced; row IPS_MAX_LEVELS covers
+ * work outside the levels (sorted check, radix min/max, an LDS-only root).
+ * Columns are the IPS_PH_* kernels: ms is the summed launch duration,
+ * elems the elements of the tasks those launches covered, launches the
+ * number of launches. */
+#define IPS_MAX_LEVELS 16
+#define IPS_PHASES 11
+enum {
+  IPS_PH_SORTED_CHECK = 0, IPS_PH_MINMAX = 1, IPS_PH_SAMPLE = 2, IPS_PH_CLASSIFY = 3,
+  IPS_PH_BOUNDARIES = 4, IPS_PH_FLAGS = 5, IPS_PH_PERMUTE = 6, IPS_PH_CLEANUP_A = 7,
+  IPS_PH_CLEANUP_B = 8, IPS_PH_LDS_SORT = 9, IPS_PH_REVERSE = 10
+};
+typedef struct {
+  uint32_t levels, pad;
+  double ms[IPS_MAX_LEVELS + 1][IPS_PHASES];
+  uint64_t elems[IPS_MAX_LEVELS + 1][IPS_PHASES];
+  uint32_t launches[IPS_MAX_LEVELS + 1][IPS_PHASES];
+} ips_profile;
+
+int ips_get_profile(ips_ctx* ctx, ips_profile* out);
 
 /* Last HIP error code seen by the context (hipError_t as int) and the
  * last kernel-reported consistency error (0 = none; bits 0-7 the error

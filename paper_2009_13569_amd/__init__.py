@@ -34,9 +34,13 @@ FLAG_EQ_ON = 0x2
 FLAG_EQ_OFF = 0x4
 FLAG_LEVEL1_ONLY = 0x8
 FLAG_GLOBAL_BUFFERS = 0x10
+FLAG_PROFILE = 0x20
+MAX_LEVELS = 16
+PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags", "permute",
+          "cleanup_a", "cleanup_b", "lds_sort", "reverse"]
 
 EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_last_hip_error",
+           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
            "ips_last_device_error", "ips_status_string", "ips_abi_version"]
 
 
@@ -62,6 +66,13 @@ class Stats(ctypes.Structure):
                 ("max_step_elems", ctypes.c_uint64)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("ms", (ctypes.c_double * len(PHASES)) * (MAX_LEVELS + 1)),
+                ("elems", (ctypes.c_uint64 * len(PHASES)) * (MAX_LEVELS + 1)),
+                ("launches", (ctypes.c_uint32 * len(PHASES)) * (MAX_LEVELS + 1))]
+
+
 _vp, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
 _lib.ips_ctx_create.argtypes = [ctypes.POINTER(_vp), _i32]
 _lib.ips_ctx_destroy.argtypes = [_vp]
@@ -70,13 +81,14 @@ _lib.ips_sort_keys.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POIN
 _lib.ips_sort_pairs.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_get_root_info.argtypes = [_vp, ctypes.POINTER(RootInfo)]
 _lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+_lib.ips_get_profile.argtypes = [_vp, ctypes.POINTER(Profile)]
 _lib.ips_last_hip_error.argtypes = [_vp]
 _lib.ips_last_device_error.argtypes = [_vp]
 _lib.ips_status_string.argtypes = [_i32]
 _lib.ips_status_string.restype = ctypes.c_char_p
 for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_last_hip_error",
-           "ips_last_device_error", "ips_abi_version"):
+           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_get_profile",
+           "ips_last_hip_error", "ips_last_device_error", "ips_abi_version"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -183,6 +195,20 @@ class Sorter:
         s = Stats()
         _lib.ips_get_stats(self._h, ctypes.byref(s))
         return s
+
+    def profile(self) -> dict:
+        """Per-level, per-kernel timing of the last sort run with FLAG_PROFILE:
+        {row: {phase: (ms, elems, launches)}}; row "outside" is work outside
+        the recursion levels."""
+        p = Profile()
+        _lib.ips_get_profile(self._h, ctypes.byref(p))
+        out = {}
+        for row in range(MAX_LEVELS + 1):
+            d = {ph: (p.ms[row][i], int(p.elems[row][i]), int(p.launches[row][i]))
+                 for i, ph in enumerate(PHASES) if p.launches[row][i]}
+            if d:
+                out["outside" if row == MAX_LEVELS else row] = d
+        return out
 
 
 _default = {}

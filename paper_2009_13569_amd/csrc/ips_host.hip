@@ -109,7 +109,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     c->b_req = paper_block(D);
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
-  if (p->flags & ~0x1Fu) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0x3Fu) return IPS_E_INVALID_ARG;
   c->L = nullptr;
   return IPS_OK;
 }
@@ -215,11 +215,60 @@ struct ips_ctx {
   int last_dev = 0;
   ips_root_info root;
   ips_stats stats;
+  ips_profile prof;
   uint8_t* pin = nullptr;   // pinned staging
   size_t pin_bytes = 0;
+  // Launch timing (IPS_FLAG_PROFILE): event pairs resolved at sync points.
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { hipEvent_t a, b; uint32_t row, ph; uint64_t elems; };
+  std::vector<Pending> pending;
+  bool profiling = false;
 };
 
 namespace {
+
+hipEvent_t take_event(ips_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Collects the durations of finished launches into ctx->prof.
+void resolve_profile(ips_ctx* ctx) {
+  for (const auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->prof.ms[p.row][p.ph] += ms;
+      ctx->prof.elems[p.row][p.ph] += p.elems;
+      ctx->prof.launches[p.row][p.ph] += 1;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+// Brackets one launch with events when profiling.
+template <class F>
+hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64_t elems, F&& launch) {
+  if (!ctx->profiling) return launch();
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  if (e != hipSuccess) return e;
+  if (row > IPS_MAX_LEVELS) row = IPS_MAX_LEVELS;
+  ctx->pending.push_back({a, b, row, ph, elems});
+  return hipSuccess;
+}
 
 #define HIPCHK(ctx, expr)                        \
   do {                                           \
@@ -275,21 +324,27 @@ int check_dev_error(Run& r) {
 int read_ctrl(Run& r) {
   HIPCHK(r.ctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st));
   HIPCHK(r.ctx, hipStreamSynchronize(r.st));
+  resolve_profile(r.ctx);
   return check_dev_error(r);
 }
 
-int launch_lds_tasks(Run& r, const std::vector<LTask>& lt) {
+int launch_lds_tasks(Run& r, const std::vector<LTask>& lt, uint32_t row) {
   size_t done = 0;
   while (done < lt.size()) {
     const size_t cnt = std::min<size_t>(lt.size() - done, r.L.LTB);
     std::memcpy(r.h_lt, lt.data() + done, cnt * sizeof(LTask));
     LTask* d_lt = wsp<LTask>(r, R_LT);
+    uint64_t el = 0;
+    for (size_t q = 0; q < cnt; ++q) el += lt[done + q].n;
     HIPCHK(r.ctx, hipMemcpyAsync(d_lt, r.h_lt, cnt * sizeof(LTask), hipMemcpyHostToDevice, r.st));
-    HIPCHK(r.ctx, r.c.L->lds_sort(d_lt, (uint32_t)cnt, r.data, r.c.cap, r.a.ctrl, r.st));
+    HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
+             return r.c.L->lds_sort(d_lt, (uint32_t)cnt, r.data, r.c.cap, r.a.ctrl, r.st);
+           }));
     done += cnt;
     r.ctx->stats.lds_tasks += (uint32_t)cnt;
     if (done < lt.size()) {   // the staging buffer is reused: wait for the copy
       HIPCHK(r.ctx, hipStreamSynchronize(r.st));
+      resolve_profile(r.ctx);
     }
   }
   return IPS_OK;
@@ -335,11 +390,15 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   std::vector<Hdr> hdr(T);
   if (!c.radix) {
     HIPCHK(ctx, hipMemcpyAsync(d_tasks, r.h_tasks, T * sizeof(PTask), hipMemcpyHostToDevice, r.st));
-    HIPCHK(ctx, c.L->sample(r.a, T, c.seed, c.k, c.n0, r.st));
+    uint64_t el = 0;
+    for (const HTask& t : bt) el += t.n;
+    HIPCHK(ctx, timed(ctx, r.st, bt[0].level, IPS_PH_SAMPLE, el,
+                      [&] { return c.L->sample(r.a, T, c.seed, c.k, c.n0, r.st); }));
     HIPCHK(ctx, hipMemcpy2DAsync(r.h_rb, sizeof(Hdr), d_recs, sizeof(StepRec), sizeof(Hdr), T,
                                  hipMemcpyDeviceToHost, r.st));
     HIPCHK(ctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st));
     HIPCHK(ctx, hipStreamSynchronize(r.st));
+    resolve_profile(ctx);
     if (int e = check_dev_error(r)) return e;
     std::memcpy(hdr.data(), r.h_rb, T * sizeof(Hdr));
   } else {
@@ -423,12 +482,19 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_CLS), h_cls, wg * 4, hipMemcpyHostToDevice, r.st));
   HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_PERM), h_perm, pwg * 4, hipMemcpyHostToDevice, r.st));
   HIPCHK(ctx, hipMemcpyAsync(wsp<uint32_t>(r, R_CLN), h_cln, cln * 4, hipMemcpyHostToDevice, r.st));
-  HIPCHK(ctx, c.L->classify(r.a, wg, (uint32_t)max_dyn, c.gbuf, r.st));
-  HIPCHK(ctx, launch_boundaries(r.a, T, c.cmax, r.st));
-  HIPCHK(ctx, launch_fill32(r.a.flags, flag_off, 0u, r.st));
-  HIPCHK(ctx, c.L->permute(r.a, pwg, r.st));
-  HIPCHK(ctx, c.L->cleanup_a(r.a, T, r.st));
-  HIPCHK(ctx, c.L->cleanup_b(r.a, cln, maxW, r.st));
+  uint64_t bel = 0;
+  for (const HTask& t : bt) bel += t.n;
+  const uint32_t row = bt[0].level;
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, bel,
+                    [&] { return c.L->classify(r.a, wg, (uint32_t)max_dyn, c.gbuf, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, bel,
+                    [&] { return launch_boundaries(r.a, T, c.cmax, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, bel,
+                    [&] { return launch_fill32(r.a.flags, flag_off, 0u, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, bel, [&] { return c.L->permute(r.a, pwg, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, bel, [&] { return c.L->cleanup_a(r.a, T, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, bel,
+                    [&] { return c.L->cleanup_b(r.a, cln, maxW, r.st); }));
   // 4. Bucket boundaries back to the host.
   const size_t sb_bytes = (size_t)bucket * 8;
   const size_t mm_bytes = c.radix ? (size_t)bucket * 8 : 0;
@@ -520,7 +586,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
       }
     }
   }
-  return launch_lds_tasks(r, lt);
+  return launch_lds_tasks(r, lt, bt[0].level);
 }
 
 int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
@@ -536,6 +602,10 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   if (n >= (1ull << 31) * (uint64_t)block_elems(r.c, max_nb(r.c))) return IPS_E_TOO_LARGE;
   std::memset(&ctx->root, 0, sizeof(ctx->root));
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+  for (const auto& p : ctx->pending) { ctx->ev_pool.push_back(p.a); ctx->ev_pool.push_back(p.b); }
+  ctx->pending.clear();
+  ctx->profiling = (r.c.flags & IPS_FLAG_PROFILE) != 0;
   ctx->last_dev = 0;
   if (n < 2) return IPS_OK;
   plan(n, r.c, &r.L);
@@ -601,14 +671,15 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_MINMAX, 2, 0xFFFFFFFFu, r.st));
   // Sorted and reverse-sorted inputs (Section 6).
   if (!(r.c.flags & (IPS_FLAG_NO_SORTED_CHECK | IPS_FLAG_LEVEL1_ONLY))) {
-    HIPCHK(ctx, r.c.L->sorted_check(r.data, n, a.ctrl, r.st));
+    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
+                      [&] { return r.c.L->sorted_check(r.data, n, a.ctrl, r.st); }));
     if (int e = read_ctrl(r)) return e;
     if (!r.h_ctrl[CTRL_DESC]) { ctx->stats.detected = 1; return IPS_OK; }
     if (!r.h_ctrl[CTRL_ASC]) {
       ctx->stats.detected = 2;
-      HIPCHK(ctx, r.c.L->reverse(r.data, n, r.st));
-      HIPCHK(ctx, hipStreamSynchronize(r.st));
-      return IPS_OK;
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_REVERSE, n,
+                        [&] { return r.c.L->reverse(r.data, n, r.st); }));
+      return read_ctrl(r);
     }
   }
   HTask root;
@@ -621,7 +692,8 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   if (r.c.flags & IPS_FLAG_EQ_ON) root.tflags |= TF_EQ_ON;
   if (r.c.flags & IPS_FLAG_EQ_OFF) root.tflags |= TF_EQ_OFF;
   if (r.c.radix) {
-    HIPCHK(ctx, r.c.L->minmax(r.data, n, a.ctrl, r.st));
+    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, n,
+                      [&] { return r.c.L->minmax(r.data, n, a.ctrl, r.st); }));
     if (int e = read_ctrl(r)) return e;
     const uint64_t mn = (uint64_t)r.h_ctrl[CTRL_MINMAX] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 1] << 32);
     const uint64_t mx = (uint64_t)r.h_ctrl[CTRL_MINMAX + 2] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 3] << 32);
@@ -636,7 +708,7 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
     lt[0].n = (uint32_t)n;
     lt[0].pad = 0;
     ctx->stats.lds_elems += n;
-    if (int e = launch_lds_tasks(r, lt)) return e;
+    if (int e = launch_lds_tasks(r, lt, IPS_MAX_LEVELS)) return e;
     return read_ctrl(r);
   }
   std::vector<HTask> cur(1, root), next;
@@ -663,6 +735,7 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
       if (r.c.flags & IPS_FLAG_LEVEL1_ONLY) return IPS_OK;
     }
     ctx->stats.levels = ++level;
+    ctx->prof.levels = std::min<uint32_t>(level, IPS_MAX_LEVELS);
     std::swap(cur, next);
   }
   return read_ctrl(r);
@@ -705,6 +778,8 @@ int ips_ctx_create(ips_ctx** out, int device) {
 
 int ips_ctx_destroy(ips_ctx* ctx) {
   if (!ctx) return IPS_OK;
+  for (const auto& p : ctx->pending) { ctx->ev_pool.push_back(p.a); ctx->ev_pool.push_back(p.b); }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
   return IPS_OK;
@@ -746,6 +821,12 @@ int ips_get_root_info(ips_ctx* ctx, ips_root_info* out) {
 int ips_get_stats(ips_ctx* ctx, ips_stats* out) {
   if (!ctx || !out) return IPS_E_INVALID_ARG;
   *out = ctx->stats;
+  return IPS_OK;
+}
+
+int ips_get_profile(ips_ctx* ctx, ips_profile* out) {
+  if (!ctx || !out) return IPS_E_INVALID_ARG;
+  *out = ctx->prof;
   return IPS_OK;
 }
 
