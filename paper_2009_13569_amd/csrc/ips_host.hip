@@ -62,13 +62,8 @@ const Launchers* launchers_for(int t) {
 }
 
 uint32_t default_cap(int t) {
-  switch (t) {
-    case 1: return 16384;
-    case 2: case 3: return 8192;
-    case 4: return 4096;
-    case 5: return 1024;
-    default: return 0;
-  }
+  const Launchers* L = launchers_for(t);
+  return L ? L->lds_cap : 0;
 }
 
 // Paper's block size max(1, 2^floor(11 - log2 D)) elements (Section 6).
@@ -328,18 +323,33 @@ int read_ctrl(Run& r) {
   return check_dev_error(r);
 }
 
-int launch_lds_tasks(Run& r, const std::vector<LTask>& lt, uint32_t row) {
+// Sorts the given small tasks in the LDS tier: tasks up to the small
+// variant's capacity with that variant, larger ones with the large variant;
+// both parts share one upload.
+int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
+  std::vector<LTask> lt;
+  lt.reserve(lt_in.size());
+  const uint32_t small = r.c.L->lds_cap_small;
+  for (const LTask& t : lt_in) if (t.n <= small) lt.push_back(t);
+  const size_t nsmall = lt.size();
+  for (const LTask& t : lt_in) if (t.n > small) lt.push_back(t);
   size_t done = 0;
   while (done < lt.size()) {
     const size_t cnt = std::min<size_t>(lt.size() - done, r.L.LTB);
     std::memcpy(r.h_lt, lt.data() + done, cnt * sizeof(LTask));
     LTask* d_lt = wsp<LTask>(r, R_LT);
-    uint64_t el = 0;
-    for (size_t q = 0; q < cnt; ++q) el += lt[done + q].n;
     HIPCHK(r.ctx, hipMemcpyAsync(d_lt, r.h_lt, cnt * sizeof(LTask), hipMemcpyHostToDevice, r.st));
-    HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
-             return r.c.L->lds_sort(d_lt, (uint32_t)cnt, r.data, r.c.cap, r.a.ctrl, r.st);
-           }));
+    for (int part = 0; part < 2; ++part) {
+      const size_t p0 = part == 0 ? done : std::max(done, nsmall);
+      const size_t p1 = part == 0 ? std::min(done + cnt, nsmall) : done + cnt;
+      if (p1 <= p0) continue;
+      uint64_t el = 0;
+      for (size_t q = p0; q < p1; ++q) el += lt[q].n;
+      HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
+               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, part == 1,
+                                      r.a.ctrl, r.st);
+             }));
+    }
     done += cnt;
     r.ctx->stats.lds_tasks += (uint32_t)cnt;
     if (done < lt.size()) {   // the staging buffer is reused: wait for the copy
@@ -672,8 +682,13 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   // Sorted and reverse-sorted inputs (Section 6).
   if (!(r.c.flags & (IPS_FLAG_NO_SORTED_CHECK | IPS_FLAG_LEVEL1_ONLY))) {
     HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
-                      [&] { return r.c.L->sorted_check(r.data, n, a.ctrl, r.st); }));
+                      [&] { return r.c.L->sorted_sample(r.data, n, a.ctrl, r.st); }));
     if (int e = read_ctrl(r)) return e;
+    if (!r.h_ctrl[CTRL_DESC] || !r.h_ctrl[CTRL_ASC]) {   // inconclusive: scan everything
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
+                        [&] { return r.c.L->sorted_check(r.data, n, a.ctrl, r.st); }));
+      if (int e = read_ctrl(r)) return e;
+    }
     if (!r.h_ctrl[CTRL_DESC]) { ctx->stats.detected = 1; return IPS_OK; }
     if (!r.h_ctrl[CTRL_ASC]) {
       ctx->stats.detected = 2;

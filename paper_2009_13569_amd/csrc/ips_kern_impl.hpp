@@ -3,20 +3,27 @@
 #pragma once
 #include "ips_kernels.hpp"
 #include "ips_launch.hpp"
+#include "ips_lds_tier.hpp"
 
 namespace ips {
 
+// LDS-tier shapes per type: (threads, keys per thread) of the small and the
+// large variant.
+template <class T> struct LdsShape;
+template <> struct LdsShape<TU32> { static constexpr uint32_t NS = 512, ES = 32, NB = 512, EB = 32, NET = 32; };
+template <> struct LdsShape<TU64> { static constexpr uint32_t NS = 512, ES = 16, NB = 1024, EB = 16, NET = 32; };
+template <> struct LdsShape<TF64> { static constexpr uint32_t NS = 512, ES = 16, NB = 1024, EB = 16, NET = 32; };
+template <> struct LdsShape<TPair> { static constexpr uint32_t NS = 512, ES = 8, NB = 512, EB = 8, NET = 32; };
+template <> struct LdsShape<TRec100> { static constexpr uint32_t NS = 256, ES = 4, NB = 256, EB = 4, NET = 16; };
+
 template <class T>
 struct LaunchImpl {
-  static size_t lds_bytes(uint32_t cap) {
-    uint32_t P = 2;
-    while (P < cap) P <<= 1;
-    size_t bytes = (size_t)P * sizeof(typename T::Key);
-    if (!T::KEYS_ONLY) bytes += (size_t)P * 4 + (size_t)cap * T::DW * 4;
-    return bytes;
-  }
+  using SH = LdsShape<T>;
+  static constexpr uint32_t CAP_SMALL = SH::NS * SH::ES;
+  static constexpr uint32_t CAP_BIG = SH::NB * SH::EB;
+
   static hipError_t sample_(const BatchArgs& a, uint32_t nt, uint64_t seed, uint32_t k, uint32_t n0,
-                           hipStream_t st) {
+                            hipStream_t st) {
     if (!nt) return hipSuccess;
     hipLaunchKernelGGL((k_sample<T>), dim3(nt), dim3(SMP_THREADS), 0, st, a, seed, k, n0);
     return hipGetLastError();
@@ -26,7 +33,7 @@ struct LaunchImpl {
     static bool attr_done = false;
     if (!attr_done) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_classify<T, false>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)BUF_LDS_BYTES);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)BUF_LDS_BYTES);
       attr_done = true;
     }
     if (gbuf)
@@ -51,17 +58,29 @@ struct LaunchImpl {
     hipLaunchKernelGGL((k_cleanup_b<T>), dim3(nwg), dim3(CLN_THREADS), dyn, st, a, max_w);
     return hipGetLastError();
   }
-  static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t cap, uint32_t* ctrl,
-                             hipStream_t st) {
-    if (!nt) return hipSuccess;
+  template <uint32_t N, uint32_t E>
+  static hipError_t lds_launch(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl,
+                               hipStream_t st) {
     static bool attr_done = false;
-    const size_t dyn = lds_bytes(cap);
+    const size_t dyn = LdsTier<T, N, E, SH::NET>::lds_bytes();
     if (!attr_done) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_sort<T>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_tier<T, N, E, SH::NET>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
       attr_done = true;
     }
-    hipLaunchKernelGGL((k_lds_sort<T>), dim3(nt), dim3(LDST_THREADS), dyn, st, lt, data, cap, ctrl);
+    hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl);
+    return hipGetLastError();
+  }
+  static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, bool big, uint32_t* ctrl,
+                             hipStream_t st) {
+    if (!nt) return hipSuccess;
+    if constexpr (CAP_BIG > CAP_SMALL) {
+      if (big) return lds_launch<SH::NB, SH::EB>(lt, nt, data, ctrl, st);
+    }
+    return lds_launch<SH::NS, SH::ES>(lt, nt, data, ctrl, st);
+  }
+  static hipError_t sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL((k_sorted_sample<T>), dim3(1), dim3(1024), 0, st, data, n, ctrl);
     return hipGetLastError();
   }
   static hipError_t sorted_check(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
@@ -90,8 +109,8 @@ struct LaunchImpl {
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
-        0, &lds_bytes, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
-        &sorted_check, &reverse, &minmax};
+        CAP_BIG, CAP_SMALL, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
+        &sorted_sample, &sorted_check, &reverse, &minmax};
     return &t;
   }
 };

@@ -8,7 +8,8 @@
 //   k_boundaries  bucket sizes, delimiters, read/write pointer pieces
 //   k_permute     block permutation with atomic read/write pointers
 //   k_cleanup_a/b cleanup of bucket heads/tails (Section 4.1 "Cleanup")
-// Tasks small enough for one workgroup's LDS are sorted by k_lds_sort.
+// Tasks small enough for one workgroup's LDS are sorted by k_lds_tier
+// (ips_lds_tier.hpp).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -886,80 +887,6 @@ __global__ void __launch_bounds__(CLN_THREADS) k_cleanup_b(BatchArgs a, uint32_t
   }
 }
 
-// ---------------------------------------------------------------- LDS tier
-
-// Sorts a task of at most `cap` elements inside one workgroup's LDS:
-// one coalesced load, a bitonic sort of (key, index) pairs, one store.
-template <class T>
-__global__ void __launch_bounds__(LDST_THREADS)
-k_lds_sort(const LTask* lt, uint32_t* data, uint32_t cap, uint32_t* ctrl) {
-  using Key = typename T::Key;
-  constexpr int DW = T::DW;
-  constexpr uint32_t NT = LDST_THREADS;
-  extern __shared__ __align__(16) uint32_t s_dyn[];
-  const LTask t = lt[blockIdx.x];
-  const uint32_t n = t.n;
-  if (n > cap) {
-    if (threadIdx.x == 0) dev_error(ctrl, DE_LDST, blockIdx.x, n);
-    return;
-  }
-  if (n < 2) return;
-  uint32_t P = 2;
-  while (P < n) P <<= 1;
-  Key* keys = reinterpret_cast<Key*>(s_dyn);
-  uint32_t* idx = reinterpret_cast<uint32_t*>(keys + P);
-  uint32_t* stage = idx + P;
-  uint32_t* gd = data + t.l * DW;
-  if constexpr (T::KEYS_ONLY) {
-    for (uint32_t i = threadIdx.x; i < P; i += NT) {
-      if (i < n) {
-        uint32_t w[DW];
-        ld_elem<DW>(gd + (uint64_t)i * DW, w);
-        keys[i] = key_of<T>(w);
-      } else {
-        keys[i] = T::kmax();
-      }
-    }
-    __syncthreads();
-    lds_bitonic_keys(keys, P);
-    for (uint32_t i = threadIdx.x; i < n; i += NT) {
-      uint32_t w[DW];
-      T::from_key(keys[i], w);
-      st_elem<DW>(gd + (uint64_t)i * DW, w);
-    }
-  } else {
-    for (uint32_t x = threadIdx.x; x < n * DW; x += NT) stage[x] = gd[x];
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < P; i += NT) {
-      if (i < n) {
-        const uint32_t* e = stage + (uint64_t)i * DW;
-        keys[i] = T::key(e[0], e[DW > 1 ? 1 : 0], e[DW > 2 ? 2 : 0]);
-      } else {
-        keys[i] = T::kmax();
-      }
-      idx[i] = i;
-    }
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = threadIdx.x; i < P / 2; i += NT) {
-          const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
-          const bool up = (lo & k) == 0;
-          const Key x = keys[lo], y = keys[hi];
-          const uint32_t ix = idx[lo], iy = idx[hi];
-          const bool ylt = kless(y, x) || (keq(x, y) && iy < ix);
-          if (ylt == up) { keys[lo] = y; keys[hi] = x; idx[lo] = iy; idx[hi] = ix; }
-        }
-        __syncthreads();
-      }
-    }
-    for (uint32_t x = threadIdx.x; x < n * DW; x += NT) {
-      const uint32_t i = x / DW, d = x - i * DW;
-      gd[x] = stage[(uint64_t)idx[i] * DW + d];
-    }
-  }
-}
-
 // -------------------------------------------------- sorted check, radix root
 
 // Sorted / reverse-sorted detection (Section 6): records whether any
@@ -992,6 +919,30 @@ __global__ void __launch_bounds__(256) k_sorted_check(const uint32_t* data, uint
     if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_DESC], 1u);
     if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_ASC], 1u);
   }
+}
+
+// Cheap first look at sortedness: 65536 adjacent pairs spread evenly over
+// the array.  If it already finds an ascent and a descent, the input is
+// neither sorted nor reverse sorted and the full scan is skipped.
+template <class T>
+__global__ void __launch_bounds__(1024) k_sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  constexpr uint64_t PAIRS = 65536;
+  uint32_t desc = 0, asc = 0;
+  for (uint64_t j = threadIdx.x; j < PAIRS; j += 1024) {
+    const uint64_t i = (uint64_t)(((unsigned __int128)j * (n - 1)) / PAIRS);
+    if (i + 1 < n) {
+      uint32_t w0[DW], w1[DW];
+      ld_elem<DW>(data + i * DW, w0);
+      ld_elem<DW>(data + (i + 1) * DW, w1);
+      const Key x = key_of<T>(w0), y = key_of<T>(w1);
+      desc |= kless(y, x) ? 1u : 0u;
+      asc |= kless(x, y) ? 1u : 0u;
+    }
+  }
+  if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_DESC], 1u);
+  if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_ASC], 1u);
 }
 
 template <int DW>

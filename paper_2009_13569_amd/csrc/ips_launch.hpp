@@ -13,16 +13,17 @@ struct Launchers {
   uint32_t dw;            // dwords per element
   uint32_t key_slot;      // bytes of a key in StepRec slots actually used
   bool keys_only, radix_ok;
-  uint32_t lds_cap;       // default LDS-tier capacity (elements)
-  size_t (*lds_bytes)(uint32_t cap);
+  uint32_t lds_cap;       // LDS-tier capacity (elements)
+  uint32_t lds_cap_small; // tasks up to this size use the smaller, faster variant
   hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, uint32_t k, uint32_t n0,
                        hipStream_t);
   hipError_t (*classify)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, bool gbuf, hipStream_t);
   hipError_t (*permute)(const BatchArgs&, uint32_t nwg, hipStream_t);
   hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);
   hipError_t (*cleanup_b)(const BatchArgs&, uint32_t nwg, uint32_t max_w, hipStream_t);
-  hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, uint32_t cap, uint32_t* ctrl,
+  hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, bool big, uint32_t* ctrl,
                          hipStream_t);
+  hipError_t (*sorted_sample)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*sorted_check)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*reverse)(uint32_t* data, uint64_t n, hipStream_t);
   hipError_t (*minmax)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);

@@ -1,0 +1,354 @@
+// LDS tier: a task small enough for one workgroup is loaded once, sorted
+// inside LDS and registers, and stored once (the base case of the
+// recursion; Section 6 of arXiv 2009.13569 uses insertion sort for IPS4o and
+// a radix sort for IPS2Ra).  Here the base case is itself one distribution
+// pass plus tiny sorts:
+//   1. keys go to registers; the task's minimum and maximum are reduced;
+//   2. each key gets the bin (key - min) >> shift, where shift leaves about
+//      NET/2 keys per bin (equal-width bins over the key range);
+//   3. bin counts by LDS atomics, an exclusive scan, a scatter into LDS;
+//   4. each thread sorts one bin of at most NET keys with a register bitonic
+//      network; a bin whose keys are all equal needs nothing; any other
+//      larger bin is sorted by one wavefront with a bitonic network in LDS;
+//      a bin above WAVE_MAX falls back to a bitonic sort of the whole task;
+//   5. one coalesced store (records are gathered from their LDS copy).
+#pragma once
+#include "ips_kernels.hpp"
+
+namespace ips {
+
+constexpr uint32_t WAVE_MAX = 1024;   // largest bin sorted by one wavefront
+
+// Order-preserving unsigned image of a key for binning.
+__device__ __forceinline__ uint64_t bin_image(uint32_t k) { return k; }
+__device__ __forceinline__ uint64_t bin_image(uint64_t k) { return k; }
+__device__ __forceinline__ unsigned __int128 bin_image(const K80& k) {
+  return ((unsigned __int128)k.hi << 16) | (unsigned __int128)k.lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_img(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned __int128 shfl_xor_img(unsigned __int128 v, int m) {
+  const uint64_t lo = shfl_xor_img((uint64_t)v, m), hi = shfl_xor_img((uint64_t)(v >> 64), m);
+  return ((unsigned __int128)hi << 64) | lo;
+}
+
+// Exclusive prefix sum of cnt[0, nb) into off[0, nb] by the whole block.
+template <uint32_t NT>
+__device__ void block_excl_scan(const uint32_t* cnt, uint32_t* off, uint32_t nb, uint32_t* s_wsum) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t per = (nb + NT - 1) / NT;
+  const uint32_t b0 = tid * per;
+  uint32_t loc = 0;
+  for (uint32_t i = 0; i < per; ++i)
+    if (b0 + i < nb) loc += cnt[b0 + i];
+  uint32_t inc = loc;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
+    if ((int)lane >= o) inc += y;
+  }
+  if (lane == 63) s_wsum[wave] = inc;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (uint32_t w = 0; w < wave; ++w) wbase += s_wsum[w];
+  uint32_t acc = wbase + inc - loc;
+  for (uint32_t i = 0; i < per; ++i) {
+    if (b0 + i < nb) { off[b0 + i] = acc; acc += cnt[b0 + i]; }
+  }
+  if (tid == NT - 1) {
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < NT / 64; ++w) tot += s_wsum[w];
+    off[nb] = tot;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t bitlen(uint64_t x) { return x ? 64u - __clzll(x) : 0u; }
+__device__ __forceinline__ uint32_t bitlen(unsigned __int128 x) {
+  const uint64_t hi = (uint64_t)(x >> 64);
+  return hi ? 128u - __clzll(hi) : bitlen((uint64_t)x);
+}
+
+template <class Key, bool IDX>
+__device__ __forceinline__ void ce_up(Key& a, Key& b, uint32_t& ia, uint32_t& ib) {
+  const bool sw = kless(b, a) || (IDX && keq(a, b) && ib < ia);
+  const Key ta = a, tb = b;
+  a = sw ? tb : ta;
+  b = sw ? ta : tb;
+  if (IDX) {
+    const uint32_t ua = ia, ub = ib;
+    ia = sw ? ub : ua;
+    ib = sw ? ua : ub;
+  }
+}
+
+// One stage of the all-ascending bitonic network on N register keys: the
+// first step of each merge of size K compares i with i ^ (K - 1), the later
+// steps (half size J) compare i with i ^ J.  Template parameters keep every
+// register index a compile-time constant.
+template <uint32_t N, uint32_t K, uint32_t J, class Key, bool IDX>
+__device__ __forceinline__ void net_stage(Key (&v)[N], uint32_t (&ix)[N]) {
+#pragma unroll
+  for (uint32_t i = 0; i < N; ++i) {
+    const uint32_t p = (J == K / 2) ? (i ^ (K - 1)) : (i ^ J);
+    if (p > i) ce_up<Key, IDX>(v[i], v[p], ix[i], ix[p]);
+  }
+}
+
+template <uint32_t N, uint32_t K, uint32_t J, class Key, bool IDX>
+__device__ __forceinline__ void net_merge(Key (&v)[N], uint32_t (&ix)[N]) {
+  net_stage<N, K, J, Key, IDX>(v, ix);
+  if constexpr (J > 1) net_merge<N, K, J / 2, Key, IDX>(v, ix);
+}
+
+template <uint32_t N, uint32_t K, class Key, bool IDX>
+__device__ __forceinline__ void net_sort(Key (&v)[N], uint32_t (&ix)[N]) {
+  net_merge<N, K, K / 2, Key, IDX>(v, ix);
+  if constexpr (K < N) net_sort<N, 2 * K, Key, IDX>(v, ix);
+}
+
+// Sorts N register keys ascending; padding with the largest key at the end
+// stays in place because every comparator puts the minimum at the lower index.
+template <uint32_t N, class Key, bool IDX>
+__device__ __forceinline__ void reg_network(Key (&v)[N], uint32_t (&ix)[N]) {
+  net_sort<N, 2, Key, IDX>(v, ix);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront sorts keys[0, s) (and their indices) in LDS with the same
+// all-ascending network over the next power of two, skipping comparators
+// that touch the virtual padding.
+template <class Key, bool IDX>
+__device__ void wave_network(Key* keys, uint16_t* idx, uint32_t s) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t P = 1;
+  while (P < s) P <<= 1;
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = lane; i < P; i += 64) {
+        const uint32_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+        if (p > i && p < s) {
+          Key a = keys[i], b = keys[p];
+          uint32_t ia = IDX ? idx[i] : 0, ib = IDX ? idx[p] : 0;
+          const bool sw = kless(b, a) || (IDX && keq(a, b) && ib < ia);
+          if (sw) {
+            keys[i] = b; keys[p] = a;
+            if (IDX) { idx[i] = (uint16_t)ib; idx[p] = (uint16_t)ia; }
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// Whole-task fallback: block-wide all-ascending network over keys[0, s).
+template <class Key, bool IDX>
+__device__ void block_network(Key* keys, uint16_t* idx, uint32_t s) {
+  uint32_t P = 1;
+  while (P < s) P <<= 1;
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        const uint32_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+        if (p > i && p < s) {
+          Key a = keys[i], b = keys[p];
+          uint32_t ia = IDX ? idx[i] : 0, ib = IDX ? idx[p] : 0;
+          const bool sw = kless(b, a) || (IDX && keq(a, b) && ib < ia);
+          if (sw) {
+            keys[i] = b; keys[p] = a;
+            if (IDX) { idx[i] = (uint16_t)ib; idx[p] = (uint16_t)ia; }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <class T, uint32_t NT, uint32_t E, uint32_t NET>
+struct LdsTier {
+  using Key = typename T::Key;
+  static constexpr uint32_t CAP = NT * E;
+  static constexpr uint32_t MAXBINS = (CAP / (NET / 2) < 2048) ? CAP / (NET / 2) : 2048;
+  static constexpr bool IDX = !T::KEYS_ONLY;
+  // dynamic LDS: keys[CAP] | idx[CAP] (records) | stage[CAP * DW] (records)
+  static constexpr size_t lds_bytes() {
+    return (size_t)CAP * sizeof(Key) + (IDX ? (size_t)CAP * 2 + (size_t)CAP * T::DW * 4 : 0);
+  }
+};
+
+template <class T, uint32_t NT, uint32_t E, uint32_t NET>
+__global__ void __launch_bounds__(NT)
+k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
+  using LT = LdsTier<T, NT, E, NET>;
+  using Key = typename T::Key;
+  using Img = decltype(bin_image(Key()));
+  constexpr int DW = T::DW;
+  constexpr uint32_t CAP = LT::CAP, MAXBINS = LT::MAXBINS;
+  constexpr bool IDX = LT::IDX;
+  extern __shared__ __align__(16) uint8_t s_raw[];
+  __shared__ uint32_t s_cnt[MAXBINS];
+  __shared__ uint32_t s_off[MAXBINS + 1];
+  __shared__ Img s_min[NT / 64], s_max[NT / 64];
+  __shared__ uint32_t s_big[64];
+  __shared__ uint32_t s_wsum[NT / 64];
+  __shared__ uint32_t s_nbig, s_fallback;
+
+  Key* keys = reinterpret_cast<Key*>(s_raw);
+  uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(idxb + CAP);
+  const LTask t = lt[blockIdx.x];
+  const uint32_t n = t.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (n > CAP) {
+    if (tid == 0) dev_error(ctrl, DE_LDST, blockIdx.x, n);
+    return;
+  }
+  if (n < 2) return;
+  uint32_t* gd = data + t.l * DW;
+
+  // 1. Load keys into registers (records: also stage the records in LDS).
+  Key k[E];
+  if constexpr (IDX) {
+    for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = e * NT + tid;
+      if (i < n) {
+        const uint32_t* r = stage + i * DW;
+        k[e] = T::key(r[0], r[DW > 1 ? 1 : 0], r[DW > 2 ? 2 : 0]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = e * NT + tid;
+      if (i < n) {
+        uint32_t w[DW];
+        ld_elem<DW>(gd + (uint64_t)i * DW, w);
+        k[e] = key_of<T>(w);
+      }
+    }
+  }
+  Img mn = ~(Img)0, mx = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    if (e * NT + tid < n) {
+      const Img b = bin_image(k[e]);
+      mn = b < mn ? b : mn;
+      mx = b > mx ? b : mx;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const Img a = shfl_xor_img(mn, o), b = shfl_xor_img(mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) { s_min[wave] = mn; s_max[wave] = mx; }
+  for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
+  if (tid == 0) { s_nbig = 0; s_fallback = 0; }
+  __syncthreads();
+  mn = s_min[0];
+  mx = s_max[0];
+  for (uint32_t w = 1; w < NT / 64; ++w) {
+    mn = s_min[w] < mn ? s_min[w] : mn;
+    mx = s_max[w] > mx ? s_max[w] : mx;
+  }
+  if (mn == mx) return;   // all keys equal: already sorted
+
+  // 2./3. Bins, counts, scan, scatter.
+  uint32_t lb = 1;
+  while ((1u << lb) < MAXBINS && (1u << lb) * (NET / 2) < n) ++lb;
+  const uint32_t span = bitlen((Img)(mx - mn));
+  const uint32_t shift = span > lb ? span - lb : 0;
+  const uint32_t nbins = 1u << lb;
+  uint32_t bin[E], rk[E];
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    if (e * NT + tid < n) {
+      bin[e] = (uint32_t)((bin_image(k[e]) - mn) >> shift);
+      rk[e] = atomicAdd(&s_cnt[bin[e]], 1u);
+    }
+  }
+  __syncthreads();
+  block_excl_scan<NT>(s_cnt, s_off, nbins, s_wsum);
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    const uint32_t i = e * NT + tid;
+    if (i < n) {
+      const uint32_t q = s_off[bin[e]] + rk[e];
+      keys[q] = k[e];
+      if constexpr (IDX) idxb[q] = (uint16_t)i;
+    }
+  }
+  __syncthreads();
+
+  // 4. Small bins in registers; larger ones listed for the wavefronts.
+  for (uint32_t b = tid; b < nbins; b += NT) {
+    const uint32_t s = s_cnt[b], o = s_off[b];
+    if (s <= 1) continue;
+    if (s <= NET) {
+      Key v[NET];
+      uint32_t ix[NET];
+#pragma unroll
+      for (uint32_t i = 0; i < NET; ++i) {
+        v[i] = (i < s) ? keys[o + i] : T::kmax();
+        ix[i] = (i < s) ? (IDX ? (uint32_t)idxb[o + i] : 0u) : 0xFFFFFFFFu;
+      }
+      reg_network<NET, Key, IDX>(v, ix);
+#pragma unroll
+      for (uint32_t i = 0; i < NET; ++i) {
+        if (i < s) {
+          keys[o + i] = v[i];
+          if constexpr (IDX) idxb[o + i] = (uint16_t)ix[i];
+        }
+      }
+    } else {
+      const uint32_t slot = atomicAdd(&s_nbig, 1u);
+      if (slot < 64) s_big[slot] = b;
+      else s_fallback = 1;
+    }
+  }
+  __syncthreads();
+  const uint32_t nbig = s_nbig < 64 ? s_nbig : 64;
+  if (!s_fallback) {
+    for (uint32_t q = wave; q < nbig; q += NT / 64) {
+      const uint32_t b = s_big[q], s = s_cnt[b], o = s_off[b];
+      bool same = true;
+      for (uint32_t i = lane; i < s; i += 64) same = same && keq(keys[o + i], keys[o]);
+      if (__all(same)) continue;
+      if (s > WAVE_MAX) {
+        if (lane == 0) s_fallback = 1;
+        continue;
+      }
+      wave_network<Key, IDX>(keys + o, idxb + o, s);
+    }
+  }
+  __syncthreads();
+  if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
+  __syncthreads();
+
+  // 5. Store.
+  if constexpr (IDX) {
+    for (uint32_t x = tid; x < n * DW; x += NT) {
+      const uint32_t i = x / DW, d = x - i * DW;
+      gd[x] = stage[(uint32_t)idxb[i] * DW + d];
+    }
+  } else {
+    for (uint32_t i = tid; i < n; i += NT) {
+      uint32_t w[DW];
+      T::from_key(keys[i], w);
+      st_elem<DW>(gd + (uint64_t)i * DW, w);
+    }
+  }
+}
+
+}  // namespace ips

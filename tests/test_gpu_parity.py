@@ -27,8 +27,8 @@ def sorter():
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_lds_tier(sorter, kind):
-    cap = {"u32": 16384, "u64": 8192, "f64": 8192, "pair": 4096, "rec100": 1024}[kind]
-    for n in (2, 3, 17, 1000, cap - 1, cap):
+    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}[kind]
+    for n in sorted({2, 3, 17, 33, 1000, cap // 2, cap // 2 + 1, cap - 1, cap}):
         a = generate(kind, "uniform", n, 100 + n)
         log(f"lds {kind} n={n}")
         assert_parity(gpu_sort(sorter, a, kind), a, kind)
@@ -189,3 +189,48 @@ def test_extreme_keys(sorter):
     r[1::3, 0] = 0x80
     log("extreme rec100")
     assert_parity(gpu_sort(sorter, r, "rec100"), r, "rec100")
+
+
+def _pattern_u64(name, n, rng):
+    u = rng.integers(0, 2**63, n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, n, dtype=np.uint64)
+    if name == "clustered":          # one bin far above the wavefront limit
+        m = int(n * 0.8)
+        u[:m] = rng.integers(0, 100, m, dtype=np.uint64)
+    elif name == "mid_cluster":      # one bin of a few hundred keys
+        u[:300] = np.uint64(1 << 62) + rng.integers(0, 1000, 300, dtype=np.uint64)
+    elif name == "three_values":
+        u = rng.integers(0, 3, n, dtype=np.uint64) * np.uint64(1 << 40)
+    elif name == "all_equal":
+        u[:] = np.uint64(12345)
+    rng.shuffle(u)
+    return u
+
+
+def _as_kind(u, kind):
+    n = u.size
+    if kind == "u64":
+        return u
+    if kind == "u32":
+        return (u >> np.uint64(32)).astype(np.uint32)
+    if kind == "f64":
+        return (u >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    if kind == "pair":
+        return np.stack([u, np.arange(n, dtype=np.uint64)], axis=1)
+    r = synth.gen_rec100("uniform", n, 5)
+    r[:, 0:2] = 0
+    r[:, 2:10] = u.astype(">u8").view(np.uint8).reshape(n, 8)
+    return r
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_lds_tier_fallbacks(sorter, kind):
+    """Bins above the register-network size, above the wavefront limit, few
+    distinct keys and all-equal keys inside single LDS-tier tasks."""
+    rng = np.random.default_rng(21)
+    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}[kind]
+    for name in ("clustered", "mid_cluster", "three_values", "all_equal"):
+        for n in sorted({cap // 2 + 7, cap}):
+            a = _as_kind(_pattern_u64(name, n, rng), kind)
+            log(f"lds fallback {kind} {name} n={n}")
+            p = ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)
+            assert_parity(gpu_sort(sorter, a, kind, params=p), a, kind)
