@@ -97,6 +97,8 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *  piece_blocks maximum blocks per pointer piece of the block permutation
  *               (default 256)
  *  seed         seed of the sampling stream (default 0)
+ *  perm_groups  target number of block-permutation groups (swap buffers) per
+ *               batch (default 32768)
  */
 typedef struct {
   uint32_t k;
@@ -106,7 +108,8 @@ typedef struct {
   uint32_t piece_blocks;
   uint32_t flags;
   uint64_t seed;
-  uint32_t reserved[4];
+  uint32_t perm_groups;
+  uint32_t reserved[3];
 } ips_params;
 
 typedef struct ips_ctx ips_ctx;

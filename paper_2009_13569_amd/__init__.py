@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32),
                 ("lds_task_max", ctypes.c_uint32), ("piece_blocks", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("perm_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class RootInfo(ctypes.Structure):
@@ -103,10 +103,11 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0) -> Params:
+def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0,
+                perm_groups=0) -> Params:
     p = Params()
     p.k, p.block_bytes, p.n0, p.lds_task_max, p.piece_blocks = k, block_bytes, n0, lds_task_max, piece_blocks
-    p.flags, p.seed = flags, seed
+    p.flags, p.seed, p.perm_groups = flags, seed, perm_groups
     return p
 
 

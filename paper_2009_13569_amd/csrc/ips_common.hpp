@@ -106,6 +106,7 @@ struct BatchArgs {
   uint32_t* b_ple;
   uint64_t* b_min;            // radix: min/max key of bucket j
   uint64_t* b_max;
+  uint64_t* b_full;           // bit i: placement piece plb + i of bucket j is full
   uint64_t* p_word;           // pieces: packed (w << 32) | (r + PTR_BIAS)
   uint32_t* p_a;              // first block of the piece
   uint32_t* p_c;              // end block (exclusive) of the piece

@@ -24,10 +24,10 @@ using namespace ips;
 
 namespace {
 
-constexpr uint32_t WG_TARGET = 512;       // classification workgroups per level
-constexpr uint32_t GRP_TARGET = 32768;    // permutation groups per batch
+constexpr uint32_t WG_TARGET = 1024;      // classification workgroups per level (4 per CU)
+constexpr uint32_t GRP_TARGET = 32768;    // default permutation groups per batch
 constexpr uint32_t TB_MAX = 512;          // tasks per batch
-constexpr uint32_t WB_MAX = 1024;         // classification workgroups per batch
+constexpr uint32_t WB_MAX = 2048;         // classification workgroups per batch
 
 struct Cfg {
   const Launchers* L;
@@ -37,6 +37,7 @@ struct Cfg {
   uint32_t k, n0, cap, cmax, flags;
   uint64_t seed;
   uint32_t b_req;   // requested block elements (0 = automatic)
+  uint32_t groups;  // permutation groups per batch
 };
 
 uint32_t elem_bytes(int t) {
@@ -95,6 +96,8 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   c->cap = p->lds_task_max ? p->lds_task_max : dcap;
   if (c->cap > dcap) return IPS_E_INVALID_ARG;
   c->cmax = p->piece_blocks ? p->piece_blocks : 256;
+  c->groups = p->perm_groups ? p->perm_groups : GRP_TARGET;
+  if (c->groups > (1u << 20)) return IPS_E_INVALID_ARG;
   c->seed = p->seed;
   c->b_req = 0;
   if (p->block_bytes) {
@@ -133,7 +136,7 @@ struct Layout {
 enum Region {
   R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
   R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
-  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_COUNT
+  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_COUNT
 };
 
 void plan(uint64_t n, const Cfg& c, Layout* L) {
@@ -151,11 +154,11 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   // Budgets scale with the data: a batch holds as many tasks as fit, and any
   // single task fits (its slots need at most max(slot, n D / 2 + W * 256)).
   const uint64_t data_budget = n * c.D / 4 + 4 * slot_max + (uint64_t)WG_TARGET * 256;
-  L->SB = std::min<uint64_t>((uint64_t)WG_TARGET * slot_max, data_budget);
+  L->SB = std::min<uint64_t>((uint64_t)(WG_TARGET + L->TB) * slot_max, data_budget);
   L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, std::max<uint64_t>(slot_max, data_budget));
   L->FB = n / bmin + L->TB + 1;
   L->PB = (uint64_t)L->TB * (2 * nbm + 2) + L->WB + L->FB / c.cmax + 16;
-  L->PWB = GRP_TARGET / 4 + 2 * L->TB + 16;
+  L->PWB = c.groups / 4 + 2 * L->TB + 16;
   L->NBE = L->TB * (uint32_t)(nbm + 1);
   L->LTB = L->TB * (uint32_t)nbm + 1;
   size_t sz[R_COUNT];
@@ -189,6 +192,7 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_TNP] = (size_t)L->TB * 4;
   sz[R_TUP] = (size_t)L->TB * 4;
   sz[R_LT] = (size_t)L->LTB * sizeof(LTask);
+  sz[R_BFULL] = (size_t)L->NBE * 8;
   size_t off = 0;
   for (int r = 0; r < R_COUNT; ++r) {
     L->off[r] = off;
@@ -367,7 +371,8 @@ struct Need {
 
 Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
   Need nd;
-  const uint64_t wub = std::max<uint64_t>(1, (uint64_t)WG_TARGET * t.n / std::max<uint64_t>(1, level_elems));
+  const uint64_t S = std::max<uint64_t>(1, level_elems / WG_TARGET);
+  const uint64_t wub = (t.n + S - 1) / S;
   nd.wg = std::min<uint64_t>(std::min<uint64_t>(wub, WG_TARGET), r.L.WB);
   nd.slot = std::min<uint64_t>(nd.wg * r.L.slot_max,
                                std::max<uint64_t>(r.L.slot_max, t.n * r.c.D / 4 + nd.wg * 256));
@@ -437,6 +442,8 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   uint32_t* h_perm = h_cls + r.L.WB;
   uint32_t* h_cln = h_perm + r.L.PWB;
   size_t max_dyn = 0;
+  uint32_t max_nb_batch = 1;
+  for (uint32_t t = 0; t < T; ++t) max_nb_batch = std::max(max_nb_batch, nbv[t]);
   for (uint32_t t = 0; t < T; ++t) {
     PTask& p = r.h_tasks[t];
     const uint32_t b = bvec[t], nb = nbv[t], NB = NBv[t];
@@ -446,7 +453,11 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.eq = hdr[t].eq;
     p.b = b;
     p.NB = NB;
-    uint64_t W = std::max<uint64_t>(1, (uint64_t)WG_TARGET * p.n / std::max<uint64_t>(1, level_elems));
+    // Stripes of at most level_elems / WG_TARGET elements (so that the
+    // largest stripe, which bounds the phase, is no larger than the mean),
+    // but at least four buffer capacities long.
+    const uint64_t S = std::max<uint64_t>(1, level_elems / WG_TARGET);
+    uint64_t W = (p.n + S - 1) / S;
     W = std::min<uint64_t>(W, std::max<uint64_t>(1, p.n / (4ull * nb * b)));
     W = std::min<uint64_t>(W, NB);
     W = std::min<uint64_t>(W, WG_TARGET);
@@ -464,15 +475,15 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.flag_off = flag_off;
     flag_off += NB;
     p.piece_base = piece;
-    p.piece_cap = 2 * nb + 2 + p.W + NB / c.cmax + 1;
+    p.piece_cap = 2 * nb + 2 + p.W + NB / c.cmax + 1;   // chunks are never smaller than cmax
     piece += p.piece_cap;
     p.bucket_base = bucket;
     bucket += nb + 1;
     const uint32_t bdw = b * c.DW;
     uint32_t gl = 4;
-    while (gl * 8 < bdw) gl *= 2;
+    while (gl * 8 < bdw) gl *= 2;   // each lane holds up to 8 dwords of the block
     p.glanes = gl;
-    uint64_t ng = std::max<uint64_t>(1, std::min<uint64_t>(NB / 4, (uint64_t)GRP_TARGET * NB / std::max<uint64_t>(1, blocks_sum)));
+    uint64_t ng = std::max<uint64_t>(1, std::min<uint64_t>(NB / 4, (uint64_t)c.groups * NB / std::max<uint64_t>(1, blocks_sum)));
     p.ngrp = (uint32_t)ng;
     const uint32_t gpw = PERM_THREADS / gl;
     const uint32_t nwg = (uint32_t)((ng + gpw - 1) / gpw);
@@ -498,7 +509,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, bel,
                     [&] { return c.L->classify(r.a, wg, (uint32_t)max_dyn, c.gbuf, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, bel,
-                    [&] { return launch_boundaries(r.a, T, c.cmax, r.st); }));
+                    [&] { return launch_boundaries(r.a, T, max_nb_batch, c.cmax, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, bel,
                     [&] { return launch_fill32(r.a.flags, flag_off, 0u, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, bel, [&] { return c.L->permute(r.a, pwg, r.st); }));
@@ -668,6 +679,7 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   a.b_ple = wsp<uint32_t>(r, R_BPLE);
   a.b_min = wsp<uint64_t>(r, R_BMIN);
   a.b_max = wsp<uint64_t>(r, R_BMAX);
+  a.b_full = wsp<uint64_t>(r, R_BFULL);
   a.p_word = wsp<uint64_t>(r, R_PWORD);
   a.p_a = wsp<uint32_t>(r, R_PA);
   a.p_c = wsp<uint32_t>(r, R_PC);

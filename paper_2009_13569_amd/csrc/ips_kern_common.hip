@@ -5,8 +5,13 @@
 
 namespace ips {
 
-hipError_t launch_boundaries(const BatchArgs& a, uint32_t nt, uint32_t cmax, hipStream_t st) {
+hipError_t launch_boundaries(const BatchArgs& a, uint32_t nt, uint32_t max_nb, uint32_t cmax,
+                             hipStream_t st) {
   if (!nt) return hipSuccess;
+  const uint32_t gpt = (max_nb + 7) / 8;
+  hipLaunchKernelGGL(k_bucket_sums, dim3(nt * gpt), dim3(512), 0, st, a, gpt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_boundaries, dim3(nt), dim3(512), 0, st, a, cmax);
   return hipGetLastError();
 }

@@ -113,6 +113,20 @@ __device__ __forceinline__ void st_elem(uint32_t* p, const uint32_t (&w)[DW]) {
   }
 }
 
+// Division by the block size: a shift when it is a power of two (the
+// branch is uniform across the workgroup).
+// Placement pieces per bucket aimed for: few enough that a 64-bit mask
+// can record which of them are full, enough to spread pointer contention.
+constexpr uint32_t MAX_PLACE_PIECES = 32;
+
+struct BlockDiv {
+  uint32_t b, sh;
+  bool pow2;
+  __device__ __forceinline__ explicit BlockDiv(uint32_t bb)
+      : b(bb), sh((uint32_t)__builtin_ctz(bb)), pow2((bb & (bb - 1)) == 0) {}
+  __device__ __forceinline__ uint32_t div(uint32_t x) const { return pow2 ? (x >> sh) : (x / b); }
+};
+
 template <class T>
 __device__ __forceinline__ typename T::Key key_of(const uint32_t (&w)[T::DW]) {
   constexpr int D = T::DW;
@@ -271,6 +285,7 @@ k_classify(BatchArgs a) {
   const PTask& tk = a.tasks[tix];
   const uint64_t tn = tk.n;
   const uint32_t b = tk.b, nb = tk.nb, NB = tk.NB, W = tk.W;
+  const BlockDiv bd(b);
   const uint32_t s = wg - tk.wg_base;
   const bool radix = (tk.tflags & TF_RADIX) != 0;
   const uint32_t logK = tk.logK, eq = tk.eq, shift = tk.shift;
@@ -329,7 +344,7 @@ k_classify(BatchArgs a) {
     __syncthreads();
     for (uint32_t j = tid; j < nb; j += NT) {
       const uint32_t fo = s_nfull[j];
-      const uint32_t nf = s_cnt[j] / b;
+      const uint32_t nf = bd.div(s_cnt[j]);
       s_oldf[j] = fo;
       if (nf > fo) {
         const uint32_t p = atomicAdd(&s_wpos, nf - fo);
@@ -344,7 +359,7 @@ k_classify(BatchArgs a) {
       const uint64_t idx = ts + (uint64_t)i * NT + tid;
       if (idx < ehi) {
         const uint32_t j = bk[i];
-        const uint32_t blk = sl[i] / b, o = sl[i] - blk * b;
+        const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == s_oldf[j]) {
           st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
         } else if (blk < s_nfull[j]) {
@@ -378,7 +393,7 @@ k_classify(BatchArgs a) {
       const uint64_t idx = ts + (uint64_t)i * NT + tid;
       if (idx < ehi) {
         const uint32_t j = bk[i];
-        const uint32_t blk = sl[i] / b, o = sl[i] - blk * b;
+        const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == s_nfull[j] && blk > s_oldf[j])
           st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
       }
@@ -445,92 +460,134 @@ __device__ void for_each_piece(uint32_t d, uint32_t dend, uint32_t e, uint32_t c
 }
 
 #ifdef IPS_COMMON_KERNELS
-// Bucket boundaries (Section 4.1): per-bucket totals over the stripes, the
-// exclusive prefix sum, delimiters rounded up to blocks, and the pieces with
-// their packed (write, read) pointers.
+// Bucket totals over the stripes: one wavefront per bucket, lanes over the
+// stripes.  Sizes go to b_start (turned into starts by k_boundaries),
+// full-block counts to b_count, radix key ranges to b_min / b_max.
+__global__ void __launch_bounds__(512) k_bucket_sums(BatchArgs a, uint32_t groups_per_task) {
+  const uint32_t tix = blockIdx.x / groups_per_task;
+  const PTask& tk = a.tasks[tix];
+  const uint32_t j = (blockIdx.x % groups_per_task) * 8 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (j >= tk.nb) return;
+  const uint32_t W = tk.W, wg0 = tk.wg_base, bb = tk.bucket_base;
+  const bool radix = (tk.tflags & TF_RADIX) != 0;
+  uint64_t full = 0, left = 0, mn = ~0ull, mx = 0;
+  for (uint32_t s = lane; s < W; s += 64) {
+    const uint64_t o = (uint64_t)(wg0 + s) * MAX_NB + j;
+    full += a.wg_nfull[o];
+    left += a.wg_left[o];
+    if (radix) {
+      const uint64_t om = (uint64_t)(wg0 + s) * MAX_K + j;
+      const uint64_t x = a.wg_min[om], y = a.wg_max[om];
+      mn = x < mn ? x : mn;
+      mx = y > mx ? y : mx;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    full += (uint64_t)__shfl_xor((long long)full, o, 64);
+    left += (uint64_t)__shfl_xor((long long)left, o, 64);
+    if (radix) {
+      const uint64_t x = (uint64_t)__shfl_xor((long long)mn, o, 64);
+      const uint64_t y = (uint64_t)__shfl_xor((long long)mx, o, 64);
+      mn = x < mn ? x : mn;
+      mx = y > mx ? y : mx;
+    }
+  }
+  if (lane == 0) {
+    a.b_start[bb + j] = full * tk.b + left;
+    a.b_count[bb + j] = (uint32_t)full;
+    if (radix) { a.b_min[bb + j] = mn; a.b_max[bb + j] = mx; }
+  }
+}
+
+// Bucket boundaries (Section 4.1): exclusive prefix sum of the bucket
+// sizes, delimiters rounded up to blocks, and the pieces with their packed
+// (write, read) pointers.
 __global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) {
   constexpr uint32_t NT = 512;
-  __shared__ uint64_t s_size[MAX_NB];
   __shared__ uint64_t s_start[MAX_NB + 1];
   __shared__ uint32_t s_cntb[MAX_NB];
   __shared__ uint32_t s_np[MAX_NB + 1], s_up[MAX_NB + 1];
-  const uint32_t tid = threadIdx.x;
+  __shared__ uint64_t s_wsum[NT / 64];
+  __shared__ uint32_t s_w32[2][NT / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tix = blockIdx.x;
   const PTask& tk = a.tasks[tix];
   const uint32_t nb = tk.nb, b = tk.b, NB = tk.NB, W = tk.W, wg0 = tk.wg_base;
   const uint32_t bb = tk.bucket_base;
-  const bool radix = (tk.tflags & TF_RADIX) != 0;
   const uint32_t* stripeF = a.wg_F + wg0;
-  for (uint32_t j = tid; j < nb; j += NT) {
-    uint64_t full = 0, left = 0;
-    uint64_t mn = ~0ull, mx = 0;
-    for (uint32_t s = 0; s < W; ++s) {
-      const uint64_t o = (uint64_t)(wg0 + s) * MAX_NB + j;
-      full += a.wg_nfull[o];
-      left += a.wg_left[o];
-      if (radix) {
-        const uint64_t om = (uint64_t)(wg0 + s) * MAX_K + j;
-        const uint64_t x = a.wg_min[om], y = a.wg_max[om];
-        mn = x < mn ? x : mn;
-        mx = y > mx ? y : mx;
-      }
-    }
-    s_cntb[j] = (uint32_t)full;
-    s_size[j] = full * b + left;
-    if (radix) { a.b_min[bb + j] = mn; a.b_max[bb + j] = mx; }
+  // sizes -> exclusive prefix (nb <= 512 = one bucket per thread)
+  uint64_t sz = tid < nb ? a.b_start[bb + tid] : 0;
+  if (tid < nb) s_cntb[tid] = a.b_count[bb + tid];
+  uint64_t inc = sz;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = (uint64_t)__shfl_up((long long)inc, o, 64);
+    if ((int)lane >= o) inc += y;
   }
+  if (lane == 63) s_wsum[wave] = inc;
   __syncthreads();
-  if (tid == 0) {
-    uint64_t acc = 0;
-    for (uint32_t j = 0; j < nb; ++j) { s_start[j] = acc; acc += s_size[j]; }
-    s_start[nb] = acc;
+  uint64_t base = 0, total = 0;
+  for (uint32_t w = 0; w < NT / 64; ++w) {
+    if (w < wave) base += s_wsum[w];
+    total += s_wsum[w];
   }
+  if (tid < nb) s_start[tid] = base + inc - sz;
+  if (tid == 0) s_start[nb] = total;
   __syncthreads();
-  for (uint32_t j = tid; j < nb; j += NT) {
-    const uint64_t st = s_start[j];
+  // pieces per bucket, then their prefix sums
+  uint32_t np = 0, up = 0;
+  if (tid < nb) {
+    const uint64_t st = s_start[tid];
     const uint32_t d = (uint32_t)((st + b - 1) / b);
-    const uint32_t dend = (j + 1 < nb) ? (uint32_t)((s_start[j + 1] + b - 1) / b) : NB;
-    const uint32_t e = d + s_cntb[j];
-    uint32_t np = 0, up = 0;
-    for_each_piece(d, dend, e, cmax, W, NB, stripeF,
+    const uint32_t dend = (tid + 1 < nb) ? (uint32_t)((s_start[tid + 1] + b - 1) / b) : NB;
+    const uint32_t e = d + s_cntb[tid];
+    const uint32_t cm = max(cmax, (s_cntb[tid] + MAX_PLACE_PIECES - 1) / MAX_PLACE_PIECES);
+    for_each_piece(d, dend, e, cm, W, NB, stripeF,
                    [&](uint32_t c0, uint32_t, int32_t ri, bool) {
                      ++np;
                      up += (uint32_t)(ri - (int32_t)c0 + 1);
                    });
-    s_np[j] = np;
-    s_up[j] = up;
-    a.b_start[bb + j] = st;
-    a.b_count[bb + j] = s_cntb[j];
-    a.b_d[bb + j] = d;
+    a.b_start[bb + tid] = st;
+    a.b_d[bb + tid] = d;
   }
+  uint32_t ip = np, iu = up;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y0 = (uint32_t)__shfl_up((int)ip, o, 64);
+    const uint32_t y1 = (uint32_t)__shfl_up((int)iu, o, 64);
+    if ((int)lane >= o) { ip += y0; iu += y1; }
+  }
+  if (lane == 63) { s_w32[0][wave] = ip; s_w32[1][wave] = iu; }
   __syncthreads();
+  uint32_t bp = 0, bu = 0, tp = 0, tu = 0;
+  for (uint32_t w = 0; w < NT / 64; ++w) {
+    if (w < wave) { bp += s_w32[0][w]; bu += s_w32[1][w]; }
+    tp += s_w32[0][w];
+    tu += s_w32[1][w];
+  }
+  if (tid < nb) { s_np[tid] = bp + ip - np; s_up[tid] = bu + iu - up; }
   if (tid == 0) {
-    uint32_t accp = 0, accu = 0;
-    for (uint32_t j = 0; j < nb; ++j) {
-      const uint32_t x = s_np[j], y = s_up[j];
-      s_np[j] = accp; s_up[j] = accu;
-      accp += x; accu += y;
-    }
-    s_np[nb] = accp;
-    s_up[nb] = accu;
-    a.b_start[bb + nb] = s_start[nb];
-    a.t_npieces[tix] = accp;
-    a.t_unproc[tix] = accu;
-    if (accp > tk.piece_cap) dev_error(a.ctrl, DE_PIECES, tix, accp);
-    if (s_start[nb] != tk.n) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, 0xFFFFFFFFu);
+    s_np[nb] = tp;
+    s_up[nb] = tu;
+    a.b_start[bb + nb] = total;
+    a.t_npieces[tix] = tp;
+    a.t_unproc[tix] = tu;
+    if (tp > tk.piece_cap) dev_error(a.ctrl, DE_PIECES, tix, tp);
+    if (total != tk.n) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, 0xFFFFFFFFu);
   }
   __syncthreads();
   if (s_np[nb] > tk.piece_cap) return;
   const uint32_t pb = tk.piece_base;
-  for (uint32_t j = tid; j < nb; j += NT) {
+  if (tid < nb) {
+    const uint32_t j = tid;
     const uint64_t st = s_start[j];
     const uint32_t d = (uint32_t)((st + b - 1) / b);
     const uint32_t dend = (j + 1 < nb) ? (uint32_t)((s_start[j + 1] + b - 1) / b) : NB;
     const uint32_t e = d + s_cntb[j];
+    const uint32_t cm = max(cmax, (s_cntb[j] + MAX_PLACE_PIECES - 1) / MAX_PLACE_PIECES);
     uint32_t p = pb + s_np[j];
     uint32_t cu = s_up[j];
     uint32_t plb = p, ple = p;
-    for_each_piece(d, dend, e, cmax, W, NB, stripeF,
+    for_each_piece(d, dend, e, cm, W, NB, stripeF,
                    [&](uint32_t c0, uint32_t c1, int32_t ri, bool place) {
                      a.p_a[p] = c0;
                      a.p_c[p] = place ? c1 : c0;
@@ -543,6 +600,7 @@ __global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) 
                    });
     a.b_plb[bb + j] = plb;
     a.b_ple[bb + j] = ple;
+    a.b_full[bb + j] = 0;
   }
 }
 
@@ -554,8 +612,10 @@ __device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t lane) {
   return (uint32_t)__shfl((int)v, (int)lane, 64);
 }
 
+constexpr int PERM_RD = 8;    // dwords of the held block per lane
+
 template <class T>
-__device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[8], uint32_t lbase,
+__device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[PERM_RD], uint32_t lbase,
                                                  const typename T::Key* tree,
                                                  const typename T::Key* spl, uint32_t logK,
                                                  uint32_t eq, bool radix, uint32_t shift,
@@ -568,9 +628,9 @@ __device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[8], uint3
 
 // Waits until every load into `v` has returned (an opaque use of each
 // register), so that a later store or flag cannot overtake them.
-__device__ __forceinline__ void wait_regs(const uint32_t (&v)[8]) {
+__device__ __forceinline__ void wait_regs(const uint32_t (&v)[PERM_RD]) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) asm volatile("" ::"v"(v[r]) : "memory");
+  for (int r = 0; r < PERM_RD; ++r) asm volatile("" ::"v"(v[r]) : "memory");
 }
 
 // Block permutation (Section 4.1).  A group of `glanes` lanes plays the
@@ -584,13 +644,19 @@ __device__ __forceinline__ void wait_regs(const uint32_t (&v)[8]) {
 // already correct), an empty slot is written.  A slot that another group
 // is still reading (w > r but w <= the piece's initial r) is written only
 // after that reader has set the block's flag (the paper's reader guard).
+//
+// Every iteration first issues the pointer operations of all groups of the
+// wavefront together, then all block loads together, so that one iteration
+// costs about one atomic and one load latency whatever mix of states the
+// groups are in.
 template <class T>
 __global__ void __launch_bounds__(PERM_THREADS)
 k_permute(BatchArgs a) {
   using Key = typename T::Key;
-  constexpr int DW = T::DW;
   __shared__ Key s_tree[MAX_K];
   __shared__ Key s_spl[MAX_K];
+  __shared__ uint32_t s_plb[MAX_NB];   // placement pieces of each bucket
+  __shared__ uint32_t s_npl[MAX_NB];
   const uint32_t tix = a.perm_task[blockIdx.x];
   const PTask& tk = a.tasks[tix];
   const bool radix = (tk.tflags & TF_RADIX) != 0;
@@ -603,6 +669,11 @@ k_permute(BatchArgs a) {
       s_spl[i] = T::from_slot(rec->spl[i]);
     }
   }
+  for (uint32_t j = threadIdx.x; j < tk.nb; j += PERM_THREADS) {
+    const uint32_t lo = a.b_plb[tk.bucket_base + j] - tk.piece_base;
+    s_plb[j] = lo;
+    s_npl[j] = a.b_ple[tk.bucket_base + j] - tk.piece_base - lo;
+  }
   __syncthreads();
   const uint32_t GL = tk.glanes;
   const uint32_t lane = threadIdx.x & 63;
@@ -610,8 +681,8 @@ k_permute(BatchArgs a) {
   const uint32_t lbase = lane - gl;
   const uint32_t gid = (blockIdx.x - tk.pwg_base) * (PERM_THREADS / GL) + threadIdx.x / GL;
   const uint32_t b = tk.b, NB = tk.NB;
-  const uint32_t BDW = b * DW;
-  uint32_t* gd = a.data + tk.l * DW;
+  const uint32_t BDW = b * T::DW;
+  uint32_t* gd = a.data + tk.l * T::DW;
   const uint32_t pb = tk.piece_base;
   const uint32_t np = a.t_npieces[tix];
   const uint32_t U = a.t_unproc[tix];
@@ -624,12 +695,19 @@ k_permute(BatchArgs a) {
   const uint32_t bb = tk.bucket_base;
   const bool partial = (tk.n % b) != 0;
   uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
-  if (BDW > 8 * GL) {
+  if (BDW > PERM_RD * GL) {
     if (threadIdx.x == 0) dev_error(a.ctrl, DE_BLOCK, tix, BDW);
     return;
   }
-
+#ifdef IPS_PERM_STATS
+  uint32_t st_claim_ok = 0, st_claim_fail = 0, st_swap = 0, st_skip = 0, st_empty = 0,
+           st_wait = 0, st_full = 0, st_waitit = 0, st_loop = 0;
+#define PSTAT(x) (++(x))
+#else
+#define PSTAT(x) ((void)0)
+#endif
   enum : uint32_t { CLAIM = 0, PLACE = 1, WAIT = 2, DONE = 3 };
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
   uint32_t mode = (gid < tk.ngrp && U > 0) ? CLAIM : DONE;
   uint32_t src = 0, src_end = 0;
   if (mode == CLAIM) {
@@ -653,126 +731,180 @@ k_permute(BatchArgs a) {
       src_end = lo;
     }
   }
-  uint32_t dat[8], tmp[8];
+  uint32_t dat[PERM_RD], tmp[PERM_RD];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) { dat[r] = 0; tmp[r] = 0; }
-  uint32_t dest = 0, probe = 0, wpos = 0, spin = 0;
+  for (int q = 0; q < PERM_RD; ++q) { dat[q] = 0; tmp[q] = 0; }
+  uint32_t dest = 0, probe = 0, wpos = 0, spin = 0, fails = 0;
+  bool use_mask = false;
+
+  auto store_block = [&](uint32_t* dst) {
+#pragma unroll
+    for (int q = 0; q < PERM_RD; ++q) {
+      const uint32_t x = gl + GL * q;
+      if (x < BDW) dst[x] = dat[q];
+    }
+  };
 
   while (true) {
     if (__all(mode == DONE)) break;
-    if (mode == CLAIM) {
-      uint32_t P = 0xFFFFFFFFu;
-      if (gl == 0) {
+    PSTAT(st_loop);
+    // 1. Pointer operations of every group (leader lanes).
+    uint32_t r0 = NONE, r1 = 0, r2 = 0;   // CLAIM: r0 = P; PLACE: r0 = w (NONE: piece full), r1 = r,
+                                          // r2 = the piece's initial r; WAIT: r0 = flag
+    if (gl == 0) {
+      if (mode == CLAIM) {
+        // Decrementing r of an exhausted piece is harmless (r only moves
+        // further below w), so each attempt is one read-modify-write.
         while (src < src_end) {
-          uint64_t wv = at_load64(&word[src]);
-          int32_t w = (int32_t)(wv >> 32), r = (int32_t)((uint32_t)wv - PTR_BIAS);
-          if (r < w) { ++src; continue; }
-          wv = at_add64(&word[src], ~0ull);
-          w = (int32_t)(wv >> 32);
-          r = (int32_t)((uint32_t)wv - PTR_BIAS);
-          if (r >= w) { P = (uint32_t)r; break; }
+          const uint64_t wv = at_add64(&word[src], ~0ull);
+          const int32_t w = (int32_t)(wv >> 32), r = (int32_t)((uint32_t)wv - PTR_BIAS);
+          if (r >= w) { r0 = (uint32_t)r; PSTAT(st_claim_ok); break; }
+          PSTAT(st_claim_fail);
           ++src;
         }
+      } else if (mode == PLACE) {
+        // A random placement piece of the bucket; after a miss the bucket's
+        // mask of full pieces restricts the choice to pieces with room.
+        // The choice avoids pieces known to be full: the bucket's mask is
+        // read through the cache (it only gains bits, so a stale copy only
+        // costs a miss), and coherently after a miss.
+        const uint32_t plb = s_plb[dest], npl = s_npl[dest];
+        uint64_t* fm = a.b_full + bb + dest;
+        uint32_t q = npl ? probe % npl : 0;
+        if (npl <= 64) {
+          const uint64_t m = npl == 64 ? ~0ull : ((1ull << npl) - 1);
+          const uint64_t seen = use_mask ? at_load64(fm) : *reinterpret_cast<volatile uint64_t*>(fm);
+          const uint64_t fr = ~seen & m;
+          if (fr) {
+            uint32_t kth = probe % (uint32_t)__popcll(fr);
+            uint64_t x = fr;
+            for (; kth > 0; --kth) x &= x - 1;
+            q = (uint32_t)__ffsll((long long)x) - 1;
+          }
+        }
+        if (npl) {
+          const uint32_t sr = plb + q;
+          // piece metadata loads are issued before the pointer update so that
+          // their latencies overlap
+          const uint32_t cap = __builtin_nontemporal_load(&pc[sr]);
+          const int32_t rin = __builtin_nontemporal_load(&pr[sr]);
+          const uint64_t wv = at_add64(&word[sr], 1ull << 32);
+          const uint32_t w = (uint32_t)(wv >> 32);
+          r2 = (uint32_t)rin;
+          if (w < cap) {
+            r0 = w;
+            r1 = (uint32_t)((int32_t)((uint32_t)wv - PTR_BIAS));
+            if (w + 1 == cap && q < 64) atomicOr((unsigned long long*)fm, 1ull << q);
+          } else {
+            if (q < 64) atomicOr((unsigned long long*)fm, 1ull << q);
+            PSTAT(st_full);
+          }
+        }
+      } else if (mode == WAIT) {
+        r0 = at_load32(&flags[wpos]);
       }
-      P = shfl32(P, lbase);
-      if (P == 0xFFFFFFFFu) {
+    }
+    r0 = shfl32(r0, lbase);
+    r1 = shfl32(r1, lbase);
+    r2 = shfl32(r2, lbase);
+    // 2. Transitions that need no data, and the block loads.
+    uint32_t ld = NONE;
+    if (mode == CLAIM) {
+      if (r0 == NONE) {
         mode = DONE;
-      } else if (P >= NB || (P == NB - 1 && partial)) {
-        if (gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, P);
+      } else if (r0 >= NB || (r0 == NB - 1 && partial)) {
+        if (gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, r0);
         mode = DONE;
       } else {
-        const uint32_t* sp = gd + (uint64_t)P * BDW;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const uint32_t x = gl + GL * r;
-          if (x < BDW) dat[r] = sp[x];
-        }
-        wait_regs(dat);
-        if (gl == 0) at_store32(&flags[P], 1u);
-        dest = block_bucket<T>(dat, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
-        probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
-        mode = PLACE;
+        ld = r0;
       }
     } else if (mode == PLACE) {
-      uint32_t w = 0, ok = 0, sr = 0;
-      int32_t r = 0;
-      if (gl == 0) {
-        const uint32_t plb = a.b_plb[bb + dest] - pb, ple = a.b_ple[bb + dest] - pb;
-        const uint32_t npl = ple - plb;
-        uint32_t tries = 0;
-        while (npl > 0 && tries < 4 * npl + 64) {
-          sr = plb + (probe % npl);
-          uint64_t wv = at_load64(&word[sr]);
-          if ((uint32_t)(wv >> 32) < pc[sr]) {
-            wv = at_add64(&word[sr], 1ull << 32);
-            w = (uint32_t)(wv >> 32);
-            r = (int32_t)((uint32_t)wv - PTR_BIAS);
-            if (w < pc[sr]) { ok = 1; break; }
-          }
-          ++probe;
-          ++tries;
+      if (r0 == NONE) {
+        use_mask = true;
+        probe = probe * 0x9E3779B1u + 0x7F4A7C15u;
+        if (++fails > 4096) {
+          if (gl == 0) dev_error(a.ctrl, DE_PLACE, tix, dest);
+          mode = DONE;
         }
-        if (!ok) dev_error(a.ctrl, DE_PLACE, tix, dest);
-      }
-      ok = shfl32(ok, lbase);
-      w = shfl32(w, lbase);
-      r = (int32_t)shfl32((uint32_t)r, lbase);
-      sr = shfl32(sr, lbase);
-      if (!ok || w >= NB || ((int32_t)w <= r && w == NB - 1 && partial)) {
-        if (ok && gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, w);
+      } else if (r0 >= NB || ((int32_t)r0 <= (int32_t)r1 && r0 == NB - 1 && partial)) {
+        if (gl == 0) dev_error(a.ctrl, DE_PERM_RANGE, tix, r0);
         mode = DONE;
-      } else if ((int32_t)w <= r) {
-        uint32_t* wp = gd + (uint64_t)w * BDW;
+      } else if ((int32_t)r0 <= (int32_t)r1) {
+        ld = r0;                                   // unprocessed: swap candidate
+      } else if ((int32_t)r0 <= (int32_t)r2) {
+        wpos = r0;                                 // being read by another group
+        spin = 0;
+        mode = WAIT;
+        PSTAT(st_wait);
+      } else {
+        store_block((r0 == NB - 1 && partial) ? ovf : gd + (uint64_t)r0 * BDW);
+        mode = CLAIM;
+        PSTAT(st_empty);
+      }
+    } else if (mode == WAIT) {
+      PSTAT(st_waitit);
+      if (r0) {
+        store_block(gd + (uint64_t)wpos * BDW);
+        mode = CLAIM;
+      } else if (++spin > (1u << 22)) {
+        if (gl == 0) dev_error(a.ctrl, DE_WAIT, tix, wpos);
+        mode = DONE;
+      }
+    }
+    if (ld != NONE) {
+      const uint32_t* sp = gd + (uint64_t)ld * BDW;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t x = gl + GL * q;
-          if (x < BDW) tmp[q] = wp[x];
-        }
-        wait_regs(tmp);
+      for (int q = 0; q < PERM_RD; ++q) {
+        const uint32_t x = gl + GL * q;
+        if (x < BDW) tmp[q] = sp[x];
+      }
+      wait_regs(tmp);
+      if (mode == CLAIM) {
+        if (gl == 0) at_store32(&flags[ld], 1u);
+#pragma unroll
+        for (int q = 0; q < PERM_RD; ++q) dat[q] = tmp[q];
+        dest = block_bucket<T>(dat, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
+        use_mask = false;
+        fails = 0;
+        mode = PLACE;
+      } else {
         const uint32_t d2 = block_bucket<T>(tmp, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
-        if (d2 != dest) {
+        if (d2 == dest) {
+          PSTAT(st_skip);                          // already in its bucket
+        } else {
+          PSTAT(st_swap);
+          uint32_t* wp = gd + (uint64_t)ld * BDW;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < PERM_RD; ++q) {
             const uint32_t x = gl + GL * q;
             if (x < BDW) wp[x] = dat[q];
             dat[q] = tmp[q];
           }
           dest = d2;
           probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
+          use_mask = false;
+          fails = 0;
         }
-      } else if ((int32_t)w <= pr[sr]) {
-        wpos = w;
-        spin = 0;
-        mode = WAIT;
-      } else {
-        uint32_t* wp = (w == NB - 1 && partial) ? ovf : gd + (uint64_t)w * BDW;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t x = gl + GL * q;
-          if (x < BDW) wp[x] = dat[q];
-        }
-        mode = CLAIM;
-      }
-    } else if (mode == WAIT) {
-      uint32_t f = 0;
-      if (gl == 0) f = at_load32(&flags[wpos]);
-      f = shfl32(f, lbase);
-      if (f) {
-        uint32_t* wp = gd + (uint64_t)wpos * BDW;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t x = gl + GL * q;
-          if (x < BDW) wp[x] = dat[q];
-        }
-        mode = CLAIM;
-      } else if (++spin > (1u << 22)) {
-        if (gl == 0) dev_error(a.ctrl, DE_WAIT, tix, wpos);
-        mode = DONE;
-      } else {
-        __builtin_amdgcn_s_sleep(1);
       }
     }
+    if (mode == WAIT) __builtin_amdgcn_s_sleep(1);
   }
+#ifdef IPS_PERM_STATS
+  if (gl == 0) {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + 32);
+    atomicAdd(&c[0], (unsigned long long)st_claim_ok);
+    atomicAdd(&c[1], (unsigned long long)st_claim_fail);
+    atomicAdd(&c[2], (unsigned long long)st_swap);
+    atomicAdd(&c[3], (unsigned long long)st_skip);
+    atomicAdd(&c[4], (unsigned long long)st_empty);
+    atomicAdd(&c[5], (unsigned long long)st_wait);
+    atomicAdd(&c[6], (unsigned long long)st_full);
+    atomicAdd(&c[7], (unsigned long long)st_waitit);
+    if (lane == 0) atomicAdd(&c[8], (unsigned long long)st_loop);
+  }
+#endif
+#undef PSTAT
 }
 
 // ----------------------------------------------------------------- cleanup

@@ -35,7 +35,8 @@ const Launchers* launchers_f64();
 const Launchers* launchers_pair();
 const Launchers* launchers_rec100();
 
-hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t cmax, hipStream_t);
+hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t max_nb, uint32_t cmax,
+                             hipStream_t);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t);
 
 }  // namespace ips
