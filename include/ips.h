@@ -90,7 +90,10 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *               max(1, block_bytes / element size) elements.  Default: the
  *               largest block for which one buffer block per bucket fits the
  *               LDS budget.  Larger requests need IPS_FLAG_GLOBAL_BUFFERS.
- *  n0           base-case size of the adaptive-k rule (default 16, Section 6)
+ *  n0           base-case size of the paper's adaptive-k rule (Section 4.2;
+ *               the paper uses 16).  0 (default): the number of buckets of a
+ *               step is the smallest power of two (at most k) that makes the
+ *               mean bucket at most a quarter of the LDS-tier capacity.
  *  lds_task_max tasks with at most this many elements are sorted inside one
  *               workgroup's LDS (default: per type, 1..16384); 1 forces every
  *               task of two or more elements through a partitioning step

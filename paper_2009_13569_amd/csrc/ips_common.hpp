@@ -70,7 +70,8 @@ struct PTask {
   uint32_t ngrp, pwg_base, glanes;   // permutation groups
   uint32_t bucket_base;              // first entry in the batch bucket tables
   uint32_t shift, width;             // radix digit
-  uint32_t pad0, pad1;
+  uint32_t kp;                       // number of buckets k' asked of the sampling phase
+  uint32_t pad1;
 };
 
 enum TaskFlags : uint32_t { TF_EQ_ON = 1u, TF_EQ_OFF = 2u, TF_RADIX = 4u };

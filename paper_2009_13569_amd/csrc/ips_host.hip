@@ -91,10 +91,10 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   c->gbuf = (p->flags & IPS_FLAG_GLOBAL_BUFFERS) != 0;
   c->k = p->k ? p->k : MAX_K;
   if (c->k < 2 || c->k > MAX_K || (c->k & (c->k - 1))) return IPS_E_INVALID_ARG;
-  c->n0 = p->n0 ? p->n0 : 16;
   const uint32_t dcap = default_cap(type);
   c->cap = p->lds_task_max ? p->lds_task_max : dcap;
   if (c->cap > dcap) return IPS_E_INVALID_ARG;
+  c->n0 = p->n0;   // 0: buckets sized for the LDS tier (see task_kprime)
   c->cmax = p->piece_blocks ? p->piece_blocks : 256;
   c->groups = p->perm_groups ? p->perm_groups : GRP_TARGET;
   if (c->groups > (1u << 20)) return IPS_E_INVALID_ARG;
@@ -110,6 +110,36 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   if (p->flags & ~0x3Fu) return IPS_E_INVALID_ARG;
   c->L = nullptr;
   return IPS_OK;
+}
+
+// Adaptive number of buckets of the paper (Section 4.2): for
+// k n0 < n < k^2 n0 the smallest power of two 2^c with 2c >= log2(n/n0)+1,
+// for n0 < n <= k n0 the smallest 2^c >= n/n0, otherwise k; in [2, k].
+uint32_t paper_kprime(uint64_t n, uint32_t k, uint32_t n0) {
+  const unsigned __int128 kn0 = (unsigned __int128)k * n0, kkn0 = kn0 * k;
+  uint64_t r = k;
+  if ((unsigned __int128)n > kn0 && (unsigned __int128)n < kkn0) {
+    uint32_t c = 1;
+    while (((unsigned __int128)n0 << (2 * c - 1)) < n) ++c;
+    r = 1ull << c;
+  } else if (n > n0 && (unsigned __int128)n <= kn0) {
+    uint32_t c = 0;
+    while (((unsigned __int128)n0 << c) < n) ++c;
+    r = 1ull << c;
+  }
+  return (uint32_t)std::min<uint64_t>(k, std::max<uint64_t>(2, r));
+}
+
+// k' of a task.  With an explicit n0 the paper's rule.  By default the base
+// case is the LDS tier of capacity cap instead of insertion sort on n0
+// elements, so k' is the smallest power of two that makes the mean bucket at
+// most cap / 4 (a bucket then exceeds the tier only with negligible
+// probability), capped at k.
+uint32_t task_kprime(const Cfg& c, uint64_t n) {
+  if (c.n0) return paper_kprime(n, c.k, c.n0);
+  uint64_t r = 2;
+  while (r < c.k && r * (c.cap / 4) < n) r *= 2;
+  return (uint32_t)r;
 }
 
 // Block elements of a step with nb buckets: in LDS mode one buffer block per
@@ -398,6 +428,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.tflags = bt[t].tflags | (c.radix ? TF_RADIX : 0u);
     p.shift = bt[t].shift;
     p.width = bt[t].width;
+    p.kp = task_kprime(c, bt[t].n);
   }
   PTask* d_tasks = wsp<PTask>(r, R_TASKS);
   StepRec* d_recs = wsp<StepRec>(r, R_RECS);
@@ -408,7 +439,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     uint64_t el = 0;
     for (const HTask& t : bt) el += t.n;
     HIPCHK(ctx, timed(ctx, r.st, bt[0].level, IPS_PH_SAMPLE, el,
-                      [&] { return c.L->sample(r.a, T, c.seed, c.k, c.n0, r.st); }));
+                      [&] { return c.L->sample(r.a, T, c.seed, r.st); }));
     HIPCHK(ctx, hipMemcpy2DAsync(r.h_rb, sizeof(Hdr), d_recs, sizeof(StepRec), sizeof(Hdr), T,
                                  hipMemcpyDeviceToHost, r.st));
     HIPCHK(ctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st));

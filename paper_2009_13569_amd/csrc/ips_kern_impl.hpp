@@ -22,10 +22,9 @@ struct LaunchImpl {
   static constexpr uint32_t CAP_SMALL = SH::NS * SH::ES;
   static constexpr uint32_t CAP_BIG = SH::NB * SH::EB;
 
-  static hipError_t sample_(const BatchArgs& a, uint32_t nt, uint64_t seed, uint32_t k, uint32_t n0,
-                            hipStream_t st) {
+  static hipError_t sample_(const BatchArgs& a, uint32_t nt, uint64_t seed, hipStream_t st) {
     if (!nt) return hipSuccess;
-    hipLaunchKernelGGL((k_sample<T>), dim3(nt), dim3(SMP_THREADS), 0, st, a, seed, k, n0);
+    hipLaunchKernelGGL((k_sample<T>), dim3(nt), dim3(SMP_THREADS), 0, st, a, seed);
     return hipGetLastError();
   }
   static hipError_t classify(const BatchArgs& a, uint32_t nwg, uint32_t dyn, bool gbuf, hipStream_t st) {

@@ -61,26 +61,6 @@ __device__ __forceinline__ uint32_t step_alpha(uint64_t n) {
   return a ? a : 1;
 }
 
-// Adaptive number of buckets (Section 4.2): 2^ceil((log2(n/n0)+1)/2) for
-// k n0 < n < k^2 n0, 2^ceil(log2(n/n0)) for n0 < n <= k n0, otherwise k;
-// decided exactly in integers and clamped to [2, k].
-__device__ __forceinline__ uint32_t step_kprime(uint64_t n, uint32_t k, uint32_t n0) {
-  const uint64_t kn0 = (uint64_t)k * n0, kkn0 = kn0 * k;
-  uint64_t r = k;
-  if (n > kn0 && n < kkn0) {
-    uint32_t c = 1;
-    while (((uint64_t)n0 << (2 * c - 1)) < n) ++c;
-    r = 1ull << c;
-  } else if (n > n0 && n <= kn0) {
-    uint32_t c = 0;
-    while (((uint64_t)n0 << c) < n) ++c;
-    r = 1ull << c;
-  }
-  if (r > k) r = k;
-  if (r < 2) r = 2;
-  return (uint32_t)r;
-}
-
 __device__ __forceinline__ uint64_t step_task_seed(uint64_t seed, uint64_t l, uint32_t level) {
   return sm64_mix((seed ^ (l * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)level << 56)) +
                   0x9E3779B97F4A7C15ull);
@@ -177,7 +157,8 @@ __device__ void lds_bitonic_keys(Key* a, uint32_t n2) {
   }
 }
 
-// Sampling phase (Section 4.1) of every task of the batch: alpha k' samples
+// Sampling phase (Section 4.1) of every task of the batch (k' chosen by the
+// host, see ips_host.hip): alpha k' samples
 // drawn with replacement at positions l + floor(n x_j / 2^64), sorted;
 // k'-1 equidistant splitters (the i-th at sorted position (i+1) alpha - 1);
 // duplicates removed; equality buckets iff a duplicate was removed; K the
@@ -185,7 +166,7 @@ __device__ void lds_bitonic_keys(Key* a, uint32_t n2) {
 // in breadth-first order.
 template <class T>
 __global__ void __launch_bounds__(SMP_THREADS)
-k_sample(BatchArgs a, uint64_t seed, uint32_t k, uint32_t n0) {
+k_sample(BatchArgs a, uint64_t seed) {
   using Key = typename T::Key;
   constexpr int DW = T::DW;
   __shared__ Key s_smp[MAX_SAMPLE];
@@ -196,7 +177,7 @@ k_sample(BatchArgs a, uint64_t seed, uint32_t k, uint32_t n0) {
   const uint64_t n = tk.n, l = tk.l;
   StepRec* rec = a.recs + tix;
   const uint32_t alpha = step_alpha(n);
-  const uint32_t kp = step_kprime(n, k, n0);
+  const uint32_t kp = tk.kp;
   const uint32_t m = alpha * kp;
   uint32_t P = 1;
   while (P < m) P <<= 1;
@@ -974,19 +955,35 @@ __global__ void __launch_bounds__(CLN_THREADS) k_cleanup_b(BatchArgs a, uint32_t
   const uint64_t hlen = hend - g.start;
   const uint64_t tlen = (g.F < g.end) ? g.end - g.F : 0;
   const uint64_t sp = (g.count > 0 && !g.ovf && g.F > g.end) ? g.F - g.end : 0;
-  if (threadIdx.x == 0) {
-    uint64_t acc = 0;
-    s_off[0] = 0;
-    acc += sp;
-    s_off[1] = acc;
-    acc += g.ovf ? b : 0;
-    s_off[2] = acc;
-    for (uint32_t s = 0; s < W; ++s) {
-      acc += a.wg_left[(uint64_t)(tk.wg_base + s) * MAX_NB + j];
-      s_off[3 + s] = acc;
+  {
+    // s_off[0..2]: spill and overflow; s_off[3 + s]: end of stripe s's
+    // leftovers (block-wide scan over the stripes)
+    __shared__ uint64_t s_ws[CLN_THREADS / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t per = (W + CLN_THREADS - 1) / CLN_THREADS;
+    const uint32_t s0 = tid * per;
+    uint64_t loc = 0;
+    for (uint32_t i = 0; i < per; ++i)
+      if (s0 + i < W) loc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * MAX_NB + j];
+    uint64_t inc = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = (uint64_t)__shfl_up((long long)inc, o, 64);
+      if ((int)lane >= o) inc += y;
     }
+    if (lane == 63) s_ws[wave] = inc;
+    __syncthreads();
+    const uint64_t head = sp + (g.ovf ? b : 0);
+    uint64_t acc = head + inc - loc;
+    for (uint32_t w = 0; w < wave; ++w) acc += s_ws[w];
+    for (uint32_t i = 0; i < per; ++i) {
+      if (s0 + i < W) {
+        acc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * MAX_NB + j];
+        s_off[3 + s0 + i] = acc;
+      }
+    }
+    if (tid == 0) { s_off[0] = 0; s_off[1] = sp; s_off[2] = head; }
+    __syncthreads();
   }
-  __syncthreads();
   const uint64_t total = s_off[2 + W];
   if (total != hlen + tlen) {
     if (threadIdx.x == 0) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, j);

@@ -15,8 +15,7 @@ struct Launchers {
   bool keys_only, radix_ok;
   uint32_t lds_cap;       // LDS-tier capacity (elements)
   uint32_t lds_cap_small; // tasks up to this size use the smaller, faster variant
-  hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, uint32_t k, uint32_t n0,
-                       hipStream_t);
+  hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, hipStream_t);
   hipError_t (*classify)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, bool gbuf, hipStream_t);
   hipError_t (*permute)(const BatchArgs&, uint32_t nwg, hipStream_t);
   hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);

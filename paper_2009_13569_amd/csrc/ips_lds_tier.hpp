@@ -185,8 +185,9 @@ struct LdsTier {
   }
 };
 
+// Two 512-thread workgroups per CU: at most 128 VGPRs (4 waves per SIMD).
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, (NT <= 512 ? 4 : 1))
 k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   using LT = LdsTier<T, NT, E, NET>;
   using Key = typename T::Key;

@@ -80,19 +80,32 @@ def _level1(sorter, a, kind, params, algo="samplesort"):
     return out, ri
 
 
-@pytest.mark.parametrize("kind,n,gbuf", [("u64", 1 << 20, True), ("u64", 1 << 20, False),
-                                         ("u32", 300_001, False), ("f64", 200_003, False),
-                                         ("pair", 100_003, False), ("rec100", 30_011, False)])
-def test_level1_exact(sorter, kind, n, gbuf):
+LDS_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}
+
+
+@pytest.mark.parametrize("kind,n,gbuf,n0", [("u64", 1 << 20, True, 16), ("u64", 1 << 20, False, 16),
+                                            ("u32", 300_001, False, 16), ("f64", 200_003, False, 16),
+                                            ("pair", 100_003, False, 16), ("rec100", 30_011, False, 16),
+                                            ("u64", 300_001, False, 0), ("rec100", 30_011, False, 0)])
+def test_level1_exact(sorter, kind, n, gbuf, n0):
     """The root step's sample, splitters, equality-bucket flag and bucket
-    boundaries equal the oracle's, and every element lies in its bucket."""
+    boundaries equal the oracle's, and every element lies in its bucket.
+    n0 = 0 checks the default base-case size (a quarter of the LDS tier)."""
     for dist in ("uniform", "rootdup"):
         a = generate(kind, dist, n, 3)
         flags = ips.FLAG_LEVEL1_ONLY | (ips.FLAG_GLOBAL_BUFFERS if gbuf else 0)
-        p = ips.make_params(block_bytes=2048 if gbuf else 0, flags=flags, seed=12345)
-        log(f"level1 {kind} {dist} n={n} gbuf={gbuf}")
+        p = ips.make_params(block_bytes=2048 if gbuf else 0, flags=flags, seed=12345, n0=n0)
+        log(f"level1 {kind} {dist} n={n} gbuf={gbuf} n0={n0}")
         out, ri = _level1(sorter, a, kind, p)
-        st = oracle.sample_step(a, kind, seed=12345)
+        if n0:
+            st = oracle.sample_step(a, kind, seed=12345, n0=n0)
+        else:
+            # default k': smallest power of two (<= 256) with mean bucket <= cap/4
+            kp = 2
+            while kp < 256 and kp * (LDS_CAP[kind] // 4) < n:
+                kp *= 2
+            assert ri.k_prime == kp
+            st = oracle.sample_step(a, kind, seed=12345, k=kp, n0=1)
         assert (ri.alpha, ri.k_prime, ri.m, ri.u, ri.K, bool(ri.eq), ri.nb) == \
             (st["alpha"], st["k_prime"], st["m"], st["u"], st["K"], st["eq"], st["nb"])
         spl = st["splitters"]
