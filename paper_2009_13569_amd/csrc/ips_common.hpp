@@ -12,7 +12,8 @@ namespace ips {
 constexpr uint32_t MAX_K = 256;
 constexpr uint32_t MAX_NB = 512;
 constexpr uint32_t MAX_BLOCK_BYTES = 2048;   // 64 lanes x 8 dwords
-constexpr uint32_t BUF_LDS_BYTES = 128u * 1024u;   // buffer blocks in LDS
+constexpr uint32_t BUF_LDS_BYTES = 128u * 1024u;   // buffer blocks in LDS (before padding)
+constexpr uint32_t BUF_PAD_DW = 2;                 // padding dwords per LDS buffer block
 constexpr uint32_t CLS_THREADS = 1024;
 constexpr uint32_t PERM_THREADS = 256;
 constexpr uint32_t SMP_THREADS = 1024;
@@ -49,11 +50,14 @@ enum DevErr : uint32_t {
 
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
 // radix step.  Keys live in 16-byte slots so that every key type fits.
+constexpr uint32_t START_BITS = 10;   // start-node table: 2^10 entries
 struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;
-  uint32_t shift, width, radix, pad;
+  uint32_t shift, width, radix, tshift;
+  uint64_t tbase;            // start-node table: key image of s_0 and shift
   uint64_t tree[MAX_K][2];   // tree[1..K-1], breadth-first order
   uint64_t spl[MAX_K][2];    // sorted splitters s_0..s_{K-1}, s_{K-1} = s_{K-2}
+  uint16_t tstart[1u << START_BITS];   // tree node to start from, by key prefix
 };
 
 // One partitioning task of a batch (a subarray A[l, l+n) of the input).

@@ -147,6 +147,7 @@ uint32_t task_kprime(const Cfg& c, uint64_t n) {
 uint32_t block_elems(const Cfg& c, uint32_t nb) {
   const uint32_t bmax = std::max<uint32_t>(1, MAX_BLOCK_BYTES / c.D);
   if (c.gbuf) return std::min(bmax, std::max<uint32_t>(1, c.b_req));
+  // LDS holds nb buffers of b elements (plus BUF_PAD_DW dwords of padding each)
   uint32_t b = std::max<uint32_t>(1, BUF_LDS_BYTES / (nb * c.D));
   b = std::min(b, bmax);
   if (c.b_req) b = std::min(b, c.b_req);
@@ -522,7 +523,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     for (uint32_t x = 0; x < nwg; ++x) h_perm[pwg + x] = t;
     pwg += nwg;
     for (uint32_t j = 0; j < nb; ++j) h_cln[cln++] = (t << 10) | j;
-    if (!c.gbuf) max_dyn = std::max<size_t>(max_dyn, (size_t)nb * b * c.D);
+    if (!c.gbuf) max_dyn = std::max<size_t>(max_dyn, (size_t)nb * (b * c.DW + BUF_PAD_DW) * 4);
   }
   if (wg > r.L.WB || pwg > r.L.PWB || slot_off > r.L.SB || spill_off > r.L.SPB || flag_off > r.L.FB ||
       piece > r.L.PB || bucket > r.L.NBE || cln > r.L.TB * max_nb(c)) {

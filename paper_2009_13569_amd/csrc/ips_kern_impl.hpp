@@ -32,7 +32,8 @@ struct LaunchImpl {
     static bool attr_done = false;
     if (!attr_done) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_classify<T, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)BUF_LDS_BYTES);
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(BUF_LDS_BYTES + MAX_NB * BUF_PAD_DW * 4));
       attr_done = true;
     }
     if (gbuf)
@@ -79,7 +80,7 @@ struct LaunchImpl {
     return lds_launch<SH::NS, SH::ES>(lt, nt, data, ctrl, st);
   }
   static hipError_t sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL((k_sorted_sample<T>), dim3(1), dim3(1024), 0, st, data, n, ctrl);
+    hipLaunchKernelGGL((k_sorted_sample<T>), dim3(64), dim3(1024), 0, st, data, n, ctrl);
     return hipGetLastError();
   }
   static hipError_t sorted_check(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {

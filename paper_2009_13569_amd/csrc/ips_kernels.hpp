@@ -139,6 +139,34 @@ __device__ __forceinline__ uint32_t bucket_of(const typename T::Key& k, const ty
   return tree_bucket(tree, spl, logK, eq, k);
 }
 
+// Start-node table (the lookup table of start nodes addressed by the most
+// significant key bits suggested in the paper's Section 8): entry p holds
+// the deepest tree node whose subtree receives every key whose image lies in
+// prefix range p, so the descent starts there and takes fewer steps.
+struct StartTable {
+  const uint16_t* start;
+  uint64_t base;
+  uint32_t shift;
+  __device__ __forceinline__ uint32_t index(uint64_t x) const {
+    if (x < base) return 0;
+    const uint64_t q = (x - base) >> shift;
+    return q >= (1u << START_BITS) ? (1u << START_BITS) - 1 : (uint32_t)q;
+  }
+};
+
+template <class T>
+__device__ __forceinline__ uint32_t tree_bucket_st(const typename T::Key* __restrict__ tree,
+                                                   const typename T::Key* __restrict__ spl,
+                                                   uint32_t logK, uint32_t eq, const StartTable& st,
+                                                   const typename T::Key& e) {
+  const uint32_t K = 1u << logK;
+  uint32_t i = st.start[st.index(T::img(e))];
+  while (i < K) i = 2 * i + (kless(tree[i], e) ? 1u : 0u);
+  i -= K;
+  if (eq) i = 2 * i + (kless(e, spl[i]) ? 0u : 1u);
+  return i;
+}
+
 // --------------------------------------------------------------- sampling
 
 // Bitonic sort of n2 (power of two) keys in LDS by all threads of the block.
@@ -228,10 +256,48 @@ k_sample(BatchArgs a, uint64_t seed) {
       T::to_slot(v, rec->tree[i]);
     }
   }
+  // Start-node table over the splitters' key range [s_0, s_{u-1}].
+  const uint64_t base = T::img(s_spl[0]);
+  const uint64_t top = T::img(s_spl[u - 1]);
+  const uint64_t span = top - base;
+  uint32_t tsh = 0;
+  while (tsh < 64 && (span >> tsh) >= (1ull << START_BITS)) ++tsh;
+  __syncthreads();
+  __shared__ Key s_tree[MAX_K];
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+    if (i >= 1) {
+      uint32_t d = 31u - __clz(i);
+      uint32_t p = i - (1u << d);
+      uint32_t idx = ((2 * p + 1) << (logK - d - 1)) - 1;
+      s_tree[i] = s_spl[idx < u ? idx : u - 1];
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < (1u << START_BITS); p += blockDim.x) {
+    const uint64_t lo = p == 0 ? 0 : base + ((uint64_t)p << tsh);
+    uint64_t hi;
+    if (p == (1u << START_BITS) - 1) {
+      hi = T::IMG_MAX;
+    } else {
+      const uint64_t nx = base + ((uint64_t)(p + 1) << tsh);
+      hi = (nx < base) ? T::IMG_MAX : nx - 1;   // saturate on wrap
+      if (hi > T::IMG_MAX) hi = T::IMG_MAX;
+    }
+    const Key klo = T::lo_of(lo), khi = T::hi_of(hi);
+    uint32_t i = 1;
+    while (i < K) {
+      if (kless(s_tree[i], klo)) i = 2 * i + 1;          // every key goes right
+      else if (!kless(s_tree[i], khi)) i = 2 * i;       // every key goes left
+      else break;
+    }
+    rec->tstart[p] = (uint16_t)i;
+  }
   if (threadIdx.x == 0) {
     rec->K = K; rec->logK = logK; rec->eq = eq; rec->nb = eq ? 2 * K : K;
     rec->u = u; rec->alpha = alpha; rec->kp = kp; rec->m = m;
     rec->shift = 0; rec->width = 0; rec->radix = 0;
+    rec->tbase = base;
+    rec->tshift = tsh;
   }
 }
 
@@ -244,6 +310,13 @@ k_sample(BatchArgs a, uint64_t seed) {
 // blocks that a single tile fills completely are written directly.  At the
 // end the partial buffers are saved in the stripe's slot and the per-bucket
 // counts are published.
+//
+// LDS buffers are laid out with a stride of b*DW + BUF_PAD dwords per bucket
+// so that lanes appending at the same offset of different buckets fall into
+// different banks; each bucket's tile state (blocks full before the tile,
+// after the tile, and its block base) is one 16-byte LDS word.
+constexpr uint32_t BUF_PAD = BUF_PAD_DW;
+
 template <class T, bool GBUF>
 __global__ void __launch_bounds__(CLS_THREADS)
 k_classify(BatchArgs a) {
@@ -254,9 +327,10 @@ k_classify(BatchArgs a) {
   constexpr uint32_t TILE = NT * EPT;
   __shared__ Key s_tree[MAX_K];
   __shared__ Key s_spl[MAX_K];
-  __shared__ uint32_t s_cnt[MAX_NB], s_nfull[MAX_NB], s_oldf[MAX_NB];
-  __shared__ int32_t s_base[MAX_NB];
+  __shared__ uint32_t s_cnt[MAX_NB];
+  __shared__ uint4 s_st[MAX_NB];          // {blocks before tile, blocks after, base, 0}
   __shared__ uint64_t s_mn[MAX_K], s_mx[MAX_K];
+  __shared__ uint16_t s_start[1u << START_BITS];
   __shared__ uint32_t s_wpos;
   extern __shared__ __align__(16) uint32_t s_buf[];
 
@@ -277,10 +351,18 @@ k_classify(BatchArgs a) {
       s_tree[i] = T::from_slot(rec->tree[i]);
       s_spl[i] = T::from_slot(rec->spl[i]);
     }
+    for (uint32_t i = tid; i < (1u << START_BITS); i += NT) s_start[i] = rec->tstart[i];
   }
-  for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_nfull[j] = 0; s_oldf[j] = 0; s_base[j] = 0; }
+  StartTable stab;
+  stab.start = s_start;
+  stab.base = radix ? 0 : rec->tbase;
+  stab.shift = radix ? 0 : rec->tshift;
+  for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_st[j] = make_uint4(0, 0, 0, 0); }
   for (uint32_t j = tid; j < MAX_K; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
   if (tid == 0) s_wpos = 0;
+  // buffer of bucket j at buf + j * bstride (dwords)
+  const uint32_t bdw = b * DW;
+  const uint32_t bstride = GBUF ? bdw : bdw + BUF_PAD;
   uint32_t* buf = GBUF ? reinterpret_cast<uint32_t*>(a.slots + tk.slot_off + (uint64_t)s * tk.slot_bytes)
                        : s_buf;
   __syncthreads();
@@ -289,80 +371,83 @@ k_classify(BatchArgs a) {
   const uint32_t bhi = (uint32_t)(((uint64_t)(s + 1) * NB) / W);
   const uint64_t elo = (uint64_t)blo * b;
   const uint64_t ehi = ((uint64_t)bhi * b < tn) ? (uint64_t)bhi * b : tn;
-  uint32_t* gd = a.data + tk.l * DW;
+  const uint32_t slen = (uint32_t)(ehi - elo);        // stripe length (elements)
+  uint32_t* gs = a.data + (tk.l + elo) * DW;          // stripe base
 
   uint32_t cur[EPT][DW];
   uint32_t nxt[EPT][DW];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const uint64_t idx = elo + (uint64_t)i * NT + tid;
-    if (idx < ehi) ld_elem<DW>(gd + idx * DW, cur[i]);
+    const uint32_t idx = (uint32_t)i * NT + tid;
+    if (idx < slen) ld_elem<DW>(gs + (uint64_t)idx * DW, cur[i]);
   }
-  for (uint64_t ts = elo; ts < ehi; ts += TILE) {
+  for (uint32_t ts = 0; ts < slen; ts += TILE) {
+    const bool full = ts + TILE <= slen;
     uint32_t bk[EPT], sl[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const uint64_t idx = ts + (uint64_t)i * NT + tid;
+      const uint32_t idx = ts + (uint32_t)i * NT + tid;
       bk[i] = 0; sl[i] = 0;
-      if (idx < ehi) {
+      if (full || idx < slen) {
         const Key key = key_of<T>(cur[i]);
-        bk[i] = bucket_of<T>(key, s_tree, s_spl, logK, eq, radix, shift, rmask);
         if constexpr (T::RADIX_OK) {
           if (radix) {
+            bk[i] = (uint32_t)((T::rkey(key) >> shift) & rmask);
             atomicMin((unsigned long long*)&s_mn[bk[i]], (unsigned long long)T::rkey(key));
             atomicMax((unsigned long long*)&s_mx[bk[i]], (unsigned long long)T::rkey(key));
+          } else {
+            bk[i] = tree_bucket_st<T>(s_tree, s_spl, logK, eq, stab, key);
           }
+        } else {
+          bk[i] = tree_bucket_st<T>(s_tree, s_spl, logK, eq, stab, key);
         }
         sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
       }
     }
     // Prefetch the next tile; it is never written while this tile is processed.
+    const uint32_t tn2 = ts + TILE;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const uint64_t idx = ts + TILE + (uint64_t)i * NT + tid;
-      if (idx < ehi) ld_elem<DW>(gd + idx * DW, nxt[i]);
+      const uint32_t idx = tn2 + (uint32_t)i * NT + tid;
+      if (idx < slen) ld_elem<DW>(gs + (uint64_t)idx * DW, nxt[i]);
     }
     __syncthreads();
     for (uint32_t j = tid; j < nb; j += NT) {
-      const uint32_t fo = s_nfull[j];
+      const uint32_t fo = s_st[j].y;          // blocks full before this tile
       const uint32_t nf = bd.div(s_cnt[j]);
-      s_oldf[j] = fo;
-      if (nf > fo) {
-        const uint32_t p = atomicAdd(&s_wpos, nf - fo);
-        s_base[j] = (int32_t)p - (int32_t)fo;
-        s_nfull[j] = nf;
-      }
+      uint32_t base = 0;
+      if (nf > fo) base = atomicAdd(&s_wpos, nf - fo) - fo;
+      s_st[j] = make_uint4(fo, nf, base, 0);
     }
     __syncthreads();
-    const uint64_t consumed = ((ts + TILE < ehi) ? ts + TILE : ehi) - elo;
+    const uint32_t consumed = (ts + TILE < slen) ? ts + TILE : slen;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const uint64_t idx = ts + (uint64_t)i * NT + tid;
-      if (idx < ehi) {
-        const uint32_t j = bk[i];
+      const uint32_t idx = ts + (uint32_t)i * NT + tid;
+      if (full || idx < slen) {
+        const uint4 st = s_st[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
-        if (blk == s_oldf[j]) {
-          st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
-        } else if (blk < s_nfull[j]) {
-          const uint64_t pos = (uint64_t)(s_base[j] + (int32_t)blk) * b + o;
-          if (pos >= consumed) dev_error(a.ctrl, DE_CLS_INPLACE, wg, (uint32_t)pos);
-          else st_elem<DW>(gd + (elo + pos) * DW, cur[i]);
+        if (blk == st.x) {
+          st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
+        } else if (blk < st.y) {
+          const uint32_t pos = (st.z + blk) * b + o;
+          if (pos >= consumed) dev_error(a.ctrl, DE_CLS_INPLACE, wg, pos);
+          else st_elem<DW>(gs + (uint64_t)pos * DW, cur[i]);
         }
       }
     }
     __syncthreads();
     {
       const uint32_t wave = tid >> 6, lane = tid & 63;
-      const uint32_t bdw = b * DW;
       for (uint32_t j = wave; j < nb; j += NT / 64) {
-        const uint32_t fo = s_oldf[j];
-        if (s_nfull[j] > fo) {
-          const uint64_t pos = (uint64_t)(s_base[j] + (int32_t)fo) * b;
+        const uint4 st = s_st[j];
+        if (st.y > st.x) {
+          const uint32_t pos = (st.z + st.x) * b;
           if (pos + b > consumed) {
-            if (lane == 0) dev_error(a.ctrl, DE_CLS_INPLACE, wg, (uint32_t)pos);
+            if (lane == 0) dev_error(a.ctrl, DE_CLS_INPLACE, wg, pos);
           } else {
-            uint32_t* dst = gd + (elo + pos) * DW;
-            const uint32_t* src = buf + (uint64_t)j * bdw;
+            uint32_t* dst = gs + (uint64_t)pos * DW;
+            const uint32_t* src = buf + j * bstride;
             for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
           }
         }
@@ -371,12 +456,11 @@ k_classify(BatchArgs a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const uint64_t idx = ts + (uint64_t)i * NT + tid;
-      if (idx < ehi) {
-        const uint32_t j = bk[i];
+      const uint32_t idx = ts + (uint32_t)i * NT + tid;
+      if (full || idx < slen) {
+        const uint4 st = s_st[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
-        if (blk == s_nfull[j] && blk > s_oldf[j])
-          st_elem<DW>(buf + ((uint64_t)j * b + o) * DW, cur[i]);
+        if (blk == st.y && blk > st.x) st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
       }
     }
 #pragma unroll
@@ -386,8 +470,9 @@ k_classify(BatchArgs a) {
   }
   __syncthreads();
   for (uint32_t j = tid; j < nb; j += NT) {
-    a.wg_nfull[(uint64_t)wg * MAX_NB + j] = s_nfull[j];
-    a.wg_left[(uint64_t)wg * MAX_NB + j] = s_cnt[j] - s_nfull[j] * b;
+    const uint32_t nfull = s_st[j].y;
+    a.wg_nfull[(uint64_t)wg * MAX_NB + j] = nfull;
+    a.wg_left[(uint64_t)wg * MAX_NB + j] = s_cnt[j] - nfull * b;
     if (radix && j < MAX_K) {
       a.wg_min[(uint64_t)wg * MAX_K + j] = s_mn[j];
       a.wg_max[(uint64_t)wg * MAX_K + j] = s_mx[j];
@@ -398,9 +483,9 @@ k_classify(BatchArgs a) {
     uint32_t* slot = reinterpret_cast<uint32_t*>(a.slots + tk.slot_off + (uint64_t)s * tk.slot_bytes);
     const uint32_t wave = tid >> 6, lane = tid & 63;
     for (uint32_t j = wave; j < nb; j += NT / 64) {
-      const uint32_t fill = (s_cnt[j] - s_nfull[j] * b) * DW;
-      const uint32_t* src = buf + (uint64_t)j * b * DW;
-      uint32_t* dst = slot + (uint64_t)j * b * DW;
+      const uint32_t fill = (s_cnt[j] - s_st[j].y * b) * DW;
+      const uint32_t* src = buf + j * bstride;
+      uint32_t* dst = slot + (uint64_t)j * bdw;
       for (uint32_t x = lane; x < fill; x += 64) dst[x] = src[x];
     }
   }
@@ -1059,7 +1144,7 @@ __global__ void __launch_bounds__(1024) k_sorted_sample(const uint32_t* data, ui
   constexpr int DW = T::DW;
   constexpr uint64_t PAIRS = 65536;
   uint32_t desc = 0, asc = 0;
-  for (uint64_t j = threadIdx.x; j < PAIRS; j += 1024) {
+  for (uint64_t j = (uint64_t)blockIdx.x * 1024 + threadIdx.x; j < PAIRS; j += (uint64_t)gridDim.x * 1024) {
     const uint64_t i = (uint64_t)(((unsigned __int128)j * (n - 1)) / PAIRS);
     if (i + 1 < n) {
       uint32_t w0[DW], w1[DW];

@@ -47,6 +47,12 @@ struct TU32 {
   __device__ static void from_key(Key k, uint32_t* w) { w[0] = k; }
   __device__ static Key from_slot(const uint64_t* s) { return (uint32_t)s[0]; }
   __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+  // Unsigned image used to index the start-node table, and the smallest /
+  // largest key whose image is x.
+  __device__ static uint64_t img(Key k) { return k; }
+  __device__ static Key lo_of(uint64_t x) { return (uint32_t)x; }
+  __device__ static Key hi_of(uint64_t x) { return (uint32_t)x; }
+  static constexpr uint64_t IMG_MAX = 0xFFFFFFFFull;
 };
 
 struct TU64 {
@@ -61,6 +67,10 @@ struct TU64 {
   __device__ static void from_key(Key k, uint32_t* w) { w[0] = (uint32_t)k; w[1] = (uint32_t)(k >> 32); }
   __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
   __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+  __device__ static uint64_t img(Key k) { return k; }
+  __device__ static Key lo_of(uint64_t x) { return x; }
+  __device__ static Key hi_of(uint64_t x) { return x; }
+  static constexpr uint64_t IMG_MAX = ~0ull;
 };
 
 struct TF64 {
@@ -78,6 +88,10 @@ struct TF64 {
   }
   __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
   __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+  __device__ static uint64_t img(Key k) { return k; }
+  __device__ static Key lo_of(uint64_t x) { return x; }
+  __device__ static Key hi_of(uint64_t x) { return x; }
+  static constexpr uint64_t IMG_MAX = ~0ull;
 };
 
 struct TPair {
@@ -91,6 +105,10 @@ struct TPair {
   __device__ static uint64_t rkey(Key k) { return k; }
   __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
   __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k; s[1] = 0; }
+  __device__ static uint64_t img(Key k) { return k; }
+  __device__ static Key lo_of(uint64_t x) { return x; }
+  __device__ static Key hi_of(uint64_t x) { return x; }
+  static constexpr uint64_t IMG_MAX = ~0ull;
 };
 
 struct TRec100 {
@@ -110,6 +128,10 @@ struct TRec100 {
     K80 k; k.hi = s[0]; k.lo = (uint32_t)s[1]; k.pad = 0; return k;
   }
   __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k.hi; s[1] = k.lo; }
+  __device__ static uint64_t img(Key k) { return k.hi; }
+  __device__ static Key lo_of(uint64_t x) { K80 k; k.hi = x; k.lo = 0; k.pad = 0; return k; }
+  __device__ static Key hi_of(uint64_t x) { K80 k; k.hi = x; k.lo = 0xFFFFu; k.pad = 0; return k; }
+  static constexpr uint64_t IMG_MAX = ~0ull;
 };
 
 }  // namespace ips
