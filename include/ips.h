@@ -148,6 +148,36 @@ int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type,
                    int algo, void* d_ws, size_t ws_bytes,
                    const ips_params* params, void* stream);
 
+/* A segment of a batched call: elements [offset, offset + n) of the data
+ * array (element units). */
+typedef struct {
+  uint64_t offset, n;
+} ips_segment;
+
+/* Workspace bytes of ips_sort_segments over a data array of n_total
+ * elements with the given segments (host array of nseg entries).  Pure host
+ * computation.  Errors: as ips_workspace_bytes, and IPS_E_INVALID_ARG for a
+ * segment outside [0, n_total) or two overlapping segments. */
+int ips_segments_workspace_bytes(uint64_t n_total, const ips_segment* segs,
+                                 uint32_t nseg, int elem_type, int algo,
+                                 const ips_params* params, size_t* out_bytes);
+
+/* Sort each of nseg segments of one device array independently, in place,
+ * in one call (batched sorting of many arrays; the paper's problem of
+ * Section 2 applied to every segment).  d_data holds n_total elements of
+ * elem_type (1..5, keys or records); segs is a HOST array of nseg
+ * non-overlapping segments (read during the call only); elements outside
+ * every segment are left unchanged.  All segments' partitioning steps of one
+ * recursion level run in shared launches (Section 4.2 breadth first);
+ * segments no larger than the LDS tier are sorted in one launch.  There is
+ * no sorted-input detection per segment.  IPS_FLAG_LEVEL1_ONLY is rejected.
+ * The workspace must hold ips_segments_workspace_bytes(...) bytes.  Errors:
+ * as ips_sort_keys, plus IPS_E_INVALID_ARG for bad segments. */
+int ips_sort_segments(ips_ctx* ctx, void* d_data, uint64_t n_total,
+                      int elem_type, int algo, const ips_segment* segs,
+                      uint32_t nseg, void* d_ws, size_t ws_bytes,
+                      const ips_params* params, void* stream);
+
 /* Description of the root partitioning step of the last sort on `ctx`
  * (Section 4.1).  For IPS_SAMPLESORT: alpha, k_prime (adaptive k), m (sample
  * size), u (distinct splitters), K (power of two >= u+1), eq (equality

@@ -40,8 +40,9 @@ PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags",
           "cleanup_a", "cleanup_b", "lds_sort", "reverse"]
 
 EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
-           "ips_last_device_error", "ips_status_string", "ips_abi_version"]
+           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_get_root_info",
+           "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
+           "ips_status_string", "ips_abi_version"]
 
 
 class Params(ctypes.Structure):
@@ -66,6 +67,10 @@ class Stats(ctypes.Structure):
                 ("max_step_elems", ctypes.c_uint64)]
 
 
+class Segment(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint64), ("n", ctypes.c_uint64)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("ms", (ctypes.c_double * len(PHASES)) * (MAX_LEVELS + 1)),
@@ -79,6 +84,10 @@ _lib.ips_ctx_destroy.argtypes = [_vp]
 _lib.ips_workspace_bytes.argtypes = [_u64, _i32, _i32, ctypes.POINTER(Params), ctypes.POINTER(_sz)]
 _lib.ips_sort_keys.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_sort_pairs.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_segments_workspace_bytes.argtypes = [_u64, ctypes.POINTER(Segment), ctypes.c_uint32, _i32, _i32,
+                                              ctypes.POINTER(Params), ctypes.POINTER(_sz)]
+_lib.ips_sort_segments.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Segment), ctypes.c_uint32,
+                                   _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_get_root_info.argtypes = [_vp, ctypes.POINTER(RootInfo)]
 _lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.ips_get_profile.argtypes = [_vp, ctypes.POINTER(Profile)]
@@ -87,8 +96,9 @@ _lib.ips_last_device_error.argtypes = [_vp]
 _lib.ips_status_string.argtypes = [_i32]
 _lib.ips_status_string.restype = ctypes.c_char_p
 for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_get_root_info", "ips_get_stats", "ips_get_profile",
-           "ips_last_hip_error", "ips_last_device_error", "ips_abi_version"):
+           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_get_root_info",
+           "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
+           "ips_abi_version"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -117,6 +127,28 @@ def workspace_bytes(n: int, kind: str, algo: str = "samplesort", params: Params 
                                   ctypes.byref(params) if params is not None else None, ctypes.byref(out))
     if rc != IPS_OK:
         raise IpsError(rc, "ips_workspace_bytes")
+    return int(out.value)
+
+
+def segment_array(offsets, sizes):
+    """ctypes array of ips_segment from two equal-length integer sequences."""
+    offsets, sizes = list(offsets), list(sizes)
+    if len(offsets) != len(sizes):
+        raise ValueError("offsets and sizes differ in length")
+    arr = (Segment * max(1, len(offsets)))()
+    for i, (o, n) in enumerate(zip(offsets, sizes)):
+        arr[i].offset, arr[i].n = int(o), int(n)
+    return arr, len(offsets)
+
+
+def segments_workspace_bytes(n_total: int, segs, nseg: int, kind: str, algo: str = "samplesort",
+                             params: Params | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    rc = _lib.ips_segments_workspace_bytes(n_total, segs, nseg, TYPES[kind], ALGOS[algo],
+                                           ctypes.byref(params) if params is not None else None,
+                                           ctypes.byref(out))
+    if rc != IPS_OK:
+        raise IpsError(rc, "ips_segments_workspace_bytes")
     return int(out.value)
 
 
@@ -185,6 +217,29 @@ class Sorter:
         if rc != IPS_OK:
             raise IpsError(rc, "ips_sort", f"(hip={_lib.ips_last_hip_error(self._h)}, "
                                            f"device={hex(_lib.ips_last_device_error(self._h))})")
+        return t
+
+    def sort_segments_(self, t, offsets, sizes, algo: str = "samplesort", params: Params | None = None,
+                       kind: str | None = None, stream=None, ws=None):
+        """Sort every segment [offsets[i], offsets[i] + sizes[i]) of tensor `t`
+        (element units along dim 0) independently, in place, in one call."""
+        import torch
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensor must be a contiguous GPU tensor")
+        kind = kind or kind_of(t)
+        segs, nseg = segment_array(offsets, sizes)
+        n = t.shape[0]
+        need = segments_workspace_bytes(n, segs, nseg, kind, algo, params)
+        ws = ws if ws is not None else self.workspace(need)
+        if stream is None:
+            stream = torch.cuda.current_stream(t.device)
+        pp = ctypes.byref(params) if params is not None else None
+        rc = _lib.ips_sort_segments(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ALGOS[algo],
+                                    segs, nseg, ctypes.c_void_p(ws.data_ptr()), ws.numel(), pp,
+                                    ctypes.c_void_p(stream.cuda_stream))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_sort_segments", f"(hip={_lib.ips_last_hip_error(self._h)}, "
+                                                    f"device={hex(_lib.ips_last_device_error(self._h))})")
         return t
 
     def root_info(self) -> RootInfo:

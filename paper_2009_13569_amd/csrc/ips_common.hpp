@@ -86,6 +86,14 @@ struct LTask {
   uint32_t n, pad;
 };
 
+// A chunk of one segment of a batched call (ips_sort_segments): elements
+// [l, l + n) of the data, belonging to segment `seg`.
+struct SegItem {
+  uint64_t l;
+  uint32_t n, seg;
+};
+constexpr uint32_t SEG_CHUNK = 65536;   // elements per chunk
+
 // Arguments shared by the kernels of one batch.
 struct BatchArgs {
   uint32_t* data;             // the array (as dwords)

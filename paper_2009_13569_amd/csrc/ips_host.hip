@@ -188,7 +188,7 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   L->SB = std::min<uint64_t>((uint64_t)(WG_TARGET + L->TB) * slot_max, data_budget);
   L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, std::max<uint64_t>(slot_max, data_budget));
   L->FB = n / bmin + L->TB + 1;
-  L->PB = (uint64_t)L->TB * (2 * nbm + 2) + L->WB + L->FB / c.cmax + 16;
+  L->PB = (uint64_t)L->TB * (2 * nbm + 3) + L->WB + L->FB / c.cmax + 16;
   L->PWB = c.groups / 4 + 2 * L->TB + 16;
   L->NBE = L->TB * (uint32_t)(nbm + 1);
   L->LTB = L->TB * (uint32_t)nbm + 1;
@@ -476,6 +476,25 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   size_t max_dyn = 0;
   uint32_t max_nb_batch = 1;
   for (uint32_t t = 0; t < T; ++t) max_nb_batch = std::max(max_nb_batch, nbv[t]);
+  // Stripe length S: the batch's elements spread over WG_TARGET workgroups
+  // (the largest stripe bounds the phase), doubled while the stripes would
+  // exceed the batch's workgroup budget.
+  (void)level_elems;
+  uint64_t S = 1, batch_elems = 0;
+  for (uint32_t t = 0; t < T; ++t) batch_elems += bt[t].n;
+  S = std::max<uint64_t>(1, batch_elems / WG_TARGET);
+  for (;;) {
+    uint64_t wsum = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+      uint64_t W = (bt[t].n + S - 1) / S;
+      W = std::min<uint64_t>(W, std::max<uint64_t>(1, bt[t].n / (4ull * nbv[t] * bvec[t])));
+      W = std::min<uint64_t>(W, NBv[t]);
+      W = std::min<uint64_t>(W, WG_TARGET);
+      wsum += W;
+    }
+    if (wsum <= r.L.WB) break;
+    S *= 2;
+  }
   for (uint32_t t = 0; t < T; ++t) {
     PTask& p = r.h_tasks[t];
     const uint32_t b = bvec[t], nb = nbv[t], NB = NBv[t];
@@ -485,10 +504,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.eq = hdr[t].eq;
     p.b = b;
     p.NB = NB;
-    // Stripes of at most level_elems / WG_TARGET elements (so that the
-    // largest stripe, which bounds the phase, is no larger than the mean),
-    // but at least four buffer capacities long.
-    const uint64_t S = std::max<uint64_t>(1, level_elems / WG_TARGET);
+    // Stripes of at most S elements, but at least four buffer capacities long.
     uint64_t W = (p.n + S - 1) / S;
     W = std::min<uint64_t>(W, std::max<uint64_t>(1, p.n / (4ull * nb * b)));
     W = std::min<uint64_t>(W, NB);
@@ -642,10 +658,21 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   return launch_lds_tasks(r, lt, bt[0].level);
 }
 
-int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
-              const ips_params* params, void* stream) {
+// Extra workspace of a segmented radix call: chunk descriptors of the
+// segments that are partitioned and their key ranges.
+size_t seg_extra_bytes(const Cfg& c, uint64_t n_total, uint64_t nseg) {
+  if (!c.radix) return 0;
+  const uint64_t items = n_total / SEG_CHUNK + nseg;
+  return ((items * sizeof(SegItem) + 255) & ~255ull) + 2 * ((nseg * 8 + 255) & ~255ull);
+}
+
+// Validation, workspace plan, pinned staging and device views shared by
+// every sort entry point.  `extra_pin` bytes of pinned memory are reserved
+// after the common staging areas (returned in *extra).
+int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, int type, int algo, void* ws,
+              size_t ws_bytes, size_t ws_extra, const ips_params* params, void* stream,
+              size_t extra_pin, uint8_t** extra) {
   if (!ctx) return IPS_E_INVALID_ARG;
-  Run r;
   std::memset(&r.a, 0, sizeof(r.a));
   int rc = make_cfg(n, type, algo, params, &r.c);
   if (rc) return rc;
@@ -660,32 +687,34 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   ctx->pending.clear();
   ctx->profiling = (r.c.flags & IPS_FLAG_PROFILE) != 0;
   ctx->last_dev = 0;
+  r.ctx = ctx;
+  r.n = n;
   if (n < 2) return IPS_OK;
   plan(n, r.c, &r.L);
   if (!ws) return IPS_E_INVALID_ARG;
-  if (ws_bytes < r.L.total) return IPS_E_WORKSPACE;
+  if (ws_bytes < r.L.total + ws_extra) return IPS_E_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return IPS_E_MISALIGNED;
   r.c.L = launchers_for(type);
-  r.ctx = ctx;
   r.ws = static_cast<uint8_t*>(ws);
   r.data = static_cast<uint32_t*>(d);
-  r.n = n;
   r.st = static_cast<hipStream_t>(stream);
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  // Pinned staging: tasks | maps | LDS tasks | readback | ctrl.
+  // Pinned staging: tasks | maps | LDS tasks | readback | ctrl | extra.
   const size_t b_tasks = (size_t)r.L.TB * sizeof(PTask);
   const size_t b_maps = ((size_t)r.L.WB + r.L.PWB + (size_t)r.L.TB * max_nb(r.c)) * 4;
   const size_t b_lt = (size_t)r.L.LTB * sizeof(LTask);
   const size_t b_rb = std::max<size_t>((size_t)r.L.NBE * 24, (size_t)r.L.TB * 64) + 4096;
   const size_t b_ctrl = CTRL_WORDS * 4;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  if (int e = ensure_pinned(ctx, al(b_tasks) + al(b_maps) + al(b_lt) + al(b_rb) + al(b_ctrl))) return e;
+  if (int e = ensure_pinned(ctx, al(b_tasks) + al(b_maps) + al(b_lt) + al(b_rb) + al(b_ctrl) + al(extra_pin)))
+    return e;
   uint8_t* pp = ctx->pin;
   r.h_tasks = reinterpret_cast<PTask*>(pp); pp += al(b_tasks);
   r.h_maps = reinterpret_cast<uint32_t*>(pp); pp += al(b_maps);
   r.h_lt = reinterpret_cast<LTask*>(pp); pp += al(b_lt);
   r.h_rb = pp; r.rb_bytes = b_rb; pp += al(b_rb);
-  r.h_ctrl = reinterpret_cast<uint32_t*>(pp);
+  r.h_ctrl = reinterpret_cast<uint32_t*>(pp); pp += al(b_ctrl);
+  if (extra) *extra = pp;
   // Device views of the workspace.
   BatchArgs& a = r.a;
   a.data = r.data;
@@ -723,54 +752,40 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
   // Control block: errors and flags cleared; min = all ones, max = 0.
   HIPCHK(ctx, launch_fill32(a.ctrl, CTRL_WORDS, 0u, r.st));
   HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_MINMAX, 2, 0xFFFFFFFFu, r.st));
-  // Sorted and reverse-sorted inputs (Section 6).
-  if (!(r.c.flags & (IPS_FLAG_NO_SORTED_CHECK | IPS_FLAG_LEVEL1_ONLY))) {
-    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
-                      [&] { return r.c.L->sorted_sample(r.data, n, a.ctrl, r.st); }));
-    if (int e = read_ctrl(r)) return e;
-    if (!r.h_ctrl[CTRL_DESC] || !r.h_ctrl[CTRL_ASC]) {   // inconclusive: scan everything
-      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
-                        [&] { return r.c.L->sorted_check(r.data, n, a.ctrl, r.st); }));
-      if (int e = read_ctrl(r)) return e;
-    }
-    if (!r.h_ctrl[CTRL_DESC]) { ctx->stats.detected = 1; return IPS_OK; }
-    if (!r.h_ctrl[CTRL_ASC]) {
-      ctx->stats.detected = 2;
-      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_REVERSE, n,
-                        [&] { return r.c.L->reverse(r.data, n, r.st); }));
-      return read_ctrl(r);
-    }
-  }
-  HTask root;
-  root.l = 0;
-  root.n = n;
-  root.level = 0;
-  root.tflags = 0;
-  root.shift = 0;
-  root.width = 0;
-  if (r.c.flags & IPS_FLAG_EQ_ON) root.tflags |= TF_EQ_ON;
-  if (r.c.flags & IPS_FLAG_EQ_OFF) root.tflags |= TF_EQ_OFF;
-  if (r.c.radix) {
-    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, n,
-                      [&] { return r.c.L->minmax(r.data, n, a.ctrl, r.st); }));
-    if (int e = read_ctrl(r)) return e;
-    const uint64_t mn = (uint64_t)r.h_ctrl[CTRL_MINMAX] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 1] << 32);
-    const uint64_t mx = (uint64_t)r.h_ctrl[CTRL_MINMAX + 2] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 3] << 32);
-    if (mn == mx) return IPS_OK;
+  return IPS_OK;
+}
+
+// Root task of a partitioned range, with the radix digit below the highest
+// bit in which its smallest and largest keys differ.  Returns false when
+// all keys are equal (radix: nothing to do).
+bool make_root(const Cfg& c, uint64_t l, uint64_t n, uint64_t mn, uint64_t mx, HTask* t) {
+  t->l = l;
+  t->n = n;
+  t->level = 0;
+  t->tflags = 0;
+  t->shift = 0;
+  t->width = 0;
+  if (c.flags & IPS_FLAG_EQ_ON) t->tflags |= TF_EQ_ON;
+  if (c.flags & IPS_FLAG_EQ_OFF) t->tflags |= TF_EQ_OFF;
+  if (c.radix) {
+    if (mn == mx) return false;
     const uint32_t h = 63u - (uint32_t)__builtin_clzll(mn ^ mx);
-    root.shift = h >= 7 ? h - 7 : 0;
-    root.width = h - root.shift + 1;
+    t->shift = h >= 7 ? h - 7 : 0;
+    t->width = h - t->shift + 1;
   }
-  if (n <= r.c.cap && !(r.c.flags & IPS_FLAG_LEVEL1_ONLY)) {
-    std::vector<LTask> lt(1);
-    lt[0].l = 0;
-    lt[0].n = (uint32_t)n;
-    lt[0].pad = 0;
-    ctx->stats.lds_elems += n;
-    if (int e = launch_lds_tasks(r, lt, IPS_MAX_LEVELS)) return e;
-    return read_ctrl(r);
+  return true;
+}
+
+// Breadth-first recursion (Section 4.2) from the given partitioning roots
+// and LDS-tier roots: every level's tasks run in as few batches as the
+// workspace allows.
+int level_loop(Run& r, std::vector<HTask> cur, const std::vector<LTask>& lds_roots, bool record_root) {
+  ips_ctx* ctx = r.ctx;
+  if (!lds_roots.empty()) {
+    for (const LTask& t : lds_roots) ctx->stats.lds_elems += t.n;
+    if (int e = launch_lds_tasks(r, lds_roots, record_root ? IPS_MAX_LEVELS : 0)) return e;
   }
-  std::vector<HTask> cur(1, root), next;
+  std::vector<HTask> next;
   uint32_t level = 0;
   while (!cur.empty()) {
     uint64_t level_elems = 0;
@@ -790,7 +805,7 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
         tot.flags += nd.flags; tot.pieces += nd.pieces;
         bt.push_back(cur[i++]);
       }
-      if (int e = run_batch(r, bt, level_elems, next, level == 0)) return e;
+      if (int e = run_batch(r, bt, level_elems, next, record_root && level == 0)) return e;
       if (r.c.flags & IPS_FLAG_LEVEL1_ONLY) return IPS_OK;
     }
     ctx->stats.levels = ++level;
@@ -798,6 +813,144 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
     std::swap(cur, next);
   }
   return read_ctrl(r);
+}
+
+int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
+              const ips_params* params, void* stream) {
+  Run r;
+  int rc = setup_run(ctx, r, d, n, type, algo, ws, ws_bytes, 0, params, stream, 0, nullptr);
+  if (rc || n < 2) return rc;
+  BatchArgs& a = r.a;
+  // Sorted and reverse-sorted inputs (Section 6).
+  if (!(r.c.flags & (IPS_FLAG_NO_SORTED_CHECK | IPS_FLAG_LEVEL1_ONLY))) {
+    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
+                      [&] { return r.c.L->sorted_sample(r.data, n, a.ctrl, r.st); }));
+    if (int e = read_ctrl(r)) return e;
+    if (!r.h_ctrl[CTRL_DESC] || !r.h_ctrl[CTRL_ASC]) {   // inconclusive: scan everything
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, n,
+                        [&] { return r.c.L->sorted_check(r.data, n, a.ctrl, r.st); }));
+      if (int e = read_ctrl(r)) return e;
+    }
+    if (!r.h_ctrl[CTRL_DESC]) { ctx->stats.detected = 1; return IPS_OK; }
+    if (!r.h_ctrl[CTRL_ASC]) {
+      ctx->stats.detected = 2;
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_REVERSE, n,
+                        [&] { return r.c.L->reverse(r.data, n, r.st); }));
+      return read_ctrl(r);
+    }
+  }
+  uint64_t mn = 0, mx = 0;
+  if (r.c.radix) {
+    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, n,
+                      [&] { return r.c.L->minmax(r.data, n, a.ctrl, r.st); }));
+    if (int e = read_ctrl(r)) return e;
+    mn = (uint64_t)r.h_ctrl[CTRL_MINMAX] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 1] << 32);
+    mx = (uint64_t)r.h_ctrl[CTRL_MINMAX + 2] | ((uint64_t)r.h_ctrl[CTRL_MINMAX + 3] << 32);
+  }
+  HTask root;
+  if (!make_root(r.c, 0, n, mn, mx, &root)) return IPS_OK;
+  if (n <= r.c.cap && !(r.c.flags & IPS_FLAG_LEVEL1_ONLY)) {
+    std::vector<LTask> lt(1);
+    lt[0].l = 0;
+    lt[0].n = (uint32_t)n;
+    lt[0].pad = 0;
+    return level_loop(r, {}, lt, true);
+  }
+  return level_loop(r, std::vector<HTask>(1, root), {}, true);
+}
+
+// Checks a segment list against the data length: every segment inside
+// [0, n_total) and no two overlapping.  Returns the sum of the lengths.
+int check_segments(const ips_segment* segs, uint32_t nseg, uint64_t n_total, uint64_t* sum) {
+  *sum = 0;
+  if (nseg && !segs) return IPS_E_INVALID_ARG;
+  std::vector<uint32_t> ord(nseg);
+  for (uint32_t i = 0; i < nseg; ++i) {
+    if (segs[i].offset > n_total || segs[i].n > n_total - segs[i].offset) return IPS_E_INVALID_ARG;
+    ord[i] = i;
+    *sum += segs[i].n;
+  }
+  std::sort(ord.begin(), ord.end(),
+            [&](uint32_t x, uint32_t y) { return segs[x].offset < segs[y].offset; });
+  for (uint32_t i = 1; i < nseg; ++i) {
+    const ips_segment& p = segs[ord[i - 1]];
+    if (p.n && segs[ord[i]].n && p.offset + p.n > segs[ord[i]].offset) return IPS_E_INVALID_ARG;
+  }
+  return IPS_OK;
+}
+
+int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
+                  const ips_segment* segs, uint32_t nseg, void* ws, size_t ws_bytes,
+                  const ips_params* params, void* stream) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  if (params && (params->flags & IPS_FLAG_LEVEL1_ONLY)) return IPS_E_INVALID_ARG;
+  uint64_t sum = 0;
+  if (int e = check_segments(segs, nseg, n_total, &sum)) return e;
+  Cfg c0;
+  if (int e = make_cfg(n_total, type, algo, params, &c0)) return e;
+  // Segments that are partitioned (larger than the LDS tier).
+  std::vector<uint32_t> big;
+  uint64_t big_elems = 0;
+  for (uint32_t i = 0; i < nseg; ++i)
+    if (segs[i].n > c0.cap) { big.push_back(i); big_elems += segs[i].n; }
+  const uint64_t items_ub = big_elems / SEG_CHUNK + big.size();
+  const size_t extra = seg_extra_bytes(c0, big_elems, big.size());
+  const size_t pin_extra = c0.radix ? items_ub * sizeof(SegItem) + big.size() * 16 : 0;
+  Run r;
+  uint8_t* hx = nullptr;
+  int rc = setup_run(ctx, r, d, n_total, type, algo, ws, ws_bytes, extra, params, stream, pin_extra, &hx);
+  if (rc || n_total < 2 || sum < 2) return rc;
+  std::vector<HTask> roots;
+  std::vector<LTask> lt;
+  for (uint32_t i = 0; i < nseg; ++i) {
+    if (segs[i].n < 2 || segs[i].n > r.c.cap) continue;
+    LTask q;
+    q.l = segs[i].offset;
+    q.n = (uint32_t)segs[i].n;
+    q.pad = 0;
+    lt.push_back(q);
+  }
+  if (r.c.radix && !big.empty()) {
+    // Key range of every partitioned segment.
+    SegItem* h_items = reinterpret_cast<SegItem*>(hx);
+    uint64_t* h_mm = reinterpret_cast<uint64_t*>(hx + ((items_ub * sizeof(SegItem) + 15) & ~15ull));
+    uint8_t* wx = r.ws + r.L.total;
+    SegItem* d_items = reinterpret_cast<SegItem*>(wx);
+    uint64_t* d_min = reinterpret_cast<uint64_t*>(wx + ((items_ub * sizeof(SegItem) + 255) & ~255ull));
+    uint64_t* d_max = d_min + ((big.size() * 8 + 255) & ~255ull) / 8;
+    uint64_t ni = 0;
+    for (uint32_t q = 0; q < big.size(); ++q) {
+      const ips_segment& sg = segs[big[q]];
+      for (uint64_t o = 0; o < sg.n; o += SEG_CHUNK) {
+        SegItem it;
+        it.l = sg.offset + o;
+        it.n = (uint32_t)std::min<uint64_t>(SEG_CHUNK, sg.n - o);
+        it.seg = q;
+        h_items[ni++] = it;
+      }
+    }
+    HIPCHK(ctx, hipMemcpyAsync(d_items, h_items, ni * sizeof(SegItem), hipMemcpyHostToDevice, r.st));
+    HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_min), 2 * big.size(), 0xFFFFFFFFu, r.st));
+    HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_max), 2 * big.size(), 0u, r.st));
+    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, big_elems, [&] {
+             return r.c.L->seg_minmax(d_items, (uint32_t)ni, r.data, d_min, d_max, r.st);
+           }));
+    HIPCHK(ctx, hipMemcpyAsync(h_mm, d_min, big.size() * 8, hipMemcpyDeviceToHost, r.st));
+    HIPCHK(ctx, hipMemcpyAsync(h_mm + big.size(), d_max, big.size() * 8, hipMemcpyDeviceToHost, r.st));
+    if (int e = read_ctrl(r)) return e;
+    for (uint32_t q = 0; q < big.size(); ++q) {
+      HTask t;
+      if (make_root(r.c, segs[big[q]].offset, segs[big[q]].n, h_mm[q], h_mm[big.size() + q], &t))
+        roots.push_back(t);
+    }
+  } else {
+    for (uint32_t q = 0; q < big.size(); ++q) {
+      HTask t;
+      make_root(r.c, segs[big[q]].offset, segs[big[q]].n, 0, 1, &t);
+      roots.push_back(t);
+    }
+  }
+  return level_loop(r, roots, lt, false);
 }
 
 }  // namespace
@@ -869,6 +1022,31 @@ int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type, int alg
                    size_t ws_bytes, const ips_params* params, void* stream) {
   if (rec_type != IPS_PAIR_U64_U64 && rec_type != IPS_REC100) return IPS_E_INVALID_ARG;
   return sort_impl(ctx, d_recs, n, rec_type, algo, d_ws, ws_bytes, params, stream);
+}
+
+int ips_segments_workspace_bytes(uint64_t n_total, const ips_segment* segs, uint32_t nseg,
+                                 int elem_type, int algo, const ips_params* params,
+                                 size_t* out_bytes) {
+  if (!out_bytes) return IPS_E_INVALID_ARG;
+  *out_bytes = 0;
+  uint64_t sum = 0;
+  if (int e = check_segments(segs, nseg, n_total, &sum)) return e;
+  int rc = ips_workspace_bytes(n_total, elem_type, algo, params, out_bytes);
+  if (rc || *out_bytes == 0) return rc;
+  Cfg c;
+  make_cfg(n_total, elem_type, algo, params, &c);
+  uint64_t big = 0, big_elems = 0;
+  for (uint32_t i = 0; i < nseg; ++i)
+    if (segs[i].n > c.cap) { ++big; big_elems += segs[i].n; }
+  *out_bytes += seg_extra_bytes(c, big_elems, big);
+  return IPS_OK;
+}
+
+int ips_sort_segments(ips_ctx* ctx, void* d_data, uint64_t n_total, int elem_type, int algo,
+                      const ips_segment* segs, uint32_t nseg, void* d_ws, size_t ws_bytes,
+                      const ips_params* params, void* stream) {
+  return segments_impl(ctx, d_data, n_total, elem_type, algo, segs, nseg, d_ws, ws_bytes, params,
+                       stream);
 }
 
 int ips_get_root_info(ips_ctx* ctx, ips_root_info* out) {

@@ -106,11 +106,21 @@ struct LaunchImpl {
       return hipErrorInvalidValue;
     }
   }
+  static hipError_t seg_minmax(const SegItem* items, uint32_t nitems, const uint32_t* data,
+                               uint64_t* smin, uint64_t* smax, hipStream_t st) {
+    if constexpr (T::RADIX_OK) {
+      if (!nitems) return hipSuccess;
+      hipLaunchKernelGGL((k_seg_minmax<T>), dim3(nitems), dim3(256), 0, st, items, data, smin, smax);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
         CAP_BIG, CAP_SMALL, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
-        &sorted_sample, &sorted_check, &reverse, &minmax};
+        &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax};
     return &t;
   }
 };

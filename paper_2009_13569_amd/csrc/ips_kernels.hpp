@@ -1196,6 +1196,35 @@ __global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n
   }
 }
 
+// Per-segment key range of a batched radix call: one workgroup per chunk,
+// combined with 64-bit atomics into smin[seg] / smax[seg] (which start at
+// all ones / zero).  The root digit of each segment is taken below the
+// highest bit in which its smallest and largest keys differ (Section 6).
+template <class T>
+__global__ void __launch_bounds__(256) k_seg_minmax(const SegItem* items, const uint32_t* data,
+                                                    uint64_t* smin, uint64_t* smax) {
+  constexpr int DW = T::DW;
+  const SegItem it = items[blockIdx.x];
+  uint64_t mn = ~0ull, mx = 0;
+  for (uint32_t i = threadIdx.x; i < it.n; i += 256) {
+    uint32_t w[DW];
+    ld_elem<DW>(data + (it.l + i) * DW, w);
+    const uint64_t k = T::rkey(key_of<T>(w));
+    mn = k < mn ? k : mn;
+    mx = k > mx ? k : mx;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = (uint64_t)__shfl_xor((long long)mn, o, 64);
+    const uint64_t b = (uint64_t)__shfl_xor((long long)mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin((unsigned long long*)&smin[it.seg], (unsigned long long)mn);
+    atomicMax((unsigned long long*)&smax[it.seg], (unsigned long long)mx);
+  }
+}
+
 #ifdef IPS_COMMON_KERNELS
 __global__ void __launch_bounds__(256) k_fill32(uint32_t* p, uint64_t n, uint32_t v) {
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = v;

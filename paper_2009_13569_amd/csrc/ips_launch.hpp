@@ -26,6 +26,8 @@ struct Launchers {
   hipError_t (*sorted_check)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*reverse)(uint32_t* data, uint64_t n, hipStream_t);
   hipError_t (*minmax)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
+  hipError_t (*seg_minmax)(const SegItem* items, uint32_t nitems, const uint32_t* data,
+                           uint64_t* smin, uint64_t* smax, hipStream_t);
 };
 
 const Launchers* launchers_u32();

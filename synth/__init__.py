@@ -206,3 +206,38 @@ def generate(kind: str, dist: str, n: int, seed: int) -> np.ndarray:
     if kind == "rec100":
         return gen_rec100(dist, n, seed)
     raise ValueError(kind)
+
+
+def batch_layout(count: int, lo_log2: float, hi_log2: float, seed: int,
+                 dists=("uniform", "twodup", "almostsorted")) -> tuple[np.ndarray, list]:
+    """Sizes and distributions of a batch of `count` arrays: size i is
+    floor(2^(lo + u_i (hi - lo))) (log-uniform) and distribution i is drawn
+    uniformly from `dists`, both from the SplitMix64 stream of `seed`."""
+    x = stream(seed, 2 * count)
+    u = (x[0::2] >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    sizes = np.floor(2.0 ** (lo_log2 + u * (hi_log2 - lo_log2))).astype(np.int64)
+    pick = (x[1::2] % np.uint64(len(dists))).astype(np.int64)
+    return sizes, [dists[int(p)] for p in pick]
+
+
+def generate_batch(kind: str, sizes, dists, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Concatenation of arrays generate(kind, dists[i], sizes[i], seed_i),
+    seed_i = SplitMix64 output i+1 of `seed`; returns (data, offsets)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    if len(sizes):
+        offs[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    seeds = stream(seed, len(sizes))
+    first = generate(kind, dists[0] if len(sizes) else "uniform", 0, 0)
+    out = np.empty((total,) + first.shape[1:], dtype=first.dtype)
+    for i, (o, n) in enumerate(zip(offs, sizes)):
+        out[o:o + n] = generate(kind, dists[i], int(n), int(seeds[i]))
+    return out, offs
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate:
+    cumulative sums of exponential gaps -log1p(-u)/rate."""
+    u = (stream(seed, count) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return np.cumsum(-np.log1p(-u) / rate_per_s)

@@ -79,3 +79,31 @@ def test_sort_rejects_bad_arguments_before_hip():
 def test_ctx_create_null_out():
     assert ips.lib().ips_ctx_create(None, 0) == -1
     assert ips.lib().ips_ctx_destroy(None) == 0
+
+
+def _segws(n_total, offs, sizes, t=2, algo=0):
+    segs, nseg = ips.segment_array(offs, sizes)
+    out = ctypes.c_size_t(0)
+    rc = ips.lib().ips_segments_workspace_bytes(n_total, segs, nseg, t, algo, None, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_segments_validation():
+    n = 1 << 20
+    rc, ws = _segws(n, [0, 1000, 500000], [1000, 400000, 524288])
+    assert rc == 0 and ws >= _ws(n, 2, 0)[1]
+    assert _segws(n, [0, 999], [1000, 10])[0] == -1            # overlap
+    assert _segws(n, [n - 10], [11])[0] == -1                  # past the end
+    assert _segws(n, [1 << 63], [1 << 63])[0] == -1            # offset + n overflows
+    assert _segws(n, [5, 5], [0, 10])[0] == 0                  # empty segments never overlap
+    assert _segws(n, [0], [n], t=5, algo=1)[0] == -2           # radix on 100-byte records
+    # the radix path needs room for the key ranges of the partitioned segments
+    assert _segws(n, [0], [n], algo=1)[1] > _ws(n, 2, 1)[1]
+    # level-1-only mode is meaningless for many arrays: rejected before any HIP call
+    L = ips.lib()
+    segs, nseg = ips.segment_array([0], [100])
+    p = ips.make_params(flags=ips.FLAG_LEVEL1_ONLY)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ips_sort_segments(ctypes.c_void_p(0x10), fake, 100, 2, 0, segs, nseg, fake, 1 << 20,
+                               ctypes.byref(p), None) == -1
+    assert L.ips_sort_segments(None, fake, 100, 2, 0, segs, nseg, fake, 1 << 20, None, None) == -1
