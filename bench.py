@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -41,11 +43,21 @@ def main() -> int:
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-radix", action="store_true", help="skip the radix-path measurement")
+    ap.add_argument("--workload", default="sort", choices=["sort", "batch", "serve"],
+                    help="sort: one 2^28-key array (default); batch: 4096 arrays of 2^8..2^22 keys; "
+                         "serve: a Poisson trace of mixed-type requests of 2^10..2^26 elements")
+    ap.add_argument("--arrays", type=int, default=4096, help="batch: number of arrays")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sort runs on a single "
               f"MI355X and has no multi-GPU path.", file=sys.stderr)
         return 2
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -197,6 +209,177 @@ def main() -> int:
         "cpu_baseline": cpu,
         "levels": levels,
         "radix": radix,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _seg_sorted_and_sum(t, offs):
+    """Per-segment non-decreasing check (unsigned order) and the sum of the
+    int64 bit patterns (multiset fingerprint), on the device."""
+    import torch
+    v = t ^ (-(1 << 63))
+    ok = v[1:] >= v[:-1]
+    starts = torch.as_tensor(offs, dtype=torch.int64, device=t.device)
+    starts = starts[(starts > 0) & (starts < t.numel())]
+    ok[starts - 1] = True              # boundaries between segments are not compared
+    return bool(ok.all()), int(t.sum())
+
+
+def bench_batch(args) -> int:
+    """4096 u64 arrays with log-uniform sizes in [2^8, 2^22] (distribution per
+    array uniform over Uniform, TwoDup, AlmostSorted), one batched call
+    (ips_sort_segments) against one call per array."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+
+    dev = torch.device("cuda:0")
+    sizes, dists = synth.batch_layout(args.arrays, 8, 22, synth.seed_for(4, 0))
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    seeds = synth.stream(synth.seed_for(4, 1), len(sizes))
+    log(f"batch: {len(sizes)} arrays, {total} keys ({total * 8 / 1e9:.2f} GB)")
+    pristine = torch.empty(total, dtype=torch.int64, device=dev)
+    for i, (o, n) in enumerate(zip(offs.tolist(), sizes.tolist())):
+        pristine[o:o + n] = sd.gen_u64(dists[i], n, int(seeds[i]), dev)
+    ref_sum = int(pristine.sum())
+    work = torch.empty_like(pristine)
+    sorter = ips.Sorter(0)
+    segs, nseg = ips.segment_array(offs.tolist(), sizes.tolist())
+    ws = sorter.workspace(ips.segments_workspace_bytes(total, segs, nseg, "u64"))
+    views = [work[o:o + n] for o, n in zip(offs.tolist(), sizes.tolist())]
+    res = {}
+    for mode in ("batched", "per_array"):
+        times = []
+        for step in range(args.warmup + args.steps):
+            work.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "batched":
+                sorter.sort_segments_(work, offs.tolist(), sizes.tolist(), kind="u64", ws=ws)
+            else:
+                for v in views:
+                    sorter.sort_(v, kind="u64", ws=ws)
+            torch.cuda.synchronize()
+            if step >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        ok, s = _seg_sorted_and_sum(work, offs.tolist())
+        assert ok and s == ref_sum, f"{mode}: output not sorted per array or multiset changed"
+        ms = 1e3 * float(np.mean(times))
+        res[mode] = {"ms_per_step": round(ms, 3), "Gkeys_per_s": round(total / (ms * 1e-3) / 1e9, 3)}
+        log(f"{mode}: {ms:.2f} ms/step, {res[mode]['Gkeys_per_s']:.2f} Gkeys/s")
+    out = {
+        "metric": f"Gkeys/s, {len(sizes)} u64 arrays of 2^8..2^22 keys sorted in one batched call",
+        "value": res["batched"]["Gkeys_per_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic: SplitMix64-seeded keys generated on the device, restored before each step (untimed)",
+        "config": {"workload": f"{len(sizes)} u64 arrays, log-uniform sizes in [2^8, 2^22], "
+                               f"Uniform/TwoDup/AlmostSorted", "keys": total},
+        "per_array_calls": res["per_array"],
+        "speedup_vs_per_array": round(res["per_array"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Poisson trace of sort requests (sizes log-uniform in [2^10, 2^26],
+    element type uniform over u32/u64/f64/Pair, distribution uniform over
+    the paper's ten), data resident in HBM at arrival; continuous batching
+    under an HBM budget against one call per request, at offered loads
+    0.5 and 0.8 of the per-request service rate."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+
+    dev = torch.device("cuda:0")
+    N = args.requests
+    x = synth.stream(synth.seed_for(5, 0), 4 * N)
+    u = (x[0::4] >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    sizes = np.floor(2.0 ** (10 + u * 16)).astype(np.int64)
+    kinds_all = ["u32", "u64", "f64", "pair"]
+    kinds = [kinds_all[int(v % np.uint64(4))] for v in x[1::4]]
+    dists = [synth.DISTRIBUTIONS[int(v % np.uint64(10))] for v in x[2::4]]
+    seeds = x[3::4]
+    D = {"u32": 4, "u64": 8, "f64": 8, "pair": 16}
+    tot_bytes = sum(int(n) * D[k] for n, k in zip(sizes, kinds))
+    log(f"serve: {N} requests, {int(sizes.sum())} elements, {tot_bytes / 1e9:.1f} GB")
+
+    def make():
+        return [sd.generate(k, d, int(n), int(s), dev) for k, d, n, s in zip(kinds, dists, sizes, seeds)]
+
+    def fp(ts):
+        return [int(t.view(torch.int64).sum()) if t.dtype != torch.int32 else int(t.to(torch.int64).sum())
+                for t in ts]
+
+    sorter = ips.Sorter(0)
+    budget = int(args.budget_gb * 1e9)
+    tens = make()
+    ref = fp(tens)
+    torch.cuda.synchronize()
+    # Service time of each request alone (one call each, back to back).
+    res0, rc = sorter.serve_trace(tens, [0.0] * N, hbm_budget=budget, policy=ips.SERVE_FIFO)
+    if rc != 0:
+        log(f"alone pass failed rc={rc} device_error={hex(ips.lib().ips_last_device_error(sorter._h))}")
+    assert rc == 0
+    svc = np.array([r["done_s"] - r["start_s"] for r in res0])
+    mean_svc = float(svc.mean())
+    log(f"mean service time alone {mean_svc * 1e3:.3f} ms (total {svc.sum():.2f} s)")
+    out_runs = {}
+    for rho in (0.5, 0.8):
+        rate = rho / mean_svc
+        arr = synth.poisson_arrivals(N, rate, synth.seed_for(5, 1))
+        arr -= arr[0]
+        for name, pol in (("batched", ips.SERVE_BATCH), ("per_request", ips.SERVE_FIFO)):
+            del tens
+            tens = make()
+            torch.cuda.synchronize()
+            res, rc = sorter.serve_trace(tens, arr, hbm_budget=budget, policy=pol)
+            torch.cuda.synchronize()
+            if rc != 0:
+                bad = [(i, kinds[i], dists[i], int(sizes[i]), r["status"], r["batch"], hex(r["detail"]))
+                       for i, r in enumerate(res) if r["status"] != 0]
+                fb = {r["batch"] for r in res if r["status"] != 0}
+                for b in sorted(fb)[:2]:
+                    log(f"  batch {b}: " + str([(i, kinds[i], dists[i], int(sizes[i]))
+                                                for i, r in enumerate(res) if r["batch"] == b]))
+                log(f"serve failed rc={rc} device_error={hex(ips.lib().ips_last_device_error(sorter._h))} "
+                    f"hip={ips.lib().ips_last_hip_error(sorter._h)} failing={bad[:8]}")
+            assert rc == 0, rc
+            assert fp(tens) == ref, "multiset changed"
+            for t, k in zip(tens[:: max(1, N // 64)], kinds[:: max(1, N // 64)]):
+                v = t[:, 0] if k == "pair" else t
+                if k == "f64":
+                    assert bool((v[1:] >= v[:-1]).all())
+                else:
+                    w = v.to(torch.int64) ^ (-(1 << 63)) if k != "u32" else v.to(torch.int64) & 0xFFFFFFFF
+                    assert bool((w[1:] >= w[:-1]).all())
+            lat = np.array([r["done_s"] - a for r, a in zip(res, arr)])
+            span = max(r["done_s"] for r in res)
+            key = f"rho{rho}_{name}"
+            out_runs[key] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                             "Gelems_per_s": round(int(sizes.sum()) / span / 1e9, 3),
+                             "batches": len({r["batch"] for r in res})}
+            log(f"{key}: {out_runs[key]}")
+    best = out_runs["rho0.8_batched"]
+    out = {
+        "metric": "p99 latency (ms) of a Poisson sort-request trace at offered load 0.8, continuous batching",
+        "value": best["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": best["p99_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed (u32, u64, f64, pair)",
+        "data": "synthetic: device-generated requests resident in HBM at arrival",
+        "config": {"workload": f"{N} requests, log-uniform sizes in [2^10, 2^26], types u32/u64/f64/pair, "
+                               f"ten distributions, HBM budget {args.budget_gb} GB",
+                   "mean_service_alone_ms": round(mean_svc * 1e3, 4)},
+        "runs": out_runs,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -169,14 +169,82 @@ int ips_segments_workspace_bytes(uint64_t n_total, const ips_segment* segs,
  * non-overlapping segments (read during the call only); elements outside
  * every segment are left unchanged.  All segments' partitioning steps of one
  * recursion level run in shared launches (Section 4.2 breadth first);
- * segments no larger than the LDS tier are sorted in one launch.  There is
- * no sorted-input detection per segment.  IPS_FLAG_LEVEL1_ONLY is rejected.
+ * segments no larger than the LDS tier are sorted in one launch.  Segments
+ * larger than the LDS tier first get the sorted / reverse-sorted detection
+ * of Section 6 (one batched scan; unless IPS_FLAG_NO_SORTED_CHECK): sorted
+ * ones are left as they are, reverse-sorted ones are reversed in place.
+ * IPS_FLAG_LEVEL1_ONLY is rejected.
  * The workspace must hold ips_segments_workspace_bytes(...) bytes.  Errors:
  * as ips_sort_keys, plus IPS_E_INVALID_ARG for bad segments. */
 int ips_sort_segments(ips_ctx* ctx, void* d_data, uint64_t n_total,
                       int elem_type, int algo, const ips_segment* segs,
                       uint32_t nseg, void* d_ws, size_t ws_bytes,
                       const ips_params* params, void* stream);
+
+/* Workspace bytes of ips_sort_batch for the given requests (device
+ * pointers d_ptrs[i] of ns[i] elements each).  Pure host computation. */
+int ips_batch_workspace_bytes(void* const* d_ptrs, const uint64_t* ns,
+                              uint32_t count, int elem_type, int algo,
+                              const ips_params* params, size_t* out_bytes);
+
+/* Sort `count` arrays in separate device buffers (d_ptrs[i], ns[i]
+ * elements of elem_type each, non-overlapping; HOST arrays read during the
+ * call) in place, as ips_sort_segments does for segments of one array:
+ * arrays whose addresses are congruent modulo the element size become
+ * segments of one batched call (one call for 4/8/16-byte elements in
+ * 256-byte aligned buffers).  Errors: as ips_sort_segments, plus
+ * IPS_E_MISALIGNED for a misaligned pointer. */
+int ips_sort_batch(ips_ctx* ctx, void* const* d_ptrs, const uint64_t* ns,
+                   uint32_t count, int elem_type, int algo, void* d_ws,
+                   size_t ws_bytes, const ips_params* params, void* stream);
+
+/* Serving: replay of an arrival trace of sort requests (no paper passage;
+ * built on the batched sort).  A request's data is in device memory at
+ * d_data when it arrives; arrival_s is its arrival time in seconds after
+ * the replay starts.  The scheduler admits waiting requests in arrival
+ * order while the admitted data plus the workspace of the round's largest
+ * batch stays within hbm_budget bytes (and the workspace within ws_bytes),
+ * then sorts the round's requests with one ips_sort_batch call per (type,
+ * algorithm) and starts the next round with everything that arrived
+ * meanwhile (continuous batching at round granularity).  Policy
+ * IPS_SERVE_FIFO instead sorts one request per call in arrival order (the
+ * comparison baseline).  Outputs per request: start_s and done_s (seconds
+ * after the replay start when its call was issued and returned), status
+ * (IPS_OK, IPS_E_WORKSPACE when the request alone exceeds the budget or
+ * the workspace, or the call's error) and the index of its batch. */
+#define IPS_SERVE_BATCH 0u
+#define IPS_SERVE_FIFO 1u
+typedef struct {
+  void* d_data;
+  uint64_t n;
+  int32_t elem_type, algo;
+  double arrival_s;
+  double start_s, done_s;   /* out */
+  int32_t status;           /* out */
+  uint32_t batch;           /* out */
+  int32_t detail;           /* out: on IPS_E_DEVICE / IPS_E_HIP, ips_last_device_error /
+                               ips_last_hip_error right after the failing call */
+  int32_t pad;
+} ips_request;
+
+typedef struct {
+  uint64_t hbm_budget;   /* bytes of request data plus workspace in flight */
+  uint32_t policy;       /* IPS_SERVE_BATCH or IPS_SERVE_FIFO */
+  uint32_t max_batch;    /* requests per round at most (0: no limit) */
+} ips_serve_config;
+
+/* Workspace bytes that any round of ips_serve_trace over these requests
+ * can need under cfg->hbm_budget.  Pure host computation. */
+int ips_serve_workspace_bytes(const ips_request* reqs, uint32_t nreq,
+                              const ips_serve_config* cfg,
+                              const ips_params* params, size_t* out_bytes);
+
+/* Replays the trace (blocking; returns when every request is finished).
+ * Returns IPS_OK, or the first error any request got (the others are
+ * still served). */
+int ips_serve_trace(ips_ctx* ctx, ips_request* reqs, uint32_t nreq,
+                    const ips_serve_config* cfg, void* d_ws, size_t ws_bytes,
+                    const ips_params* params, void* stream);
 
 /* Description of the root partitioning step of the last sort on `ctx`
  * (Section 4.1).  For IPS_SAMPLESORT: alpha, k_prime (adaptive k), m (sample

@@ -40,9 +40,12 @@ PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags",
           "cleanup_a", "cleanup_b", "lds_sort", "reverse"]
 
 EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_get_root_info",
-           "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
-           "ips_status_string", "ips_abi_version"]
+           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments",
+           "ips_batch_workspace_bytes", "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace",
+           "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
+           "ips_last_device_error", "ips_status_string", "ips_abi_version"]
+SERVE_BATCH = 0
+SERVE_FIFO = 1
 
 
 class Params(ctypes.Structure):
@@ -71,6 +74,17 @@ class Segment(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_uint64), ("n", ctypes.c_uint64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("d_data", ctypes.c_void_p), ("n", ctypes.c_uint64), ("elem_type", ctypes.c_int32),
+                ("algo", ctypes.c_int32), ("arrival_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("status", ctypes.c_int32), ("batch", ctypes.c_uint32),
+                ("detail", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("policy", ctypes.c_uint32), ("max_batch", ctypes.c_uint32)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("ms", (ctypes.c_double * len(PHASES)) * (MAX_LEVELS + 1)),
@@ -88,6 +102,14 @@ _lib.ips_segments_workspace_bytes.argtypes = [_u64, ctypes.POINTER(Segment), cty
                                               ctypes.POINTER(Params), ctypes.POINTER(_sz)]
 _lib.ips_sort_segments.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Segment), ctypes.c_uint32,
                                    _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_batch_workspace_bytes.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_u64), ctypes.c_uint32, _i32,
+                                           _i32, ctypes.POINTER(Params), ctypes.POINTER(_sz)]
+_lib.ips_sort_batch.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64), ctypes.c_uint32, _i32, _i32,
+                                _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_serve_workspace_bytes.argtypes = [ctypes.POINTER(Request), ctypes.c_uint32, ctypes.POINTER(ServeConfig),
+                                           ctypes.POINTER(Params), ctypes.POINTER(_sz)]
+_lib.ips_serve_trace.argtypes = [_vp, ctypes.POINTER(Request), ctypes.c_uint32, ctypes.POINTER(ServeConfig),
+                                 _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_get_root_info.argtypes = [_vp, ctypes.POINTER(RootInfo)]
 _lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.ips_get_profile.argtypes = [_vp, ctypes.POINTER(Profile)]
@@ -96,7 +118,8 @@ _lib.ips_last_device_error.argtypes = [_vp]
 _lib.ips_status_string.argtypes = [_i32]
 _lib.ips_status_string.restype = ctypes.c_char_p
 for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
-           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_get_root_info",
+           "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_batch_workspace_bytes",
+           "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace", "ips_get_root_info",
            "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
            "ips_abi_version"):
     getattr(_lib, _f).restype = _i32
@@ -241,6 +264,66 @@ class Sorter:
             raise IpsError(rc, "ips_sort_segments", f"(hip={_lib.ips_last_hip_error(self._h)}, "
                                                     f"device={hex(_lib.ips_last_device_error(self._h))})")
         return t
+
+    def sort_batch_(self, tensors, algo: str = "samplesort", params: Params | None = None, kind: str | None = None,
+                    stream=None, ws=None):
+        """Sort every tensor of the list (same element kind, separate buffers)
+        in place with one batched call."""
+        import torch
+        if not tensors:
+            return tensors
+        kind = kind or kind_of(tensors[0])
+        for t in tensors:
+            if not t.is_cuda or not t.is_contiguous() or kind_of(t) != kind:
+                raise ValueError("tensors must be contiguous GPU tensors of one element kind")
+        cnt = len(tensors)
+        ptrs = (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in tensors])
+        ns = (ctypes.c_uint64 * cnt)(*[t.shape[0] for t in tensors])
+        pp = ctypes.byref(params) if params is not None else None
+        out = ctypes.c_size_t(0)
+        rc = _lib.ips_batch_workspace_bytes(ptrs, ns, cnt, TYPES[kind], ALGOS[algo], pp, ctypes.byref(out))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_batch_workspace_bytes")
+        ws = ws if ws is not None else self.workspace(out.value)
+        if stream is None:
+            stream = torch.cuda.current_stream(tensors[0].device)
+        rc = _lib.ips_sort_batch(self._h, ptrs, ns, cnt, TYPES[kind], ALGOS[algo], ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), pp, ctypes.c_void_p(stream.cuda_stream))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_sort_batch", f"(hip={_lib.ips_last_hip_error(self._h)}, "
+                                                 f"device={hex(_lib.ips_last_device_error(self._h))})")
+        return tensors
+
+    def serve_trace(self, tensors, arrivals, algos=None, hbm_budget: int = 64 << 30, policy: int = SERVE_BATCH,
+                    max_batch: int = 0, params: Params | None = None, stream=None):
+        """Replay an arrival trace: request i is tensor i (sorted in place),
+        arriving arrivals[i] seconds after the start.  Returns the list of
+        per-request dicts (start_s, done_s, status, batch) and the return code."""
+        import torch
+        cnt = len(tensors)
+        reqs = (Request * max(1, cnt))()
+        for i, t in enumerate(tensors):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous GPU tensors")
+            r = reqs[i]
+            r.d_data, r.n = t.data_ptr(), t.shape[0]
+            r.elem_type = TYPES[kind_of(t)]
+            r.algo = ALGOS[algos[i] if algos else "samplesort"]
+            r.arrival_s = float(arrivals[i])
+        cfg = ServeConfig(hbm_budget, policy, max_batch)
+        pp = ctypes.byref(params) if params is not None else None
+        out = ctypes.c_size_t(0)
+        rc = _lib.ips_serve_workspace_bytes(reqs, cnt, ctypes.byref(cfg), pp, ctypes.byref(out))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_serve_workspace_bytes")
+        ws = self.workspace(out.value)
+        if stream is None:
+            stream = torch.cuda.current_stream(tensors[0].device if cnt else None)
+        rc = _lib.ips_serve_trace(self._h, reqs, cnt, ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel(), pp, ctypes.c_void_p(stream.cuda_stream))
+        res = [{"start_s": reqs[i].start_s, "done_s": reqs[i].done_s, "status": reqs[i].status,
+                "batch": reqs[i].batch, "detail": reqs[i].detail} for i in range(cnt)]
+        return res, rc
 
     def root_info(self) -> RootInfo:
         ri = RootInfo()

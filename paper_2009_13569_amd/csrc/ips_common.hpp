@@ -91,6 +91,13 @@ struct LTask {
 struct SegItem {
   uint64_t l;
   uint32_t n, seg;
+  uint32_t first, pad;   // first: the chunk starts its segment
+};
+// A chunk of the in-place reversal of a segment [l, l + len): the pairs
+// (i, len - 1 - i) for i in [c0, c0 + cn).
+struct RevItem {
+  uint64_t l, len, c0;
+  uint32_t cn, pad;
 };
 constexpr uint32_t SEG_CHUNK = 65536;   // elements per chunk
 
@@ -125,6 +132,7 @@ struct BatchArgs {
   uint32_t* p_c;              // end block (exclusive) of the piece
   int32_t* p_rinit;           // last unprocessed block at the start (a-1: none)
   uint32_t* p_cum;            // unprocessed blocks of the earlier pieces
+  uint32_t* p_fcnt;           // full pieces of the mask chunk starting at this piece
   uint32_t* t_npieces;        // [task] number of pieces
   uint32_t* t_unproc;         // [task] unprocessed blocks in total
   uint32_t gbuf;              // buffer blocks in the slots instead of LDS

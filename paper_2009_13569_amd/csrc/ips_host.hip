@@ -167,7 +167,7 @@ struct Layout {
 enum Region {
   R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
   R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
-  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_COUNT
+  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_COUNT
 };
 
 void plan(uint64_t n, const Cfg& c, Layout* L) {
@@ -220,6 +220,7 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_PC] = L->PB * 4;
   sz[R_PR] = L->PB * 4;
   sz[R_PCUM] = L->PB * 4;
+  sz[R_PFCNT] = L->PB * 4;
   sz[R_TNP] = (size_t)L->TB * 4;
   sz[R_TUP] = (size_t)L->TB * 4;
   sz[R_LT] = (size_t)L->LTB * sizeof(LTask);
@@ -478,23 +479,25 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   for (uint32_t t = 0; t < T; ++t) max_nb_batch = std::max(max_nb_batch, nbv[t]);
   // Stripe length S: the batch's elements spread over WG_TARGET workgroups
   // (the largest stripe bounds the phase), doubled while the stripes would
-  // exceed the batch's workgroup budget.
-  (void)level_elems;
-  uint64_t S = 1, batch_elems = 0;
+  // exceed the batch's workgroup or buffer-slot budget.  At the level's
+  // stripe length (which the batch was packed for) both budgets hold.
+  uint64_t batch_elems = 0;
   for (uint32_t t = 0; t < T; ++t) batch_elems += bt[t].n;
-  S = std::max<uint64_t>(1, batch_elems / WG_TARGET);
-  for (;;) {
-    uint64_t wsum = 0;
+  const uint64_t S_level = std::max<uint64_t>(1, level_elems / WG_TARGET);
+  uint64_t S = std::max<uint64_t>(1, batch_elems / WG_TARGET);
+  for (; S < S_level; S *= 2) {
+    uint64_t wsum = 0, ssum = 0;
     for (uint32_t t = 0; t < T; ++t) {
       uint64_t W = (bt[t].n + S - 1) / S;
       W = std::min<uint64_t>(W, std::max<uint64_t>(1, bt[t].n / (4ull * nbv[t] * bvec[t])));
       W = std::min<uint64_t>(W, NBv[t]);
       W = std::min<uint64_t>(W, WG_TARGET);
       wsum += W;
+      ssum += W * (((uint64_t)nbv[t] * bvec[t] * c.D + 255) & ~255ull);
     }
-    if (wsum <= r.L.WB) break;
-    S *= 2;
+    if (wsum <= r.L.WB && ssum <= r.L.SB) break;
   }
+  S = std::min(S, S_level);
   for (uint32_t t = 0; t < T; ++t) {
     PTask& p = r.h_tasks[t];
     const uint32_t b = bvec[t], nb = nbv[t], NB = NBv[t];
@@ -658,19 +661,39 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   return launch_lds_tasks(r, lt, bt[0].level);
 }
 
-// Extra workspace of a segmented radix call: chunk descriptors of the
-// segments that are partitioned and their key ranges.
+// Extra areas of a segmented call, in the workspace and in pinned host
+// memory alike: chunk descriptors of the partitioned segments, their order
+// flags, their radix key ranges and the reversal chunks.
+struct SegAreas {
+  uint64_t items_ub, rev_ub;
+  size_t o_items, o_flags, o_min, o_max, o_rev, total;
+};
+
+SegAreas seg_areas(const Cfg& c, uint64_t n, uint64_t nseg) {
+  SegAreas s;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  s.items_ub = n / SEG_CHUNK + nseg;
+  s.rev_ub = n / (2 * SEG_CHUNK) + nseg;
+  s.o_items = 0;
+  s.o_flags = al(s.items_ub * sizeof(SegItem));
+  s.o_min = s.o_flags + al(nseg * 8);
+  s.o_max = s.o_min + (c.radix ? al(nseg * 8) : 0);
+  s.o_rev = s.o_max + (c.radix ? al(nseg * 8) : 0);
+  s.total = s.o_rev + al(s.rev_ub * sizeof(RevItem));
+  return s;
+}
+
 size_t seg_extra_bytes(const Cfg& c, uint64_t n_total, uint64_t nseg) {
-  if (!c.radix) return 0;
-  const uint64_t items = n_total / SEG_CHUNK + nseg;
-  return ((items * sizeof(SegItem) + 255) & ~255ull) + 2 * ((nseg * 8 + 255) & ~255ull);
+  return nseg ? seg_areas(c, n_total, nseg).total : 0;
 }
 
 // Validation, workspace plan, pinned staging and device views shared by
-// every sort entry point.  `extra_pin` bytes of pinned memory are reserved
-// after the common staging areas (returned in *extra).
-int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, int type, int algo, void* ws,
-              size_t ws_bytes, size_t ws_extra, const ips_params* params, void* stream,
+// every sort entry point.  n is the length of the data array, n_plan the
+// number of elements to be sorted (the workspace is planned for n_plan).
+// `extra_pin` bytes of pinned memory are reserved after the common staging
+// areas (returned in *extra).
+int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int type, int algo,
+              void* ws, size_t ws_bytes, size_t ws_extra, const ips_params* params, void* stream,
               size_t extra_pin, uint8_t** extra) {
   if (!ctx) return IPS_E_INVALID_ARG;
   std::memset(&r.a, 0, sizeof(r.a));
@@ -689,8 +712,8 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, int type, int algo, voi
   ctx->last_dev = 0;
   r.ctx = ctx;
   r.n = n;
-  if (n < 2) return IPS_OK;
-  plan(n, r.c, &r.L);
+  if (n < 2 || n_plan < 2) return IPS_OK;
+  plan(n_plan, r.c, &r.L);
   if (!ws) return IPS_E_INVALID_ARG;
   if (ws_bytes < r.L.total + ws_extra) return IPS_E_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return IPS_E_MISALIGNED;
@@ -746,6 +769,7 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, int type, int algo, voi
   a.p_c = wsp<uint32_t>(r, R_PC);
   a.p_rinit = wsp<int32_t>(r, R_PR);
   a.p_cum = wsp<uint32_t>(r, R_PCUM);
+  a.p_fcnt = wsp<uint32_t>(r, R_PFCNT);
   a.t_npieces = wsp<uint32_t>(r, R_TNP);
   a.t_unproc = wsp<uint32_t>(r, R_TUP);
   a.gbuf = r.c.gbuf ? 1 : 0;
@@ -818,7 +842,7 @@ int level_loop(Run& r, std::vector<HTask> cur, const std::vector<LTask>& lds_roo
 int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
               const ips_params* params, void* stream) {
   Run r;
-  int rc = setup_run(ctx, r, d, n, type, algo, ws, ws_bytes, 0, params, stream, 0, nullptr);
+  int rc = setup_run(ctx, r, d, n, n, type, algo, ws, ws_bytes, 0, params, stream, 0, nullptr);
   if (rc || n < 2) return rc;
   BatchArgs& a = r.a;
   // Sorted and reverse-sorted inputs (Section 6).
@@ -879,6 +903,25 @@ int check_segments(const ips_segment* segs, uint32_t nseg, uint64_t n_total, uin
   return IPS_OK;
 }
 
+// Workspace of a segmented call: planned for the sum of the segment
+// lengths, plus the radix key-range area of the partitioned segments.
+int segments_ws(uint64_t sum, const ips_segment* segs, uint32_t nseg, int type, int algo,
+                const ips_params* params, size_t* out) {
+  *out = 0;
+  Cfg c;
+  if (int e = make_cfg(sum, type, algo, params, &c)) return e;
+  if (sum >= (1ull << 31) * (uint64_t)block_elems(c, max_nb(c))) return IPS_E_TOO_LARGE;
+  if (sum < 2) return IPS_OK;
+  Layout L;
+  plan(sum, c, &L);
+  uint64_t big = 0, big_elems = 0;
+  for (uint32_t i = 0; i < nseg; ++i)
+    if (segs[i].n > c.cap) { ++big; big_elems += segs[i].n; }
+  *out = L.total + seg_extra_bytes(c, big_elems, big);
+  return IPS_OK;
+}
+
+// Sorts the (validated, non-overlapping) segments of the array at d.
 int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
                   const ips_segment* segs, uint32_t nseg, void* ws, size_t ws_bytes,
                   const ips_params* params, void* stream) {
@@ -887,18 +930,18 @@ int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
   uint64_t sum = 0;
   if (int e = check_segments(segs, nseg, n_total, &sum)) return e;
   Cfg c0;
-  if (int e = make_cfg(n_total, type, algo, params, &c0)) return e;
+  if (int e = make_cfg(sum, type, algo, params, &c0)) return e;
   // Segments that are partitioned (larger than the LDS tier).
   std::vector<uint32_t> big;
   uint64_t big_elems = 0;
   for (uint32_t i = 0; i < nseg; ++i)
     if (segs[i].n > c0.cap) { big.push_back(i); big_elems += segs[i].n; }
-  const uint64_t items_ub = big_elems / SEG_CHUNK + big.size();
+  const SegAreas sa = seg_areas(c0, big_elems, big.size());
   const size_t extra = seg_extra_bytes(c0, big_elems, big.size());
-  const size_t pin_extra = c0.radix ? items_ub * sizeof(SegItem) + big.size() * 16 : 0;
   Run r;
   uint8_t* hx = nullptr;
-  int rc = setup_run(ctx, r, d, n_total, type, algo, ws, ws_bytes, extra, params, stream, pin_extra, &hx);
+  int rc = setup_run(ctx, r, d, n_total, sum, type, algo, ws, ws_bytes, extra, params, stream,
+                     big.empty() ? 0 : sa.total, &hx);
   if (rc || n_total < 2 || sum < 2) return rc;
   std::vector<HTask> roots;
   std::vector<LTask> lt;
@@ -910,47 +953,174 @@ int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
     q.pad = 0;
     lt.push_back(q);
   }
-  if (r.c.radix && !big.empty()) {
-    // Key range of every partitioned segment.
-    SegItem* h_items = reinterpret_cast<SegItem*>(hx);
-    uint64_t* h_mm = reinterpret_cast<uint64_t*>(hx + ((items_ub * sizeof(SegItem) + 15) & ~15ull));
+  const bool check = !(r.c.flags & IPS_FLAG_NO_SORTED_CHECK);
+  std::vector<uint64_t> mn(big.size(), 0), mx(big.size(), 1);
+  std::vector<char> finished(big.size(), 0);
+  const uint32_t nbig = (uint32_t)big.size();
+  if (nbig && (check || r.c.radix)) {
+    // Order flags and key ranges of the partitioned segments.
     uint8_t* wx = r.ws + r.L.total;
-    SegItem* d_items = reinterpret_cast<SegItem*>(wx);
-    uint64_t* d_min = reinterpret_cast<uint64_t*>(wx + ((items_ub * sizeof(SegItem) + 255) & ~255ull));
-    uint64_t* d_max = d_min + ((big.size() * 8 + 255) & ~255ull) / 8;
+    SegItem* h_items = reinterpret_cast<SegItem*>(hx + sa.o_items);
+    uint32_t* h_flags = reinterpret_cast<uint32_t*>(hx + sa.o_flags);
+    uint64_t* h_min = reinterpret_cast<uint64_t*>(hx + sa.o_min);
+    uint64_t* h_max = reinterpret_cast<uint64_t*>(hx + sa.o_max);
+    SegItem* d_items = reinterpret_cast<SegItem*>(wx + sa.o_items);
+    uint32_t* d_flags = reinterpret_cast<uint32_t*>(wx + sa.o_flags);
+    uint64_t* d_min = reinterpret_cast<uint64_t*>(wx + sa.o_min);
+    uint64_t* d_max = reinterpret_cast<uint64_t*>(wx + sa.o_max);
     uint64_t ni = 0;
-    for (uint32_t q = 0; q < big.size(); ++q) {
+    for (uint32_t q = 0; q < nbig; ++q) {
       const ips_segment& sg = segs[big[q]];
       for (uint64_t o = 0; o < sg.n; o += SEG_CHUNK) {
         SegItem it;
         it.l = sg.offset + o;
         it.n = (uint32_t)std::min<uint64_t>(SEG_CHUNK, sg.n - o);
         it.seg = q;
+        it.first = o == 0 ? 1u : 0u;
+        it.pad = 0;
         h_items[ni++] = it;
       }
     }
     HIPCHK(ctx, hipMemcpyAsync(d_items, h_items, ni * sizeof(SegItem), hipMemcpyHostToDevice, r.st));
-    HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_min), 2 * big.size(), 0xFFFFFFFFu, r.st));
-    HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_max), 2 * big.size(), 0u, r.st));
-    HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, big_elems, [&] {
-             return r.c.L->seg_minmax(d_items, (uint32_t)ni, r.data, d_min, d_max, r.st);
-           }));
-    HIPCHK(ctx, hipMemcpyAsync(h_mm, d_min, big.size() * 8, hipMemcpyDeviceToHost, r.st));
-    HIPCHK(ctx, hipMemcpyAsync(h_mm + big.size(), d_max, big.size() * 8, hipMemcpyDeviceToHost, r.st));
-    if (int e = read_ctrl(r)) return e;
-    for (uint32_t q = 0; q < big.size(); ++q) {
-      HTask t;
-      if (make_root(r.c, segs[big[q]].offset, segs[big[q]].n, h_mm[q], h_mm[big.size() + q], &t))
-        roots.push_back(t);
+    if (check) {
+      HIPCHK(ctx, launch_fill32(d_flags, 2 * nbig, 0u, r.st));
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_SORTED_CHECK, big_elems, [&] {
+               return r.c.L->seg_order(d_items, (uint32_t)ni, r.data, d_flags, r.st);
+             }));
+      HIPCHK(ctx, hipMemcpyAsync(h_flags, d_flags, 2 * nbig * 4, hipMemcpyDeviceToHost, r.st));
     }
-  } else {
-    for (uint32_t q = 0; q < big.size(); ++q) {
-      HTask t;
-      make_root(r.c, segs[big[q]].offset, segs[big[q]].n, 0, 1, &t);
-      roots.push_back(t);
+    if (r.c.radix) {
+      HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_min), 2 * nbig, 0xFFFFFFFFu, r.st));
+      HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(d_max), 2 * nbig, 0u, r.st));
+      HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_MINMAX, big_elems, [&] {
+               return r.c.L->seg_minmax(d_items, (uint32_t)ni, r.data, d_min, d_max, r.st);
+             }));
+      HIPCHK(ctx, hipMemcpyAsync(h_min, d_min, nbig * 8, hipMemcpyDeviceToHost, r.st));
+      HIPCHK(ctx, hipMemcpyAsync(h_max, d_max, nbig * 8, hipMemcpyDeviceToHost, r.st));
+    }
+    if (int e = read_ctrl(r)) return e;
+    if (r.c.radix)
+      for (uint32_t q = 0; q < nbig; ++q) { mn[q] = h_min[q]; mx[q] = h_max[q]; }
+    if (check) {
+      // Sorted segments are done; reverse-sorted ones are reversed in place.
+      RevItem* h_rev = reinterpret_cast<RevItem*>(hx + sa.o_rev);
+      RevItem* d_rev = reinterpret_cast<RevItem*>(wx + sa.o_rev);
+      uint64_t nr = 0;
+      for (uint32_t q = 0; q < nbig; ++q) {
+        if (!h_flags[2 * q]) { finished[q] = 1; continue; }
+        if (h_flags[2 * q + 1]) continue;
+        finished[q] = 1;
+        const ips_segment& sg = segs[big[q]];
+        for (uint64_t o = 0; o < sg.n / 2; o += SEG_CHUNK) {
+          RevItem it;
+          it.l = sg.offset;
+          it.len = sg.n;
+          it.c0 = o;
+          it.cn = (uint32_t)std::min<uint64_t>(SEG_CHUNK, sg.n / 2 - o);
+          it.pad = 0;
+          h_rev[nr++] = it;
+        }
+      }
+      if (nr) {
+        HIPCHK(ctx, hipMemcpyAsync(d_rev, h_rev, nr * sizeof(RevItem), hipMemcpyHostToDevice, r.st));
+        HIPCHK(ctx, timed(ctx, r.st, IPS_MAX_LEVELS, IPS_PH_REVERSE, big_elems, [&] {
+                 return r.c.L->seg_reverse(d_rev, (uint32_t)nr, r.data, r.st);
+               }));
+      }
     }
   }
+  for (uint32_t q = 0; q < nbig; ++q) {
+    HTask t;
+    if (finished[q]) continue;
+    if (make_root(r.c, segs[big[q]].offset, segs[big[q]].n, mn[q], mx[q], &t)) roots.push_back(t);
+  }
   return level_loop(r, roots, lt, false);
+}
+
+// Requests in separate device buffers: those whose addresses are congruent
+// modulo the element size share a base pointer and become segments of one
+// call.  Each group's workspace is planned separately; the largest is
+// returned.
+struct PtrGroup {
+  uintptr_t base;
+  uint64_t span;
+  std::vector<ips_segment> segs;
+};
+
+int group_batch(void* const* ptrs, const uint64_t* ns, uint32_t count, int type,
+                std::vector<PtrGroup>* groups) {
+  groups->clear();
+  if (count && (!ptrs || !ns)) return IPS_E_INVALID_ARG;
+  const uint32_t D = elem_bytes(type);
+  if (!D) return IPS_E_INVALID_ARG;
+  const uint32_t align = (type == 1 || type == 5) ? 4 : 8;
+  std::vector<uint32_t> ord;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (ns[i] == 0) continue;
+    if (!ptrs[i]) return IPS_E_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(ptrs[i]) % align) return IPS_E_MISALIGNED;
+    if (ns[i] > (~(uintptr_t)0 - reinterpret_cast<uintptr_t>(ptrs[i])) / D) return IPS_E_INVALID_ARG;
+    ord.push_back(i);
+  }
+  // No two buffers may overlap (byte ranges, over all groups).
+  std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+    return reinterpret_cast<uintptr_t>(ptrs[x]) < reinterpret_cast<uintptr_t>(ptrs[y]);
+  });
+  for (uint32_t q = 1; q < ord.size(); ++q) {
+    const uintptr_t e = reinterpret_cast<uintptr_t>(ptrs[ord[q - 1]]) + ns[ord[q - 1]] * D;
+    if (e > reinterpret_cast<uintptr_t>(ptrs[ord[q]])) return IPS_E_INVALID_ARG;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+    return reinterpret_cast<uintptr_t>(ptrs[x]) % D < reinterpret_cast<uintptr_t>(ptrs[y]) % D;
+  });
+  for (uint32_t q = 0; q < ord.size(); ++q) {
+    const uintptr_t p = reinterpret_cast<uintptr_t>(ptrs[ord[q]]);
+    if (groups->empty() || groups->back().base % D != p % D) {
+      PtrGroup g;
+      g.base = p;
+      g.span = 0;
+      groups->push_back(g);
+    }
+    PtrGroup& g = groups->back();
+    ips_segment sg;
+    sg.offset = (p - g.base) / D;
+    sg.n = ns[ord[q]];
+    g.segs.push_back(sg);
+    g.span = sg.offset + sg.n;
+  }
+  return IPS_OK;
+}
+
+int batch_ws(void* const* ptrs, const uint64_t* ns, uint32_t count, int type, int algo,
+             const ips_params* params, size_t* out) {
+  *out = 0;
+  std::vector<PtrGroup> groups;
+  if (int e = group_batch(ptrs, ns, count, type, &groups)) return e;
+  Cfg c;
+  if (int e = make_cfg(0, type, algo, params, &c)) return e;
+  for (const PtrGroup& g : groups) {
+    uint64_t sum = 0;
+    for (const ips_segment& sg : g.segs) sum += sg.n;
+    size_t b = 0;
+    if (int e = segments_ws(sum, g.segs.data(), (uint32_t)g.segs.size(), type, algo, params, &b)) return e;
+    *out = std::max(*out, b);
+  }
+  return IPS_OK;
+}
+
+int batch_impl(ips_ctx* ctx, void* const* ptrs, const uint64_t* ns, uint32_t count, int type,
+               int algo, void* ws, size_t ws_bytes, const ips_params* params, void* stream) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  std::vector<PtrGroup> groups;
+  if (int e = group_batch(ptrs, ns, count, type, &groups)) return e;
+  Cfg c;
+  if (int e = make_cfg(0, type, algo, params, &c)) return e;
+  for (const PtrGroup& g : groups) {
+    if (int e = segments_impl(ctx, reinterpret_cast<void*>(g.base), g.span, type, algo, g.segs.data(),
+                              (uint32_t)g.segs.size(), ws, ws_bytes, params, stream))
+      return e;
+  }
+  return IPS_OK;
 }
 
 }  // namespace
@@ -1031,15 +1201,31 @@ int ips_segments_workspace_bytes(uint64_t n_total, const ips_segment* segs, uint
   *out_bytes = 0;
   uint64_t sum = 0;
   if (int e = check_segments(segs, nseg, n_total, &sum)) return e;
-  int rc = ips_workspace_bytes(n_total, elem_type, algo, params, out_bytes);
-  if (rc || *out_bytes == 0) return rc;
+  return segments_ws(sum, segs, nseg, elem_type, algo, params, out_bytes);
+}
+
+int ips_batch_workspace_bytes(void* const* d_ptrs, const uint64_t* ns, uint32_t count,
+                              int elem_type, int algo, const ips_params* params,
+                              size_t* out_bytes) {
+  if (!out_bytes) return IPS_E_INVALID_ARG;
+  return batch_ws(d_ptrs, ns, count, elem_type, algo, params, out_bytes);
+}
+
+// Upper bound of the workspace of any batch of nseg segments holding n
+// elements in total (used by the serving scheduler for admission).
+__attribute__((visibility("hidden")))
+size_t ips_internal_ws_bound(uint64_t n, uint64_t nseg, int type, int algo, const ips_params* params) {
   Cfg c;
-  make_cfg(n_total, elem_type, algo, params, &c);
-  uint64_t big = 0, big_elems = 0;
-  for (uint32_t i = 0; i < nseg; ++i)
-    if (segs[i].n > c.cap) { ++big; big_elems += segs[i].n; }
-  *out_bytes += seg_extra_bytes(c, big_elems, big);
-  return IPS_OK;
+  if (make_cfg(n, type, algo, params, &c) != IPS_OK || n < 2) return 0;
+  Layout L;
+  plan(n, c, &L);
+  return L.total + seg_extra_bytes(c, n, nseg);
+}
+
+int ips_sort_batch(ips_ctx* ctx, void* const* d_ptrs, const uint64_t* ns, uint32_t count,
+                   int elem_type, int algo, void* d_ws, size_t ws_bytes, const ips_params* params,
+                   void* stream) {
+  return batch_impl(ctx, d_ptrs, ns, count, elem_type, algo, d_ws, ws_bytes, params, stream);
 }
 
 int ips_sort_segments(ips_ctx* ctx, void* d_data, uint64_t n_total, int elem_type, int algo,

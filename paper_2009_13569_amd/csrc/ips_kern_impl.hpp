@@ -116,11 +116,22 @@ struct LaunchImpl {
       return hipErrorInvalidValue;
     }
   }
+  static hipError_t seg_order(const SegItem* items, uint32_t nitems, const uint32_t* data,
+                              uint32_t* flags, hipStream_t st) {
+    if (!nitems) return hipSuccess;
+    hipLaunchKernelGGL((k_seg_order<T>), dim3(nitems), dim3(256), 0, st, items, data, flags);
+    return hipGetLastError();
+  }
+  static hipError_t seg_reverse(const RevItem* items, uint32_t nitems, uint32_t* data, hipStream_t st) {
+    if (!nitems) return hipSuccess;
+    hipLaunchKernelGGL((k_seg_reverse<T::DW>), dim3(nitems), dim3(256), 0, st, items, data);
+    return hipGetLastError();
+  }
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
         CAP_BIG, CAP_SMALL, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
-        &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax};
+        &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax, &seg_order, &seg_reverse};
     return &t;
   }
 };

@@ -659,6 +659,7 @@ __global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) 
                      a.p_c[p] = place ? c1 : c0;
                      a.p_rinit[p] = ri;
                      a.p_cum[p] = cu;
+                     a.p_fcnt[p] = 0;
                      a.p_word[p] = ((uint64_t)c0 << 32) | (uint64_t)((uint32_t)ri + PTR_BIAS);
                      cu += (uint32_t)(ri - (int32_t)c0 + 1);
                      ++p;
@@ -800,7 +801,7 @@ k_permute(BatchArgs a) {
   uint32_t dat[PERM_RD], tmp[PERM_RD];
 #pragma unroll
   for (int q = 0; q < PERM_RD; ++q) { dat[q] = 0; tmp[q] = 0; }
-  uint32_t dest = 0, probe = 0, wpos = 0, spin = 0, fails = 0;
+  uint32_t dest = 0, probe = 0, wpos = 0, spin = 0, fails = 0, cur_q = 0;
   bool use_mask = false;
 
   auto store_block = [&](uint32_t* dst) {
@@ -829,26 +830,43 @@ k_permute(BatchArgs a) {
           ++src;
         }
       } else if (mode == PLACE) {
-        // A random placement piece of the bucket; after a miss the bucket's
-        // mask of full pieces restricts the choice to pieces with room.
-        // The choice avoids pieces known to be full: the bucket's mask is
-        // read through the cache (it only gains bits, so a stale copy only
-        // costs a miss), and coherently after a miss.
+        // A placement piece of the bucket with room.  The bucket's mask has
+        // one bit per chunk of cs consecutive pieces (cs = 1 for up to 64
+        // pieces); a bit is set once every piece of its chunk is full.  The
+        // first choice is a random piece of a random chunk not known to be
+        // full (mask read through the cache: it only gains bits, so a stale
+        // copy only costs a miss).  After a miss the mask is read
+        // coherently: with cs = 1 a random non-full piece is taken again;
+        // with cs > 1 the search moves on linearly from the missed piece,
+        // skipping full chunks, so it visits every piece with room.
         const uint32_t plb = s_plb[dest], npl = s_npl[dest];
         uint64_t* fm = a.b_full + bb + dest;
-        uint32_t q = npl ? probe % npl : 0;
-        if (npl <= 64) {
-          const uint64_t m = npl == 64 ? ~0ull : ((1ull << npl) - 1);
+        const uint32_t cs = (npl + 63) >> 6;
+        const uint32_t nch = cs ? (npl + cs - 1) / cs : 0;
+        const uint64_t m = nch >= 64 ? ~0ull : ((1ull << nch) - 1);
+        if (npl) {
           const uint64_t seen = use_mask ? at_load64(fm) : *reinterpret_cast<volatile uint64_t*>(fm);
           const uint64_t fr = ~seen & m;
-          if (fr) {
-            uint32_t kth = probe % (uint32_t)__popcll(fr);
-            uint64_t x = fr;
-            for (; kth > 0; --kth) x &= x - 1;
-            q = (uint32_t)__ffsll((long long)x) - 1;
+          if (cs == 1 || !use_mask) {
+            uint32_t ch = probe % nch;
+            if (fr) {
+              uint32_t kth = probe % (uint32_t)__popcll(fr);
+              uint64_t x = fr;
+              for (; kth > 0; --kth) x &= x - 1;
+              ch = (uint32_t)__ffsll((long long)x) - 1;
+            }
+            const uint32_t c0 = ch * cs, clen = min(cs, npl - c0);
+            cur_q = c0 + (cs == 1 ? 0u : (probe >> 7) % clen);
+          } else {
+            cur_q = cur_q + 1 < npl ? cur_q + 1 : 0;
+            const uint32_t ch = cur_q / cs;
+            if (((seen >> ch) & 1ull) && fr) {
+              const uint64_t up = fr & (~0ull << ch);
+              const uint32_t nc = (uint32_t)__ffsll((long long)(up ? up : fr)) - 1;
+              cur_q = nc * cs;
+            }
           }
-        }
-        if (npl) {
+          const uint32_t q = cur_q;
           const uint32_t sr = plb + q;
           // piece metadata loads are issued before the pointer update so that
           // their latencies overlap
@@ -860,9 +878,17 @@ k_permute(BatchArgs a) {
           if (w < cap) {
             r0 = w;
             r1 = (uint32_t)((int32_t)((uint32_t)wv - PTR_BIAS));
-            if (w + 1 == cap && q < 64) atomicOr((unsigned long long*)fm, 1ull << q);
+            if (w + 1 == cap) {            // this placement filled the piece
+              if (cs == 1) {
+                atomicOr((unsigned long long*)fm, 1ull << q);
+              } else {
+                const uint32_t c0 = (q / cs) * cs, clen = min(cs, npl - c0);
+                if (atomicAdd(&a.p_fcnt[pb + plb + c0], 1u) + 1 == clen)
+                  atomicOr((unsigned long long*)fm, 1ull << (q / cs));
+              }
+            }
           } else {
-            if (q < 64) atomicOr((unsigned long long*)fm, 1ull << q);
+            if (cs == 1) atomicOr((unsigned long long*)fm, 1ull << q);
             PSTAT(st_full);
           }
         }
@@ -888,7 +914,10 @@ k_permute(BatchArgs a) {
       if (r0 == NONE) {
         use_mask = true;
         probe = probe * 0x9E3779B1u + 0x7F4A7C15u;
-        if (++fails > 4096) {
+        // A held block always has a slot left in its bucket (a bucket
+        // receives exactly as many blocks as its placement pieces hold), so
+        // the search ends; the bound only stops a broken invariant.
+        if (++fails > 4 * s_npl[dest] + 4096) {
           if (gl == 0) dev_error(a.ctrl, DE_PLACE, tix, dest);
           mode = DONE;
         }
@@ -1193,6 +1222,43 @@ __global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n
     uint64_t* mm = reinterpret_cast<uint64_t*>(ctrl + CTRL_MINMAX);
     atomicMin((unsigned long long*)&mm[0], (unsigned long long)mn);
     atomicMax((unsigned long long*)&mm[1], (unsigned long long)mx);
+  }
+}
+
+// Per-segment order check of a batched call (the sorted-input detection of
+// Section 6 applied to every segment): flags[2 seg] is set on a descent,
+// flags[2 seg + 1] on an ascent.  A chunk compares each element with its
+// predecessor unless the element starts the segment.
+template <class T>
+__global__ void __launch_bounds__(256) k_seg_order(const SegItem* items, const uint32_t* data,
+                                                   uint32_t* flags) {
+  using Key = typename T::Key;
+  constexpr int DW = T::DW;
+  const SegItem it = items[blockIdx.x];
+  uint32_t desc = 0, asc = 0;
+  for (uint32_t q = threadIdx.x + (it.first ? 1u : 0u); q < it.n; q += 256) {
+    uint32_t w0[DW], w1[DW];
+    ld_elem<DW>(data + (it.l + q - 1) * DW, w0);
+    ld_elem<DW>(data + (it.l + q) * DW, w1);
+    const Key x = key_of<T>(w0), y = key_of<T>(w1);
+    desc |= kless(y, x) ? 1u : 0u;
+    asc |= kless(x, y) ? 1u : 0u;
+  }
+  if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&flags[2 * it.seg], 1u);
+  if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&flags[2 * it.seg + 1], 1u);
+}
+
+// In-place reversal of reverse-sorted segments, one workgroup per chunk.
+template <int DW>
+__global__ void __launch_bounds__(256) k_seg_reverse(const RevItem* items, uint32_t* data) {
+  const RevItem it = items[blockIdx.x];
+  for (uint32_t q = threadIdx.x; q < it.cn; q += 256) {
+    const uint64_t i = it.c0 + q, j = it.len - 1 - i;
+    uint32_t x[DW], y[DW];
+    ld_elem<DW>(data + (it.l + i) * DW, x);
+    ld_elem<DW>(data + (it.l + j) * DW, y);
+    st_elem<DW>(data + (it.l + i) * DW, y);
+    st_elem<DW>(data + (it.l + j) * DW, x);
   }
 }
 

@@ -28,6 +28,9 @@ struct Launchers {
   hipError_t (*minmax)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*seg_minmax)(const SegItem* items, uint32_t nitems, const uint32_t* data,
                            uint64_t* smin, uint64_t* smax, hipStream_t);
+  hipError_t (*seg_order)(const SegItem* items, uint32_t nitems, const uint32_t* data,
+                          uint32_t* flags, hipStream_t);
+  hipError_t (*seg_reverse)(const RevItem* items, uint32_t nitems, uint32_t* data, hipStream_t);
 };
 
 const Launchers* launchers_u32();

@@ -158,13 +158,22 @@ def gen_u32(dist: str, n: int, seed: int) -> np.ndarray:
 
 
 def gen_f64(dist: str, n: int, seed: int) -> np.ndarray:
-    """IEEE doubles: uniform in [0,1) or exponential with rate 1."""
-    u = (stream(seed, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
-    if dist == "uniform":
+    """IEEE doubles: uniform in [0,1), exponential with rate 1, sorted or
+    reverse-sorted uniform doubles, or the integer distribution `dist`
+    converted to double (exact: its values are below 2^53)."""
+    if dist in ("uniform", "exponential", "sorted", "reversesorted"):
+        u = (stream(seed, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+        if dist == "exponential":
+            return -np.log1p(-u)
+        if dist == "sorted":
+            return np.sort(u)
+        if dist == "reversesorted":
+            return np.sort(u)[::-1].copy()
         return u
-    if dist == "exponential":
-        return -np.log1p(-u)
-    raise ValueError(dist)
+    v = gen_u64(dist, n, seed)
+    if v.size and int(v.max()) >= (1 << 53):
+        raise ValueError(f"{dist} at n={n} is not exact in double")
+    return v.astype(np.float64)
 
 
 def gen_pair(dist: str, n: int, seed: int) -> np.ndarray:

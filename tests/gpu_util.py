@@ -55,7 +55,7 @@ def assert_parity(out: np.ndarray, inp: np.ndarray, kind: str, ref: np.ndarray |
 
 def generate(kind: str, dist: str, n: int, seed: int) -> np.ndarray:
     if kind == "f64":
-        return synth.gen_f64(dist if dist in ("uniform", "exponential") else "uniform", n, seed)
+        return synth.gen_f64(dist, n, seed)
     if kind == "rec100":
         return synth.gen_rec100(dist if dist in ("uniform", "rootdup") else "uniform", n, seed)
     return synth.generate(kind, dist, n, seed)

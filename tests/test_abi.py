@@ -91,7 +91,8 @@ def _segws(n_total, offs, sizes, t=2, algo=0):
 def test_segments_validation():
     n = 1 << 20
     rc, ws = _segws(n, [0, 1000, 500000], [1000, 400000, 524288])
-    assert rc == 0 and ws >= _ws(n, 2, 0)[1]
+    base = _ws(1000 + 400000 + 524288, 2, 0)[1]       # planned for the elements sorted
+    assert rc == 0 and base <= ws <= base + 16384     # plus the per-segment order flags
     assert _segws(n, [0, 999], [1000, 10])[0] == -1            # overlap
     assert _segws(n, [n - 10], [11])[0] == -1                  # past the end
     assert _segws(n, [1 << 63], [1 << 63])[0] == -1            # offset + n overflows
@@ -107,3 +108,65 @@ def test_segments_validation():
     assert L.ips_sort_segments(ctypes.c_void_p(0x10), fake, 100, 2, 0, segs, nseg, fake, 1 << 20,
                                ctypes.byref(p), None) == -1
     assert L.ips_sort_segments(None, fake, 100, 2, 0, segs, nseg, fake, 1 << 20, None, None) == -1
+
+
+def test_exported_symbols_are_exactly_the_declared_ones():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", ips.LIB_PATH], capture_output=True, text=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if " T ips_" in ln})
+    assert exported == _declared()
+
+
+def _batchws(ptrs, ns, t=2, algo=0):
+    cnt = len(ptrs)
+    P = (ctypes.c_void_p * max(1, cnt))(*ptrs)
+    N = (ctypes.c_uint64 * max(1, cnt))(*ns)
+    out = ctypes.c_size_t(0)
+    rc = ips.lib().ips_batch_workspace_bytes(P, N, cnt, t, algo, None, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_batch_validation():
+    base = 1 << 40
+    rc, ws = _batchws([base, base + 8 * 5000, base + (1 << 30)], [5000, 100000, 20000])
+    assert rc == 0 and ws > 0
+    assert _batchws([base, base + 8 * 4999], [5000, 10])[0] == -1        # overlap
+    assert _batchws([base + 4], [100])[0] == -4                            # u64 misaligned
+    assert _batchws([0], [100])[0] == -1                                   # null with n > 0
+    assert _batchws([0, base], [0, 100])[0] == 0                           # empty entries are ignored
+    assert _batchws([base + 4], [100], t=1)[0] == 0                        # u32 needs 4 bytes
+    assert _batchws([base], [100], t=5, algo=1)[0] == -2                   # radix on records
+    # records at addresses that differ by a non-multiple of 100 bytes form
+    # separate groups: each is planned on its own
+    r1 = _batchws([base, base + 2_000_064], [20000, 20000], t=5)
+    assert r1[0] == 0 and r1[1] > 0
+    assert _batchws([base, base + 1_999_964], [20000, 20000], t=5)[0] == -1   # overlap across groups
+
+
+def _requests(specs):
+    arr = (ips.Request * max(1, len(specs)))()
+    for i, (ptr, n, t, algo, at) in enumerate(specs):
+        arr[i].d_data, arr[i].n, arr[i].elem_type, arr[i].algo, arr[i].arrival_s = ptr, n, t, algo, at
+    return arr
+
+
+def test_serve_validation_and_rejection_without_device():
+    L = ips.lib()
+    base = 1 << 40
+    cfg = ips.ServeConfig(1 << 20, ips.SERVE_BATCH, 0)
+    reqs = _requests([(base, 1 << 20, 2, 0, 0.0), (base + (1 << 24), 1 << 21, 1, 0, 0.001)])
+    out = ctypes.c_size_t(0)
+    assert L.ips_serve_workspace_bytes(reqs, 2, ctypes.byref(cfg), None, ctypes.byref(out)) == 0
+    assert out.value > 0
+    bad = ips.ServeConfig(1 << 20, 7, 0)
+    fake_ctx = ctypes.c_void_p(0x10)
+    assert L.ips_serve_trace(fake_ctx, reqs, 2, ctypes.byref(bad), None, 0, None, None) == -1
+    assert L.ips_serve_trace(None, reqs, 2, ctypes.byref(cfg), None, 0, None, None) == -1
+    neg = _requests([(base, 10, 2, 0, -1.0)])
+    assert L.ips_serve_trace(fake_ctx, neg, 1, ctypes.byref(cfg), None, 0, None, None) == -1
+    # Both requests exceed the 1 MiB budget alone: the admission step rejects
+    # them without ever calling a sort (so no device is touched).
+    rc = L.ips_serve_trace(fake_ctx, reqs, 2, ctypes.byref(cfg), ctypes.c_void_p(0x1000), 1 << 30, None, None)
+    assert rc == -3
+    assert [reqs[i].status for i in range(2)] == [-3, -3]
+    assert reqs[1].done_s >= 0.001                  # rejected only once it had arrived

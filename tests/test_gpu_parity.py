@@ -247,3 +247,16 @@ def test_lds_tier_fallbacks(sorter, kind):
             log(f"lds fallback {kind} {name} n={n}")
             p = ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)
             assert_parity(gpu_sort(sorter, a, kind, params=p), a, kind)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
+def test_presorted_inputs_through_partitioning(sorter, kind):
+    # Sorted and reverse-sorted inputs with the detection switched off go
+    # through the partitioning steps (as segments of a batched call do).
+    p = ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)
+    for dist in ("sorted", "reversesorted", "zero"):
+        for n in (20_011, 300_001):
+            a = generate(kind, dist, n, 11)
+            for algo in ("samplesort", "radix"):
+                log(f"presorted {kind} {dist} n={n} {algo}")
+                assert_parity(gpu_sort(sorter, a, kind, algo=algo, params=p), a, kind)

@@ -113,3 +113,56 @@ def test_batch_workload_scaled(sorter):
     log(f"batch workload scaled: {len(sizes)} arrays, {int(sizes.sum())} keys")
     out = _run_segments(sorter, data, offs, sizes, "u64")
     _check(out, data, offs, sizes, "u64")
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
+def test_segments_all_distributions(sorter, kind):
+    # One segment per distribution of the paper, sizes above the LDS tier.
+    sizes = [70_000 + 1000 * i for i in range(len(synth.DISTRIBUTIONS))]
+    offs, total = _layout(sizes, gap=1)
+    data = np.zeros((total,) + generate(kind, "uniform", 1, 0).shape[1:],
+                    dtype=generate(kind, "uniform", 1, 0).dtype)
+    for i, (dist, o, n) in enumerate(zip(synth.DISTRIBUTIONS, offs, sizes)):
+        data[o:o + n] = generate(kind, dist, n, 50 + i)
+    for algo in ("samplesort", "radix"):
+        log(f"segments all distributions {kind} {algo}")
+        out = _run_segments(sorter, data, offs, sizes, kind, algo=algo)
+        _check(out, data, offs, sizes, kind)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "pair"])
+def test_segments_one_bucket_many_pieces(sorter, kind):
+    # All-equal keys in large segments: the single equality bucket spans
+    # every stripe, so its placement pieces far outnumber one mask word.
+    sizes = [4_000_037, 1_500_000, 20_000]
+    offs, total = _layout(sizes, gap=2)
+    data = generate(kind, "uniform", total, 70)
+    for o, n in zip(offs[:2], sizes[:2]):
+        data[o:o + n] = generate(kind, "zero", n, 71)
+    log(f"segments one bucket many pieces {kind}")
+    out = _run_segments(sorter, data, offs, sizes, kind)
+    _check(out, data, offs, sizes, kind)
+
+
+@pytest.mark.parametrize("kind", ["u32", "f64", "pair", "rec100"])
+def test_segments_sorted_detection(sorter, kind):
+    # Sorted segments stay, reverse-sorted ones are reversed, ties allowed;
+    # with the detection off the same segments are partitioned.
+    n = 30_000 if kind == "rec100" else 100_003
+    parts = []
+    for i, dist in enumerate(["sorted", "reversesorted", "zero", "uniform"]):
+        a = generate(kind, dist if kind != "rec100" else "uniform", n, 75 + i)
+        if kind == "rec100" and dist in ("sorted", "reversesorted"):
+            a = oracle.sort(a, kind)
+            if dist == "reversesorted":
+                a = a[::-1].copy()
+        parts.append(a)
+    sizes = [n] * 4
+    offs, total = _layout(sizes, gap=3)
+    data = np.zeros((total,) + parts[0].shape[1:], dtype=parts[0].dtype)
+    for o, a in zip(offs, parts):
+        data[o:o + n] = a
+    for flags in (0, ips.FLAG_NO_SORTED_CHECK):
+        log(f"segments sorted detection {kind} flags={flags}")
+        out = _run_segments(sorter, data, offs, sizes, kind, params=ips.make_params(flags=flags))
+        _check(out, data, offs, sizes, kind)
