@@ -49,7 +49,19 @@ def main() -> int:
     ap.add_argument("--arrays", type=int, default=4096, help="batch: number of arrays")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
+                    help="turn four rocprofv3 --pmc output folders into the traffic summary (markdown)")
+    ap.add_argument("--kernel-stats-summary", metavar="CSV",
+                    help="print a rocprofv3 kernel_stats.csv as a markdown table")
     args = ap.parse_args()
+    if args.kernel_stats_summary:
+        return kernel_stats_summary(args.kernel_stats_summary)
+    if args.traffic_summary:
+        return traffic_summary(*args.traffic_summary)
+    if args.calib_copy:
+        return calib_copy()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sort runs on a single "
               f"MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -149,7 +161,9 @@ def main() -> int:
                       "minmax": D, "reverse": 2 * D}.get(dom, 2 * D)
     achieved = bytes_per_elem * delems / dla / (dms / dla * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom) if (kind == "u64" and args.log2n == 28
+                                                     and args.dist == "uniform") else None,
                 "avg_launch_ms": round(dms / dla, 4), "bytes_per_launch": int(bytes_per_elem * delems / dla)}
     log(f"dominant kernel {dom}: {dms / steps:.3f} ms/step, {achieved:.0f} GB/s")
 
@@ -212,6 +226,145 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+# --------------------------------------------------------------- traffic
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_u64_uniform_2p28.md")
+KERNEL_NAMES = {"classify": "k_classify<", "permute": "k_permute<", "lds_sort": "k_lds_tier<",
+                "cleanup_b": "k_cleanup_b<", "cleanup_a": "k_cleanup_a<", "sample": "k_sample<",
+                "boundaries": "k_boundaries", "sorted_check": "k_sorted_"}
+# Files whose change invalidates the measured traffic of the kernels.
+KERNEL_SOURCES = ["ips_common.hpp", "ips_traits.hpp", "ips_kernels.hpp", "ips_lds_tier.hpp",
+                  "ips_kern_impl.hpp", "ips_launch.hpp", "ips_host.hip"]
+CALIB_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2009_13569_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def calib_copy() -> int:
+    """A plain copy of known size: 1 GiB read and 1 GiB written, 3 times."""
+    import torch
+    src = torch.arange(CALIB_BYTES // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    assert bool((dst == src).all())
+    log(f"calibration copy: 3 x {CALIB_BYTES} bytes")
+    return 0
+
+
+def _pmc_rows(folder: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_write_dir: str) -> int:
+    """Mean FETCH_SIZE / WRITE_SIZE per dispatch of each sort kernel, scaled by
+    the factor that maps the same counter of the calibration copy onto its
+    known bytes; prints the markdown summary (with a JSON line for bench.py)."""
+    out = {"source_hash": kernel_source_hash(), "kernels": {}}
+    factors = {}
+    for counter, cal in (("FETCH_SIZE", cal_fetch_dir), ("WRITE_SIZE", cal_write_dir)):
+        rows = [r for r in _pmc_rows(cal) if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+        gmax = max(int(r["Grid_Size"]) for r in rows)
+        vals = [float(r["Counter_Value"]) for r in rows if int(r["Grid_Size"]) == gmax]
+        kib = sum(vals) / len(vals)
+        factors[counter] = CALIB_BYTES / (kib * 1024.0)
+        out[f"calib_{counter}_kib"] = round(kib, 1)
+        out[f"factor_{counter}"] = round(factors[counter], 4)
+    for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _pmc_rows(folder) if r["Counter_Name"] == counter]
+        for short, pat in KERNEL_NAMES.items():
+            vals = [float(r["Counter_Value"]) for r in rows if pat in r["Kernel_Name"]]
+            if not vals:
+                continue
+            k = out["kernels"].setdefault(short, {"dispatches": len(vals)})
+            k[f"{counter}_kib_mean"] = round(sum(vals) / len(vals), 1)
+            k[f"{counter}_bytes_mean"] = round(sum(vals) / len(vals) * 1024.0 * factors[counter])
+    for k in out["kernels"].values():
+        k["hbm_bytes_per_launch"] = k.get("FETCH_SIZE_bytes_mean", 0) + k.get("WRITE_SIZE_bytes_mean", 0)
+    lines = ["# HBM traffic per launch, u64 Uniform n=2^28 (samplesort)", "",
+             "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one pass per counter (repo root, `cd /tmp`",
+             "and `TMPDIR=/tmp` first, R = repo root):", "",
+             "```",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_FETCH_SIZE -o p -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-radix",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_WRITE_SIZE -o p -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-radix",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/cal_FETCH_SIZE -o p -- "
+             "python3 $R/bench.py --calib-copy",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/cal_WRITE_SIZE -o p -- "
+             "python3 $R/bench.py --calib-copy",
+             "python3 bench.py --traffic-summary gpurun_out/pmc_FETCH_SIZE gpurun_out/pmc_WRITE_SIZE "
+             "gpurun_out/cal_FETCH_SIZE gpurun_out/cal_WRITE_SIZE",
+             "```", "",
+             "Each counter is scaled by the factor that maps the same counter of the plain 1 GiB",
+             "device-to-device copy (`__amd_rocclr_copyBuffer`) onto its 1 GiB read and 1 GiB written.", "",
+             "| kernel | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | scaled HBM bytes/launch |",
+             "|---|---|---|---|---|"]
+    for name, k in out["kernels"].items():
+        lines.append(f"| {name} | {k['dispatches']} | {k.get('FETCH_SIZE_kib_mean', '-')} | "
+                     f"{k.get('WRITE_SIZE_kib_mean', '-')} | {k['hbm_bytes_per_launch']} |")
+    lines += ["", f"Calibration copy: FETCH_SIZE {out['calib_FETCH_SIZE_kib']} KiB (factor "
+                  f"{out['factor_FETCH_SIZE']}), WRITE_SIZE {out['calib_WRITE_SIZE_kib']} KiB (factor "
+                  f"{out['factor_WRITE_SIZE']}) for 1048576 KiB each way.", "",
+              "Machine-readable (bench.py reads it; `source_hash` covers the kernel sources):", "",
+              "```json", json.dumps(out), "```", ""]
+    print("\n".join(lines))
+    return 0
+
+
+def kernel_stats_summary(csv_path: str) -> int:
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort\n")
+    print("Command (`cd /tmp`, `TMPDIR=/tmp`, R = repo root): `rocprofv3 --kernel-trace --stats --output-format csv "
+          "-d $R/gpurun_out/ktrace -o kt -- python3 $R/bench.py --steps 3 --warmup 1 --no-cpu --no-radix`; "
+          "table from `python3 bench.py --kernel-stats-summary gpurun_out/ktrace/kt_kernel_stats.csv`.\n")
+    print("4 sorts (1 warmup + 3 timed) plus the bench's own copies and checks; durations in microseconds.\n")
+    print("| kernel | calls | total us | avg us | % |")
+    print("|---|---|---|---|---|")
+    for r in rows[:16]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 70:
+            name = name[:67] + "..."
+        print(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+              f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return 0
+
+
+def measured_traffic(kernel: str):
+    """Scaled HBM bytes per launch of `kernel` from the committed counter
+    summary, or None if there is none or the kernel sources changed since."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        js = txt.split("```json", 1)[1].split("```", 1)[0]
+        d = json.loads(js)
+    except (OSError, IndexError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return int(k["hbm_bytes_per_launch"]) if k else None
 
 
 def _seg_sorted_and_sum(t, offs):
