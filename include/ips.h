@@ -98,10 +98,10 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *               workgroup's LDS (default: per type, 1..16384); 1 forces every
  *               task of two or more elements through a partitioning step
  *  piece_blocks maximum blocks per pointer piece of the block permutation
- *               (default 256)
+ *               (default 1024)
  *  seed         seed of the sampling stream (default 0)
  *  perm_groups  target number of block-permutation groups (swap buffers) per
- *               batch (default 32768)
+ *               batch (default 131072)
  */
 typedef struct {
   uint32_t k;

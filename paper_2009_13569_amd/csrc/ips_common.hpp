@@ -14,6 +14,21 @@ constexpr uint32_t MAX_NB = 512;
 constexpr uint32_t MAX_BLOCK_BYTES = 2048;   // 64 lanes x 8 dwords
 constexpr uint32_t BUF_LDS_BYTES = 128u * 1024u;   // buffer blocks in LDS (before padding)
 constexpr uint32_t BUF_PAD_DW = 2;                 // padding dwords per LDS buffer block
+// Block permutation tuning: dwords of the held block per lane, spacing of
+// the pieces' pointer words (in 8-byte words), and the number of placement
+// pieces a bucket's block range is cut into at most (besides stripe ends).
+#ifndef IPS_PERM_RD
+#define IPS_PERM_RD 8
+#endif
+#ifndef IPS_PWORD_STRIDE
+#define IPS_PWORD_STRIDE 4    // pointer words 32 bytes apart
+#endif
+#ifndef IPS_MAX_PLACE_PIECES
+#define IPS_MAX_PLACE_PIECES 32
+#endif
+constexpr int PERM_RD = IPS_PERM_RD;
+constexpr uint32_t PWORD_STRIDE = IPS_PWORD_STRIDE;
+constexpr uint32_t MAX_PLACE_PIECES = IPS_MAX_PLACE_PIECES;
 constexpr uint32_t CLS_THREADS = 1024;
 constexpr uint32_t PERM_THREADS = 256;
 constexpr uint32_t SMP_THREADS = 1024;

@@ -25,7 +25,7 @@ using namespace ips;
 namespace {
 
 constexpr uint32_t WG_TARGET = 1024;      // classification workgroups per level (4 per CU)
-constexpr uint32_t GRP_TARGET = 32768;    // default permutation groups per batch
+constexpr uint32_t GRP_TARGET = 131072;   // default permutation groups per batch
 constexpr uint32_t TB_MAX = 512;          // tasks per batch
 constexpr uint32_t WB_MAX = 2048;         // classification workgroups per batch
 
@@ -95,7 +95,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   c->cap = p->lds_task_max ? p->lds_task_max : dcap;
   if (c->cap > dcap) return IPS_E_INVALID_ARG;
   c->n0 = p->n0;   // 0: buckets sized for the LDS tier (see task_kprime)
-  c->cmax = p->piece_blocks ? p->piece_blocks : 256;
+  c->cmax = p->piece_blocks ? p->piece_blocks : 1024;
   c->groups = p->perm_groups ? p->perm_groups : GRP_TARGET;
   if (c->groups > (1u << 20)) return IPS_E_INVALID_ARG;
   c->seed = p->seed;
@@ -188,7 +188,14 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   L->SB = std::min<uint64_t>((uint64_t)(WG_TARGET + L->TB) * slot_max, data_budget);
   L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, std::max<uint64_t>(slot_max, data_budget));
   L->FB = n / bmin + L->TB + 1;
-  L->PB = (uint64_t)L->TB * (2 * nbm + 3) + L->WB + L->FB / c.cmax + 16;
+  // Pieces: a task with k' buckets (2k' with equality buckets) has at most
+  // 4k' + 3 + W + NB / cmax of them.  Under the default k' rule k' is below
+  // 8 n' / cap (or 2), so a samplesort batch needs at most 32 n / cap + 13
+  // per task besides the stripe and chunk terms (radix steps always have up
+  // to 256 buckets).
+  uint64_t pb_buckets = (uint64_t)L->TB * (2 * nbm + 3);
+  if (!c.n0 && !c.radix) pb_buckets = std::min<uint64_t>(pb_buckets, 32 * n / c.cap + 13ull * L->TB);
+  L->PB = pb_buckets + L->WB + L->FB / c.cmax + 16;
   L->PWB = c.groups / 4 + 2 * L->TB + 16;
   L->NBE = L->TB * (uint32_t)(nbm + 1);
   L->LTB = L->TB * (uint32_t)nbm + 1;
@@ -215,7 +222,7 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_BPLE] = (size_t)L->NBE * 4;
   sz[R_BMIN] = c.radix ? (size_t)L->NBE * 8 : 0;
   sz[R_BMAX] = sz[R_BMIN];
-  sz[R_PWORD] = L->PB * 8;
+  sz[R_PWORD] = L->PB * 8 * PWORD_STRIDE;
   sz[R_PA] = L->PB * 4;
   sz[R_PC] = L->PB * 4;
   sz[R_PR] = L->PB * 4;
@@ -359,31 +366,35 @@ int read_ctrl(Run& r) {
   return check_dev_error(r);
 }
 
-// Sorts the given small tasks in the LDS tier: tasks up to the small
-// variant's capacity with that variant, larger ones with the large variant;
-// both parts share one upload.
+// Sorts the given small tasks in the LDS tier: each task runs on the
+// smallest of the three workgroup variants that holds it; all parts share
+// one upload.
 int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
+  const uint32_t* caps = r.c.L->lds_caps;
   std::vector<LTask> lt;
   lt.reserve(lt_in.size());
-  const uint32_t small = r.c.L->lds_cap_small;
-  for (const LTask& t : lt_in) if (t.n <= small) lt.push_back(t);
-  const size_t nsmall = lt.size();
-  for (const LTask& t : lt_in) if (t.n > small) lt.push_back(t);
+  size_t bound[4] = {0, 0, 0, 0};
+  for (uint32_t v = 0; v < 3; ++v) {
+    const uint32_t lo = v ? caps[v - 1] : 0;
+    if (v && caps[v] == caps[v - 1]) { bound[v + 1] = lt.size(); continue; }
+    for (const LTask& t : lt_in)
+      if (t.n > lo && t.n <= caps[v]) lt.push_back(t);
+    bound[v + 1] = lt.size();
+  }
   size_t done = 0;
   while (done < lt.size()) {
     const size_t cnt = std::min<size_t>(lt.size() - done, r.L.LTB);
     std::memcpy(r.h_lt, lt.data() + done, cnt * sizeof(LTask));
     LTask* d_lt = wsp<LTask>(r, R_LT);
     HIPCHK(r.ctx, hipMemcpyAsync(d_lt, r.h_lt, cnt * sizeof(LTask), hipMemcpyHostToDevice, r.st));
-    for (int part = 0; part < 2; ++part) {
-      const size_t p0 = part == 0 ? done : std::max(done, nsmall);
-      const size_t p1 = part == 0 ? std::min(done + cnt, nsmall) : done + cnt;
+    for (uint32_t v = 0; v < 3; ++v) {
+      const size_t p0 = std::max(done, bound[v]);
+      const size_t p1 = std::min(done + cnt, bound[v + 1]);
       if (p1 <= p0) continue;
       uint64_t el = 0;
       for (size_t q = p0; q < p1; ++q) el += lt[q].n;
       HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
-               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, part == 1,
-                                      r.a.ctrl, r.st);
+               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, v, r.a.ctrl, r.st);
              }));
     }
     done += cnt;
@@ -411,7 +422,8 @@ Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
   nd.spill = r.L.slot_max;
   const uint32_t bmin = block_elems(r.c, max_nb(r.c));
   nd.flags = t.n / bmin + 1;
-  nd.pieces = 2 * (uint64_t)max_nb(r.c) + 2 + nd.wg + nd.flags / r.c.cmax + 1;
+  const uint64_t nbt = r.c.radix ? MAX_K : 2ull * task_kprime(r.c, t.n);   // buckets at most
+  nd.pieces = 2 * nbt + 3 + nd.wg + nd.flags / r.c.cmax + 1;
   return nd;
 }
 
@@ -532,7 +544,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     bucket += nb + 1;
     const uint32_t bdw = b * c.DW;
     uint32_t gl = 4;
-    while (gl * 8 < bdw) gl *= 2;   // each lane holds up to 8 dwords of the block
+    while (gl * PERM_RD < bdw) gl *= 2;   // each lane holds up to PERM_RD dwords of the block
     p.glanes = gl;
     uint64_t ng = std::max<uint64_t>(1, std::min<uint64_t>(NB / 4, (uint64_t)c.groups * NB / std::max<uint64_t>(1, blocks_sum)));
     p.ngrp = (uint32_t)ng;

@@ -7,20 +7,29 @@
 
 namespace ips {
 
-// LDS-tier shapes per type: (threads, keys per thread) of the small and the
-// large variant.
+// LDS-tier shapes per type: (threads, keys per thread) of three variants of
+// increasing capacity; a task runs on the smallest variant that holds it.
 template <class T> struct LdsShape;
-template <> struct LdsShape<TU32> { static constexpr uint32_t NS = 512, ES = 32, NB = 512, EB = 32, NET = 32; };
-template <> struct LdsShape<TU64> { static constexpr uint32_t NS = 512, ES = 16, NB = 1024, EB = 16, NET = 32; };
-template <> struct LdsShape<TF64> { static constexpr uint32_t NS = 512, ES = 16, NB = 1024, EB = 16, NET = 32; };
-template <> struct LdsShape<TPair> { static constexpr uint32_t NS = 512, ES = 8, NB = 512, EB = 8, NET = 32; };
-template <> struct LdsShape<TRec100> { static constexpr uint32_t NS = 256, ES = 4, NB = 256, EB = 4, NET = 16; };
+template <> struct LdsShape<TU32> {
+  static constexpr uint32_t N0 = 256, E0 = 32, N1 = 512, E1 = 32, N2 = 512, E2 = 32, NET = 32;
+};
+template <> struct LdsShape<TU64> {
+  static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
+};
+template <> struct LdsShape<TF64> {
+  static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
+};
+template <> struct LdsShape<TPair> {
+  static constexpr uint32_t N0 = 256, E0 = 8, N1 = 512, E1 = 8, N2 = 512, E2 = 8, NET = 32;
+};
+template <> struct LdsShape<TRec100> {
+  static constexpr uint32_t N0 = 256, E0 = 4, N1 = 256, E1 = 4, N2 = 256, E2 = 4, NET = 16;
+};
 
 template <class T>
 struct LaunchImpl {
   using SH = LdsShape<T>;
-  static constexpr uint32_t CAP_SMALL = SH::NS * SH::ES;
-  static constexpr uint32_t CAP_BIG = SH::NB * SH::EB;
+  static constexpr uint32_t CAP0 = SH::N0 * SH::E0, CAP1 = SH::N1 * SH::E1, CAP2 = SH::N2 * SH::E2;
 
   static hipError_t sample_(const BatchArgs& a, uint32_t nt, uint64_t seed, hipStream_t st) {
     if (!nt) return hipSuccess;
@@ -71,13 +80,12 @@ struct LaunchImpl {
     hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl);
     return hipGetLastError();
   }
-  static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, bool big, uint32_t* ctrl,
+  static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
                              hipStream_t st) {
     if (!nt) return hipSuccess;
-    if constexpr (CAP_BIG > CAP_SMALL) {
-      if (big) return lds_launch<SH::NB, SH::EB>(lt, nt, data, ctrl, st);
-    }
-    return lds_launch<SH::NS, SH::ES>(lt, nt, data, ctrl, st);
+    if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, st);
+    if (variant == 1) return lds_launch<SH::N1, SH::E1>(lt, nt, data, ctrl, st);
+    return lds_launch<SH::N0, SH::E0>(lt, nt, data, ctrl, st);
   }
   static hipError_t sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
     hipLaunchKernelGGL((k_sorted_sample<T>), dim3(64), dim3(1024), 0, st, data, n, ctrl);
@@ -130,7 +138,7 @@ struct LaunchImpl {
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
-        CAP_BIG, CAP_SMALL, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
+        CAP2, {CAP0, CAP1, CAP2}, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
         &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax, &seg_order, &seg_reverse};
     return &t;
   }

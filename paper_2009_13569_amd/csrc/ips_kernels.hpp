@@ -97,7 +97,6 @@ __device__ __forceinline__ void st_elem(uint32_t* p, const uint32_t (&w)[DW]) {
 // branch is uniform across the workgroup).
 // Placement pieces per bucket aimed for: few enough that a 64-bit mask
 // can record which of them are full, enough to spread pointer contention.
-constexpr uint32_t MAX_PLACE_PIECES = 32;
 
 struct BlockDiv {
   uint32_t b, sh;
@@ -660,7 +659,7 @@ __global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) 
                      a.p_rinit[p] = ri;
                      a.p_cum[p] = cu;
                      a.p_fcnt[p] = 0;
-                     a.p_word[p] = ((uint64_t)c0 << 32) | (uint64_t)((uint32_t)ri + PTR_BIAS);
+                     a.p_word[(uint64_t)p * PWORD_STRIDE] = ((uint64_t)c0 << 32) | (uint64_t)((uint32_t)ri + PTR_BIAS);
                      cu += (uint32_t)(ri - (int32_t)c0 + 1);
                      ++p;
                      if (place) ple = p;
@@ -679,7 +678,6 @@ __device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t lane) {
   return (uint32_t)__shfl((int)v, (int)lane, 64);
 }
 
-constexpr int PERM_RD = 8;    // dwords of the held block per lane
 
 template <class T>
 __device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[PERM_RD], uint32_t lbase,
@@ -753,7 +751,7 @@ k_permute(BatchArgs a) {
   const uint32_t pb = tk.piece_base;
   const uint32_t np = a.t_npieces[tix];
   const uint32_t U = a.t_unproc[tix];
-  uint64_t* word = a.p_word + pb;
+  uint64_t* word = a.p_word + (uint64_t)pb * PWORD_STRIDE;
   const uint32_t* pa = a.p_a + pb;
   const uint32_t* pc = a.p_c + pb;
   const int32_t* pr = a.p_rinit + pb;
@@ -823,7 +821,7 @@ k_permute(BatchArgs a) {
         // Decrementing r of an exhausted piece is harmless (r only moves
         // further below w), so each attempt is one read-modify-write.
         while (src < src_end) {
-          const uint64_t wv = at_add64(&word[src], ~0ull);
+          const uint64_t wv = at_add64(&word[(uint64_t)src * PWORD_STRIDE], ~0ull);
           const int32_t w = (int32_t)(wv >> 32), r = (int32_t)((uint32_t)wv - PTR_BIAS);
           if (r >= w) { r0 = (uint32_t)r; PSTAT(st_claim_ok); break; }
           PSTAT(st_claim_fail);
@@ -872,7 +870,7 @@ k_permute(BatchArgs a) {
           // their latencies overlap
           const uint32_t cap = __builtin_nontemporal_load(&pc[sr]);
           const int32_t rin = __builtin_nontemporal_load(&pr[sr]);
-          const uint64_t wv = at_add64(&word[sr], 1ull << 32);
+          const uint64_t wv = at_add64(&word[(uint64_t)sr * PWORD_STRIDE], 1ull << 32);
           const uint32_t w = (uint32_t)(wv >> 32);
           r2 = (uint32_t)rin;
           if (w < cap) {

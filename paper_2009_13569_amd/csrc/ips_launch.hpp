@@ -14,13 +14,13 @@ struct Launchers {
   uint32_t key_slot;      // bytes of a key in StepRec slots actually used
   bool keys_only, radix_ok;
   uint32_t lds_cap;       // LDS-tier capacity (elements)
-  uint32_t lds_cap_small; // tasks up to this size use the smaller, faster variant
+  uint32_t lds_caps[3];   // capacities of the three LDS-tier variants (ascending)
   hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, hipStream_t);
   hipError_t (*classify)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, bool gbuf, hipStream_t);
   hipError_t (*permute)(const BatchArgs&, uint32_t nwg, hipStream_t);
   hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);
   hipError_t (*cleanup_b)(const BatchArgs&, uint32_t nwg, uint32_t max_w, hipStream_t);
-  hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, bool big, uint32_t* ctrl,
+  hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
                          hipStream_t);
   hipError_t (*sorted_sample)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*sorted_check)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);

@@ -214,6 +214,13 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   }
   if (n < 2) return;
   uint32_t* gd = data + t.l * DW;
+#ifdef IPS_LDS_STATS
+  uint64_t ts[6];
+  ts[0] = clock64();
+#define LDS_TS(i) (ts[i] = clock64())
+#else
+#define LDS_TS(i) ((void)0)
+#endif
 
   // 1. Load keys into registers (records: also stage the records in LDS).
   Key k[E];
@@ -264,6 +271,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
     mx = s_max[w] > mx ? s_max[w] : mx;
   }
   if (mn == mx) return;   // all keys equal: already sorted
+  LDS_TS(1);
 
   // 2./3. Bins, counts, scan, scatter.
   uint32_t lb = 1;
@@ -291,6 +299,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
     }
   }
   __syncthreads();
+  LDS_TS(2);
 
   // 4. Small bins in registers; larger ones listed for the wavefronts.
   for (uint32_t b = tid; b < nbins; b += NT) {
@@ -319,6 +328,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
     }
   }
   __syncthreads();
+  LDS_TS(3);
   const uint32_t nbig = s_nbig < 64 ? s_nbig : 64;
   if (!s_fallback) {
     for (uint32_t q = wave; q < nbig; q += NT / 64) {
@@ -336,6 +346,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   __syncthreads();
   if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
   __syncthreads();
+  LDS_TS(4);
 
   // 5. Store.
   if constexpr (IDX) {
@@ -350,6 +361,17 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
       st_elem<DW>(gd + (uint64_t)i * DW, w);
     }
   }
+#ifdef IPS_LDS_STATS
+  __syncthreads();
+  LDS_TS(5);
+  if (tid == 0) {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(ctrl + 50);
+    for (int i = 0; i < 5; ++i) atomicAdd(&c[i], (unsigned long long)(ts[i + 1] - ts[i]));
+    atomicAdd(&c[5], 1ull);
+    atomicAdd(&c[6], (unsigned long long)n);
+  }
+#endif
+#undef LDS_TS
 }
 
 }  // namespace ips

@@ -28,7 +28,7 @@ def sorter():
 @pytest.mark.parametrize("kind", KINDS)
 def test_lds_tier(sorter, kind):
     cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}[kind]
-    for n in sorted({2, 3, 17, 33, 1000, cap // 2, cap // 2 + 1, cap - 1, cap}):
+    for n in sorted({2, 3, 17, 33, 1000, cap // 4, cap // 4 + 1, cap // 2, cap // 2 + 1, cap - 1, cap}):
         a = generate(kind, "uniform", n, 100 + n)
         log(f"lds {kind} n={n}")
         assert_parity(gpu_sort(sorter, a, kind), a, kind)
