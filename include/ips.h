@@ -102,6 +102,9 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *  seed         seed of the sampling stream (default 0)
  *  perm_groups  target number of block-permutation groups (swap buffers) per
  *               batch (default 131072)
+ *  profile_mask with IPS_FLAG_PROFILE: bit (1 << IPS_PH_x) selects the phases
+ *               whose launches are timed (0 = all phases).  Every timed
+ *               launch adds two event records to the stream.
  */
 typedef struct {
   uint32_t k;
@@ -112,7 +115,8 @@ typedef struct {
   uint32_t flags;
   uint64_t seed;
   uint32_t perm_groups;
-  uint32_t reserved[3];
+  uint32_t profile_mask;
+  uint32_t reserved[2];
 } ips_params;
 
 typedef struct ips_ctx ips_ctx;

@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32),
                 ("lds_task_max", ctypes.c_uint32), ("piece_blocks", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
-                ("perm_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("perm_groups", ctypes.c_uint32), ("profile_mask", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class RootInfo(ctypes.Structure):
@@ -137,10 +138,12 @@ def lib() -> ctypes.CDLL:
 
 
 def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0,
-                perm_groups=0) -> Params:
+                perm_groups=0, profile_phases=None) -> Params:
+    """profile_phases: names from PHASES to time with FLAG_PROFILE (None: all)."""
     p = Params()
     p.k, p.block_bytes, p.n0, p.lds_task_max, p.piece_blocks = k, block_bytes, n0, lds_task_max, piece_blocks
     p.flags, p.seed, p.perm_groups = flags, seed, perm_groups
+    p.profile_mask = 0 if profile_phases is None else sum(1 << PHASES.index(x) for x in profile_phases)
     return p
 
 

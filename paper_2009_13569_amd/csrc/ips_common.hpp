@@ -45,6 +45,9 @@ enum CtrlSlot : uint32_t {
   CTRL_DESC = 4,       // sorted check: a descent was found
   CTRL_ASC = 5,        // sorted check: an ascent was found
   CTRL_MINMAX = 8,     // two u64: min and max radix key (dword index 8..11)
+  CTRL_NLDS = 12,      // children of a batch: LDS-tier tasks per variant (12..14)
+  CTRL_NNEXT = 15,     // children of a batch: next-level tasks
+  CTRL_LDSEL = 16,     // children of a batch: u64 elements per LDS-tier variant (16..21)
   CTRL_WORDS = 64
 };
 
@@ -65,7 +68,7 @@ enum DevErr : uint32_t {
 
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
 // radix step.  Keys live in 16-byte slots so that every key type fits.
-constexpr uint32_t START_BITS = 10;   // start-node table: 2^10 entries
+constexpr uint32_t START_BITS = 12;   // start-node table: 2^12 entries
 struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;
   uint32_t shift, width, radix, tshift;
@@ -115,6 +118,21 @@ struct RevItem {
   uint32_t cn, pad;
 };
 constexpr uint32_t SEG_CHUNK = 65536;   // elements per chunk
+
+// A next-level partitioning task produced on the device.
+struct CTask {
+  uint64_t l, n;
+  uint32_t level, tflags, shift, width;
+};
+
+// Where the children of a batch go: LDS-tier tasks by variant (the smallest
+// variant that holds the task), larger ones to the next level.
+struct ChildArgs {
+  LTask* lt[3];
+  CTask* next;
+  uint32_t caps[3];
+  uint32_t lt_cap, next_cap;
+};
 
 // Arguments shared by the kernels of one batch.
 struct BatchArgs {

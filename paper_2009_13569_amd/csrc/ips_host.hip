@@ -108,6 +108,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
   if (p->flags & ~0x3Fu) return IPS_E_INVALID_ARG;
+  if (p->profile_mask >> IPS_PHASES) return IPS_E_INVALID_ARG;
   c->L = nullptr;
   return IPS_OK;
 }
@@ -158,6 +159,7 @@ uint32_t max_nb(const Cfg& c) { return c.radix ? MAX_K : 2 * c.k; }
 
 struct Layout {
   uint32_t TB, WB, PWB, LTB, NBE;   // tasks, cls WGs, perm WGs, LDS tasks, bucket entries
+  uint32_t NXB;                     // next-level tasks one batch can produce
   uint64_t SB, SPB, FB, PB;         // slot bytes, spill bytes, flag words, pieces
   uint64_t slot_max;
   size_t off[40];
@@ -167,7 +169,7 @@ struct Layout {
 enum Region {
   R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
   R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
-  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_COUNT
+  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_LTC, R_NEXT, R_COUNT
 };
 
 void plan(uint64_t n, const Cfg& c, Layout* L) {
@@ -228,6 +230,9 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_PR] = L->PB * 4;
   sz[R_PCUM] = L->PB * 4;
   sz[R_PFCNT] = L->PB * 4;
+  sz[R_LTC] = 3 * (size_t)L->LTB * sizeof(LTask);     // children for the LDS tier, per variant
+  L->NXB = (uint32_t)std::min<uint64_t>((uint64_t)L->TB * nbm, tasks_ub + L->TB);
+  sz[R_NEXT] = (size_t)L->NXB * sizeof(CTask);
   sz[R_TNP] = (size_t)L->TB * 4;
   sz[R_TUP] = (size_t)L->TB * 4;
   sz[R_LT] = (size_t)L->LTB * sizeof(LTask);
@@ -261,6 +266,7 @@ struct ips_ctx {
   struct Pending { hipEvent_t a, b; uint32_t row, ph; uint64_t elems; };
   std::vector<Pending> pending;
   bool profiling = false;
+  uint32_t profile_mask = 0;   // phases timed (0: all)
 };
 
 namespace {
@@ -294,7 +300,7 @@ void resolve_profile(ips_ctx* ctx) {
 // Brackets one launch with events when profiling.
 template <class F>
 hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64_t elems, F&& launch) {
-  if (!ctx->profiling) return launch();
+  if (!ctx->profiling || (ctx->profile_mask && !((ctx->profile_mask >> ph) & 1u))) return launch();
   hipEvent_t a = take_event(ctx), b = take_event(ctx);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, st);
@@ -407,6 +413,22 @@ int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
   return IPS_OK;
 }
 
+// Launches the LDS tier on the per-variant task lists the children kernel
+// wrote on the device (counts read back by the host).
+hipError_t launch_lds_lists(Run& r, const ChildArgs& ca, const uint32_t (&cnt)[3], const uint64_t (&el)[3],
+                            uint32_t row) {
+  for (uint32_t v = 0; v < 3; ++v) {
+    if (!cnt[v]) continue;
+    if (v && r.c.L->lds_caps[v] == r.c.L->lds_caps[v - 1]) return hipErrorInvalidValue;
+    hipError_t e = timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el[v], [&] {
+      return r.c.L->lds_sort(ca.lt[v], cnt[v], r.data, v, r.a.ctrl, r.st);
+    });
+    if (e != hipSuccess) return e;
+    r.ctx->stats.lds_tasks += cnt[v];
+  }
+  return hipSuccess;
+}
+
 // Upper bounds of one task's resources before its step is sampled.
 struct Need {
   uint64_t wg, slot, spill, flags, pieces;
@@ -500,7 +522,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   for (; S < S_level; S *= 2) {
     uint64_t wsum = 0, ssum = 0;
     for (uint32_t t = 0; t < T; ++t) {
-      uint64_t W = (bt[t].n + S - 1) / S;
+      uint64_t W = std::max<uint64_t>(1, (bt[t].n + S / 2) / S);
       W = std::min<uint64_t>(W, std::max<uint64_t>(1, bt[t].n / (4ull * nbv[t] * bvec[t])));
       W = std::min<uint64_t>(W, NBv[t]);
       W = std::min<uint64_t>(W, WG_TARGET);
@@ -519,8 +541,10 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.eq = hdr[t].eq;
     p.b = b;
     p.NB = NB;
-    // Stripes of at most S elements, but at least four buffer capacities long.
-    uint64_t W = (p.n + S - 1) / S;
+    // About n / S stripes (rounded to the nearest count, so that a batch of
+    // equal tasks fills whole rounds of workgroups), but at least four
+    // buffer capacities long.
+    uint64_t W = std::max<uint64_t>(1, (p.n + S / 2) / S);
     W = std::min<uint64_t>(W, std::max<uint64_t>(1, p.n / (4ull * nb * b)));
     W = std::min<uint64_t>(W, NB);
     W = std::min<uint64_t>(W, WG_TARGET);
@@ -579,23 +603,37 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, bel, [&] { return c.L->cleanup_a(r.a, T, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, bel,
                     [&] { return c.L->cleanup_b(r.a, cln, maxW, r.st); }));
-  // 4. Bucket boundaries back to the host.
-  const size_t sb_bytes = (size_t)bucket * 8;
-  const size_t mm_bytes = c.radix ? (size_t)bucket * 8 : 0;
-  if (sb_bytes + 2 * mm_bytes > r.rb_bytes) { ctx->last_dev = 0x101; return IPS_E_DEVICE; }
-  HIPCHK(ctx, hipMemcpyAsync(r.h_rb, r.a.b_start, sb_bytes, hipMemcpyDeviceToHost, r.st));
-  if (c.radix) {
-    HIPCHK(ctx, hipMemcpyAsync(r.h_rb + sb_bytes, r.a.b_min, mm_bytes, hipMemcpyDeviceToHost, r.st));
-    HIPCHK(ctx, hipMemcpyAsync(r.h_rb + sb_bytes + mm_bytes, r.a.b_max, mm_bytes, hipMemcpyDeviceToHost, r.st));
+  // 4. Children on the device: LDS-tier task lists and next-level tasks.
+  const bool want_root = root_level && T == 1;
+  const bool level1 = (c.flags & IPS_FLAG_LEVEL1_ONLY) != 0;
+  ChildArgs ca;
+  LTask* d_ltc = wsp<LTask>(r, R_LTC);
+  for (uint32_t v = 0; v < 3; ++v) {
+    ca.lt[v] = d_ltc + (size_t)v * r.L.LTB;
+    ca.caps[v] = std::min(c.cap, c.L->lds_caps[v]);
+  }
+  ca.next = wsp<CTask>(r, R_NEXT);
+  ca.lt_cap = r.L.LTB;
+  ca.next_cap = r.L.NXB;
+  CTask* h_next = reinterpret_cast<CTask*>(r.h_rb);
+  const uint32_t next_pre = (uint32_t)std::min<size_t>(r.L.NXB, (r.rb_bytes / 2) / sizeof(CTask));
+  uint64_t* h_root = reinterpret_cast<uint64_t*>(r.h_rb + r.rb_bytes / 2);
+  if (!level1) {
+    HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 10, 0u, r.st));
+    HIPCHK(ctx, launch_children(r.a, ca, T, r.st));
+    HIPCHK(ctx, hipMemcpyAsync(h_next, ca.next, (size_t)next_pre * sizeof(CTask), hipMemcpyDeviceToHost, r.st));
+  }
+  if (want_root) {
+    const PTask& p = r.h_tasks[0];
+    if ((size_t)(p.nb + 1) * 8 > r.rb_bytes / 2) { ctx->last_dev = 0x101; return IPS_E_DEVICE; }
+    HIPCHK(ctx, hipMemcpyAsync(h_root, r.a.b_start + p.bucket_base, (size_t)(p.nb + 1) * 8,
+                               hipMemcpyDeviceToHost, r.st));
   }
   if (int e = read_ctrl(r)) return e;
-  const uint64_t* hstart = reinterpret_cast<const uint64_t*>(r.h_rb);
-  const uint64_t* hmin = reinterpret_cast<const uint64_t*>(r.h_rb + sb_bytes);
-  const uint64_t* hmax = reinterpret_cast<const uint64_t*>(r.h_rb + sb_bytes + mm_bytes);
   ctx->stats.steps += T;
   ctx->stats.batches += 1;
   // Root-step description for ips_get_root_info.
-  if (root_level && T == 1) {
+  if (want_root) {
     ips_root_info& ri = ctx->root;
     const PTask& p = r.h_tasks[0];
     ri.valid = 1;
@@ -612,65 +650,65 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     ri.block_elems = p.b;
     ri.stripes = p.W;
     ri.n = p.n;
-    for (uint32_t j = 0; j <= p.nb && j < 513; ++j) ri.bucket_start[j] = hstart[p.bucket_base + j];
+    for (uint32_t j2 = 0; j2 <= p.nb && j2 < 513; ++j2) ri.bucket_start[j2] = h_root[j2];
     if (!c.radix) {
       std::vector<uint64_t> spl((size_t)p.K * 2);
       HIPCHK(ctx, hipMemcpy(spl.data(), &d_recs[0].spl[0][0], spl.size() * 8, hipMemcpyDeviceToHost));
-      for (uint32_t i = 0; i < p.K && i < 256; ++i) {
-        uint64_t k0 = spl[2 * i], k1 = spl[2 * i + 1];
+      for (uint32_t q = 0; q < p.K && q < 256; ++q) {
+        uint64_t k0 = spl[2 * q], k1 = spl[2 * q + 1];
         if (c.type == 3) k0 = (k0 >> 63) ? (k0 & ~(1ull << 63)) : ~k0;   // ordered image -> bits
         if (c.type == 5) {
-          uint8_t* d = ri.splitters[i];
-          for (int q = 0; q < 8; ++q) d[q] = (uint8_t)(k0 >> (56 - 8 * q));
+          uint8_t* d = ri.splitters[q];
+          for (int x = 0; x < 8; ++x) d[x] = (uint8_t)(k0 >> (56 - 8 * x));
           d[8] = (uint8_t)(k1 >> 8);
           d[9] = (uint8_t)k1;
         } else {
-          std::memcpy(ri.splitters[i], &k0, 8);
+          std::memcpy(ri.splitters[q], &k0, 8);
         }
       }
     }
   }
-  if (c.flags & IPS_FLAG_LEVEL1_ONLY) return IPS_OK;
-  // 5. Children: next-level tasks and LDS-tier tasks.
-  std::vector<LTask> lt;
+  if (level1) return IPS_OK;
   for (uint32_t t = 0; t < T; ++t) {
-    const PTask& p = r.h_tasks[t];
-    ctx->stats.partitioned_elems += p.n;
-    ctx->stats.max_step_elems = std::max<uint64_t>(ctx->stats.max_step_elems, p.n);
-    for (uint32_t j = 0; j < p.nb; ++j) {
-      const uint64_t s0 = hstart[p.bucket_base + j], s1 = hstart[p.bucket_base + j + 1];
-      const uint64_t sz = s1 - s0;
-      if (sz <= 1) continue;
-      if (!c.radix && p.eq && (j & 1u) && j != 2 * p.K - 1) continue;   // equality bucket
-      HTask ch;
-      ch.l = p.l + s0;
-      ch.n = sz;
-      ch.level = p.level + 1;
-      ch.tflags = 0;
-      ch.shift = 0;
-      ch.width = 0;
-      if (c.radix) {
-        const uint64_t mn = hmin[p.bucket_base + j], mx = hmax[p.bucket_base + j];
-        if (mn == mx) continue;
-        const uint32_t h = 63u - (uint32_t)__builtin_clzll(mn ^ mx);
-        ch.shift = h >= 7 ? h - 7 : 0;
-        ch.width = h - ch.shift + 1;
-      } else if (sz == p.n) {
-        ch.tflags = TF_EQ_ON;   // no progress without equality buckets
-      }
-      if (sz <= c.cap) {
-        LTask q;
-        q.l = ch.l;
-        q.n = (uint32_t)sz;
-        q.pad = 0;
-        lt.push_back(q);
-        ctx->stats.lds_elems += sz;
-      } else {
-        next.push_back(ch);
-      }
-    }
+    ctx->stats.partitioned_elems += r.h_tasks[t].n;
+    ctx->stats.max_step_elems = std::max<uint64_t>(ctx->stats.max_step_elems, r.h_tasks[t].n);
   }
-  return launch_lds_tasks(r, lt, bt[0].level);
+  // 5. Next-level tasks (read back beyond the first part if there are many),
+  // in a fixed order, and the LDS tier on the device lists.
+  const uint32_t nnext = r.h_ctrl[CTRL_NNEXT];
+  const uint32_t nlds[3] = {r.h_ctrl[CTRL_NLDS], r.h_ctrl[CTRL_NLDS + 1], r.h_ctrl[CTRL_NLDS + 2]};
+  uint64_t lel[3];
+  for (uint32_t v = 0; v < 3; ++v) {
+    lel[v] = (uint64_t)r.h_ctrl[CTRL_LDSEL + 2 * v] | ((uint64_t)r.h_ctrl[CTRL_LDSEL + 2 * v + 1] << 32);
+    ctx->stats.lds_elems += lel[v];
+  }
+  if (nnext > r.L.NXB || nlds[0] > r.L.LTB || nlds[1] > r.L.LTB || nlds[2] > r.L.LTB) {
+    ctx->last_dev = 0x102;
+    return IPS_E_DEVICE;
+  }
+  HIPCHK(ctx, launch_lds_lists(r, ca, nlds, lel, bt[0].level));
+  std::vector<CTask> ch(nnext);
+  const uint32_t first = std::min(nnext, next_pre);
+  if (first) std::memcpy(ch.data(), h_next, (size_t)first * sizeof(CTask));
+  for (uint32_t done = first; done < nnext;) {
+    const uint32_t cnt = std::min(nnext - done, next_pre);
+    HIPCHK(ctx, hipMemcpyAsync(h_next, ca.next + done, (size_t)cnt * sizeof(CTask), hipMemcpyDeviceToHost, r.st));
+    HIPCHK(ctx, hipStreamSynchronize(r.st));
+    std::memcpy(ch.data() + done, h_next, (size_t)cnt * sizeof(CTask));
+    done += cnt;
+  }
+  std::sort(ch.begin(), ch.end(), [](const CTask& x, const CTask& y) { return x.l < y.l; });
+  for (const CTask& q : ch) {
+    HTask h;
+    h.l = q.l;
+    h.n = q.n;
+    h.level = q.level;
+    h.tflags = q.tflags;
+    h.shift = q.shift;
+    h.width = q.width;
+    next.push_back(h);
+  }
+  return IPS_OK;
 }
 
 // Extra areas of a segmented call, in the workspace and in pinned host
@@ -721,6 +759,7 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   for (const auto& p : ctx->pending) { ctx->ev_pool.push_back(p.a); ctx->ev_pool.push_back(p.b); }
   ctx->pending.clear();
   ctx->profiling = (r.c.flags & IPS_FLAG_PROFILE) != 0;
+  ctx->profile_mask = params ? params->profile_mask : 0u;
   ctx->last_dev = 0;
   r.ctx = ctx;
   r.n = n;
@@ -738,7 +777,9 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   const size_t b_tasks = (size_t)r.L.TB * sizeof(PTask);
   const size_t b_maps = ((size_t)r.L.WB + r.L.PWB + (size_t)r.L.TB * max_nb(r.c)) * 4;
   const size_t b_lt = (size_t)r.L.LTB * sizeof(LTask);
-  const size_t b_rb = std::max<size_t>((size_t)r.L.NBE * 24, (size_t)r.L.TB * 64) + 4096;
+  // readback: sampling headers, or next-level tasks (first half) and the
+  // root step's bucket starts (second half)
+  const size_t b_rb = std::max<size_t>((size_t)r.L.TB * 64, 2 * 4096 * sizeof(CTask)) + 8192;
   const size_t b_ctrl = CTRL_WORDS * 4;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   if (int e = ensure_pinned(ctx, al(b_tasks) + al(b_maps) + al(b_lt) + al(b_rb) + al(b_ctrl) + al(extra_pin)))

@@ -302,6 +302,50 @@ k_sample(BatchArgs a, uint64_t seed) {
 
 // --------------------------------------------------------- classification
 
+// s_waitcnt immediate that waits for every outstanding vector memory
+// operation of the wave (vmcnt(0); LDS and export counts unrestricted).
+constexpr int WAITCNT_VM0 = 0x0F70;
+
+// Buckets of the EPT elements a thread holds, all stepping through the
+// decision tree together: the start nodes come from the start table, then
+// every level reads the node of each element not yet at a leaf (a
+// branch-free step), so the LDS reads of all elements are in flight at once.
+template <class T, int EPT>
+__device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
+                                             const typename T::Key* __restrict__ tree,
+                                             const typename T::Key* __restrict__ spl,
+                                             uint32_t logK, uint32_t eq, const StartTable& st,
+                                             uint32_t (&bk)[EPT]) {
+  const uint32_t K = 1u << logK;
+  uint32_t j[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) j[i] = st.start[st.index(T::img(key[i]))];
+  for (uint32_t l = 0; l < logK; ++l) {
+    bool act = false;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) act = act || j[i] < K;
+    if (!__any(act)) break;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const bool in = j[i] < K;
+      const typename T::Key t = tree[in ? j[i] : 1u];
+      const uint32_t nj = 2 * j[i] + (kless(t, key[i]) ? 1u : 0u);
+      j[i] = in ? nj : j[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) j[i] -= K;
+  if (eq) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const typename T::Key sp = spl[j[i]];
+      j[i] = 2 * j[i] + (kless(key[i], sp) ? 0u : 1u);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) bk[i] = j[i];
+}
+
 // Classification phase (Section 4.1): the workgroup scans its stripe of
 // blocks tile by tile, classifies each element, and appends it to the
 // buffer block of its bucket.  A full buffer block is written back to the
@@ -328,7 +372,8 @@ k_classify(BatchArgs a) {
   __shared__ Key s_spl[MAX_K];
   __shared__ uint32_t s_cnt[MAX_NB];
   __shared__ uint4 s_st[MAX_NB];          // {blocks before tile, blocks after, base, 0}
-  __shared__ uint64_t s_mn[MAX_K], s_mx[MAX_K];
+  constexpr uint32_t NMM = T::RADIX_OK ? MAX_K : 1;   // radix key ranges per bucket
+  __shared__ uint64_t s_mn[NMM], s_mx[NMM];
   __shared__ uint16_t s_start[1u << START_BITS];
   __shared__ uint32_t s_wpos;
   extern __shared__ __align__(16) uint32_t s_buf[];
@@ -357,7 +402,7 @@ k_classify(BatchArgs a) {
   stab.base = radix ? 0 : rec->tbase;
   stab.shift = radix ? 0 : rec->tshift;
   for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_st[j] = make_uint4(0, 0, 0, 0); }
-  for (uint32_t j = tid; j < MAX_K; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
+  for (uint32_t j = tid; j < NMM; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
   if (tid == 0) s_wpos = 0;
   // buffer of bucket j at buf + j * bstride (dwords)
   const uint32_t bdw = b * DW;
@@ -380,27 +425,39 @@ k_classify(BatchArgs a) {
     const uint32_t idx = (uint32_t)i * NT + tid;
     if (idx < slen) ld_elem<DW>(gs + (uint64_t)idx * DW, cur[i]);
   }
+  // Loads issued before the loop are complete when it starts, so that no
+  // wait inside the loop is tied to them (the wave's one memory counter also
+  // counts the block stores of the previous tile).
+  __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
   for (uint32_t ts = 0; ts < slen; ts += TILE) {
     const bool full = ts + TILE <= slen;
     uint32_t bk[EPT], sl[EPT];
+    Key key[EPT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const uint32_t idx = ts + (uint32_t)i * NT + tid;
-      bk[i] = 0; sl[i] = 0;
-      if (full || idx < slen) {
-        const Key key = key_of<T>(cur[i]);
-        if constexpr (T::RADIX_OK) {
-          if (radix) {
-            bk[i] = (uint32_t)((T::rkey(key) >> shift) & rmask);
-            atomicMin((unsigned long long*)&s_mn[bk[i]], (unsigned long long)T::rkey(key));
-            atomicMax((unsigned long long*)&s_mx[bk[i]], (unsigned long long)T::rkey(key));
-          } else {
-            bk[i] = tree_bucket_st<T>(s_tree, s_spl, logK, eq, stab, key);
+    for (int i = 0; i < EPT; ++i) key[i] = key_of<T>(cur[i]);
+    bool radix_done = false;
+    if constexpr (T::RADIX_OK) {
+      if (radix) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          bk[i] = (uint32_t)((T::rkey(key[i]) >> shift) & rmask);
+          if (full || ts + (uint32_t)i * NT + tid < slen) {
+            atomicMin((unsigned long long*)&s_mn[bk[i]], (unsigned long long)T::rkey(key[i]));
+            atomicMax((unsigned long long*)&s_mx[bk[i]], (unsigned long long)T::rkey(key[i]));
           }
-        } else {
-          bk[i] = tree_bucket_st<T>(s_tree, s_spl, logK, eq, stab, key);
         }
-        sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
+        radix_done = true;
+      }
+    }
+    if (!radix_done) tree_buckets<T, EPT>(key, s_tree, s_spl, logK, eq, stab, bk);
+    if (full) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        sl[i] = 0;
+        if (ts + (uint32_t)i * NT + tid < slen) sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
       }
     }
     // Prefetch the next tile; it is never written while this tile is processed.
@@ -420,11 +477,19 @@ k_classify(BatchArgs a) {
     }
     __syncthreads();
     const uint32_t consumed = (ts + TILE < slen) ? ts + TILE : slen;
+    // Per-bucket tile states of the elements, read together (kept in
+    // registers when there are at most 8 elements per thread).
+    constexpr int NST = EPT <= 8 ? EPT : 1;
+    uint4 stv[NST];
+    if constexpr (EPT <= 8) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) stv[i] = s_st[bk[i]];
+    }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint4 st = s_st[bk[i]];
+        const uint4 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_st[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.x) {
           st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
@@ -436,6 +501,10 @@ k_classify(BatchArgs a) {
       }
     }
     __syncthreads();
+    // The next tile's loads (issued two barriers ago) are waited for here,
+    // before this tile's block stores, so that using them later does not
+    // wait for the stores.
+    __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
     {
       const uint32_t wave = tid >> 6, lane = tid & 63;
       for (uint32_t j = wave; j < nb; j += NT / 64) {
@@ -447,7 +516,13 @@ k_classify(BatchArgs a) {
           } else {
             uint32_t* dst = gs + (uint64_t)pos * DW;
             const uint32_t* src = buf + j * bstride;
-            for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
+            if ((bdw & 1) == 0 && (reinterpret_cast<uintptr_t>(dst) & 7) == 0) {   // 8-byte pieces
+              uint2* d2 = reinterpret_cast<uint2*>(dst);
+              const uint2* s2 = reinterpret_cast<const uint2*>(src);
+              for (uint32_t x = lane; x < bdw / 2; x += 64) d2[x] = s2[x];
+            } else {
+              for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
+            }
           }
         }
       }
@@ -457,7 +532,7 @@ k_classify(BatchArgs a) {
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint4 st = s_st[bk[i]];
+        const uint4 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_st[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.y && blk > st.x) st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
       }
@@ -1290,6 +1365,70 @@ __global__ void __launch_bounds__(256) k_seg_minmax(const SegItem* items, const 
 }
 
 #ifdef IPS_COMMON_KERNELS
+// Children of every task of a batch (Section 4.2): one workgroup per task,
+// threads over its buckets.  A bucket of at most one element, an equality
+// bucket, or (radix) a bucket whose keys are all equal is final; a bucket of
+// at most caps[2] elements becomes an LDS-tier task of the smallest variant
+// that holds it; any other bucket becomes a next-level task (with
+// equality buckets forced on when it holds the whole parent, and for radix
+// with the digit below the highest bit in which its keys differ).
+__global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c) {
+  const PTask& tk = a.tasks[blockIdx.x];
+  const bool radix = (tk.tflags & TF_RADIX) != 0;
+  const uint32_t nb = tk.nb, bb = tk.bucket_base;
+  uint32_t* cnt = a.ctrl + CTRL_NLDS;
+  unsigned long long* ldsel = reinterpret_cast<unsigned long long*>(a.ctrl + CTRL_LDSEL);
+  uint64_t mine[3] = {0, 0, 0};
+  for (uint32_t j = threadIdx.x; j < nb; j += 256) {
+    const uint64_t s0 = a.b_start[bb + j], sz = a.b_start[bb + j + 1] - s0;
+    if (sz <= 1) continue;
+    if (!radix && tk.eq && (j & 1u) && j != 2 * tk.K - 1) continue;   // equality bucket
+    uint32_t tflags = 0, shift = 0, width = 0;
+    if (radix) {
+      const uint64_t mn = a.b_min[bb + j], mx = a.b_max[bb + j];
+      if (mn == mx) continue;
+      const uint32_t h = 63u - (uint32_t)__clzll(mn ^ mx);
+      shift = h >= 7 ? h - 7 : 0;
+      width = h - shift + 1;
+    } else if (sz == tk.n) {
+      tflags = TF_EQ_ON;   // no progress without equality buckets
+    }
+    if (sz <= c.caps[2]) {
+      const uint32_t v = sz <= c.caps[0] ? 0u : (sz <= c.caps[1] ? 1u : 2u);
+      const uint32_t q = atomicAdd(&cnt[v], 1u);
+      if (q < c.lt_cap) {
+        LTask t;
+        t.l = tk.l + s0;
+        t.n = (uint32_t)sz;
+        t.pad = 0;
+        c.lt[v][q] = t;
+      } else {
+        dev_error(a.ctrl, DE_CLN_RANGE, blockIdx.x, q);
+      }
+      mine[v] += sz;
+    } else {
+      const uint32_t q = atomicAdd(&a.ctrl[CTRL_NNEXT], 1u);
+      if (q < c.next_cap) {
+        CTask t;
+        t.l = tk.l + s0;
+        t.n = sz;
+        t.level = tk.level + 1;
+        t.tflags = tflags;
+        t.shift = shift;
+        t.width = width;
+        c.next[q] = t;
+      } else {
+        dev_error(a.ctrl, DE_CLN_RANGE, blockIdx.x, q);
+      }
+    }
+  }
+  for (int v = 0; v < 3; ++v) {
+    uint64_t m = mine[v];
+    for (int o = 32; o > 0; o >>= 1) m += (uint64_t)__shfl_xor((long long)m, o, 64);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&ldsel[v], (unsigned long long)m);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_fill32(uint32_t* p, uint64_t n, uint32_t v) {
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = v;
 }

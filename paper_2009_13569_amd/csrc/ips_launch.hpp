@@ -42,5 +42,6 @@ const Launchers* launchers_rec100();
 hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t max_nb, uint32_t cmax,
                              hipStream_t);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t);
+hipError_t launch_children(const BatchArgs&, const ChildArgs&, uint32_t ntask, hipStream_t);
 
 }  // namespace ips
