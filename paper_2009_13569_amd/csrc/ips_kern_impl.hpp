@@ -8,7 +8,9 @@
 namespace ips {
 
 // LDS-tier shapes per type: (threads, keys per thread) of three variants of
-// increasing capacity; a task runs on the smallest variant that holds it.
+// increasing capacity (a task runs on the smallest variant that holds it),
+// and NET: bins hold about NET/4 keys and are sorted in registers up to
+// NET/2 keys.
 template <class T> struct LdsShape;
 template <> struct LdsShape<TU32> {
   static constexpr uint32_t N0 = 256, E0 = 32, N1 = 512, E1 = 32, N2 = 512, E2 = 32, NET = 32;

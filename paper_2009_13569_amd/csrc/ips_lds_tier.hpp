@@ -5,11 +5,13 @@
 // pass plus tiny sorts:
 //   1. keys go to registers; the task's minimum and maximum are reduced;
 //   2. each key gets the bin (key - min) >> shift, where shift leaves about
-//      NET/2 keys per bin (equal-width bins over the key range);
+//      NET/4 keys per bin (equal-width bins over the key range);
 //   3. bin counts by LDS atomics, an exclusive scan, a scatter into LDS;
-//   4. each thread sorts one bin of at most NET keys with a register bitonic
-//      network; a bin whose keys are all equal needs nothing; any other
-//      larger bin is sorted by one wavefront with a bitonic network in LDS;
+//   4. each thread sorts one bin of at most NET/2 keys with a register
+//      bitonic network of size NET/4 or NET/2, the smaller one that holds it
+//      (bins are grouped by that size, one pass per size); a bin whose keys
+//      are all equal needs nothing; any other larger bin is sorted by one
+//      wavefront with a bitonic network in LDS;
 //      a bin above WAVE_MAX falls back to a bitonic sort of the whole task;
 //   5. one coalesced store (records are gathered from their LDS copy).
 #pragma once
@@ -173,11 +175,33 @@ __device__ void block_network(Key* keys, uint16_t* idx, uint32_t s) {
   }
 }
 
+// Sorts the s <= N keys keys[o, o + s) (and their indices) with a register
+// network of size N, padding with the largest key.
+template <class T, bool IDX, uint32_t N>
+__device__ __forceinline__ void sort_bin(typename T::Key* keys, uint16_t* idxb, uint32_t o, uint32_t s) {
+  typename T::Key v[N];
+  uint32_t ix[N];
+#pragma unroll
+  for (uint32_t i = 0; i < N; ++i) {
+    v[i] = (i < s) ? keys[o + i] : T::kmax();
+    ix[i] = (i < s) ? (IDX ? (uint32_t)idxb[o + i] : 0u) : 0xFFFFFFFFu;
+  }
+  reg_network<N, typename T::Key, IDX>(v, ix);
+#pragma unroll
+  for (uint32_t i = 0; i < N; ++i) {
+    if (i < s) {
+      keys[o + i] = v[i];
+      if constexpr (IDX) idxb[o + i] = (uint16_t)ix[i];
+    }
+  }
+}
+
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
 struct LdsTier {
   using Key = typename T::Key;
   static constexpr uint32_t CAP = NT * E;
-  static constexpr uint32_t MAXBINS = (CAP / (NET / 2) < 2048) ? CAP / (NET / 2) : 2048;
+  static constexpr uint32_t MEAN = NET / 4;   // target keys per bin
+  static constexpr uint32_t MAXBINS = (CAP / MEAN < 2048) ? CAP / MEAN : 2048;
   static constexpr bool IDX = !T::KEYS_ONLY;
   // dynamic LDS: keys[CAP] | idx[CAP] (records) | stage[CAP * DW] (records)
   static constexpr size_t lds_bytes() {
@@ -199,6 +223,8 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   __shared__ uint32_t s_cnt[MAXBINS];
   __shared__ uint32_t s_off[MAXBINS + 1];
   __shared__ Img s_min[NT / 64], s_max[NT / 64];
+  __shared__ uint16_t s_list[MAXBINS];       // bins grouped by size class
+  __shared__ uint32_t s_ccnt[3], s_cbase[3];
   __shared__ uint32_t s_big[64];
   __shared__ uint32_t s_wsum[NT / 64];
   __shared__ uint32_t s_nbig, s_fallback;
@@ -214,13 +240,6 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   }
   if (n < 2) return;
   uint32_t* gd = data + t.l * DW;
-#ifdef IPS_LDS_STATS
-  uint64_t ts[6];
-  ts[0] = clock64();
-#define LDS_TS(i) (ts[i] = clock64())
-#else
-#define LDS_TS(i) ((void)0)
-#endif
 
   // 1. Load keys into registers (records: also stage the records in LDS).
   Key k[E];
@@ -263,6 +282,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   if (lane == 0) { s_min[wave] = mn; s_max[wave] = mx; }
   for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
   if (tid == 0) { s_nbig = 0; s_fallback = 0; }
+  if (tid < 3) s_ccnt[tid] = 0;
   __syncthreads();
   mn = s_min[0];
   mx = s_max[0];
@@ -271,11 +291,10 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
     mx = s_max[w] > mx ? s_max[w] : mx;
   }
   if (mn == mx) return;   // all keys equal: already sorted
-  LDS_TS(1);
 
   // 2./3. Bins, counts, scan, scatter.
   uint32_t lb = 1;
-  while ((1u << lb) < MAXBINS && (1u << lb) * (NET / 2) < n) ++lb;
+  while ((1u << lb) < MAXBINS && (1u << lb) * LT::MEAN < n) ++lb;
   const uint32_t span = bitlen((Img)(mx - mn));
   const uint32_t shift = span > lb ? span - lb : 0;
   const uint32_t nbins = 1u << lb;
@@ -299,36 +318,57 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
     }
   }
   __syncthreads();
-  LDS_TS(2);
 
-  // 4. Small bins in registers; larger ones listed for the wavefronts.
-  for (uint32_t b = tid; b < nbins; b += NT) {
-    const uint32_t s = s_cnt[b], o = s_off[b];
-    if (s <= 1) continue;
-    if (s <= NET) {
-      Key v[NET];
-      uint32_t ix[NET];
+  // 4. Bins by size class: up to NET/4 and up to NET/2 keys are sorted in
+  // registers by one thread each with a network of that size (each class in
+  // its own pass, so that a wavefront runs one network size); the few larger
+  // bins are listed for the wavefronts.
+  constexpr uint32_t BPT = (MAXBINS + NT - 1) / NT;   // bins per thread
+  uint32_t cls_of[BPT];
 #pragma unroll
-      for (uint32_t i = 0; i < NET; ++i) {
-        v[i] = (i < s) ? keys[o + i] : T::kmax();
-        ix[i] = (i < s) ? (IDX ? (uint32_t)idxb[o + i] : 0u) : 0xFFFFFFFFu;
-      }
-      reg_network<NET, Key, IDX>(v, ix);
-#pragma unroll
-      for (uint32_t i = 0; i < NET; ++i) {
-        if (i < s) {
-          keys[o + i] = v[i];
-          if constexpr (IDX) idxb[o + i] = (uint16_t)ix[i];
+  for (uint32_t q = 0; q < BPT; ++q) {
+    const uint32_t b = q * NT + tid;
+    cls_of[q] = 4;
+    if (b < nbins) {
+      const uint32_t sz = s_cnt[b];
+      if (sz > 1) {
+        cls_of[q] = sz <= NET / 4 ? 0u : (sz <= NET / 2 ? 1u : 3u);
+        if (cls_of[q] < 3) {
+          atomicAdd(&s_ccnt[cls_of[q]], 1u);
+        } else {
+          const uint32_t slot = atomicAdd(&s_nbig, 1u);
+          if (slot < 64) s_big[slot] = b;
+          else s_fallback = 1;
         }
       }
-    } else {
-      const uint32_t slot = atomicAdd(&s_nbig, 1u);
-      if (slot < 64) s_big[slot] = b;
-      else s_fallback = 1;
     }
   }
   __syncthreads();
-  LDS_TS(3);
+  if (tid == 0) {
+    s_cbase[0] = 0;
+    s_cbase[1] = s_ccnt[0];
+    s_cbase[2] = s_ccnt[0] + s_ccnt[1];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < BPT; ++q) {
+    const uint32_t c = cls_of[q];
+    if (c < 3) s_list[atomicAdd(&s_cbase[c], 1u)] = (uint16_t)(q * NT + tid);
+  }
+  __syncthreads();
+  {
+    const uint32_t n0 = s_ccnt[0], n1 = s_ccnt[1], n2 = s_ccnt[2];
+    for (uint32_t q = tid; q < n0; q += NT) {
+      const uint32_t b = s_list[q];
+      sort_bin<T, IDX, NET / 4>(keys, idxb, s_off[b], s_cnt[b]);
+    }
+    for (uint32_t q = tid; q < n1; q += NT) {
+      const uint32_t b = s_list[n0 + q];
+      sort_bin<T, IDX, NET / 2>(keys, idxb, s_off[b], s_cnt[b]);
+    }
+    (void)n2;
+  }
+  __syncthreads();
   const uint32_t nbig = s_nbig < 64 ? s_nbig : 64;
   if (!s_fallback) {
     for (uint32_t q = wave; q < nbig; q += NT / 64) {
@@ -346,7 +386,6 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   __syncthreads();
   if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
   __syncthreads();
-  LDS_TS(4);
 
   // 5. Store.
   if constexpr (IDX) {
@@ -361,17 +400,6 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
       st_elem<DW>(gd + (uint64_t)i * DW, w);
     }
   }
-#ifdef IPS_LDS_STATS
-  __syncthreads();
-  LDS_TS(5);
-  if (tid == 0) {
-    unsigned long long* c = reinterpret_cast<unsigned long long*>(ctrl + 50);
-    for (int i = 0; i < 5; ++i) atomicAdd(&c[i], (unsigned long long)(ts[i + 1] - ts[i]));
-    atomicAdd(&c[5], 1ull);
-    atomicAdd(&c[6], (unsigned long long)n);
-  }
-#endif
-#undef LDS_TS
 }
 
 }  // namespace ips
