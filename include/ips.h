@@ -78,6 +78,13 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
                                           ips_get_root_info */
 #define IPS_FLAG_PROFILE 0x20u        /* time every kernel launch with HIP events on
                                           `stream`; see ips_get_profile */
+#define IPS_FLAG_GRAPH 0x40u          /* capture a round of device-planned steps as a HIP
+                                          graph once per call and replay it until the task
+                                          queue is empty; `stream` must be a created stream
+                                          (not the null stream) that is not capturing;
+                                          IPS_FLAG_PROFILE is ignored */
+#define IPS_FLAG_HOST_PLAN 0x80u      /* plan every batch on the host from read-back bucket
+                                          sizes instead of on the device */
 #define IPS_FLAG_GLOBAL_BUFFERS 0x10u /* keep the classification buffer blocks in the
                                           workspace instead of LDS, so that block_bytes
                                           may exceed the LDS budget (e.g. 2 KiB blocks

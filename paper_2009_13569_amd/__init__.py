@@ -35,6 +35,8 @@ FLAG_EQ_OFF = 0x4
 FLAG_LEVEL1_ONLY = 0x8
 FLAG_GLOBAL_BUFFERS = 0x10
 FLAG_PROFILE = 0x20
+FLAG_GRAPH = 0x40
+FLAG_HOST_PLAN = 0x80
 MAX_LEVELS = 16
 PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags", "permute",
           "cleanup_a", "cleanup_b", "lds_sort", "reverse"]

@@ -48,7 +48,24 @@ enum CtrlSlot : uint32_t {
   CTRL_NLDS = 12,      // children of a batch: LDS-tier tasks per variant (12..14)
   CTRL_NNEXT = 15,     // children of a batch: next-level tasks
   CTRL_LDSEL = 16,     // children of a batch: u64 elements per LDS-tier variant (16..21)
-  CTRL_WORDS = 64
+  // device-planned execution (queue of tasks, per-step counts, statistics)
+  CTRL_QHEAD = 64,     // next task to take from the queue
+  CTRL_QTAIL = 65,     // end of the queued tasks
+  CTRL_T = 66,         // tasks of the current step
+  CTRL_NWG = 67,       // classification workgroups of the step
+  CTRL_NPWG = 68,      // permutation workgroups of the step
+  CTRL_NCLN = 69,      // buckets of the step (cleanup items)
+  CTRL_NFLAGS = 70,    // block flags of the step
+  CTRL_MAXW = 71,      // largest stripe count of the step
+  CTRL_SPOP = 72,      // stripe length the step's tasks were chosen for (u64: 72..73)
+  CTRL_STEPS = 74,     // statistics: partitioning steps (tasks)
+  CTRL_BATCHES = 75,   // statistics: steps with tasks
+  CTRL_LEVELS = 76,    // statistics: deepest level + 1
+  CTRL_LDSTASKS = 77,  // statistics: LDS-tier tasks
+  CTRL_PARTEL = 78,    // statistics: u64 elements partitioned (78..79)
+  CTRL_LDSELT = 80,    // statistics: u64 elements sorted in the LDS tier (80..81)
+  CTRL_MAXSTEP = 82,   // statistics: u64 largest task (82..83)
+  CTRL_WORDS = 128
 };
 
 // Device error codes.
@@ -64,6 +81,8 @@ enum DevErr : uint32_t {
   DE_CLN_RANGE = 8,
   DE_LDST = 9,            // task too large for the LDS tier
   DE_BLOCK = 10,          // block larger than the group can hold
+  DE_PLAN = 11,           // a step's geometry exceeds the workspace budgets
+  DE_QUEUE = 12,          // task queue overflow
 };
 
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
@@ -134,6 +153,14 @@ struct ChildArgs {
   uint32_t lt_cap, next_cap;
 };
 
+// Workspace budgets and parameters of the device-planned execution (the
+// same rules the host applies when it plans a batch).
+struct PlanCfg {
+  uint64_t SB, SPB, FB, PB, slot_max;
+  uint32_t TB, WB, PWB, NBE, QCAP, CLNB;
+  uint32_t D, DW, k, n0, cap, cmax, groups, b_req, gbuf, radix, tflags0, wg_target;
+};
+
 // Arguments shared by the kernels of one batch.
 struct BatchArgs {
   uint32_t* data;             // the array (as dwords)
@@ -170,6 +197,12 @@ struct BatchArgs {
   uint32_t* t_unproc;         // [task] unprocessed blocks in total
   uint32_t gbuf;              // buffer blocks in the slots instead of LDS
   uint32_t ntasks;
+  CTask* queue;               // device-planned execution: task ring buffer
+  uint32_t qcap;              // its capacity
+  uint32_t devplan;           // 1: counts of the step come from the control block
+  uint32_t step;              // device-planned execution: step number of the launch
+  uint64_t* step_el;          // [step][0]: elements partitioned, [1 + v]: LDS-tier variant v
 };
+constexpr uint32_t MAX_STEPS_RECORDED = 64;
 
 }  // namespace ips

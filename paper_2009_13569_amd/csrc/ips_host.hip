@@ -107,7 +107,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     c->b_req = paper_block(D);
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
-  if (p->flags & ~0x3Fu) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0xFFu) return IPS_E_INVALID_ARG;
   if (p->profile_mask >> IPS_PHASES) return IPS_E_INVALID_ARG;
   c->L = nullptr;
   return IPS_OK;
@@ -160,6 +160,7 @@ uint32_t max_nb(const Cfg& c) { return c.radix ? MAX_K : 2 * c.k; }
 struct Layout {
   uint32_t TB, WB, PWB, LTB, NBE;   // tasks, cls WGs, perm WGs, LDS tasks, bucket entries
   uint32_t NXB;                     // next-level tasks one batch can produce
+  uint32_t QCAP;                    // task queue of the device-planned execution
   uint64_t SB, SPB, FB, PB;         // slot bytes, spill bytes, flag words, pieces
   uint64_t slot_max;
   size_t off[40];
@@ -169,7 +170,7 @@ struct Layout {
 enum Region {
   R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
   R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
-  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_LTC, R_NEXT, R_COUNT
+  R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_LTC, R_NEXT, R_QUEUE, R_STEPEL, R_COUNT
 };
 
 void plan(uint64_t n, const Cfg& c, Layout* L) {
@@ -233,6 +234,9 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_LTC] = 3 * (size_t)L->LTB * sizeof(LTask);     // children for the LDS tier, per variant
   L->NXB = (uint32_t)std::min<uint64_t>((uint64_t)L->TB * nbm, tasks_ub + L->TB);
   sz[R_NEXT] = (size_t)L->NXB * sizeof(CTask);
+  L->QCAP = (uint32_t)std::min<uint64_t>(tasks_ub + L->TB, 0xFFFFFFF0ull);
+  sz[R_QUEUE] = (size_t)L->QCAP * sizeof(CTask);
+  sz[R_STEPEL] = (size_t)MAX_STEPS_RECORDED * 4 * 8;
   sz[R_TNP] = (size_t)L->TB * 4;
   sz[R_TUP] = (size_t)L->TB * 4;
   sz[R_LT] = (size_t)L->LTB * sizeof(LTask);
@@ -263,7 +267,8 @@ struct ips_ctx {
   size_t pin_bytes = 0;
   // Launch timing (IPS_FLAG_PROFILE): event pairs resolved at sync points.
   std::vector<hipEvent_t> ev_pool;
-  struct Pending { hipEvent_t a, b; uint32_t row, ph; uint64_t elems; };
+  // src >= 0: elems are read from the device's per-step record src of step row
+  struct Pending { hipEvent_t a, b; uint32_t row, ph; uint64_t elems; int src; };
   std::vector<Pending> pending;
   bool profiling = false;
   uint32_t profile_mask = 0;   // phases timed (0: all)
@@ -299,7 +304,8 @@ void resolve_profile(ips_ctx* ctx) {
 
 // Brackets one launch with events when profiling.
 template <class F>
-hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64_t elems, F&& launch) {
+hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64_t elems, F&& launch,
+                 int src = -1) {
   if (!ctx->profiling || (ctx->profile_mask && !((ctx->profile_mask >> ph) & 1u))) return launch();
   hipEvent_t a = take_event(ctx), b = take_event(ctx);
   if (!a || !b) return hipErrorOutOfMemory;
@@ -310,7 +316,7 @@ hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64
   e = hipEventRecord(b, st);
   if (e != hipSuccess) return e;
   if (row > IPS_MAX_LEVELS) row = IPS_MAX_LEVELS;
-  ctx->pending.push_back({a, b, row, ph, elems});
+  ctx->pending.push_back({a, b, row, ph, elems, src});
   return hipSuccess;
 }
 
@@ -400,7 +406,8 @@ int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
       uint64_t el = 0;
       for (size_t q = p0; q < p1; ++q) el += lt[q].n;
       HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
-               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, v, r.a.ctrl, r.st);
+               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, v, r.a.ctrl, nullptr,
+                                      0, r.st);
              }));
     }
     done += cnt;
@@ -421,7 +428,7 @@ hipError_t launch_lds_lists(Run& r, const ChildArgs& ca, const uint32_t (&cnt)[3
     if (!cnt[v]) continue;
     if (v && r.c.L->lds_caps[v] == r.c.L->lds_caps[v - 1]) return hipErrorInvalidValue;
     hipError_t e = timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el[v], [&] {
-      return r.c.L->lds_sort(ca.lt[v], cnt[v], r.data, v, r.a.ctrl, r.st);
+      return r.c.L->lds_sort(ca.lt[v], cnt[v], r.data, v, r.a.ctrl, nullptr, 0, r.st);
     });
     if (e != hipSuccess) return e;
     r.ctx->stats.lds_tasks += cnt[v];
@@ -826,6 +833,11 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   a.t_npieces = wsp<uint32_t>(r, R_TNP);
   a.t_unproc = wsp<uint32_t>(r, R_TUP);
   a.gbuf = r.c.gbuf ? 1 : 0;
+  a.queue = wsp<CTask>(r, R_QUEUE);
+  a.qcap = r.L.QCAP;
+  a.devplan = 0;
+  a.step = 0;
+  a.step_el = wsp<uint64_t>(r, R_STEPEL);
   // Control block: errors and flags cleared; min = all ones, max = 0.
   HIPCHK(ctx, launch_fill32(a.ctrl, CTRL_WORDS, 0u, r.st));
   HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_MINMAX, 2, 0xFFFFFFFFu, r.st));
@@ -892,6 +904,153 @@ int level_loop(Run& r, std::vector<HTask> cur, const std::vector<LTask>& lds_roo
   return read_ctrl(r);
 }
 
+// Device-planned execution (the same steps as level_loop, planned on the
+// device): the roots go into a task queue in the workspace; each step takes
+// the next batch from the queue, partitions it, pushes its large buckets
+// back onto the queue and sorts its small ones in the LDS tier.  The host
+// enqueues several steps at a time and only reads the queue state between
+// rounds of steps; with IPS_FLAG_GRAPH a round is captured once as a HIP
+// graph and replayed.
+int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) {
+  ips_ctx* ctx = r.ctx;
+  const Cfg& c = r.c;
+  BatchArgs a = r.a;
+  a.devplan = 1;
+  a.step = step;
+  const uint32_t row = std::min<uint32_t>(step, IPS_MAX_LEVELS - 1);
+  const uint32_t nbm = max_nb(c);
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_SAMPLE, 0, [&] {
+           hipError_t e = launch_plan_pop(a, pc, r.st);
+           if (e != hipSuccess || c.radix) return e;
+           return c.L->sample(a, r.L.TB, c.seed, r.st);
+         }, 0));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, 0, [&] {
+           hipError_t e = launch_plan_geom(a, pc, r.st);
+           if (e != hipSuccess) return e;
+           return launch_fill32_cnt(a.flags, a.ctrl + CTRL_NFLAGS, (uint32_t)std::min<uint64_t>(r.L.FB, 0xFFFFFFFFu),
+                                    0u, r.st);
+         }, 0));
+  const size_t dyn = c.gbuf ? 0 : (size_t)BUF_LDS_BYTES + (size_t)MAX_NB * BUF_PAD_DW * 4;
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, 0,
+                    [&] { return c.L->classify(a, r.L.WB, (uint32_t)dyn, c.gbuf, r.st); }, 0));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0,
+                    [&] { return launch_boundaries(a, r.L.TB, nbm, c.cmax, r.st); }, 0));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, 0, [&] { return c.L->permute(a, r.L.PWB, r.st); }, 0));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, 0, [&] { return c.L->cleanup_a(a, r.L.TB, r.st); }, 0));
+  const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
+                    [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
+  HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_NLDS, 10, 0u, r.st));
+  HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
+  for (uint32_t v = 0; v < 3; ++v) {
+    if (v && c.L->lds_caps[v] == c.L->lds_caps[v - 1]) continue;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(r.L.LTB, 2048);
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_LDS_SORT, 0, [&] {
+             return c.L->lds_sort(ca.lt[v], grid, r.data, v, a.ctrl, a.ctrl + CTRL_NLDS + v, ca.lt_cap, r.st);
+           }, 1 + (int)v));
+  }
+  return IPS_OK;
+}
+
+int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask>& lds_roots) {
+  ips_ctx* ctx = r.ctx;
+  const Cfg& c = r.c;
+  if (!lds_roots.empty()) {
+    for (const LTask& t : lds_roots) ctx->stats.lds_elems += t.n;
+    if (int e = launch_lds_tasks(r, lds_roots, 0)) return e;
+  }
+  if (roots.empty()) return read_ctrl(r);
+  if (roots.size() > r.L.QCAP) { ctx->last_dev = 0x103; return IPS_E_DEVICE; }
+  // Roots onto the queue (through the readback staging area, in chunks).
+  CTask* h = reinterpret_cast<CTask*>(r.h_rb);
+  const size_t chunk = r.rb_bytes / sizeof(CTask);
+  for (size_t done = 0; done < roots.size();) {
+    const size_t cnt = std::min(chunk, roots.size() - done);
+    for (size_t i = 0; i < cnt; ++i) {
+      const HTask& t = roots[done + i];
+      h[i].l = t.l; h[i].n = t.n; h[i].level = t.level; h[i].tflags = t.tflags;
+      h[i].shift = t.shift; h[i].width = t.width;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(r.a.queue + done, h, cnt * sizeof(CTask), hipMemcpyHostToDevice, r.st));
+    HIPCHK(ctx, hipStreamSynchronize(r.st));
+    done += cnt;
+  }
+  HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_QHEAD, 1, 0u, r.st));
+  HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_QTAIL, 1, (uint32_t)roots.size(), r.st));
+  HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(r.a.step_el), MAX_STEPS_RECORDED * 8, 0u, r.st));
+  PlanCfg pc;
+  pc.SB = r.L.SB; pc.SPB = r.L.SPB; pc.FB = r.L.FB; pc.PB = r.L.PB; pc.slot_max = r.L.slot_max;
+  pc.TB = r.L.TB; pc.WB = r.L.WB; pc.PWB = r.L.PWB; pc.NBE = r.L.NBE; pc.QCAP = r.L.QCAP;
+  pc.CLNB = r.L.TB * max_nb(c);
+  pc.D = c.D; pc.DW = c.DW; pc.k = c.k; pc.n0 = c.n0; pc.cap = c.cap; pc.cmax = c.cmax;
+  pc.groups = c.groups; pc.b_req = c.b_req; pc.gbuf = c.gbuf ? 1 : 0; pc.radix = c.radix ? 1 : 0;
+  pc.tflags0 = 0; pc.wg_target = WG_TARGET;
+  ChildArgs ca;
+  LTask* d_ltc = wsp<LTask>(r, R_LTC);
+  for (uint32_t v = 0; v < 3; ++v) {
+    ca.lt[v] = d_ltc + (size_t)v * r.L.LTB;
+    ca.caps[v] = std::min(c.cap, c.L->lds_caps[v]);
+  }
+  ca.next = wsp<CTask>(r, R_NEXT);
+  ca.lt_cap = r.L.LTB;
+  ca.next_cap = r.L.NXB;
+  const bool graph = (c.flags & IPS_FLAG_GRAPH) != 0;
+  if (graph) ctx->profiling = false;   // no event records inside a captured graph
+  uint64_t* h_sel = reinterpret_cast<uint64_t*>(r.h_rb);
+  uint32_t step = 0, round_steps = 4;
+  hipGraphExec_t exec = nullptr;
+  int rc = IPS_OK;
+  for (uint32_t round = 0;; ++round) {
+    if (graph) {
+      if (!exec) {   // one round of steps, captured once and replayed
+        hipGraph_t g = nullptr;
+        HIPCHK(ctx, hipStreamBeginCapture(r.st, hipStreamCaptureModeThreadLocal));
+        int e = IPS_OK;
+        for (uint32_t s = 0; s < round_steps && e == IPS_OK; ++s) e = enqueue_step(r, pc, ca, MAX_STEPS_RECORDED);
+        hipError_t ce = hipStreamEndCapture(r.st, &g);
+        if (e != IPS_OK) { if (g) (void)hipGraphDestroy(g); return e; }
+        if (ce != hipSuccess) { ctx->last_hip = (int)ce; return IPS_E_HIP; }
+        hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) { ctx->last_hip = (int)ie; return IPS_E_HIP; }
+      }
+      hipError_t le = hipGraphLaunch(exec, r.st);
+      if (le != hipSuccess) { ctx->last_hip = (int)le; rc = IPS_E_HIP; break; }
+      step += round_steps;
+    } else {
+      for (uint32_t s = 0; s < round_steps; ++s, ++step)
+        if (int e = enqueue_step(r, pc, ca, step)) return e;
+    }
+    hipError_t e1 = hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, r.st);
+    hipError_t e2 = hipMemcpyAsync(h_sel, r.a.step_el, MAX_STEPS_RECORDED * 32, hipMemcpyDeviceToHost, r.st);
+    hipError_t e3 = hipStreamSynchronize(r.st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      ctx->last_hip = (int)(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3);
+      rc = IPS_E_HIP;
+      break;
+    }
+    for (auto& pe : ctx->pending)
+      if (pe.src >= 0 && pe.row < MAX_STEPS_RECORDED) pe.elems = h_sel[pe.row * 4 + pe.src];
+    resolve_profile(ctx);
+    if ((rc = check_dev_error(r)) != IPS_OK) break;
+    if (r.h_ctrl[CTRL_QHEAD] == r.h_ctrl[CTRL_QTAIL]) break;
+    if (!graph) round_steps = std::min<uint32_t>(round_steps * 2, 32);
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (rc != IPS_OK) return rc;
+  ips_stats& st = ctx->stats;
+  auto u64at = [&](uint32_t w) { return (uint64_t)r.h_ctrl[w] | ((uint64_t)r.h_ctrl[w + 1] << 32); };
+  st.steps += r.h_ctrl[CTRL_STEPS];
+  st.batches += r.h_ctrl[CTRL_BATCHES];
+  st.levels = std::max<uint32_t>(st.levels, r.h_ctrl[CTRL_LEVELS]);
+  st.lds_tasks += r.h_ctrl[CTRL_LDSTASKS];
+  st.partitioned_elems += u64at(CTRL_PARTEL);
+  st.lds_elems += u64at(CTRL_LDSELT);
+  st.max_step_elems = std::max<uint64_t>(st.max_step_elems, u64at(CTRL_MAXSTEP));
+  ctx->prof.levels = std::min<uint32_t>(std::min<uint32_t>(step, IPS_MAX_LEVELS), st.levels);
+  return IPS_OK;
+}
+
 int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, size_t ws_bytes,
               const ips_params* params, void* stream) {
   Run r;
@@ -933,7 +1092,9 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
     lt[0].pad = 0;
     return level_loop(r, {}, lt, true);
   }
-  return level_loop(r, std::vector<HTask>(1, root), {}, true);
+  if (r.c.flags & (IPS_FLAG_LEVEL1_ONLY | IPS_FLAG_HOST_PLAN))
+    return level_loop(r, std::vector<HTask>(1, root), {}, true);
+  return device_loop(r, std::vector<HTask>(1, root), {});
 }
 
 // Checks a segment list against the data length: every segment inside
@@ -1087,7 +1248,8 @@ int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
     if (finished[q]) continue;
     if (make_root(r.c, segs[big[q]].offset, segs[big[q]].n, mn[q], mx[q], &t)) roots.push_back(t);
   }
-  return level_loop(r, roots, lt, false);
+  if (r.c.flags & IPS_FLAG_HOST_PLAN) return level_loop(r, roots, lt, false);
+  return device_loop(r, roots, lt);
 }
 
 // Requests in separate device buffers: those whose addresses are congruent

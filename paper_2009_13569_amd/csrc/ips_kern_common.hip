@@ -29,4 +29,21 @@ hipError_t launch_children(const BatchArgs& a, const ChildArgs& c, uint32_t nt, 
   return hipGetLastError();
 }
 
+hipError_t launch_plan_pop(const BatchArgs& a, const PlanCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_pop, dim3(1), dim3(PLAN_THREADS), 0, st, a, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_geom(const BatchArgs& a, const PlanCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_geom, dim3(1), dim3(PLAN_THREADS), 0, st, a, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n, uint32_t v, hipStream_t st) {
+  if (!max_n) return hipSuccess;
+  uint32_t g = (max_n + 255) / 256 < 4096 ? (max_n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_fill32_cnt, dim3(g), dim3(256), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
 }  // namespace ips

@@ -71,7 +71,7 @@ struct LaunchImpl {
   }
   template <uint32_t N, uint32_t E>
   static hipError_t lds_launch(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl,
-                               hipStream_t st) {
+                               const uint32_t* cnt, uint32_t cnt_cap, hipStream_t st) {
     static bool attr_done = false;
     const size_t dyn = LdsTier<T, N, E, SH::NET>::lds_bytes();
     if (!attr_done) {
@@ -79,15 +79,17 @@ struct LaunchImpl {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
       attr_done = true;
     }
-    hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl);
+    hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl, cnt,
+                       cnt_cap);
     return hipGetLastError();
   }
+  // nt workgroups; with `cnt` (a device count) they loop over the list.
   static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
-                             hipStream_t st) {
+                             const uint32_t* cnt, uint32_t cnt_cap, hipStream_t st) {
     if (!nt) return hipSuccess;
-    if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, st);
-    if (variant == 1) return lds_launch<SH::N1, SH::E1>(lt, nt, data, ctrl, st);
-    return lds_launch<SH::N0, SH::E0>(lt, nt, data, ctrl, st);
+    if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, cnt, cnt_cap, st);
+    if (variant == 1) return lds_launch<SH::N1, SH::E1>(lt, nt, data, ctrl, cnt, cnt_cap, st);
+    return lds_launch<SH::N0, SH::E0>(lt, nt, data, ctrl, cnt, cnt_cap, st);
   }
   static hipError_t sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
     hipLaunchKernelGGL((k_sorted_sample<T>), dim3(64), dim3(1024), 0, st, data, n, ctrl);

@@ -21,7 +21,7 @@ struct Launchers {
   hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);
   hipError_t (*cleanup_b)(const BatchArgs&, uint32_t nwg, uint32_t max_w, hipStream_t);
   hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
-                         hipStream_t);
+                         const uint32_t* cnt, uint32_t cnt_cap, hipStream_t);
   hipError_t (*sorted_sample)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*sorted_check)(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t);
   hipError_t (*reverse)(uint32_t* data, uint64_t n, hipStream_t);
@@ -43,5 +43,8 @@ hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t max_nb, 
                              hipStream_t);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t);
 hipError_t launch_children(const BatchArgs&, const ChildArgs&, uint32_t ntask, hipStream_t);
+hipError_t launch_plan_pop(const BatchArgs&, const PlanCfg&, hipStream_t);
+hipError_t launch_plan_geom(const BatchArgs&, const PlanCfg&, hipStream_t);
+hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n, uint32_t v, hipStream_t);
 
 }  // namespace ips

@@ -209,10 +209,9 @@ struct LdsTier {
   }
 };
 
-// Two 512-thread workgroups per CU: at most 128 VGPRs (4 waves per SIMD).
+// Sorts LDS-tier task number `ti` of the list.
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
-__global__ void __launch_bounds__(NT, (NT <= 512 ? 4 : 1))
-k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
+__device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint32_t* ctrl) {
   using LT = LdsTier<T, NT, E, NET>;
   using Key = typename T::Key;
   using Img = decltype(bin_image(Key()));
@@ -232,10 +231,10 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
   uint32_t* stage = reinterpret_cast<uint32_t*>(idxb + CAP);
-  const LTask t = lt[blockIdx.x];
+  const LTask t = lt[ti];
   const uint32_t n = t.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (n > CAP) {
-    if (tid == 0) dev_error(ctrl, DE_LDST, blockIdx.x, n);
+    if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
     return;
   }
   if (n < 2) return;
@@ -302,7 +301,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
 #pragma unroll
   for (uint32_t e = 0; e < E; ++e) {
     if (e * NT + tid < n) {
-      bin[e] = (uint32_t)((bin_image(k[e]) - mn) >> shift);
+      bin[e] = lo32_shr((Img)(bin_image(k[e]) - mn), shift);
       rk[e] = atomicAdd(&s_cnt[bin[e]], 1u);
     }
   }
@@ -399,6 +398,19 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl) {
       T::from_key(keys[i], w);
       st_elem<DW>(gd + (uint64_t)i * DW, w);
     }
+  }
+}
+
+// One workgroup per task of the list; with a device count (`cnt` not null,
+// at most cnt_cap) the grid loops over the list.  At most 128 VGPRs (4 waves per SIMD).
+template <class T, uint32_t NT, uint32_t E, uint32_t NET>
+__global__ void __launch_bounds__(NT, (NT <= 512 ? 4 : 1))
+k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap) {
+  uint32_t count = gridDim.x;
+  if (cnt) count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
+  for (uint32_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    lds_tier_task<T, NT, E, NET>(lt, ti, data, ctrl);
+    __syncthreads();
   }
 }
 

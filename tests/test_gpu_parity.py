@@ -34,6 +34,26 @@ def test_lds_tier(sorter, kind):
         assert_parity(gpu_sort(sorter, a, kind), a, kind)
 
 
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
+def test_lds_tier_sorted_reverse_repeated(sorter, kind):
+    """Sorted and reverse inputs whose last keys sit in a partly filled
+    register slot, each sorted many times.  A 64-bit shift reading its amount
+    from outside the wavefront's register allocation once gave one
+    wavefront's keys wrong bins in about one run in ten for such inputs (u64,
+    5000 and 5832 keys); the kernels now build those shifts from 32-bit
+    operations."""
+    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096}[kind]
+    flags = ips.FLAG_NO_SORTED_CHECK
+    for n in (5000, 5832, int(cap * 0.3) + 7, int(cap * 0.7) + 3):
+        n = min(n, cap)
+        base = generate(kind, "uniform", n, 7 + n)
+        ref = oracle.sort(base, kind)
+        for name, a in (("sorted", ref), ("reverse", ref[::-1].copy())):
+            log(f"lds repeat {kind} {name} n={n}")
+            for _ in range(12):
+                assert_parity(gpu_sort(sorter, a, kind, params=ips.make_params(flags=flags)), a, kind, ref)
+
+
 DISTS = {
     "u32": ["uniform", "exponential", "rootdup", "twodup", "eightdup", "almostsorted", "zipf"],
     "u64": ["uniform", "exponential", "rootdup", "twodup", "eightdup", "almostsorted", "zipf"],
