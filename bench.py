@@ -355,7 +355,8 @@ def kernel_stats_summary(csv_path: str) -> int:
     print("Command (`cd /tmp`, `TMPDIR=/tmp`, R = repo root): `rocprofv3 --kernel-trace --stats --output-format csv "
           "-d $R/gpurun_out/ktrace -o kt -- python3 $R/bench.py --steps 3 --warmup 1 --no-cpu --no-radix`; "
           "table from `python3 bench.py --kernel-stats-summary gpurun_out/ktrace/kt_kernel_stats.csv`.\n")
-    print("4 sorts (1 warmup + 3 timed) plus the bench's own copies and checks; durations in microseconds.\n")
+    print("6 sorts (1 warmup, 3 timed, 2 timed per kernel for the per-level table) plus the bench's own "
+          "copies and checks; durations in microseconds.\n")
     print("| kernel | calls | total us | avg us | % |")
     print("|---|---|---|---|---|")
     for r in rows[:16]:

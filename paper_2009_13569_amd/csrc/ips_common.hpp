@@ -48,6 +48,7 @@ enum CtrlSlot : uint32_t {
   CTRL_NLDS = 12,      // children of a batch: LDS-tier tasks per variant (12..14)
   CTRL_NNEXT = 15,     // children of a batch: next-level tasks
   CTRL_LDSEL = 16,     // children of a batch: u64 elements per LDS-tier variant (16..21)
+  CTRL_LDSPOP = 22,    // LDS-tier tasks claimed per variant (22..24), zeroed with NLDS..LDSEL
   // device-planned execution (queue of tasks, per-step counts, statistics)
   CTRL_QHEAD = 64,     // next task to take from the queue
   CTRL_QTAIL = 65,     // end of the queued tasks

@@ -626,7 +626,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   const uint32_t next_pre = (uint32_t)std::min<size_t>(r.L.NXB, (r.rb_bytes / 2) / sizeof(CTask));
   uint64_t* h_root = reinterpret_cast<uint64_t*>(r.h_rb + r.rb_bytes / 2);
   if (!level1) {
-    HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 10, 0u, r.st));
+    HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 13, 0u, r.st));
     HIPCHK(ctx, launch_children(r.a, ca, T, r.st));
     HIPCHK(ctx, hipMemcpyAsync(h_next, ca.next, (size_t)next_pre * sizeof(CTask), hipMemcpyDeviceToHost, r.st));
   }
@@ -940,7 +940,7 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
   const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
                     [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
-  HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_NLDS, 10, 0u, r.st));
+  HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_NLDS, 13, 0u, r.st));
   HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
   for (uint32_t v = 0; v < 3; ++v) {
     if (v && c.L->lds_caps[v] == c.L->lds_caps[v - 1]) continue;

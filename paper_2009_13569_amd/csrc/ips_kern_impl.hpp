@@ -71,25 +71,40 @@ struct LaunchImpl {
   }
   template <uint32_t N, uint32_t E>
   static hipError_t lds_launch(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl,
-                               const uint32_t* cnt, uint32_t cnt_cap, hipStream_t st) {
+                               const uint32_t* cnt, uint32_t cnt_cap, uint32_t* pop, hipStream_t st) {
     static bool attr_done = false;
+    static uint32_t resident = 0;   // workgroups of this kernel the device holds at once
     const size_t dyn = LdsTier<T, N, E, SH::NET>::lds_bytes();
     if (!attr_done) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_tier<T, N, E, SH::NET>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+      int per_cu = 0, cus = 0, dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(
+                                                           &k_lds_tier<T, N, E, SH::NET>), (int)N, dyn) ==
+              hipSuccess &&
+          per_cu > 0 && cus > 0)
+        resident = (uint32_t)(per_cu * cus);
       attr_done = true;
     }
+    // Claiming workgroups (device count): more than the resident ones only
+    // add empty launches.
+    if (cnt && resident && nt > resident) nt = resident;
     hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl, cnt,
-                       cnt_cap);
+                       cnt_cap, pop);
     return hipGetLastError();
   }
-  // nt workgroups; with `cnt` (a device count) they loop over the list.
+  // nt workgroups; with `cnt` (a device count) they claim the list's tasks
+  // through the variant's counter ctrl[CTRL_LDSPOP + variant] (zero at launch).
   static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
                              const uint32_t* cnt, uint32_t cnt_cap, hipStream_t st) {
     if (!nt) return hipSuccess;
-    if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, cnt, cnt_cap, st);
-    if (variant == 1) return lds_launch<SH::N1, SH::E1>(lt, nt, data, ctrl, cnt, cnt_cap, st);
-    return lds_launch<SH::N0, SH::E0>(lt, nt, data, ctrl, cnt, cnt_cap, st);
+    if (variant > 2) return hipErrorInvalidValue;
+    uint32_t* pop = cnt ? ctrl + CTRL_LDSPOP + variant : nullptr;
+    if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, cnt, cnt_cap, pop, st);
+    if (variant == 1) return lds_launch<SH::N1, SH::E1>(lt, nt, data, ctrl, cnt, cnt_cap, pop, st);
+    return lds_launch<SH::N0, SH::E0>(lt, nt, data, ctrl, cnt, cnt_cap, pop, st);
   }
   static hipError_t sorted_sample(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
     hipLaunchKernelGGL((k_sorted_sample<T>), dim3(64), dim3(1024), 0, st, data, n, ctrl);

@@ -87,6 +87,10 @@ __device__ __forceinline__ uint64_t shl64(uint64_t x, uint32_t s) {
   const uint32_t rlo = up ? 0u : (lo << r);
   return ((uint64_t)rhi << 32) | rlo;
 }
+// A shift amount that is the same in every lane, moved to a scalar register:
+// 64-bit shifts by an SGPR amount are not affected by the hazard above and
+// take one instruction.
+__device__ __forceinline__ uint32_t uniform_amount(uint32_t s) { return __builtin_amdgcn_readfirstlane(s); }
 __device__ __forceinline__ uint64_t bit64(uint32_t q) {   // 1 << q
   const uint32_t b = 1u << (q & 31);
   return q >= 32 ? ((uint64_t)b << 32) : (uint64_t)b;
@@ -179,7 +183,7 @@ __device__ __forceinline__ uint32_t bucket_of(const typename T::Key& k, const ty
                                               uint32_t eq, bool radix, uint32_t shift,
                                               uint32_t rmask) {
   if constexpr (T::RADIX_OK) {
-    if (radix) return lo32_shr(T::rkey(k), shift) & rmask;
+    if (radix) return (uint32_t)(T::rkey(k) >> uniform_amount(shift)) & rmask;   // shift is the task's
   }
   return tree_bucket(tree, spl, logK, eq, k);
 }
@@ -194,10 +198,8 @@ struct StartTable {
   uint32_t shift;
   __device__ __forceinline__ uint32_t index(uint64_t x) const {
     if (x < base) return 0;
-    const uint64_t d = x - base;
-    const uint32_t len = d ? 64u - (uint32_t)__clzll(d) : 0u;
-    if (len > shift + START_BITS) return (1u << START_BITS) - 1;
-    return shift >= 64 ? 0u : lo32_shr(d, shift);
+    const uint64_t q = (x - base) >> uniform_amount(shift);   // one table per workgroup
+    return q >= (1u << START_BITS) ? (1u << START_BITS) - 1 : (uint32_t)q;
   }
 };
 
@@ -493,7 +495,7 @@ k_classify(BatchArgs a) {
       if (radix) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-          bk[i] = lo32_shr(T::rkey(key[i]), shift) & rmask;
+          bk[i] = (uint32_t)(T::rkey(key[i]) >> uniform_amount(shift)) & rmask;
           if (full || ts + (uint32_t)i * NT + tid < slen) {
             atomicMin((unsigned long long*)&s_mn[bk[i]], (unsigned long long)T::rkey(key[i]));
             atomicMax((unsigned long long*)&s_mx[bk[i]], (unsigned long long)T::rkey(key[i]));
@@ -1764,12 +1766,24 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
     q.piece_base = (uint32_t)e_piece; q.piece_cap = piece_cap;
     q.bucket_base = (uint32_t)e_bucket;
     q.glanes = gl; q.ngrp = (uint32_t)ng; q.pwg_base = (uint32_t)e_pwg;
+  }
+  // Workgroup-to-task maps of the later kernels, one wavefront per task (a
+  // task may own tens of thousands of entries, a step up to PLAN_THREADS tasks).
+  __shared__ uint32_t s_mb[3][PLAN_THREADS], s_mc[3][PLAN_THREADS];
+  s_mb[0][t] = (uint32_t)e_wg;  s_mc[0][t] = act ? W : 0;
+  s_mb[1][t] = (uint32_t)e_pwg; s_mc[1][t] = act ? nwg : 0;
+  s_mb[2][t] = (uint32_t)e_cln; s_mc[2][t] = act ? nb : 0;
+  __syncthreads();
+  {
     uint32_t* cls = const_cast<uint32_t*>(a.cls_task);
     uint32_t* perm = const_cast<uint32_t*>(a.perm_task);
     uint32_t* cln = const_cast<uint32_t*>(a.cln_map);
-    for (uint32_t x = 0; x < W; ++x) cls[e_wg + x] = t;
-    for (uint32_t x = 0; x < nwg; ++x) perm[e_pwg + x] = t;
-    for (uint32_t j = 0; j < nb; ++j) cln[e_cln + j] = (t << 10) | j;
+    const uint32_t lane = t & 63;
+    for (uint32_t i = t >> 6; i < T; i += PLAN_THREADS / 64) {
+      for (uint32_t x = lane; x < s_mc[0][i]; x += 64) cls[s_mb[0][i] + x] = i;
+      for (uint32_t x = lane; x < s_mc[1][i]; x += 64) perm[s_mb[1][i] + x] = i;
+      for (uint32_t x = lane; x < s_mc[2][i]; x += 64) cln[s_mb[2][i] + x] = (i << 10) | x;
+    }
   }
   if (t == 0) {
     a.ctrl[CTRL_NWG] = (uint32_t)t_wg;

@@ -211,7 +211,7 @@ struct LdsTier {
 
 // Sorts LDS-tier task number `ti` of the list.
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
-__device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint32_t* ctrl) {
+__device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint32_t* ctrl, uint32_t tid) {
   using LT = LdsTier<T, NT, E, NET>;
   using Key = typename T::Key;
   using Img = decltype(bin_image(Key()));
@@ -232,7 +232,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
   uint32_t* stage = reinterpret_cast<uint32_t*>(idxb + CAP);
   const LTask t = lt[ti];
-  const uint32_t n = t.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t n = t.n, lane = tid & 63, wave = tid >> 6;
   if (n > CAP) {
     if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
     return;
@@ -297,11 +297,12 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   const uint32_t span = bitlen((Img)(mx - mn));
   const uint32_t shift = span > lb ? span - lb : 0;
   const uint32_t nbins = 1u << lb;
+  const uint32_t ush = uniform_amount(shift);   // the same in every lane
   uint32_t bin[E], rk[E];
 #pragma unroll
   for (uint32_t e = 0; e < E; ++e) {
     if (e * NT + tid < n) {
-      bin[e] = lo32_shr((Img)(bin_image(k[e]) - mn), shift);
+      bin[e] = (uint32_t)((Img)(bin_image(k[e]) - mn) >> ush);
       rk[e] = atomicAdd(&s_cnt[bin[e]], 1u);
     }
   }
@@ -401,16 +402,40 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
 }
 
-// One workgroup per task of the list; with a device count (`cnt` not null,
-// at most cnt_cap) the grid loops over the list.  At most 128 VGPRs (4 waves per SIMD).
+// One workgroup per task of the list (cnt == nullptr: the grid is the
+// list).  With a device count `cnt` (at most cnt_cap) the workgroups claim
+// tasks from the counter `pop` (zero at launch) until the list is used up,
+// so that long and short tasks balance as with one workgroup per task; the
+// claim of the next task is issued before the current task's key loads and
+// waits with them.
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
 __global__ void __launch_bounds__(NT, (NT <= 512 ? 4 : 1))
-k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap) {
-  uint32_t count = gridDim.x;
-  if (cnt) count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
-  for (uint32_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
-    lds_tier_task<T, NT, E, NET>(lt, ti, data, ctrl);
+k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap,
+           uint32_t* pop) {
+  __shared__ uint32_t s_next;
+  uint32_t count, ti;
+  if (cnt) {
+    count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
+    if (threadIdx.x == 0) s_next = atomicAdd(pop, 1u);
     __syncthreads();
+    ti = s_next;
+  } else {
+    ti = blockIdx.x;
+    count = ti + 1;
+  }
+  while (ti < count) {
+    __syncthreads();   // every thread has read s_next
+    // The thread index is made opaque on every pass so that the compiler
+    // recomputes the many addresses derived from it inside the loop instead
+    // of keeping them all live across it (which costs registers).
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t nxt = count;   // the grid's own task only, without a device count
+    if (cnt && tid == 0) nxt = atomicAdd(pop, 1u);
+    lds_tier_task<T, NT, E, NET>(lt, ti, data, ctrl, tid);
+    if (tid == 0) s_next = nxt;
+    __syncthreads();
+    ti = s_next;
   }
 }
 
