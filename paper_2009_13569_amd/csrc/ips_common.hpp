@@ -88,6 +88,7 @@ enum DevErr : uint32_t {
 
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
 // radix step.  Keys live in 16-byte slots so that every key type fits.
+constexpr uint32_t CHILD_WGS = 1024;   // workgroups of the children kernel (at most)
 constexpr uint32_t START_BITS = 12;   // start-node table: 2^12 entries
 struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;

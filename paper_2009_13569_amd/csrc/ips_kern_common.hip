@@ -25,7 +25,8 @@ hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
 
 hipError_t launch_children(const BatchArgs& a, const ChildArgs& c, uint32_t nt, hipStream_t st) {
   if (!nt) return hipSuccess;
-  hipLaunchKernelGGL(k_children, dim3(nt), dim3(256), 0, st, a, c);
+  const uint32_t grid = nt < CHILD_WGS ? nt : CHILD_WGS;
+  hipLaunchKernelGGL(k_children, dim3(grid), dim3(256), 0, st, a, c, nt);
   return hipGetLastError();
 }
 

@@ -1435,81 +1435,110 @@ __global__ void __launch_bounds__(256) k_seg_minmax(const SegItem* items, const 
 }
 
 #ifdef IPS_COMMON_KERNELS
-// Children of every task of a batch (Section 4.2): one workgroup per task,
-// threads over its buckets.  A bucket of at most one element, an equality
-// bucket, or (radix) a bucket whose keys are all equal is final; a bucket of
-// at most caps[2] elements becomes an LDS-tier task of the smallest variant
-// that holds it; any other bucket becomes a next-level task (with
-// equality buckets forced on when it holds the whole parent, and for radix
-// with the digit below the highest bit in which its keys differ).
-__global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c) {
-  if (a.devplan && blockIdx.x >= a.ctrl[CTRL_T]) return;
-  const PTask& tk = a.tasks[blockIdx.x];
+// Children of every task of a batch (Section 4.2).  A bucket of at most one
+// element, an equality bucket, or (radix) a bucket whose keys are all equal
+// is final; a bucket of at most caps[2] elements becomes an LDS-tier task of
+// the smallest variant that holds it; any other bucket becomes a next-level
+// task (with equality buckets forced on when it holds the whole parent, and
+// for radix with the digit below the highest bit in which its keys differ).
+struct Child {
+  uint32_t dest;            // 0..2: LDS-tier variant, 3: next level, 4: final
+  uint32_t tflags, shift, width;
+  uint64_t s0, sz;
+};
+
+__device__ __forceinline__ Child child_of(const BatchArgs& a, const ChildArgs& c, const PTask& tk, uint32_t j) {
+  Child ch;
+  ch.dest = 4; ch.tflags = 0; ch.shift = 0; ch.width = 0;
   const bool radix = (tk.tflags & TF_RADIX) != 0;
-  const uint32_t nb = tk.nb, bb = tk.bucket_base;
-  uint32_t* cnt = a.ctrl + CTRL_NLDS;
-  unsigned long long* ldsel = reinterpret_cast<unsigned long long*>(a.ctrl + CTRL_LDSEL);
-  uint64_t mine[3] = {0, 0, 0};
-  uint32_t nlds = 0;
-  for (uint32_t j = threadIdx.x; j < nb; j += 256) {
-    const uint64_t s0 = a.b_start[bb + j], sz = a.b_start[bb + j + 1] - s0;
-    if (sz <= 1) continue;
-    if (!radix && tk.eq && (j & 1u) && j != 2 * tk.K - 1) continue;   // equality bucket
-    uint32_t tflags = 0, shift = 0, width = 0;
-    if (radix) {
-      const uint64_t mn = a.b_min[bb + j], mx = a.b_max[bb + j];
-      if (mn == mx) continue;
-      const uint32_t h = 63u - (uint32_t)__clzll(mn ^ mx);
-      shift = h >= 7 ? h - 7 : 0;
-      width = h - shift + 1;
-    } else if (sz == tk.n) {
-      tflags = TF_EQ_ON;   // no progress without equality buckets
+  const uint32_t bb = tk.bucket_base;
+  ch.s0 = a.b_start[bb + j];
+  ch.sz = a.b_start[bb + j + 1] - ch.s0;
+  if (ch.sz <= 1) return ch;
+  if (!radix && tk.eq && (j & 1u) && j != 2 * tk.K - 1) return ch;   // equality bucket
+  if (radix) {
+    const uint64_t mn = a.b_min[bb + j], mx = a.b_max[bb + j];
+    if (mn == mx) return ch;
+    const uint32_t h = 63u - (uint32_t)__clzll(mn ^ mx);
+    ch.shift = h >= 7 ? h - 7 : 0;
+    ch.width = h - ch.shift + 1;
+  } else if (ch.sz == tk.n) {
+    ch.tflags = TF_EQ_ON;   // no progress without equality buckets
+  }
+  ch.dest = ch.sz <= c.caps[2] ? (ch.sz <= c.caps[0] ? 0u : (ch.sz <= c.caps[1] ? 1u : 2u)) : 3u;
+  return ch;
+}
+
+// Workgroups take the tasks by stride, threads the buckets.  A first pass
+// counts each workgroup's children per destination in LDS, one atomic per
+// destination reserves the workgroup's positions in the lists (or the task
+// queue), and a second pass writes the entries: the shared counters see one
+// atomic per workgroup instead of one per child.  `ntask` is the number of
+// tasks (device-planned steps read it from the control block).
+__global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint32_t ntask) {
+  const uint32_t T = a.devplan ? a.ctrl[CTRL_T] : ntask;
+  __shared__ uint32_t s_n[4], s_base[4], s_pos[4];
+  __shared__ unsigned long long s_el[3];
+  const uint32_t tid = threadIdx.x;
+  if (tid < 4) { s_n[tid] = 0; s_pos[tid] = 0; }
+  if (tid < 3) s_el[tid] = 0;
+  __syncthreads();
+  for (uint32_t ti = blockIdx.x; ti < T; ti += gridDim.x) {
+    const PTask& tk = a.tasks[ti];
+    for (uint32_t j = tid; j < tk.nb; j += 256) {
+      const Child ch = child_of(a, c, tk, j);
+      if (ch.dest < 4) atomicAdd(&s_n[ch.dest], 1u);
+      if (ch.dest < 3) atomicAdd(&s_el[ch.dest], (unsigned long long)ch.sz);
     }
-    if (sz <= c.caps[2]) {
-      const uint32_t v = sz <= c.caps[0] ? 0u : (sz <= c.caps[1] ? 1u : 2u);
-      const uint32_t q = atomicAdd(&cnt[v], 1u);
-      if (q < c.lt_cap) {
-        LTask t;
-        t.l = tk.l + s0;
-        t.n = (uint32_t)sz;
-        t.pad = 0;
-        c.lt[v][q] = t;
+  }
+  __syncthreads();
+  if (tid < 4 && s_n[tid]) {
+    uint32_t* ctr = tid < 3 ? a.ctrl + CTRL_NLDS + tid : (a.devplan ? a.ctrl + CTRL_QTAIL : a.ctrl + CTRL_NNEXT);
+    s_base[tid] = atomicAdd(ctr, s_n[tid]);
+  }
+  if (tid < 3 && s_el[tid]) {
+    unsigned long long* ldsel = reinterpret_cast<unsigned long long*>(a.ctrl + CTRL_LDSEL);
+    atomicAdd(&ldsel[tid], s_el[tid]);
+    atomicAdd((unsigned long long*)(a.ctrl + CTRL_LDSELT), s_el[tid]);
+    if (a.devplan && a.step < MAX_STEPS_RECORDED)
+      atomicAdd((unsigned long long*)&a.step_el[a.step * 4 + 1 + tid], s_el[tid]);
+  }
+  if (tid == 0 && s_n[0] + s_n[1] + s_n[2]) atomicAdd(&a.ctrl[CTRL_LDSTASKS], s_n[0] + s_n[1] + s_n[2]);
+  __syncthreads();
+  for (uint32_t ti = blockIdx.x; ti < T; ti += gridDim.x) {
+    const PTask& tk = a.tasks[ti];
+    for (uint32_t j = tid; j < tk.nb; j += 256) {
+      const Child ch = child_of(a, c, tk, j);
+      if (ch.dest >= 4) continue;
+      const uint32_t q = s_base[ch.dest] + atomicAdd(&s_pos[ch.dest], 1u);
+      if (ch.dest < 3) {
+        if (q < c.lt_cap) {
+          LTask t;
+          t.l = tk.l + ch.s0;
+          t.n = (uint32_t)ch.sz;
+          t.pad = 0;
+          c.lt[ch.dest][q] = t;
+        } else {
+          dev_error(a.ctrl, DE_CLN_RANGE, ti, q);
+        }
       } else {
-        dev_error(a.ctrl, DE_CLN_RANGE, blockIdx.x, q);
-      }
-      mine[v] += sz;
-      ++nlds;
-    } else {
-      CTask t;
-      t.l = tk.l + s0;
-      t.n = sz;
-      t.level = tk.level + 1;
-      t.tflags = tflags;
-      t.shift = shift;
-      t.width = width;
-      if (a.devplan) {           // onto the task queue
-        const uint32_t q = atomicAdd(&a.ctrl[CTRL_QTAIL], 1u);
-        if (q - a.ctrl[CTRL_QHEAD] < a.qcap) a.queue[q % a.qcap] = t;
-        else dev_error(a.ctrl, DE_QUEUE, blockIdx.x, q);
-      } else {
-        const uint32_t q = atomicAdd(&a.ctrl[CTRL_NNEXT], 1u);
-        if (q < c.next_cap) c.next[q] = t;
-        else dev_error(a.ctrl, DE_CLN_RANGE, blockIdx.x, q);
+        CTask t;
+        t.l = tk.l + ch.s0;
+        t.n = ch.sz;
+        t.level = tk.level + 1;
+        t.tflags = ch.tflags;
+        t.shift = ch.shift;
+        t.width = ch.width;
+        if (a.devplan) {           // onto the task queue
+          if (q - a.ctrl[CTRL_QHEAD] < a.qcap) a.queue[q % a.qcap] = t;
+          else dev_error(a.ctrl, DE_QUEUE, ti, q);
+        } else {
+          if (q < c.next_cap) c.next[q] = t;
+          else dev_error(a.ctrl, DE_CLN_RANGE, ti, q);
+        }
       }
     }
   }
-  for (int v = 0; v < 3; ++v) {
-    uint64_t m = mine[v];
-    for (int o = 32; o > 0; o >>= 1) m += (uint64_t)__shfl_xor((long long)m, o, 64);
-    if ((threadIdx.x & 63) == 0 && m) {
-      atomicAdd(&ldsel[v], (unsigned long long)m);
-      atomicAdd((unsigned long long*)(a.ctrl + CTRL_LDSELT), (unsigned long long)m);
-      if (a.devplan && a.step < MAX_STEPS_RECORDED)
-        atomicAdd((unsigned long long*)&a.step_el[a.step * 4 + 1 + v], (unsigned long long)m);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) nlds += (uint32_t)__shfl_xor((int)nlds, o, 64);
-  if ((threadIdx.x & 63) == 0 && nlds) atomicAdd(&a.ctrl[CTRL_LDSTASKS], nlds);
 }
 
 // ------------------------------------------- device-planned execution
