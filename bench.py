@@ -91,7 +91,7 @@ def main() -> int:
     sorter = ips.Sorter(0)
     prof_flags = ips.FLAG_PROFILE
     params = ips.make_params(flags=prof_flags)
-    ws = sorter.workspace(ips.workspace_bytes(n, kind, "samplesort", params))
+    ws = sorter.workspace(ips.workspace_bytes(n, kind, "samplesort", sorter.params_for(n, kind, params=params)))
     log(f"workspace {ws.numel() / 2**20:.1f} MiB for {n * D / 2**30:.2f} GiB of data")
 
     # Warmup steps, timing every kernel, pick the dominant kernel.
@@ -419,7 +419,8 @@ def bench_batch(args) -> int:
     work = torch.empty_like(pristine)
     sorter = ips.Sorter(0)
     segs, nseg = ips.segment_array(offs.tolist(), sizes.tolist())
-    ws = sorter.workspace(ips.segments_workspace_bytes(total, segs, nseg, "u64"))
+    ws = sorter.workspace(ips.segments_workspace_bytes(total, segs, nseg, "u64", "samplesort",
+                                                       sorter.params_for(total, "u64", batched=True)))
     views = [work[o:o + n] for o, n in zip(offs.tolist(), sizes.tolist())]
     res = {}
     for mode in ("batched", "per_array"):

@@ -312,6 +312,43 @@ typedef struct {
 
 int ips_get_profile(ips_ctx* ctx, ips_profile* out);
 
+/* Autotuned parameters.  The paper tunes k, the block size and the base
+ * case per machine (Section 6) and notes that the best values depend on the
+ * input size; an entry of this table holds measured best values for one
+ * element type and algorithm over a range of size classes (floor(log2 n)
+ * of the elements of one call, all segments or arrays of a batched call
+ * together), separately for single-array calls (batched = 0) and batched
+ * calls (batched = 1).  The table is written by the tuning script of the
+ * Python package from timings on the GPU; the library stores none.
+ * A zero field means "no tuned value" (the default applies). */
+typedef struct {
+  int32_t elem_type;      /* IPS_U32 .. IPS_REC100 */
+  int32_t algo;           /* IPS_SAMPLESORT or IPS_RADIX */
+  uint32_t log2n_min;     /* size classes [log2n_min, log2n_max] */
+  uint32_t log2n_max;
+  uint32_t batched;       /* 0: ips_sort_keys/pairs, 1: segments or batch calls */
+  uint32_t k;             /* as in ips_params */
+  uint32_t block_bytes;
+  uint32_t n0;
+  uint32_t lds_task_max;  /* selects which of the LDS tier's workgroup shapes run */
+  uint32_t piece_blocks;
+  uint32_t perm_groups;
+  uint32_t reserved;
+} ips_tune_entry;
+
+/* Parameters for one call from a tuning table: *out = *base (zeroed when
+ * base is NULL), then every field of *out that is zero and tunable (k,
+ * block_bytes, n0, lds_task_max, piece_blocks, perm_groups) takes the value
+ * of the first entry of table[0, count) that matches elem_type, algo,
+ * batched and floor(log2 n) (n >= 1).  Fields the caller set are kept; flags,
+ * seed and profile_mask are never changed.  Pass the same *out to the
+ * workspace query and to the sort.  Pure host computation.  Returns 1 when
+ * an entry matched, 0 when none did (then *out = *base), or
+ * IPS_E_INVALID_ARG for a null `out`, a null table with count > 0, or an
+ * entry whose log2n_min exceeds log2n_max. */
+int ips_tuned_params(const ips_tune_entry* table, uint32_t count, uint64_t n, int elem_type, int algo,
+                     int batched, const ips_params* base, ips_params* out);
+
 /* Last HIP error code seen by the context (hipError_t as int) and the
  * last kernel-reported consistency error (0 = none; bits 0-7 the error
  * code, bits 8-19 and 20-31 the low bits of its two arguments). */

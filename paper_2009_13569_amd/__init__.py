@@ -45,7 +45,7 @@ EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments",
            "ips_batch_workspace_bytes", "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace",
            "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
-           "ips_last_device_error", "ips_status_string", "ips_abi_version"]
+           "ips_last_device_error", "ips_status_string", "ips_abi_version", "ips_tuned_params"]
 SERVE_BATCH = 0
 SERVE_FIFO = 1
 
@@ -71,6 +71,18 @@ class Stats(ctypes.Structure):
                 ("lds_tasks", ctypes.c_uint32), ("detected", ctypes.c_uint32), ("pad0", ctypes.c_uint32),
                 ("partitioned_elems", ctypes.c_uint64), ("lds_elems", ctypes.c_uint64),
                 ("max_step_elems", ctypes.c_uint64)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("elem_type", ctypes.c_int32), ("algo", ctypes.c_int32), ("log2n_min", ctypes.c_uint32),
+                ("log2n_max", ctypes.c_uint32), ("batched", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32), ("lds_task_max", ctypes.c_uint32),
+                ("piece_blocks", ctypes.c_uint32), ("perm_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+TUNE_FIELDS = ("k", "block_bytes", "n0", "lds_task_max", "piece_blocks", "perm_groups")
+# The table written by `python -m paper_2009_13569_amd.tune` (loaded by Sorter).
+TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 
 class Segment(ctypes.Structure):
@@ -114,6 +126,8 @@ _lib.ips_serve_workspace_bytes.argtypes = [ctypes.POINTER(Request), ctypes.c_uin
 _lib.ips_serve_trace.argtypes = [_vp, ctypes.POINTER(Request), ctypes.c_uint32, ctypes.POINTER(ServeConfig),
                                  _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_get_root_info.argtypes = [_vp, ctypes.POINTER(RootInfo)]
+_lib.ips_tuned_params.argtypes = [ctypes.POINTER(TuneEntry), ctypes.c_uint32, _u64, _i32, _i32, _i32,
+                                  ctypes.POINTER(Params), ctypes.POINTER(Params)]
 _lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.ips_get_profile.argtypes = [_vp, ctypes.POINTER(Profile)]
 _lib.ips_last_hip_error.argtypes = [_vp]
@@ -124,7 +138,7 @@ for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_batch_workspace_bytes",
            "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace", "ips_get_root_info",
            "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
-           "ips_abi_version"):
+           "ips_abi_version", "ips_tuned_params"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -180,6 +194,40 @@ def segments_workspace_bytes(n_total: int, segs, nseg: int, kind: str, algo: str
     return int(out.value)
 
 
+def tune_table(entries):
+    """ctypes array of ips_tune_entry from a list of dicts (keys: kind, algo,
+    log2n_min, log2n_max, batched and any of TUNE_FIELDS)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        t = arr[i]
+        t.elem_type, t.algo = TYPES[e["kind"]], ALGOS[e.get("algo", "samplesort")]
+        t.log2n_min, t.log2n_max, t.batched = int(e["log2n_min"]), int(e["log2n_max"]), int(e.get("batched", 0))
+        for f in TUNE_FIELDS:
+            setattr(t, f, int(e.get(f, 0)))
+    return arr, len(entries)
+
+
+def load_tuning(path: str = TUNING_PATH):
+    """Entries of a tuning file, or [] when there is none."""
+    import json
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f)["entries"]
+
+
+def tuned_params(table, count: int, n: int, kind: str, algo: str = "samplesort", batched: bool = False,
+                 base: Params | None = None) -> Params:
+    """ips_tuned_params: `base` with its zero tunable fields filled from the
+    first matching entry of the table."""
+    out = Params()
+    rc = _lib.ips_tuned_params(table, count, n, TYPES[kind], ALGOS[algo], int(bool(batched)),
+                               ctypes.byref(base) if base is not None else None, ctypes.byref(out))
+    if rc < 0:
+        raise IpsError(rc, "ips_tuned_params")
+    return out
+
+
 def kind_of(t) -> str:
     """Element kind of a torch tensor: 1-D uint32/uint64/float64 keys, (n, 2)
     64-bit pairs, or (n, 100) uint8 records."""
@@ -195,9 +243,14 @@ def kind_of(t) -> str:
 
 
 class Sorter:
-    """A context on one device plus a cached workspace tensor."""
+    """A context on one device, a cached workspace tensor and a tuning table.
 
-    def __init__(self, device: int = 0):
+    tuning: "default" loads TUNING_PATH when it exists; None uses no table;
+    a list of entry dicts uses those.  Every call fills the zero tunable
+    fields of its parameters from the table (ips_tuned_params) and sizes the
+    workspace for the same parameters."""
+
+    def __init__(self, device: int = 0, tuning="default"):
         h = ctypes.c_void_p()
         rc = _lib.ips_ctx_create(ctypes.byref(h), device)
         if rc != IPS_OK:
@@ -205,6 +258,18 @@ class Sorter:
         self._h = h
         self.device = device
         self._ws = None
+        self.tuning = load_tuning() if tuning == "default" else list(tuning or [])
+        self._table, self._tcount = tune_table(self.tuning)
+
+    def params_for(self, n: int, kind: str, algo: str = "samplesort", batched: bool = False,
+                   params: Params | None = None) -> Params:
+        """The parameters a call on n elements in total uses."""
+        return tuned_params(self._table, self._tcount, max(int(n), 1), kind, algo, batched, params)
+
+    def _check_ws(self, ws, need: int):
+        if ws.numel() < need:
+            raise ValueError(f"workspace of {ws.numel()} bytes is smaller than the {need} bytes this call needs "
+                             f"(size it with the parameters from Sorter.params_for)")
 
     def close(self):
         if self._h:
@@ -233,12 +298,14 @@ class Sorter:
             raise ValueError("tensor must be contiguous")
         kind = kind or kind_of(t)
         n = t.shape[0]
+        params = self.params_for(n, kind, algo, False, params)
         need = workspace_bytes(n, kind, algo, params)
         ws = ws if ws is not None else self.workspace(need)
+        self._check_ws(ws, need)
         if stream is None:
             stream = torch.cuda.current_stream(t.device)
         sp = ctypes.c_void_p(stream.cuda_stream)
-        pp = ctypes.byref(params) if params is not None else None
+        pp = ctypes.byref(params)
         fn = _lib.ips_sort_keys if kind in ("u32", "u64", "f64") else _lib.ips_sort_pairs
         rc = fn(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ALGOS[algo],
                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), pp, sp)
@@ -257,11 +324,13 @@ class Sorter:
         kind = kind or kind_of(t)
         segs, nseg = segment_array(offsets, sizes)
         n = t.shape[0]
+        params = self.params_for(sum(int(x) for x in sizes), kind, algo, True, params)
         need = segments_workspace_bytes(n, segs, nseg, kind, algo, params)
         ws = ws if ws is not None else self.workspace(need)
+        self._check_ws(ws, need)
         if stream is None:
             stream = torch.cuda.current_stream(t.device)
-        pp = ctypes.byref(params) if params is not None else None
+        pp = ctypes.byref(params)
         rc = _lib.ips_sort_segments(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ALGOS[algo],
                                     segs, nseg, ctypes.c_void_p(ws.data_ptr()), ws.numel(), pp,
                                     ctypes.c_void_p(stream.cuda_stream))
@@ -284,12 +353,14 @@ class Sorter:
         cnt = len(tensors)
         ptrs = (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in tensors])
         ns = (ctypes.c_uint64 * cnt)(*[t.shape[0] for t in tensors])
-        pp = ctypes.byref(params) if params is not None else None
+        params = self.params_for(sum(t.shape[0] for t in tensors), kind, algo, True, params)
+        pp = ctypes.byref(params)
         out = ctypes.c_size_t(0)
         rc = _lib.ips_batch_workspace_bytes(ptrs, ns, cnt, TYPES[kind], ALGOS[algo], pp, ctypes.byref(out))
         if rc != IPS_OK:
             raise IpsError(rc, "ips_batch_workspace_bytes")
         ws = ws if ws is not None else self.workspace(out.value)
+        self._check_ws(ws, out.value)
         if stream is None:
             stream = torch.cuda.current_stream(tensors[0].device)
         rc = _lib.ips_sort_batch(self._h, ptrs, ns, cnt, TYPES[kind], ALGOS[algo], ctypes.c_void_p(ws.data_ptr()),

@@ -997,7 +997,10 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
   const bool graph = (c.flags & IPS_FLAG_GRAPH) != 0;
   if (graph) ctx->profiling = false;   // no event records inside a captured graph
   uint64_t* h_sel = reinterpret_cast<uint64_t*>(r.h_rb);
-  uint32_t step = 0, round_steps = 4;
+  // Rounds of steps between readbacks: one step first (a small sort is done
+  // after its root step, and steps beyond the work cost their launches),
+  // then 4, doubling to 32; a captured graph holds 4 steps.
+  uint32_t step = 0, round_steps = graph ? 4u : 1u;
   hipGraphExec_t exec = nullptr;
   int rc = IPS_OK;
   for (uint32_t round = 0;; ++round) {
@@ -1034,7 +1037,7 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
     resolve_profile(ctx);
     if ((rc = check_dev_error(r)) != IPS_OK) break;
     if (r.h_ctrl[CTRL_QHEAD] == r.h_ctrl[CTRL_QTAIL]) break;
-    if (!graph) round_steps = std::min<uint32_t>(round_steps * 2, 32);
+    if (!graph) round_steps = round_steps == 1 ? 4u : std::min<uint32_t>(round_steps * 2, 32);
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (rc != IPS_OK) return rc;
@@ -1341,6 +1344,34 @@ int batch_impl(ips_ctx* ctx, void* const* ptrs, const uint64_t* ns, uint32_t cou
 }  // namespace
 
 extern "C" {
+
+int ips_tuned_params(const ips_tune_entry* table, uint32_t count, uint64_t n, int elem_type, int algo,
+                     int batched, const ips_params* base, ips_params* out) {
+  if (!out || (!table && count)) return IPS_E_INVALID_ARG;
+  for (uint32_t i = 0; i < count; ++i)
+    if (table[i].log2n_min > table[i].log2n_max) return IPS_E_INVALID_ARG;
+  ips_params p;
+  if (base) p = *base;
+  else std::memset(&p, 0, sizeof(p));
+  *out = p;
+  if (n < 1) return 0;
+  const uint32_t cls = 63u - (uint32_t)__builtin_clzll(n);
+  for (uint32_t i = 0; i < count; ++i) {
+    const ips_tune_entry& e = table[i];
+    if (e.elem_type != elem_type || e.algo != algo || e.batched != (batched ? 1u : 0u) ||
+        cls < e.log2n_min || cls > e.log2n_max)
+      continue;
+    if (!p.k) p.k = e.k;
+    if (!p.block_bytes) p.block_bytes = e.block_bytes;
+    if (!p.n0) p.n0 = e.n0;
+    if (!p.lds_task_max) p.lds_task_max = e.lds_task_max;
+    if (!p.piece_blocks) p.piece_blocks = e.piece_blocks;
+    if (!p.perm_groups) p.perm_groups = e.perm_groups;
+    *out = p;
+    return 1;
+  }
+  return 0;
+}
 
 int ips_abi_version(void) { return IPS_ABI_VERSION; }
 

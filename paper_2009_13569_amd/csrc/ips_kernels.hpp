@@ -1627,7 +1627,16 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
   if (t < cand) q = a.queue[(head + t) % a.qcap];
   uint64_t tot_n = 0;
   (void)block_incl_scan64<PLAN_THREADS>(t < cand ? q.n : 0, s_w, &tot_n);
-  const uint64_t S = tot_n / c.wg_target ? tot_n / c.wg_target : 1;
+  uint64_t S = tot_n / c.wg_target ? tot_n / c.wg_target : 1;
+  // Stripes long enough that all candidates fit the workgroup budget (each
+  // task adds at most one rounding workgroup): with a budget below the
+  // stripe target, a stripe length taken from the candidates alone would
+  // let every step take only part of the queue, and the next step (fewer
+  // candidates, shorter stripes) again only part of the rest.
+  if (c.WB > cand) {
+    const uint64_t room = c.WB - cand, Sw = (tot_n + room - 1) / room;
+    if (Sw > S) S = Sw;
+  }
   // resource needs of the task (upper bounds, as the host estimates them)
   uint64_t nw = 0, nslot = 0, nspill = 0, nflags = 0, npieces = 0;
   if (t < cand) {

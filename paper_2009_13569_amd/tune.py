@@ -1,0 +1,230 @@
+"""Autotuner: measures the sort under candidate parameters on the GPU and
+writes the tuning table (TUNING_PATH) that Sorter applies to every call.
+
+    python -m paper_2009_13569_amd.tune [--kinds u64 u32] [--classes 16 18 20 22 24 26 28]
+                                        [--batch] [--reps 5] [--out PATH]
+
+For each element kind and size class 2^c it sorts a Uniform array of 2^c
+keys (generated on the device, restored before every run, untimed) and
+times each run with HIP events on the sort's stream (median of `reps`).
+Starting from the library defaults it tunes one parameter at a time over a
+small candidate list, keeping a change only when it is at least 1% faster,
+for two rounds over the list (coordinate descent).  The paper tunes k, the
+block size and the base case per machine (Section 6); the parameters here
+are the same three plus the pieces and groups of the block permutation.
+The workgroup shapes are compiled per kernel, and the LDS-tier threshold
+(lds_task_max) selects which of the tier's shapes take the small tasks.
+
+--batch tunes the batched call on 4096 arrays with log-uniform sizes in
+[2^8, 2^22] (one entry for batched calls).  Every run's output is checked
+on the device (sorted, same key sum); a failing candidate stops the tuner.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+CANDIDATES = {
+    "k": [32, 64, 128, 256],
+    "block_bytes": [0, 128, 256, 512, 1024],
+    "lds_task_max": [0, "cap/2", "cap/4"],
+    "n0": [0, 1024, 4096],
+    "piece_blocks": [256, 512, 1024, 2048],
+    "perm_groups": [32768, 65536, 131072, 262144],
+}
+CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}
+
+
+def _resolve(field, v, kind):
+    if isinstance(v, str):
+        return CAP[kind] // int(v.split("/")[1])
+    return v
+
+
+def _descend(measure, kind):
+    """Coordinate descent from the defaults; returns (best dict, best ms)."""
+    cur = {f: 0 for f in CANDIDATES}
+    best = measure(cur)
+    _log(f"    defaults: {best:.3f} ms")
+    for rnd in range(2):
+        changed = False
+        for f, cands in CANDIDATES.items():
+            for v in cands:
+                v = _resolve(f, v, kind)
+                if v == cur[f]:
+                    continue
+                trial = dict(cur)
+                trial[f] = v
+                try:
+                    ms = measure(trial)
+                except ValueError as e:   # rejected by the library: not a candidate
+                    _log(f"    {f}={v}: rejected ({e})")
+                    continue
+                if ms < best * 0.99:
+                    _log(f"    {f}={v}: {ms:.3f} ms (was {best:.3f})")
+                    cur, best, changed = trial, ms, True
+        if not changed:
+            break
+    return cur, best
+
+
+def tune_single(kind: str, log2n: int, reps: int):
+    import torch
+
+    import paper_2009_13569_amd as ips
+    from synth import device as sd
+
+    n = 1 << log2n
+    dev = torch.device("cuda:0")
+    src = sd.generate(kind, "uniform", n, 1000 + log2n, dev)
+    work = torch.empty_like(src)
+    sorter = ips.Sorter(0, tuning=None)
+    is_u64 = src.dtype == torch.int64
+    ref_sum = int(src.view(torch.int64).sum()) if is_u64 else int((src.to(torch.int64) & 0xFFFFFFFF).sum())
+
+    def measure(cfg):
+        p = ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK, **{f: int(v) for f, v in cfg.items()})
+        try:
+            need = ips.workspace_bytes(n, kind, "samplesort", p)
+        except ips.IpsError as e:
+            raise ValueError(str(e))
+        ws = sorter.workspace(need)
+        times = []
+        for r in range(reps + 1):
+            work.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sorter.sort_(work, params=p, kind=kind, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1))
+        _check(work, ref_sum, is_u64)
+        times.sort()
+        return times[len(times) // 2]
+
+    _log(f"  {kind} 2^{log2n}")
+    return _descend(measure, kind)
+
+
+def _check(work, ref_sum, is_u64):
+    import torch
+    if is_u64:
+        v = work.view(torch.int64) ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=work.device)
+        s = int(work.view(torch.int64).sum())
+    else:   # u32 keys held as int32: compare as unsigned
+        v = work.to(torch.int64) & 0xFFFFFFFF
+        s = int(v.sum())
+    if not bool((v[1:] >= v[:-1]).all()) or s != ref_sum:
+        raise RuntimeError("tuner run produced a wrong result")
+
+
+def tune_batch(reps: int, arrays: int = 4096):
+    import numpy as np
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+
+    dev = torch.device("cuda:0")
+    sizes, dists = synth.batch_layout(arrays, 8, 22, synth.seed_for(4, 0))
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    seeds = synth.stream(synth.seed_for(4, 1), len(sizes))
+    src = torch.empty(total, dtype=torch.int64, device=dev)
+    for i, (o, m) in enumerate(zip(offs.tolist(), sizes.tolist())):
+        src[o:o + m] = sd.gen_u64(dists[i], m, int(seeds[i]), dev)
+    ref_sum = int(src.sum())
+    work = torch.empty_like(src)
+    sorter = ips.Sorter(0, tuning=None)
+    offl, szl = offs.tolist(), sizes.tolist()
+    segs, nseg = ips.segment_array(offl, szl)
+    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+    ends = torch.tensor((offs + sizes - 1).tolist(), device=dev)
+
+    def measure(cfg):
+        p = ips.make_params(**{f: int(v) for f, v in cfg.items()})
+        try:
+            need = ips.segments_workspace_bytes(total, segs, nseg, "u64", "samplesort", p)
+        except ips.IpsError as e:
+            raise ValueError(str(e))
+        ws = sorter.workspace(need)
+        times = []
+        for r in range(reps + 1):
+            work.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sorter.sort_segments_(work, offl, szl, params=p, kind="u64", ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1))
+        v = work ^ sign
+        bad = (v[1:] < v[:-1])
+        bad[ends[:-1]] = False   # array boundaries
+        if bool(bad.any()) or int(work.sum()) != ref_sum:
+            raise RuntimeError("tuner run produced a wrong result")
+        times.sort()
+        return times[len(times) // 2]
+
+    _log(f"  batch: {arrays} u64 arrays, {total} keys")
+    cfg, ms = _descend(measure, "u64")
+    return cfg, ms, total
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--kinds", nargs="+", default=["u64"])
+    ap.add_argument("--classes", nargs="+", type=int, default=[16, 18, 20, 22, 24, 26, 28])
+    ap.add_argument("--batch", action="store_true", help="also tune batched calls (4096 arrays)")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    sys.path.insert(0, ROOT)
+    import torch
+
+    import paper_2009_13569_amd as ips
+
+    out = args.out or ips.TUNING_PATH
+    entries, notes = [], []
+    t0 = time.time()
+    classes = sorted(args.classes)
+    for kind in args.kinds:
+        for i, c in enumerate(classes):
+            cfg, ms = tune_single(kind, c, args.reps)
+            hi = classes[i + 1] - 1 if i + 1 < len(classes) else 40
+            e = {"kind": kind, "algo": "samplesort", "log2n_min": c, "log2n_max": hi, "batched": 0}
+            e.update({f: int(v) for f, v in cfg.items() if v})
+            entries.append(e)
+            notes.append({"kind": kind, "log2n": c, "ms": round(ms, 4), "params": e})
+            torch.cuda.empty_cache()
+    if args.batch:
+        cfg, ms, total = tune_batch(args.reps)
+        e = {"kind": "u64", "algo": "samplesort", "log2n_min": 0, "log2n_max": 40, "batched": 1}
+        e.update({f: int(v) for f, v in cfg.items() if v})
+        entries.append(e)
+        notes.append({"kind": "u64", "batch_keys": total, "ms": round(ms, 4), "params": e})
+    doc = {"device": torch.cuda.get_device_name(0), "seconds": round(time.time() - t0, 1),
+           "method": "coordinate descent from the defaults, median of reps HIP-event timings per candidate",
+           "entries": entries, "measurements": notes}
+    with open(out, "w") as f:
+        json.dump(doc, f, indent=1)
+    _log(f"wrote {out} ({len(entries)} entries) in {time.time() - t0:.0f}s")
+    print(json.dumps(doc))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

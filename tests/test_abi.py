@@ -170,3 +170,52 @@ def test_serve_validation_and_rejection_without_device():
     assert rc == -3
     assert [reqs[i].status for i in range(2)] == [-3, -3]
     assert reqs[1].done_s >= 0.001                  # rejected only once it had arrived
+
+
+def test_tuned_params_lookup():
+    table, cnt = ips.tune_table([
+        {"kind": "u64", "log2n_min": 16, "log2n_max": 19, "k": 64, "block_bytes": 512},
+        {"kind": "u64", "log2n_min": 20, "log2n_max": 40, "k": 128, "piece_blocks": 2048},
+        {"kind": "u64", "log2n_min": 20, "log2n_max": 40, "k": 32},                       # shadowed
+        {"kind": "u64", "log2n_min": 0, "log2n_max": 40, "batched": 1, "perm_groups": 65536},
+        {"kind": "u32", "algo": "radix", "log2n_min": 0, "log2n_max": 40, "n0": 4096},
+    ])
+    L = ips.lib()
+    out = ips.Params()
+    # first matching entry; untouched fields stay zero
+    p = ips.tuned_params(table, cnt, (1 << 20) + 5, "u64")
+    assert (p.k, p.block_bytes, p.piece_blocks, p.perm_groups) == (128, 0, 2048, 0)
+    p = ips.tuned_params(table, cnt, 1 << 17, "u64")
+    assert (p.k, p.block_bytes) == (64, 512)
+    # no entry below 2^16 for single calls
+    assert L.ips_tuned_params(table, cnt, 1000, 2, 0, 0, None, ctypes.byref(out)) == 0
+    assert out.k == 0
+    # caller's fields and flags are kept
+    base = ips.make_params(k=16, flags=ips.FLAG_NO_SORTED_CHECK, seed=7)
+    p = ips.tuned_params(table, cnt, 1 << 24, "u64", base=base)
+    assert (p.k, p.piece_blocks, p.flags, p.seed) == (16, 2048, ips.FLAG_NO_SORTED_CHECK, 7)
+    # batched calls and other algorithms have entries of their own
+    p = ips.tuned_params(table, cnt, 1 << 24, "u64", batched=True)
+    assert (p.k, p.perm_groups) == (0, 65536)
+    p = ips.tuned_params(table, cnt, 1 << 24, "u32", "radix")
+    assert p.n0 == 4096
+    assert ips.tuned_params(table, cnt, 1 << 24, "u32").n0 == 0
+    # errors
+    assert L.ips_tuned_params(table, cnt, 1 << 20, 2, 0, 0, None, None) == -1
+    assert L.ips_tuned_params(None, 1, 1 << 20, 2, 0, 0, None, ctypes.byref(out)) == -1
+    bad, bc = ips.tune_table([{"kind": "u64", "log2n_min": 30, "log2n_max": 20}])
+    assert L.ips_tuned_params(bad, bc, 1 << 20, 2, 0, 0, None, ctypes.byref(out)) == -1
+    # an empty table matches nothing
+    assert L.ips_tuned_params(None, 0, 1 << 20, 2, 0, 0, None, ctypes.byref(out)) == 0
+
+
+def test_tuning_file_entries_are_valid():
+    """The committed tuning table (if any) only names valid kinds and fields,
+    and every entry's parameters are accepted by the library."""
+    entries = ips.load_tuning()
+    table, cnt = ips.tune_table(entries)
+    for e in entries:
+        assert set(e) <= {"kind", "algo", "log2n_min", "log2n_max", "batched", *ips.TUNE_FIELDS}
+        n = 1 << max(int(e["log2n_min"]), 1)
+        p = ips.tuned_params(table, cnt, n, e["kind"], e.get("algo", "samplesort"), bool(e.get("batched", 0)))
+        assert ips.workspace_bytes(n, e["kind"], e.get("algo", "samplesort"), p) > 0
