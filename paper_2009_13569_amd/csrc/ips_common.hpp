@@ -49,6 +49,7 @@ enum CtrlSlot : uint32_t {
   CTRL_NNEXT = 15,     // children of a batch: next-level tasks
   CTRL_LDSEL = 16,     // children of a batch: u64 elements per LDS-tier variant (16..21)
   CTRL_LDSPOP = 22,    // LDS-tier tasks claimed per variant (22..24), zeroed with NLDS..LDSEL
+  CTRL_LDSRUN = 25,    // device-planned step: 1 when this step's LDS-tier launches sort the lists
   // device-planned execution (queue of tasks, per-step counts, statistics)
   CTRL_QHEAD = 64,     // next task to take from the queue
   CTRL_QTAIL = 65,     // end of the queued tasks
@@ -89,6 +90,7 @@ enum DevErr : uint32_t {
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
 // radix step.  Keys live in 16-byte slots so that every key type fits.
 constexpr uint32_t CHILD_WGS = 1024;   // workgroups of the children kernel (at most)
+constexpr uint32_t LDS_DEFER_TASKS = 16384;   // device-planned steps: LDS-tier lists run from this many tasks
 constexpr uint32_t START_BITS = 12;   // start-node table: 2^12 entries
 struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;

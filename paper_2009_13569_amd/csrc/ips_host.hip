@@ -201,7 +201,12 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   L->PB = pb_buckets + L->WB + L->FB / c.cmax + 16;
   L->PWB = c.groups / 4 + 2 * L->TB + 16;
   L->NBE = L->TB * (uint32_t)(nbm + 1);
-  L->LTB = L->TB * (uint32_t)nbm + 1;
+  // LDS-tier children of one batch: at most 2k' (equality buckets) per task;
+  // under the default k' rule k' < 8 n' / cap (or 2), so a batch has fewer
+  // than 16 n / cap + 4 TB of them.
+  uint64_t ltb = (uint64_t)L->TB * nbm;
+  if (!c.n0 && !c.radix) ltb = std::min<uint64_t>(ltb, 16 * n / c.cap + 4ull * L->TB);
+  L->LTB = (uint32_t)ltb + 1;
   size_t sz[R_COUNT];
   sz[R_CTRL] = CTRL_WORDS * 4;
   sz[R_TASKS] = (size_t)L->TB * sizeof(PTask);
@@ -231,7 +236,9 @@ void plan(uint64_t n, const Cfg& c, Layout* L) {
   sz[R_PR] = L->PB * 4;
   sz[R_PCUM] = L->PB * 4;
   sz[R_PFCNT] = L->PB * 4;
-  sz[R_LTC] = 3 * (size_t)L->LTB * sizeof(LTask);     // children for the LDS tier, per variant
+  // children for the LDS tier, per variant: two steps' worth (device-planned
+  // steps let the lists fill over several steps)
+  sz[R_LTC] = 3 * 2 * (size_t)L->LTB * sizeof(LTask);
   L->NXB = (uint32_t)std::min<uint64_t>((uint64_t)L->TB * nbm, tasks_ub + L->TB);
   sz[R_NEXT] = (size_t)L->NXB * sizeof(CTask);
   L->QCAP = (uint32_t)std::min<uint64_t>(tasks_ub + L->TB, 0xFFFFFFF0ull);
@@ -940,15 +947,16 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
   const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
                     [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
-  HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_NLDS, 13, 0u, r.st));
   HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
+  HIPCHK(ctx, launch_lds_decide(a.ctrl, LDS_DEFER_TASKS, r.L.LTB, r.st));
   for (uint32_t v = 0; v < 3; ++v) {
     if (v && c.L->lds_caps[v] == c.L->lds_caps[v - 1]) continue;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(r.L.LTB, 2048);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ca.lt_cap, 2048);
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_LDS_SORT, 0, [&] {
              return c.L->lds_sort(ca.lt[v], grid, r.data, v, a.ctrl, a.ctrl + CTRL_NLDS + v, ca.lt_cap, r.st);
            }, 1 + (int)v));
   }
+  HIPCHK(ctx, launch_lds_reset(a.ctrl, r.st));
   return IPS_OK;
 }
 
@@ -988,12 +996,13 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
   ChildArgs ca;
   LTask* d_ltc = wsp<LTask>(r, R_LTC);
   for (uint32_t v = 0; v < 3; ++v) {
-    ca.lt[v] = d_ltc + (size_t)v * r.L.LTB;
+    ca.lt[v] = d_ltc + (size_t)v * 2 * r.L.LTB;
     ca.caps[v] = std::min(c.cap, c.L->lds_caps[v]);
   }
   ca.next = wsp<CTask>(r, R_NEXT);
-  ca.lt_cap = r.L.LTB;
+  ca.lt_cap = 2 * r.L.LTB;
   ca.next_cap = r.L.NXB;
+  HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 14, 0u, r.st));   // lists empty, no run pending
   const bool graph = (c.flags & IPS_FLAG_GRAPH) != 0;
   if (graph) ctx->profiling = false;   // no event records inside a captured graph
   uint64_t* h_sel = reinterpret_cast<uint64_t*>(r.h_rb);

@@ -40,6 +40,16 @@ hipError_t launch_plan_geom(const BatchArgs& a, const PlanCfg& c, hipStream_t st
   return hipGetLastError();
 }
 
+hipError_t launch_lds_decide(uint32_t* ctrl, uint32_t min_tasks, uint32_t step_cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_lds_decide, dim3(1), dim3(64), 0, st, ctrl, min_tasks, step_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_lds_reset(uint32_t* ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(k_lds_reset, dim3(1), dim3(64), 0, st, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n, uint32_t v, hipStream_t st) {
   if (!max_n) return hipSuccess;
   uint32_t g = (max_n + 255) / 256 < 4096 ? (max_n + 255) / 256 : 4096;

@@ -1831,6 +1831,33 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   }
 }
 
+// Device-planned steps defer the LDS tier: the children of several steps
+// collect in the lists (2 * step_cap entries per variant) and are sorted in
+// one pass, which keeps the tier's launches large.  After a step's children
+// the lists run when they hold at least `min_tasks` tasks, when a list could
+// overflow during the next step (more than step_cap entries), or when the
+// task queue is empty (nothing further will be added); ctrl[CTRL_LDSRUN]
+// tells the step's LDS-tier launches and k_lds_reset.
+__global__ void k_lds_decide(uint32_t* ctrl, uint32_t min_tasks, uint32_t step_cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t n0 = ctrl[CTRL_NLDS], n1 = ctrl[CTRL_NLDS + 1], n2 = ctrl[CTRL_NLDS + 2];
+  const uint32_t pending = n0 + n1 + n2;
+  const bool full = n0 > step_cap || n1 > step_cap || n2 > step_cap;
+  const bool last = ctrl[CTRL_QHEAD] == ctrl[CTRL_QTAIL];
+  ctrl[CTRL_LDSRUN] = (pending && (pending >= min_tasks || full || last)) ? 1u : 0u;
+}
+
+// After the LDS-tier launches of a step: empty the lists if they ran.
+__global__ void k_lds_reset(uint32_t* ctrl) {
+  const uint32_t t = threadIdx.x;
+  if (!ctrl[CTRL_LDSRUN]) return;
+  __syncthreads();   // every lane has read the flag
+  if (t < 3) { ctrl[CTRL_NLDS + t] = 0; ctrl[CTRL_LDSPOP + t] = 0; }
+  if (t < 6) ctrl[CTRL_LDSEL + t] = 0;
+  __syncthreads();
+  if (t == 0) ctrl[CTRL_LDSRUN] = 0;
+}
+
 // Fills p[0, *count) with v.
 __global__ void __launch_bounds__(256) k_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t v) {
   const uint32_t n = *count;

@@ -42,6 +42,8 @@ const Launchers* launchers_rec100();
 hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t max_nb, uint32_t cmax,
                              hipStream_t);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t);
+hipError_t launch_lds_decide(uint32_t* ctrl, uint32_t min_tasks, uint32_t step_cap, hipStream_t);
+hipError_t launch_lds_reset(uint32_t* ctrl, hipStream_t);
 hipError_t launch_children(const BatchArgs&, const ChildArgs&, uint32_t ntask, hipStream_t);
 hipError_t launch_plan_pop(const BatchArgs&, const PlanCfg&, hipStream_t);
 hipError_t launch_plan_geom(const BatchArgs&, const PlanCfg&, hipStream_t);

@@ -415,6 +415,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt,
   __shared__ uint32_t s_next;
   uint32_t count, ti;
   if (cnt) {
+    if (!ctrl[CTRL_LDSRUN]) return;          // device-planned step that defers the lists
     count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
     if (threadIdx.x == 0) s_next = atomicAdd(pop, 1u);
     __syncthreads();
