@@ -423,7 +423,9 @@ def bench_batch(args) -> int:
                                                        sorter.params_for(total, "u64", batched=True)))
     views = [work[o:o + n] for o, n in zip(offs.tolist(), sizes.tolist())]
     res = {}
-    for mode in ("batched", "per_array"):
+    gstream = torch.cuda.Stream()
+    gparams = ips.make_params(flags=ips.FLAG_GRAPH)
+    for mode in ("batched", "batched_graph", "per_array"):
         times = []
         for step in range(args.warmup + args.steps):
             work.copy_(pristine)
@@ -431,6 +433,10 @@ def bench_batch(args) -> int:
             t0 = time.perf_counter()
             if mode == "batched":
                 sorter.sort_segments_(work, offs.tolist(), sizes.tolist(), kind="u64", ws=ws)
+            elif mode == "batched_graph":   # steps replayed from a captured HIP graph
+                with torch.cuda.stream(gstream):
+                    sorter.sort_segments_(work, offs.tolist(), sizes.tolist(), params=gparams, kind="u64",
+                                          ws=ws, stream=gstream)
             else:
                 for v in views:
                     sorter.sort_(v, kind="u64", ws=ws)
@@ -450,7 +456,9 @@ def bench_batch(args) -> int:
         "data": "synthetic: SplitMix64-seeded keys generated on the device, restored before each step (untimed)",
         "config": {"workload": f"{len(sizes)} u64 arrays, log-uniform sizes in [2^8, 2^22], "
                                f"Uniform/TwoDup/AlmostSorted", "keys": total},
+        "graph_replay": res["batched_graph"],
         "per_array_calls": res["per_array"],
+        "tuning": [e for e in sorter.tuning if e.get("batched")],
         "speedup_vs_per_array": round(res["per_array"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
     }
     print(json.dumps(out), flush=True)
