@@ -13,7 +13,7 @@ namespace ips {
 // NET/2 keys.
 template <class T> struct LdsShape;
 template <> struct LdsShape<TU32> {
-  static constexpr uint32_t N0 = 256, E0 = 32, N1 = 512, E1 = 32, N2 = 512, E2 = 32, NET = 32;
+  static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
 };
 template <> struct LdsShape<TU64> {
   static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;

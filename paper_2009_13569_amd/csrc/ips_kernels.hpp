@@ -1288,6 +1288,7 @@ __global__ void __launch_bounds__(256) k_sorted_check(const uint32_t* data, uint
     if (threadIdx.x == 0) { s_f[0] = at_load32(&ctrl[CTRL_DESC]); s_f[1] = at_load32(&ctrl[CTRL_ASC]); }
     __syncthreads();
     const bool stop = s_f[0] && s_f[1];
+    const bool had_desc = s_f[0] != 0, had_asc = s_f[1] != 0;
     __syncthreads();
     if (stop) return;
     uint32_t desc = 0, asc = 0;
@@ -1302,8 +1303,10 @@ __global__ void __launch_bounds__(256) k_sorted_check(const uint32_t* data, uint
         asc |= kless(x, y) ? 1u : 0u;
       }
     }
-    if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_DESC], 1u);
-    if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_ASC], 1u);
+    // a flag already seen set needs no atomic (a sorted input would otherwise
+    // send one atomic per wavefront and chunk to the same word)
+    if (!had_desc && __any(desc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_DESC], 1u);
+    if (!had_asc && __any(asc) && (threadIdx.x & 63) == 0) atomicOr(&ctrl[CTRL_ASC], 1u);
   }
 }
 

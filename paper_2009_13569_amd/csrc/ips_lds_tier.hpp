@@ -10,16 +10,25 @@
 //   4. each thread sorts one bin of at most NET/2 keys with a register
 //      bitonic network of size NET/4 or NET/2, the smaller one that holds it
 //      (bins are grouped by that size, one pass per size); a bin whose keys
-//      are all equal needs nothing; any other larger bin is sorted by one
-//      wavefront with a bitonic network in LDS;
-//      a bin above WAVE_MAX falls back to a bitonic sort of the whole task;
-//   5. one coalesced store (records are gathered from their LDS copy).
+//      are all equal needs nothing;
+//   5. a bin above WAVE_NET keys is binned again by the whole workgroup over
+//      its own key range (bins that collect many keys are the ones skewed or
+//      duplicate-heavy inputs produce): its sub-bins of at most NET/2 keys
+//      are sorted in registers at once, larger ones are queued again; every
+//      round splits a bin (its minimum and maximum land in different
+//      sub-bins) and a sub-bin of one value is final;
+//   6. bins of NET/2 .. WAVE_NET keys are sorted by one wavefront each with a
+//      bitonic network in LDS; only if a list overflows does the whole task
+//      fall back to a block-wide bitonic network;
+//   7. one coalesced store (records are gathered from their LDS copy).
 #pragma once
 #include "ips_kernels.hpp"
 
 namespace ips {
 
-constexpr uint32_t WAVE_MAX = 1024;   // largest bin sorted by one wavefront
+constexpr uint32_t WAVE_NET = 128;    // largest bin sorted by one wavefront's network
+constexpr uint32_t FATCAP = 128;      // bins waiting to be binned again (each > WAVE_NET keys)
+constexpr uint32_t FAT_ROUNDS = 1024; // re-binning rounds per task before the fallback
 
 // Order-preserving unsigned image of a key for binning.
 __device__ __forceinline__ uint64_t bin_image(uint32_t k) { return k; }
@@ -224,9 +233,11 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   __shared__ Img s_min[NT / 64], s_max[NT / 64];
   __shared__ uint16_t s_list[MAXBINS];       // bins grouped by size class
   __shared__ uint32_t s_ccnt[3], s_cbase[3];
-  __shared__ uint32_t s_big[64];
+  constexpr uint32_t MIDCAP = MAXBINS / 2;   // > CAP / (NET/2 + 1): never overflows
+  __shared__ uint32_t s_mid[MIDCAP];         // (offset << 16) | size, for the wavefronts
+  __shared__ uint32_t s_fat_o[FATCAP], s_fat_s[FATCAP];
   __shared__ uint32_t s_wsum[NT / 64];
-  __shared__ uint32_t s_nbig, s_fallback;
+  __shared__ uint32_t s_nmid, s_fat_head, s_fat_tail, s_fallback;
 
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
@@ -239,11 +250,80 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
   if (n < 2) return;
   uint32_t* gd = data + t.l * DW;
+  if (tid == 0) { s_nmid = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
+  if constexpr (IDX) {   // records: staged in LDS, gathered at the store
+    for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
+  }
 
-  // 1. Load keys into registers (records: also stage the records in LDS).
+  // A bin of more than NET/2 keys at [o, o + sz): listed for a wavefront up
+  // to WAVE_NET keys, otherwise queued for another binning round.
+  auto push_big = [&](uint32_t o, uint32_t sz) {
+    if (sz <= WAVE_NET) {
+      const uint32_t slot = atomicAdd(&s_nmid, 1u);
+      if (slot < MIDCAP) s_mid[slot] = (o << 16) | sz;
+      else s_fallback = 1;
+    } else {
+      const uint32_t slot = atomicAdd(&s_fat_tail, 1u);
+      if (slot - s_fat_head < FATCAP) {
+        s_fat_o[slot % FATCAP] = o;
+        s_fat_s[slot % FATCAP] = sz;
+      } else {
+        s_fallback = 1;
+      }
+    }
+  };
+
+  // Bins sorted by size class: up to NET/4 and up to NET/2 keys are sorted
+  // in registers by one thread each with a network of that size (each class
+  // in its own pass, so that a wavefront runs one network size); larger bins
+  // go to the wavefront list or the queue of re-binning rounds.  Bin b of
+  // nbins lies at o + s_off[b] and holds s_cnt[b] keys.
+  auto sort_bins = [&](uint32_t o, uint32_t nbins) {
+    constexpr uint32_t BPT = (MAXBINS + NT - 1) / NT;   // bins per thread
+    uint32_t cls_of[BPT];
+    if (tid < 3) s_ccnt[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t b = q * NT + tid;
+      cls_of[q] = 4;
+      if (b < nbins) {
+        const uint32_t sz = s_cnt[b];
+        if (sz > 1) {
+          cls_of[q] = sz <= NET / 4 ? 0u : (sz <= NET / 2 ? 1u : 3u);
+          if (cls_of[q] < 3) atomicAdd(&s_ccnt[cls_of[q]], 1u);
+          else push_big(o + s_off[b], sz);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_cbase[0] = 0;
+      s_cbase[1] = s_ccnt[0];
+      s_cbase[2] = s_ccnt[0] + s_ccnt[1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t c = cls_of[q];
+      if (c < 3) s_list[atomicAdd(&s_cbase[c], 1u)] = (uint16_t)(q * NT + tid);
+    }
+    __syncthreads();
+    const uint32_t n0 = s_ccnt[0], n1 = s_ccnt[1];
+    for (uint32_t q = tid; q < n0; q += NT) {
+      const uint32_t b = s_list[q];
+      sort_bin<T, IDX, NET / 4>(keys, idxb, o + s_off[b], s_cnt[b]);
+    }
+    for (uint32_t q = tid; q < n1; q += NT) {
+      const uint32_t b = s_list[n0 + q];
+      sort_bin<T, IDX, NET / 2>(keys, idxb, o + s_off[b], s_cnt[b]);
+    }
+    __syncthreads();
+  };
+
+  // 1. Load keys into registers (records: from their LDS stage).
   Key k[E];
   if constexpr (IDX) {
-    for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
     __syncthreads();
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
@@ -273,15 +353,13 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
       mx = b > mx ? b : mx;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const Img a = shfl_xor_img(mn, o), b = shfl_xor_img(mx, o);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    const Img a2 = shfl_xor_img(mn, sh), b2 = shfl_xor_img(mx, sh);
+    mn = a2 < mn ? a2 : mn;
+    mx = b2 > mx ? b2 : mx;
   }
   if (lane == 0) { s_min[wave] = mn; s_max[wave] = mx; }
   for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
-  if (tid == 0) { s_nbig = 0; s_fallback = 0; }
-  if (tid < 3) s_ccnt[tid] = 0;
   __syncthreads();
   mn = s_min[0];
   mx = s_max[0];
@@ -291,95 +369,120 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
   if (mn == mx) return;   // all keys equal: already sorted
 
-  // 2./3. Bins, counts, scan, scatter.
-  uint32_t lb = 1;
-  while ((1u << lb) < MAXBINS && (1u << lb) * LT::MEAN < n) ++lb;
-  const uint32_t span = bitlen((Img)(mx - mn));
-  const uint32_t shift = span > lb ? span - lb : 0;
-  const uint32_t nbins = 1u << lb;
-  const uint32_t ush = uniform_amount(shift);   // the same in every lane
-  uint32_t bin[E], rk[E];
+  // 2./3. Bins of about MEAN keys over [mn, mx], counts, scan, scatter.
+  {
+    uint32_t lb = 1;
+    while ((1u << lb) < MAXBINS && (1u << lb) * LT::MEAN < n) ++lb;
+    const uint32_t span = bitlen((Img)(mx - mn));
+    const uint32_t nbins = 1u << lb;
+    const uint32_t ush = uniform_amount(span > lb ? span - lb : 0);   // the same in every lane
+    uint32_t bin[E], rk[E];
 #pragma unroll
-  for (uint32_t e = 0; e < E; ++e) {
-    if (e * NT + tid < n) {
-      bin[e] = (uint32_t)((Img)(bin_image(k[e]) - mn) >> ush);
-      rk[e] = atomicAdd(&s_cnt[bin[e]], 1u);
-    }
-  }
-  __syncthreads();
-  block_excl_scan<NT>(s_cnt, s_off, nbins, s_wsum);
-#pragma unroll
-  for (uint32_t e = 0; e < E; ++e) {
-    const uint32_t i = e * NT + tid;
-    if (i < n) {
-      const uint32_t q = s_off[bin[e]] + rk[e];
-      keys[q] = k[e];
-      if constexpr (IDX) idxb[q] = (uint16_t)i;
-    }
-  }
-  __syncthreads();
-
-  // 4. Bins by size class: up to NET/4 and up to NET/2 keys are sorted in
-  // registers by one thread each with a network of that size (each class in
-  // its own pass, so that a wavefront runs one network size); the few larger
-  // bins are listed for the wavefronts.
-  constexpr uint32_t BPT = (MAXBINS + NT - 1) / NT;   // bins per thread
-  uint32_t cls_of[BPT];
-#pragma unroll
-  for (uint32_t q = 0; q < BPT; ++q) {
-    const uint32_t b = q * NT + tid;
-    cls_of[q] = 4;
-    if (b < nbins) {
-      const uint32_t sz = s_cnt[b];
-      if (sz > 1) {
-        cls_of[q] = sz <= NET / 4 ? 0u : (sz <= NET / 2 ? 1u : 3u);
-        if (cls_of[q] < 3) {
-          atomicAdd(&s_ccnt[cls_of[q]], 1u);
-        } else {
-          const uint32_t slot = atomicAdd(&s_nbig, 1u);
-          if (slot < 64) s_big[slot] = b;
-          else s_fallback = 1;
-        }
+    for (uint32_t e = 0; e < E; ++e) {
+      if (e * NT + tid < n) {
+        bin[e] = (uint32_t)((Img)(bin_image(k[e]) - mn) >> ush);
+        rk[e] = atomicAdd(&s_cnt[bin[e]], 1u);
       }
     }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    s_cbase[0] = 0;
-    s_cbase[1] = s_ccnt[0];
-    s_cbase[2] = s_ccnt[0] + s_ccnt[1];
-  }
-  __syncthreads();
+    __syncthreads();
+    block_excl_scan<NT>(s_cnt, s_off, nbins, s_wsum);
 #pragma unroll
-  for (uint32_t q = 0; q < BPT; ++q) {
-    const uint32_t c = cls_of[q];
-    if (c < 3) s_list[atomicAdd(&s_cbase[c], 1u)] = (uint16_t)(q * NT + tid);
-  }
-  __syncthreads();
-  {
-    const uint32_t n0 = s_ccnt[0], n1 = s_ccnt[1], n2 = s_ccnt[2];
-    for (uint32_t q = tid; q < n0; q += NT) {
-      const uint32_t b = s_list[q];
-      sort_bin<T, IDX, NET / 4>(keys, idxb, s_off[b], s_cnt[b]);
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = e * NT + tid;
+      if (i < n) {
+        const uint32_t q = s_off[bin[e]] + rk[e];
+        keys[q] = k[e];
+        if constexpr (IDX) idxb[q] = (uint16_t)i;
+      }
     }
-    for (uint32_t q = tid; q < n1; q += NT) {
-      const uint32_t b = s_list[n0 + q];
-      sort_bin<T, IDX, NET / 2>(keys, idxb, s_off[b], s_cnt[b]);
-    }
-    (void)n2;
+    __syncthreads();
+    // 4. Bins by size class.
+    sort_bins(0, nbins);
   }
+
+  // 5. Re-binning rounds, one queued bin [o, o + s) at a time by the whole
+  // workgroup, with one key per thread at a time: the keys (and indices) are
+  // copied to the task's own range in HBM, which is free until the store,
+  // counted by sub-bin, and scattered back from the copy through per-sub-bin
+  // cursors.
+  constexpr uint32_t KW = (uint32_t)(sizeof(Key) / 4);        // key dwords
+  constexpr uint32_t SW = KW + (IDX ? 1u : 0u);               // copy dwords per element
+  static_assert(SW <= (uint32_t)DW, "the copy of an element fits the element");
+  for (uint32_t round = 0;; ++round) {
+    const uint32_t head = s_fat_head, tail = s_fat_tail;
+    if (head == tail || s_fallback) break;
+    if (round >= FAT_ROUNDS) {
+      __syncthreads();
+      if (tid == 0) s_fallback = 1;
+      __syncthreads();
+      break;
+    }
+    const uint32_t o = s_fat_o[head % FATCAP], s = s_fat_s[head % FATCAP];
+    Img mn2 = ~(Img)0, mx2 = 0;
+    for (uint32_t i = tid; i < s; i += NT) {
+      const Key x = keys[o + i];
+      const Img b = bin_image(x);
+      mn2 = b < mn2 ? b : mn2;
+      mx2 = b > mx2 ? b : mx2;
+      uint32_t* dst = gd + (uint64_t)(o + i) * DW;
+      const uint32_t* xw = reinterpret_cast<const uint32_t*>(&x);
+#pragma unroll
+      for (uint32_t d = 0; d < KW; ++d) dst[d] = xw[d];
+      if constexpr (IDX) dst[KW] = idxb[o + i];
+    }
+    for (int sh = 32; sh > 0; sh >>= 1) {
+      const Img a2 = shfl_xor_img(mn2, sh), b2 = shfl_xor_img(mx2, sh);
+      mn2 = a2 < mn2 ? a2 : mn2;
+      mx2 = b2 > mx2 ? b2 : mx2;
+    }
+    __syncthreads();   // every lane has read head and the entry
+    if (lane == 0) { s_min[wave] = mn2; s_max[wave] = mx2; }
+    if (tid == 0) s_fat_head = head + 1;
+    for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
+    __syncthreads();
+    mn2 = s_min[0];
+    mx2 = s_max[0];
+    for (uint32_t w = 1; w < NT / 64; ++w) {
+      mn2 = s_min[w] < mn2 ? s_min[w] : mn2;
+      mx2 = s_max[w] > mx2 ? s_max[w] : mx2;
+    }
+    if (mn2 == mx2) continue;   // one value: final (the next round reads the list after the barrier above)
+    uint32_t lb2 = 1;
+    while ((1u << lb2) < MAXBINS && (1u << lb2) * LT::MEAN < s) ++lb2;
+    const uint32_t span2 = bitlen((Img)(mx2 - mn2));
+    const uint32_t nsub = 1u << lb2;
+    const uint32_t ush2 = uniform_amount(span2 > lb2 ? span2 - lb2 : 0);
+    for (uint32_t i = tid; i < s; i += NT)
+      atomicAdd(&s_cnt[(uint32_t)((Img)(bin_image(keys[o + i]) - mn2) >> ush2)], 1u);
+    __syncthreads();
+    block_excl_scan<NT>(s_cnt, s_off, nsub, s_wsum);
+    for (uint32_t j = tid; j < nsub; j += NT) s_cnt[j] = s_off[j];   // cursors
+    __syncthreads();
+    for (uint32_t i = tid; i < s; i += NT) {
+      const uint32_t* src = gd + (uint64_t)(o + i) * DW;
+      Key x;
+      uint32_t* xw = reinterpret_cast<uint32_t*>(&x);
+#pragma unroll
+      for (uint32_t d = 0; d < KW; ++d) xw[d] = src[d];
+      const uint32_t p = o + atomicAdd(&s_cnt[(uint32_t)((Img)(bin_image(x) - mn2) >> ush2)], 1u);
+      keys[p] = x;
+      if constexpr (IDX) idxb[p] = (uint16_t)src[KW];
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < nsub; j += NT) s_cnt[j] = s_off[j + 1] - s_off[j];   // sizes
+    __syncthreads();
+    sort_bins(o, nsub);
+  }
+
+  // 6. Bins of NET/2 .. WAVE_NET keys by the wavefronts.
   __syncthreads();
-  const uint32_t nbig = s_nbig < 64 ? s_nbig : 64;
   if (!s_fallback) {
-    for (uint32_t q = wave; q < nbig; q += NT / 64) {
-      const uint32_t b = s_big[q], s = s_cnt[b], o = s_off[b];
+    const uint32_t nmid = s_nmid < MIDCAP ? s_nmid : MIDCAP;
+    for (uint32_t q = wave; q < nmid; q += NT / 64) {
+      const uint32_t ent = s_mid[q], o = ent >> 16, s = ent & 0xFFFFu;
       bool same = true;
       for (uint32_t i = lane; i < s; i += 64) same = same && keq(keys[o + i], keys[o]);
       if (__all(same)) continue;
-      if (s > WAVE_MAX) {
-        if (lane == 0) s_fallback = 1;
-        continue;
-      }
       wave_network<Key, IDX>(keys + o, idxb + o, s);
     }
   }
@@ -387,7 +490,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
   __syncthreads();
 
-  // 5. Store.
+  // 7. Store.
   if constexpr (IDX) {
     for (uint32_t x = tid; x < n * DW; x += NT) {
       const uint32_t i = x / DW, d = x - i * DW;
