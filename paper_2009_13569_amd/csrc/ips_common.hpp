@@ -35,6 +35,7 @@ constexpr uint32_t SMP_THREADS = 1024;
 constexpr uint32_t CLN_THREADS = 256;
 constexpr uint32_t LDST_THREADS = 512;
 constexpr uint32_t MAX_SAMPLE = 4096;        // padded sample of one step
+constexpr uint32_t DEEP_ALPHA = 16;          // least oversampling below the root
 constexpr uint32_t PTR_BIAS = 0x80000000u;   // bias of the read pointer half
 
 // Control block at the start of the workspace.
