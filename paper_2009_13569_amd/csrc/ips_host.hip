@@ -1008,7 +1008,7 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
   uint64_t* h_sel = reinterpret_cast<uint64_t*>(r.h_rb);
   // Rounds of steps between readbacks: one step first (a small sort is done
   // after its root step, and steps beyond the work cost their launches),
-  // then 4, doubling to 32; a captured graph holds 4 steps.
+  // then doubling to 32; a captured graph holds 4 steps.
   uint32_t step = 0, round_steps = graph ? 4u : 1u;
   hipGraphExec_t exec = nullptr;
   int rc = IPS_OK;
@@ -1046,7 +1046,7 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
     resolve_profile(ctx);
     if ((rc = check_dev_error(r)) != IPS_OK) break;
     if (r.h_ctrl[CTRL_QHEAD] == r.h_ctrl[CTRL_QTAIL]) break;
-    if (!graph) round_steps = round_steps == 1 ? 4u : std::min<uint32_t>(round_steps * 2, 32);
+    if (!graph) round_steps = std::min<uint32_t>(round_steps * 2, 32);
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (rc != IPS_OK) return rc;
