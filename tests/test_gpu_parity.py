@@ -280,3 +280,19 @@ def test_presorted_inputs_through_partitioning(sorter, kind):
             for algo in ("samplesort", "radix"):
                 log(f"presorted {kind} {dist} n={n} {algo}")
                 assert_parity(gpu_sort(sorter, a, kind, algo=algo, params=p), a, kind)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "pair", "rec100"])
+def test_block_sizes(kind):
+    """Every block size the parameters allow (which sets how many lanes move
+    one block in the permutation: 4 to 64) sorts like the oracle, on inputs
+    that need two partitioning levels.  2 KiB blocks need global buffers."""
+    s = ips.Sorter(0, tuning=None)
+    n = {"u32": 3_000_017, "u64": 2_100_001, "pair": 600_011, "rec100": 120_007}[kind]
+    a = generate(kind, "uniform", n, 4242)
+    ref = oracle.sort(a, kind)
+    for bb in (128, 256, 512, 1024, 2048):
+        flags = ips.FLAG_GLOBAL_BUFFERS if bb == 2048 else 0
+        p = ips.make_params(block_bytes=bb, flags=flags | ips.FLAG_NO_SORTED_CHECK)
+        log(f"block bytes {kind} {bb}")
+        assert_parity(gpu_sort(s, a, kind, params=p), a, kind, ref)
