@@ -418,6 +418,46 @@ __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
 // after the tile, and its block base) is one 16-byte LDS word.
 constexpr uint32_t BUF_PAD = BUF_PAD_DW;
 
+// Copies the listed buffer blocks (bucket s_cj[q] for q < ncp) to their
+// stripe positions, unit u of the flattened list going to lane u mod NT;
+// CP_UNROLL units per lane are loaded before any is stored.  A block that
+// would land at or beyond the read position is reported and not written.
+constexpr int CP_UNROLL = 4;
+template <class U, int UW>
+__device__ __forceinline__ void copy_units(uint32_t ncp, uint32_t upb, const BlockDiv& ud,
+                                           const uint16_t* s_cj, const uint4* s_st,
+                                           const uint32_t* buf, uint32_t bstride, uint32_t* gs,
+                                           uint32_t b, uint32_t DW, uint32_t consumed, uint32_t* ctrl,
+                                           uint32_t wg) {
+  const uint32_t tot = ncp * upb;
+  for (uint32_t u0 = threadIdx.x; u0 < tot; u0 += CLS_THREADS * CP_UNROLL) {
+    U v[CP_UNROLL];
+    uint64_t off[CP_UNROLL];
+    bool ok[CP_UNROLL];
+#pragma unroll
+    for (int r = 0; r < CP_UNROLL; ++r) {
+      const uint32_t u = u0 + (uint32_t)r * CLS_THREADS;
+      ok[r] = false;
+      if (u < tot) {
+        const uint32_t q = ud.div(u), x = u - q * upb;
+        const uint32_t j = s_cj[q];
+        const uint4 st = s_st[j];
+        const uint32_t pos = (st.z + st.x) * b;
+        if (pos + b > consumed) {
+          if (x == 0) dev_error(ctrl, DE_CLS_INPLACE, wg, pos);
+        } else {
+          v[r] = reinterpret_cast<const U*>(buf + j * bstride)[x];
+          off[r] = (uint64_t)pos * DW + x * UW;
+          ok[r] = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < CP_UNROLL; ++r)
+      if (ok[r]) *reinterpret_cast<U*>(gs + off[r]) = v[r];
+  }
+}
+
 template <class T, bool GBUF>
 __global__ void __launch_bounds__(CLS_THREADS)
 k_classify(BatchArgs a) {
@@ -433,8 +473,10 @@ k_classify(BatchArgs a) {
   constexpr uint32_t NMM = T::RADIX_OK ? MAX_K : 1;   // radix key ranges per bucket
   __shared__ uint64_t s_mn[NMM], s_mx[NMM];
   __shared__ uint16_t s_start[1u << START_BITS];
-  __shared__ uint32_t s_wpos;
+  __shared__ uint16_t s_cj[MAX_NB];       // buckets whose LDS buffer block fills in this tile
+  __shared__ uint32_t s_wpos, s_ncopy;
   extern __shared__ __align__(16) uint32_t s_buf[];
+  static_assert(MAX_NB <= CLS_THREADS, "one bucket per thread in the block-state pass");
 
   const uint32_t tid = threadIdx.x;
   const uint32_t wg = blockIdx.x;
@@ -462,7 +504,7 @@ k_classify(BatchArgs a) {
   stab.shift = radix ? 0 : rec->tshift;
   for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_st[j] = make_uint4(0, 0, 0, 0); }
   for (uint32_t j = tid; j < NMM; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
-  if (tid == 0) s_wpos = 0;
+  if (tid == 0) { s_wpos = 0; s_ncopy = 0; }
   // buffer of bucket j at buf + j * bstride (dwords)
   const uint32_t bdw = b * DW;
   const uint32_t bstride = GBUF ? bdw : bdw + BUF_PAD;
@@ -476,6 +518,8 @@ k_classify(BatchArgs a) {
   const uint64_t ehi = ((uint64_t)bhi * b < tn) ? (uint64_t)bhi * b : tn;
   const uint32_t slen = (uint32_t)(ehi - elo);        // stripe length (elements)
   uint32_t* gs = a.data + (tk.l + elo) * DW;          // stripe base
+  const bool pair_units = (bdw & 1) == 0 && (reinterpret_cast<uintptr_t>(gs) & 7) == 0;
+  const BlockDiv ud(pair_units ? bdw / 2 : bdw);
 
   uint32_t cur[EPT][DW];
   uint32_t nxt[EPT][DW];
@@ -527,12 +571,39 @@ k_classify(BatchArgs a) {
       if (idx < slen) ld_elem<DW>(gs + (uint64_t)idx * DW, nxt[i]);
     }
     __syncthreads();
-    for (uint32_t j = tid; j < nb; j += NT) {
-      const uint32_t fo = s_st[j].y;          // blocks full before this tile
-      const uint32_t nf = bd.div(s_cnt[j]);
-      uint32_t base = 0;
-      if (nf > fo) base = atomicAdd(&s_wpos, nf - fo) - fo;
-      s_st[j] = make_uint4(fo, nf, base, 0);
+    // Block state of each bucket (thread j): blocks full before and after
+    // the tile, and where its new full blocks go.  The new blocks of a
+    // wavefront's buckets are numbered by a prefix sum over the wavefront
+    // and placed after the blocks already written (one counter update per
+    // wavefront); buckets whose buffer block fills are listed for the copy.
+    if ((tid & ~63u) < nb) {
+      const uint32_t lane = tid & 63;
+      const bool valid = tid < nb;
+      const uint32_t fo = valid ? s_st[tid].y : 0u;          // blocks full before this tile
+      const uint32_t nf = valid ? bd.div(s_cnt[tid]) : 0u;
+      const uint32_t d = nf - fo;
+      uint32_t inc = d;
+#pragma unroll
+      for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += t;
+      }
+      const uint64_t cm = __ballot(d != 0);
+      uint32_t wb = 0, cb = 0;
+      if (lane == 63) {
+        wb = atomicAdd(&s_wpos, inc);
+        cb = atomicAdd(&s_ncopy, (uint32_t)__popcll(cm));
+      }
+      wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 63);
+      cb = (uint32_t)__builtin_amdgcn_readlane((int)cb, 63);
+      if (valid) {
+        s_st[tid] = make_uint4(fo, nf, wb + inc - d - fo, 0);
+        if (d) {
+          const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+          s_cj[cb + r] = (uint16_t)tid;
+        }
+      }
     }
     __syncthreads();
     const uint32_t consumed = (ts + TILE < slen) ? ts + TILE : slen;
@@ -564,29 +635,16 @@ k_classify(BatchArgs a) {
     // before this tile's block stores, so that using them later does not
     // wait for the stores.
     __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
+    // Copy of the buffer blocks that filled (listed in s_cj) to their
+    // places in the stripe, spread over all lanes in 8-byte units (dwords
+    // when a block is not made of whole 8-byte units).
     {
-      const uint32_t wave = tid >> 6, lane = tid & 63;
-      for (uint32_t j = wave; j < nb; j += NT / 64) {
-        const uint4 st = s_st[j];
-        if (st.y > st.x) {
-          const uint32_t pos = (st.z + st.x) * b;
-          if (pos + b > consumed) {
-            if (lane == 0) dev_error(a.ctrl, DE_CLS_INPLACE, wg, pos);
-          } else {
-            uint32_t* dst = gs + (uint64_t)pos * DW;
-            const uint32_t* src = buf + j * bstride;
-            if ((bdw & 1) == 0 && (reinterpret_cast<uintptr_t>(dst) & 7) == 0) {   // 8-byte pieces
-              uint2* d2 = reinterpret_cast<uint2*>(dst);
-              const uint2* s2 = reinterpret_cast<const uint2*>(src);
-              for (uint32_t x = lane; x < bdw / 2; x += 64) d2[x] = s2[x];
-            } else {
-              for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
-            }
-          }
-        }
-      }
+      const uint32_t ncp = s_ncopy;
+      if (pair_units) copy_units<uint2, 2>(ncp, bdw / 2, ud, s_cj, s_st, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
+      else copy_units<uint32_t, 1>(ncp, bdw, ud, s_cj, s_st, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
     }
     __syncthreads();
+    if (tid == 0) s_ncopy = 0;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
