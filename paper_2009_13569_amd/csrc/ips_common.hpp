@@ -93,13 +93,19 @@ enum DevErr : uint32_t {
 constexpr uint32_t CHILD_WGS = 1024;   // workgroups of the children kernel (at most)
 constexpr uint32_t LDS_DEFER_TASKS = 16384;   // device-planned steps: LDS-tier lists run from this many tasks
 constexpr uint32_t START_BITS = 12;   // start-node table: 2^12 entries
+// A start-table entry either names the tree node to descend from, or (with
+// START_DIRECT set) the first bucket of its key range in bits 0-8 and the
+// number of further buckets the range reaches (at most START_SPAN - 1) in
+// bits 9-11: the bucket is then found by comparing with those splitters.
+constexpr uint32_t START_DIRECT = 0x8000u;
+constexpr uint32_t START_SPAN = 8;
 struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;
   uint32_t shift, width, radix, tshift;
   uint64_t tbase;            // start-node table: key image of s_0 and shift
   uint64_t tree[MAX_K][2];   // tree[1..K-1], breadth-first order
   uint64_t spl[MAX_K][2];    // sorted splitters s_0..s_{K-1}, s_{K-1} = s_{K-2}
-  uint16_t tstart[1u << START_BITS];   // tree node to start from, by key prefix
+  uint16_t tstart[1u << START_BITS];   // start-table entries (tree node or first bucket and span), by key prefix
 };
 
 // One partitioning task of a batch (a subarray A[l, l+n) of the input).

@@ -189,9 +189,12 @@ __device__ __forceinline__ uint32_t bucket_of(const typename T::Key& k, const ty
 }
 
 // Start-node table (the lookup table of start nodes addressed by the most
-// significant key bits suggested in the paper's Section 8): entry p holds
-// the deepest tree node whose subtree receives every key whose image lies in
-// prefix range p, so the descent starts there and takes fewer steps.
+// significant key bits suggested in the paper's Section 8).  Entry p covers
+// the keys whose image lies in prefix range p.  When those keys fall into at
+// most START_SPAN consecutive buckets the entry holds the first of them and
+// how many follow, and a key's bucket is found by comparing it with the
+// splitters in between (usually none or one); otherwise it holds the deepest
+// tree node whose subtree receives all of them, and the descent starts there.
 struct StartTable {
   const uint16_t* start;
   uint64_t base;
@@ -202,19 +205,6 @@ struct StartTable {
     return q >= (1u << START_BITS) ? (1u << START_BITS) - 1 : (uint32_t)q;
   }
 };
-
-template <class T>
-__device__ __forceinline__ uint32_t tree_bucket_st(const typename T::Key* __restrict__ tree,
-                                                   const typename T::Key* __restrict__ spl,
-                                                   uint32_t logK, uint32_t eq, const StartTable& st,
-                                                   const typename T::Key& e) {
-  const uint32_t K = 1u << logK;
-  uint32_t i = st.start[st.index(T::img(e))];
-  while (i < K) i = 2 * i + (kless(tree[i], e) ? 1u : 0u);
-  i -= K;
-  if (eq) i = 2 * i + (kless(e, spl[i]) ? 0u : 1u);
-  return i;
-}
 
 // --------------------------------------------------------------- sampling
 
@@ -341,13 +331,22 @@ k_sample(BatchArgs a, uint64_t seed) {
       if (hi > T::IMG_MAX) hi = T::IMG_MAX;
     }
     const Key klo = T::lo_of(lo), khi = T::hi_of(hi);
-    uint32_t i = 1;
-    while (i < K) {
-      if (kless(s_tree[i], klo)) i = 2 * i + 1;          // every key goes right
-      else if (!kless(s_tree[i], khi)) i = 2 * i;       // every key goes left
-      else break;
+    uint32_t bl = 1, bh = 1;   // buckets of the range's lowest and highest key
+    while (bl < K) bl = 2 * bl + (kless(s_tree[bl], klo) ? 1u : 0u);
+    while (bh < K) bh = 2 * bh + (kless(s_tree[bh], khi) ? 1u : 0u);
+    bl -= K; bh -= K;
+    uint32_t v;
+    if (bh - bl < START_SPAN) {
+      v = START_DIRECT | ((bh - bl) << 9) | bl;
+    } else {
+      v = 1;
+      while (v < K) {
+        if (kless(s_tree[v], klo)) v = 2 * v + 1;          // every key goes right
+        else if (!kless(s_tree[v], khi)) v = 2 * v;       // every key goes left
+        else break;
+      }
     }
-    rec->tstart[p] = (uint16_t)i;
+    rec->tstart[p] = (uint16_t)v;
   }
   if (threadIdx.x == 0) {
     rec->K = K; rec->logK = logK; rec->eq = eq; rec->nb = eq ? 2 * K : K;
@@ -364,10 +363,14 @@ k_sample(BatchArgs a, uint64_t seed) {
 // operation of the wave (vmcnt(0); LDS and export counts unrestricted).
 constexpr int WAITCNT_VM0 = 0x0F70;
 
-// Buckets of the EPT elements a thread holds, all stepping through the
-// decision tree together: the start nodes come from the start table, then
-// every level reads the node of each element not yet at a leaf (a
-// branch-free step), so the LDS reads of all elements are in flight at once.
+// Buckets of the EPT elements a thread holds, all stepping together.  Each
+// element starts from its start-table entry: a tree node to descend from,
+// or a first bucket and a number of splitters to compare with in order
+// (the bucket grows while the splitter is below the key).  Every step reads
+// one tree node or splitter for each element not yet done (a branch-free
+// step), so the LDS reads of all elements are in flight at once; the steps
+// end when no element of the wavefront has one left.  State per element:
+// the node (leaves K + bucket) in bits 0-15, splitters left in bits 16-31.
 template <class T, int EPT>
 __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
                                              const typename T::Key* __restrict__ tree,
@@ -375,33 +378,36 @@ __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
                                              uint32_t logK, uint32_t eq, const StartTable& st,
                                              uint32_t (&bk)[EPT]) {
   const uint32_t K = 1u << logK;
-  uint32_t j[EPT];
+  uint32_t w[EPT];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) j[i] = st.start[st.index(T::img(key[i]))];
-  for (uint32_t l = 0; l < logK; ++l) {
+  for (int i = 0; i < EPT; ++i) {
+    const uint32_t v = st.start[st.index(T::img(key[i]))];
+    w[i] = (v & START_DIRECT) ? ((K + (v & 0x1FFu)) | (((v >> 9) & 7u) << 16)) : v;
+  }
+  for (uint32_t l = 0; l < logK + START_SPAN; ++l) {
     bool act = false;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) act = act || j[i] < K;
+    for (int i = 0; i < EPT; ++i) act = act || (w[i] & 0xFFFFu) < K || (w[i] >> 16) != 0;
     if (!__any(act)) break;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const bool in = j[i] < K;
-      const typename T::Key t = tree[in ? j[i] : 1u];
-      const uint32_t nj = 2 * j[i] + (kless(t, key[i]) ? 1u : 0u);
-      j[i] = in ? nj : j[i];
+      const uint32_t node = w[i] & 0xFFFFu, r = w[i] >> 16;
+      const bool tr = node < K, cm = !tr && r != 0;
+      const typename T::Key* p = tr ? tree + node : (cm ? spl + (node - K) : tree + 1);
+      const bool gt = kless(*p, key[i]);
+      const uint32_t nw = tr ? 2 * node + (gt ? 1u : 0u) : (gt ? ((node + 1) | ((r - 1) << 16)) : node);
+      w[i] = (tr || cm) ? nw : w[i];
     }
   }
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) j[i] -= K;
+  for (int i = 0; i < EPT; ++i) bk[i] = (w[i] & 0xFFFFu) - K;
   if (eq) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const typename T::Key sp = spl[j[i]];
-      j[i] = 2 * j[i] + (kless(key[i], sp) ? 0u : 1u);
+      const typename T::Key sp = spl[bk[i]];
+      bk[i] = 2 * bk[i] + (kless(key[i], sp) ? 0u : 1u);
     }
   }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) bk[i] = j[i];
 }
 
 // Classification phase (Section 4.1): the workgroup scans its stripe of
