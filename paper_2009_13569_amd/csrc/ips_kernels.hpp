@@ -373,10 +373,10 @@ constexpr int WAITCNT_VM0 = 0x0F70;
 // the node (leaves K + bucket) in bits 0-15, splitters left in bits 16-31.
 template <class T, int EPT>
 __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
-                                             const typename T::Key* __restrict__ tree,
-                                             const typename T::Key* __restrict__ spl,
+                                             const typename T::Key* __restrict__ ts,
                                              uint32_t logK, uint32_t eq, const StartTable& st,
                                              uint32_t (&bk)[EPT]) {
+  using Key = typename T::Key;
   const uint32_t K = 1u << logK;
   uint32_t w[EPT];
 #pragma unroll
@@ -389,14 +389,23 @@ __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
 #pragma unroll
     for (int i = 0; i < EPT; ++i) act = act || (w[i] & 0xFFFFu) < K || (w[i] >> 16) != 0;
     if (!__any(act)) break;
+    // All reads first: tree node, else splitter node - K (read but unused
+    // once the element is done).
+    Key t[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint32_t node = w[i] & 0xFFFFu;
+      t[i] = ts[node < K ? node : node - K + MAX_K];
+    }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const uint32_t node = w[i] & 0xFFFFu, r = w[i] >> 16;
-      const bool tr = node < K, cm = !tr && r != 0;
-      const typename T::Key* p = tr ? tree + node : (cm ? spl + (node - K) : tree + 1);
-      const bool gt = kless(*p, key[i]);
-      const uint32_t nw = tr ? 2 * node + (gt ? 1u : 0u) : (gt ? ((node + 1) | ((r - 1) << 16)) : node);
-      w[i] = (tr || cm) ? nw : w[i];
+      const uint32_t g = kless(t[i], key[i]) ? 1u : 0u;
+      const uint32_t wt = 2 * node + g;                        // descend
+      const uint32_t wc = (node + g) | ((g * (r - 1)) << 16);  // next splitter, or stop
+      const uint32_t mt = 0u - (uint32_t)(node < K);
+      const uint32_t mc = 0u - (uint32_t)(node >= K && r != 0);
+      w[i] = (wt & mt) | (wc & mc) | (w[i] & ~(mt | mc));
     }
   }
 #pragma unroll
@@ -404,7 +413,7 @@ __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
   if (eq) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const typename T::Key sp = spl[bk[i]];
+      const Key sp = ts[MAX_K + bk[i]];
       bk[i] = 2 * bk[i] + (kless(key[i], sp) ? 0u : 1u);
     }
   }
@@ -472,8 +481,7 @@ k_classify(BatchArgs a) {
   constexpr int EPT = T::EPT;
   constexpr uint32_t NT = CLS_THREADS;
   constexpr uint32_t TILE = NT * EPT;
-  __shared__ Key s_tree[MAX_K];
-  __shared__ Key s_spl[MAX_K];
+  __shared__ Key s_ts[2 * MAX_K];         // tree nodes [0, K), splitters from MAX_K
   __shared__ uint32_t s_cnt[MAX_NB];
   __shared__ uint4 s_st[MAX_NB];          // {blocks before tile, blocks after, base, 0}
   constexpr uint32_t NMM = T::RADIX_OK ? MAX_K : 1;   // radix key ranges per bucket
@@ -499,8 +507,8 @@ k_classify(BatchArgs a) {
   const StepRec* rec = a.recs + tix;
   if (!radix) {
     for (uint32_t i = tid; i < tk.K; i += NT) {
-      s_tree[i] = T::from_slot(rec->tree[i]);
-      s_spl[i] = T::from_slot(rec->spl[i]);
+      s_ts[i] = T::from_slot(rec->tree[i]);
+      s_ts[MAX_K + i] = T::from_slot(rec->spl[i]);
     }
     for (uint32_t i = tid; i < (1u << START_BITS); i += NT) s_start[i] = rec->tstart[i];
   }
@@ -558,7 +566,7 @@ k_classify(BatchArgs a) {
         radix_done = true;
       }
     }
-    if (!radix_done) tree_buckets<T, EPT>(key, s_tree, s_spl, logK, eq, stab, bk);
+    if (!radix_done) tree_buckets<T, EPT>(key, s_ts, logK, eq, stab, bk);
     if (full) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) sl[i] = atomicAdd(&s_cnt[bk[i]], 1u);
