@@ -429,18 +429,20 @@ __device__ __forceinline__ void tree_buckets(const typename T::Key (&key)[EPT],
 //
 // LDS buffers are laid out with a stride of b*DW + BUF_PAD dwords per bucket
 // so that lanes appending at the same offset of different buckets fall into
-// different banks; each bucket's tile state (blocks full before the tile,
-// after the tile, and its block base) is one 16-byte LDS word.
+// different banks.  Each bucket's tile state is an 8-byte word (blocks full
+// before the tile, after it) that every element reads, beside its block base
+// that only elements stored straight to the stripe read; 8-byte words of
+// random buckets spread over twice as many banks as 16-byte ones.
 constexpr uint32_t BUF_PAD = BUF_PAD_DW;
 
-// Copies the listed buffer blocks (bucket s_cj[q] for q < ncp) to their
-// stripe positions, unit u of the flattened list going to lane u mod NT;
+// Copies the listed buffer blocks (bucket s_cj[q] for q < ncp, to stripe
+// block s_cpos[q]), unit u of the flattened list going to lane u mod NT;
 // CP_UNROLL units per lane are loaded before any is stored.  A block that
 // would land at or beyond the read position is reported and not written.
 constexpr int CP_UNROLL = 4;
 template <class U, int UW>
 __device__ __forceinline__ void copy_units(uint32_t ncp, uint32_t upb, const BlockDiv& ud,
-                                           const uint16_t* s_cj, const uint4* s_st,
+                                           const uint16_t* s_cj, const uint32_t* s_cpos,
                                            const uint32_t* buf, uint32_t bstride, uint32_t* gs,
                                            uint32_t b, uint32_t DW, uint32_t consumed, uint32_t* ctrl,
                                            uint32_t wg) {
@@ -456,8 +458,7 @@ __device__ __forceinline__ void copy_units(uint32_t ncp, uint32_t upb, const Blo
       if (u < tot) {
         const uint32_t q = ud.div(u), x = u - q * upb;
         const uint32_t j = s_cj[q];
-        const uint4 st = s_st[j];
-        const uint32_t pos = (st.z + st.x) * b;
+        const uint32_t pos = s_cpos[q] * b;
         if (pos + b > consumed) {
           if (x == 0) dev_error(ctrl, DE_CLS_INPLACE, wg, pos);
         } else {
@@ -483,11 +484,13 @@ k_classify(BatchArgs a) {
   constexpr uint32_t TILE = NT * EPT;
   __shared__ Key s_ts[2 * MAX_K];         // tree nodes [0, K), splitters from MAX_K
   __shared__ uint32_t s_cnt[MAX_NB];
-  __shared__ uint4 s_st[MAX_NB];          // {blocks before tile, blocks after, base, 0}
+  __shared__ uint2 s_fn[MAX_NB];          // {blocks full before the tile, after it}
+  __shared__ uint32_t s_base[MAX_NB];     // block j of the bucket goes to stripe block base + j
   constexpr uint32_t NMM = T::RADIX_OK ? MAX_K : 1;   // radix key ranges per bucket
   __shared__ uint64_t s_mn[NMM], s_mx[NMM];
   __shared__ uint16_t s_start[1u << START_BITS];
   __shared__ uint16_t s_cj[MAX_NB];       // buckets whose LDS buffer block fills in this tile
+  __shared__ uint32_t s_cpos[MAX_NB];     // and the stripe block it goes to
   __shared__ uint32_t s_wpos, s_ncopy;
   extern __shared__ __align__(16) uint32_t s_buf[];
   static_assert(MAX_NB <= CLS_THREADS, "one bucket per thread in the block-state pass");
@@ -516,7 +519,7 @@ k_classify(BatchArgs a) {
   stab.start = s_start;
   stab.base = radix ? 0 : rec->tbase;
   stab.shift = radix ? 0 : rec->tshift;
-  for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_st[j] = make_uint4(0, 0, 0, 0); }
+  for (uint32_t j = tid; j < nb; j += NT) { s_cnt[j] = 0; s_fn[j] = make_uint2(0, 0); s_base[j] = 0; }
   for (uint32_t j = tid; j < NMM; j += NT) { s_mn[j] = ~0ull; s_mx[j] = 0; }
   if (tid == 0) { s_wpos = 0; s_ncopy = 0; }
   // buffer of bucket j at buf + j * bstride (dwords)
@@ -593,7 +596,7 @@ k_classify(BatchArgs a) {
     if ((tid & ~63u) < nb) {
       const uint32_t lane = tid & 63;
       const bool valid = tid < nb;
-      const uint32_t fo = valid ? s_st[tid].y : 0u;          // blocks full before this tile
+      const uint32_t fo = valid ? s_fn[tid].y : 0u;          // blocks full before this tile
       const uint32_t nf = valid ? bd.div(s_cnt[tid]) : 0u;
       const uint32_t d = nf - fo;
       uint32_t inc = d;
@@ -611,11 +614,13 @@ k_classify(BatchArgs a) {
       wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 63);
       cb = (uint32_t)__builtin_amdgcn_readlane((int)cb, 63);
       if (valid) {
-        s_st[tid] = make_uint4(fo, nf, wb + inc - d - fo, 0);
+        s_fn[tid] = make_uint2(fo, nf);
+        s_base[tid] = wb + inc - d - fo;
         if (d) {
           const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
           s_cj[cb + r] = (uint16_t)tid;
+          s_cpos[cb + r] = wb + inc - d;
         }
       }
     }
@@ -624,21 +629,21 @@ k_classify(BatchArgs a) {
     // Per-bucket tile states of the elements, read together (kept in
     // registers when there are at most 8 elements per thread).
     constexpr int NST = EPT <= 8 ? EPT : 1;
-    uint4 stv[NST];
+    uint2 stv[NST];
     if constexpr (EPT <= 8) {
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) stv[i] = s_st[bk[i]];
+      for (int i = 0; i < EPT; ++i) stv[i] = s_fn[bk[i]];
     }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint4 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_st[bk[i]];
+        const uint2 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.x) {
           st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
         } else if (blk < st.y) {
-          const uint32_t pos = (st.z + blk) * b + o;
+          const uint32_t pos = (s_base[bk[i]] + blk) * b + o;
           if (pos >= consumed) dev_error(a.ctrl, DE_CLS_INPLACE, wg, pos);
           else st_elem<DW>(gs + (uint64_t)pos * DW, cur[i]);
         }
@@ -654,8 +659,8 @@ k_classify(BatchArgs a) {
     // when a block is not made of whole 8-byte units).
     {
       const uint32_t ncp = s_ncopy;
-      if (pair_units) copy_units<uint2, 2>(ncp, bdw / 2, ud, s_cj, s_st, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
-      else copy_units<uint32_t, 1>(ncp, bdw, ud, s_cj, s_st, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
+      if (pair_units) copy_units<uint2, 2>(ncp, bdw / 2, ud, s_cj, s_cpos, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
+      else copy_units<uint32_t, 1>(ncp, bdw, ud, s_cj, s_cpos, buf, bstride, gs, b, DW, consumed, a.ctrl, wg);
     }
     __syncthreads();
     if (tid == 0) s_ncopy = 0;
@@ -663,7 +668,7 @@ k_classify(BatchArgs a) {
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint4 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_st[bk[i]];
+        const uint2 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.y && blk > st.x) st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
       }
@@ -675,7 +680,7 @@ k_classify(BatchArgs a) {
   }
   __syncthreads();
   for (uint32_t j = tid; j < nb; j += NT) {
-    const uint32_t nfull = s_st[j].y;
+    const uint32_t nfull = s_fn[j].y;
     a.wg_nfull[(uint64_t)wg * MAX_NB + j] = nfull;
     a.wg_left[(uint64_t)wg * MAX_NB + j] = s_cnt[j] - nfull * b;
     if (radix && j < MAX_K) {
@@ -688,7 +693,7 @@ k_classify(BatchArgs a) {
     uint32_t* slot = reinterpret_cast<uint32_t*>(a.slots + tk.slot_off + (uint64_t)s * tk.slot_bytes);
     const uint32_t wave = tid >> 6, lane = tid & 63;
     for (uint32_t j = wave; j < nb; j += NT / 64) {
-      const uint32_t fill = (s_cnt[j] - s_st[j].y * b) * DW;
+      const uint32_t fill = (s_cnt[j] - s_fn[j].y * b) * DW;
       const uint32_t* src = buf + j * bstride;
       uint32_t* dst = slot + (uint64_t)j * bdw;
       for (uint32_t x = lane; x < fill; x += 64) dst[x] = src[x];
