@@ -18,8 +18,9 @@
 //      round splits a bin (its minimum and maximum land in different
 //      sub-bins) and a sub-bin of one value is final;
 //   6. bins of NET/2 .. WAVE_NET keys are sorted by one wavefront each with a
-//      bitonic network in LDS; only if a list overflows does the whole task
-//      fall back to a block-wide bitonic network;
+//      bitonic network in registers across its lanes (one or two keys per
+//      lane, partners read by lane shuffles); only if a list overflows does
+//      the whole task fall back to a block-wide bitonic network in LDS;
 //   7. one coalesced store (records are gathered from their LDS copy).
 #pragma once
 #include "ips_kernels.hpp"
@@ -127,35 +128,75 @@ __device__ __forceinline__ void reg_network(Key (&v)[N], uint32_t (&ix)[N]) {
   net_sort<N, 2, Key, IDX>(v, ix);
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// A key from lane `src` of the wavefront (every dword of it).
+template <class Key>
+__device__ __forceinline__ Key shfl_key(const Key& k, uint32_t src) {
+  constexpr int KW = (int)(sizeof(Key) / 4);
+  uint32_t w[KW];
+  __builtin_memcpy(w, &k, sizeof(Key));
+#pragma unroll
+  for (int d = 0; d < KW; ++d) w[d] = (uint32_t)__shfl((int)w[d], (int)src, 64);
+  Key r;
+  __builtin_memcpy(&r, w, sizeof(Key));
+  return r;
 }
 
-// One wavefront sorts keys[0, s) (and their indices) in LDS with the same
-// all-ascending network over the next power of two, skipping comparators
-// that touch the virtual padding.
-template <class Key, bool IDX>
-__device__ void wave_network(Key* keys, uint16_t* idx, uint32_t s) {
+// One wavefront sorts keys[0, s) (s <= 64 R) and their indices in
+// registers, R keys per lane (element i = lane * R + r), with the same
+// all-ascending network over the next power of two, padded with the largest
+// key.  A comparator whose partner i ^ m lies in another lane reads the
+// partner through a lane shuffle; the lower index keeps the smaller of the
+// two (key, index) pairs, the upper one the larger, so both sides of a
+// comparator agree.
+template <class T, bool IDX, uint32_t R>
+__device__ void wave_reg_network(typename T::Key* keys, uint16_t* idx, uint32_t s) {
+  using Key = typename T::Key;
+  static_assert(R == 1 || R == 2, "one or two keys per lane");
   const uint32_t lane = threadIdx.x & 63;
-  uint32_t P = 1;
+  uint32_t P = 2;
   while (P < s) P <<= 1;
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = lane; i < P; i += 64) {
-        const uint32_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
-        if (p > i && p < s) {
-          Key a = keys[i], b = keys[p];
-          uint32_t ia = IDX ? idx[i] : 0, ib = IDX ? idx[p] : 0;
-          const bool sw = kless(b, a) || (IDX && keq(a, b) && ib < ia);
-          if (sw) {
-            keys[i] = b; keys[p] = a;
-            if (IDX) { idx[i] = (uint16_t)ib; idx[p] = (uint16_t)ia; }
-          }
+  Key v[R];
+  uint32_t ix[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = lane * R + r;
+    v[r] = i < s ? keys[i] : T::kmax();
+    ix[r] = i < s ? (IDX ? (uint32_t)idx[i] : 0u) : 0xFFFFFFFFu;
+  }
+  for (uint32_t K = 2; K <= P; K <<= 1) {
+    for (uint32_t J = K >> 1; J > 0; J >>= 1) {
+      const uint32_t m = (J == (K >> 1)) ? K - 1 : J;   // partner i ^ m
+      Key nv[R];
+      uint32_t nix[R];
+#pragma unroll
+      for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t i = lane * R + r;
+        const uint32_t pr = r ^ (m & (R - 1));            // partner's register
+        const Key own = (pr == 0) ? v[0] : v[R - 1];
+        const uint32_t oix = (pr == 0) ? ix[0] : ix[R - 1];
+        Key pv = own;
+        uint32_t pix = oix;
+        if (m >= R) {                                       // partner in lane lane ^ (m / R)
+          const uint32_t pl = lane ^ (m / R);
+          pv = shfl_key(own, pl);
+          if (IDX) pix = (uint32_t)__shfl((int)oix, (int)pl, 64);
         }
+        const bool pless = kless(pv, v[r]) || (IDX && keq(pv, v[r]) && pix < ix[r]);
+        const bool mless = kless(v[r], pv) || (IDX && keq(v[r], pv) && ix[r] < pix);
+        const bool take = (i & J) == 0 ? pless : mless;
+        nv[r] = take ? pv : v[r];
+        nix[r] = take ? pix : ix[r];
       }
-      wave_sync();
+#pragma unroll
+      for (uint32_t r = 0; r < R; ++r) { v[r] = nv[r]; ix[r] = nix[r]; }
+    }
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = lane * R + r;
+    if (i < s) {
+      keys[i] = v[r];
+      if (IDX) idx[i] = (uint16_t)ix[r];
     }
   }
 }
@@ -483,7 +524,8 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
       bool same = true;
       for (uint32_t i = lane; i < s; i += 64) same = same && keq(keys[o + i], keys[o]);
       if (__all(same)) continue;
-      wave_network<Key, IDX>(keys + o, idxb + o, s);
+      if (s <= 64) wave_reg_network<T, IDX, 1>(keys + o, idxb + o, s);
+      else wave_reg_network<T, IDX, 2>(keys + o, idxb + o, s);
     }
   }
   __syncthreads();
