@@ -148,6 +148,11 @@ __device__ __forceinline__ void st_elem(uint32_t* p, const uint32_t (&w)[DW]) {
 // Placement pieces per bucket aimed for: few enough that a 64-bit mask
 // can record which of them are full, enough to spread pointer contention.
 
+// Number of lanes below this one whose bit is set in the wavefront mask m.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 struct BlockDiv {
   uint32_t b, sh;
   bool pow2;
@@ -617,8 +622,7 @@ k_classify(BatchArgs a) {
         s_fn[tid] = make_uint2(fo, nf);
         s_base[tid] = wb + inc - d - fo;
         if (d) {
-          const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+          const uint32_t r = lanes_below(cm);
           s_cj[cb + r] = (uint16_t)tid;
           s_cpos[cb + r] = wb + inc - d;
         }

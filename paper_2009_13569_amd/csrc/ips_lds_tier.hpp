@@ -273,7 +273,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   __shared__ uint32_t s_off[MAXBINS + 1];
   __shared__ Img s_min[NT / 64], s_max[NT / 64];
   __shared__ uint16_t s_list[MAXBINS];       // bins grouped by size class
-  __shared__ uint32_t s_ccnt[3], s_cbase[3];
+  __shared__ uint32_t s_ccnt[2];
   constexpr uint32_t MIDCAP = MAXBINS / 2;   // > CAP / (NET/2 + 1): never overflows
   __shared__ uint32_t s_mid[MIDCAP];         // (offset << 16) | size, for the wavefronts
   __shared__ uint32_t s_fat_o[FATCAP], s_fat_s[FATCAP];
@@ -319,11 +319,15 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   // in its own pass, so that a wavefront runs one network size); larger bins
   // go to the wavefront list or the queue of re-binning rounds.  Bin b of
   // nbins lies at o + s_off[b] and holds s_cnt[b] keys.
+  // The list of each class is built without per-bin atomics: a bin's place
+  // is its rank among the wavefront's bins of that class (ballots) after the
+  // wavefront's base (one counter update per wavefront and class).
   auto sort_bins = [&](uint32_t o, uint32_t nbins) {
     constexpr uint32_t BPT = (MAXBINS + NT - 1) / NT;   // bins per thread
-    uint32_t cls_of[BPT];
-    if (tid < 3) s_ccnt[tid] = 0;
+    uint32_t cls_of[BPT], rk[BPT];
+    if (tid < 2) s_ccnt[tid] = 0;
     __syncthreads();
+    uint32_t run0 = 0, run1 = 0;
 #pragma unroll
     for (uint32_t q = 0; q < BPT; ++q) {
       const uint32_t b = q * NT + tid;
@@ -332,25 +336,30 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
         const uint32_t sz = s_cnt[b];
         if (sz > 1) {
           cls_of[q] = sz <= NET / 4 ? 0u : (sz <= NET / 2 ? 1u : 3u);
-          if (cls_of[q] < 3) atomicAdd(&s_ccnt[cls_of[q]], 1u);
-          else push_big(o + s_off[b], sz);
+          if (cls_of[q] == 3) push_big(o + s_off[b], sz);
         }
       }
+      const uint64_t m0 = __ballot(cls_of[q] == 0), m1 = __ballot(cls_of[q] == 1);
+      rk[q] = cls_of[q] == 0 ? run0 + lanes_below(m0) : run1 + lanes_below(m1);
+      run0 += (uint32_t)__popcll(m0);
+      run1 += (uint32_t)__popcll(m1);
     }
-    __syncthreads();
-    if (tid == 0) {
-      s_cbase[0] = 0;
-      s_cbase[1] = s_ccnt[0];
-      s_cbase[2] = s_ccnt[0] + s_ccnt[1];
+    uint32_t wb0 = 0, wb1 = 0;
+    if (lane == 0) {
+      wb0 = atomicAdd(&s_ccnt[0], run0);
+      wb1 = atomicAdd(&s_ccnt[1], run1);
     }
+    wb0 = (uint32_t)__builtin_amdgcn_readlane((int)wb0, 0);
+    wb1 = (uint32_t)__builtin_amdgcn_readlane((int)wb1, 0);
     __syncthreads();
+    const uint32_t n0 = s_ccnt[0], n1 = s_ccnt[1];
 #pragma unroll
     for (uint32_t q = 0; q < BPT; ++q) {
       const uint32_t c = cls_of[q];
-      if (c < 3) s_list[atomicAdd(&s_cbase[c], 1u)] = (uint16_t)(q * NT + tid);
+      if (c == 0) s_list[wb0 + rk[q]] = (uint16_t)(q * NT + tid);
+      else if (c == 1) s_list[n0 + wb1 + rk[q]] = (uint16_t)(q * NT + tid);
     }
     __syncthreads();
-    const uint32_t n0 = s_ccnt[0], n1 = s_ccnt[1];
     for (uint32_t q = tid; q < n0; q += NT) {
       const uint32_t b = s_list[q];
       sort_bin<T, IDX, NET / 4>(keys, idxb, o + s_off[b], s_cnt[b]);
