@@ -9,18 +9,19 @@
 //   3. bin counts by LDS atomics, an exclusive scan, a scatter into LDS;
 //   4. each thread sorts one bin of at most NET/2 keys with a register
 //      bitonic network of size NET/4 or NET/2, the smaller one that holds it
-//      (bins are grouped by that size, one pass per size); a bin whose keys
-//      are all equal needs nothing;
+//      (bins are grouped by that size, one pass per size); in the same phase
+//      each bin of NET/2 .. WAVE_NET keys is sorted by one wavefront with a
+//      bitonic network in registers across its lanes (one or two keys per
+//      lane, partners read by lane shuffles); a bin whose keys are all equal
+//      needs nothing;
 //   5. a bin above WAVE_NET keys is binned again by the whole workgroup over
 //      its own key range (bins that collect many keys are the ones skewed or
 //      duplicate-heavy inputs produce): its sub-bins of at most NET/2 keys
 //      are sorted in registers at once, larger ones are queued again; every
 //      round splits a bin (its minimum and maximum land in different
 //      sub-bins) and a sub-bin of one value is final;
-//   6. bins of NET/2 .. WAVE_NET keys are sorted by one wavefront each with a
-//      bitonic network in registers across its lanes (one or two keys per
-//      lane, partners read by lane shuffles); only if a list overflows does
-//      the whole task fall back to a block-wide bitonic network in LDS;
+//   6. only if a list overflows does the whole task fall back to a
+//      block-wide bitonic network in LDS;
 //   7. one coalesced store (records are gathered from their LDS copy).
 #pragma once
 #include "ips_kernels.hpp"
@@ -278,7 +279,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   __shared__ uint32_t s_mid[MIDCAP];         // (offset << 16) | size, for the wavefronts
   __shared__ uint32_t s_fat_o[FATCAP], s_fat_s[FATCAP];
   __shared__ uint32_t s_wsum[NT / 64];
-  __shared__ uint32_t s_nmid, s_fat_head, s_fat_tail, s_fallback;
+  __shared__ uint32_t s_nmid, s_mdone, s_fat_head, s_fat_tail, s_fallback;
 
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
@@ -291,7 +292,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
   if (n < 2) return;
   uint32_t* gd = data + t.l * DW;
-  if (tid == 0) { s_nmid = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
+  if (tid == 0) { s_nmid = 0; s_mdone = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
   if constexpr (IDX) {   // records: staged in LDS, gathered at the store
     for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
   }
@@ -368,7 +369,22 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
       const uint32_t b = s_list[n0 + q];
       sort_bin<T, IDX, NET / 2>(keys, idxb, o + s_off[b], s_cnt[b]);
     }
+    // The bins of NET/2 .. WAVE_NET keys listed since the last call, one per
+    // wavefront, from the last wavefront down (the class passes give the
+    // first threads the most bins); a bin of one value needs nothing.
+    const uint32_t m0 = s_mdone, m1 = s_nmid < MIDCAP ? s_nmid : MIDCAP;
+    if (!s_fallback) {
+      for (uint32_t q = m0 + (NT / 64 - 1 - wave); q < m1; q += NT / 64) {
+        const uint32_t ent = s_mid[q], mo = ent >> 16, ms = ent & 0xFFFFu;
+        bool same = true;
+        for (uint32_t i = lane; i < ms; i += 64) same = same && keq(keys[mo + i], keys[mo]);
+        if (__all(same)) continue;
+        if (ms <= 64) wave_reg_network<T, IDX, 1>(keys + mo, idxb + mo, ms);
+        else wave_reg_network<T, IDX, 2>(keys + mo, idxb + mo, ms);
+      }
+    }
     __syncthreads();
+    if (tid == 0) s_mdone = m1;
   };
 
   // 1. Load keys into registers (records: from their LDS stage).
@@ -524,19 +540,8 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     sort_bins(o, nsub);
   }
 
-  // 6. Bins of NET/2 .. WAVE_NET keys by the wavefronts.
-  __syncthreads();
-  if (!s_fallback) {
-    const uint32_t nmid = s_nmid < MIDCAP ? s_nmid : MIDCAP;
-    for (uint32_t q = wave; q < nmid; q += NT / 64) {
-      const uint32_t ent = s_mid[q], o = ent >> 16, s = ent & 0xFFFFu;
-      bool same = true;
-      for (uint32_t i = lane; i < s; i += 64) same = same && keq(keys[o + i], keys[o]);
-      if (__all(same)) continue;
-      if (s <= 64) wave_reg_network<T, IDX, 1>(keys + o, idxb + o, s);
-      else wave_reg_network<T, IDX, 2>(keys + o, idxb + o, s);
-    }
-  }
+  // 6. (Bins of NET/2 .. WAVE_NET keys were sorted with their size classes.)
+  // A list overflow leaves the whole task to the block-wide network.
   __syncthreads();
   if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
   __syncthreads();
