@@ -12,8 +12,10 @@
 //      (bins are grouped by that size, one pass per size); in the same phase
 //      each bin of NET/2 .. WAVE_NET keys is sorted by one wavefront with a
 //      bitonic network in registers across its lanes (one or two keys per
-//      lane, partners read by lane shuffles); a bin whose keys are all equal
-//      needs nothing;
+//      lane, partners read by lane shuffles), or, when the bin spans at most
+//      64 possible key values, by a counting sort over those values (ranks
+//      from ballots; duplicate-heavy inputs make such bins); a bin whose keys
+//      are all equal needs nothing;
 //   5. a bin above WAVE_NET keys is binned again by the whole workgroup over
 //      its own key range (bins that collect many keys are the ones skewed or
 //      duplicate-heavy inputs produce): its sub-bins of at most NET/2 keys
@@ -202,6 +204,61 @@ __device__ void wave_reg_network(typename T::Key* keys, uint16_t* idx, uint32_t 
   }
 }
 
+// Counting-sort information of a binning with shift ush from image mn: a
+// bin spans at most 2^ush consecutive images, so for ush <= 6 a key's rank
+// inside its bin is (image - mn) mod 2^ush, and only mn mod 64 is needed.
+// Bits 8-10: ush + 1 (0: no counting sort), bits 11-16: mn mod 64.
+template <class Img>
+__device__ __forceinline__ uint32_t count_info(uint32_t ush, Img mn) {
+  return ush <= 6 ? (((ush + 1) << 8) | (((uint32_t)mn & 63u) << 11)) : 0u;
+}
+
+// One wavefront sorts keys[0, s) (s <= 64 R, R per lane) whose images lie
+// in a window of 2^ush <= 64 consecutive values starting at an image equal
+// to mnl modulo 64: each key's value index d = (image - mnl) mod 2^ush, and
+// for each value in turn the lanes holding it take the next places, ranked
+// by ballots.  Equal keys end up in an arbitrary order.
+template <class T, bool IDX, uint32_t R>
+__device__ void wave_count_sort(typename T::Key* keys, uint16_t* idx, uint32_t s, uint32_t ush,
+                                uint32_t mnl) {
+  using Key = typename T::Key;
+  using Img = decltype(bin_image(Key()));
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nv = 1u << ush, mask = nv - 1;
+  Key v[R];
+  uint32_t ix[R], d[R], pos[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = lane * R + r;
+    d[r] = nv;            // no key
+    pos[r] = 0;
+    ix[r] = 0;
+    if (i < s) {
+      v[r] = keys[i];
+      if (IDX) ix[r] = idx[i];
+      d[r] = (uint32_t)(bin_image(v[r]) - (Img)mnl) & mask;
+    }
+  }
+  uint32_t base = 0;
+  for (uint32_t val = 0; val < nv && base < s; ++val) {
+    uint32_t below = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint64_t m = __ballot(d[r] == val);
+      if (d[r] == val) pos[r] = base + below + lanes_below(m);
+      below += (uint32_t)__popcll(m);
+    }
+    base += below;
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    if (lane * R + r < s) {
+      keys[pos[r]] = v[r];
+      if (IDX) idx[pos[r]] = (uint16_t)ix[r];
+    }
+  }
+}
+
 // Whole-task fallback: block-wide all-ascending network over keys[0, s).
 template <class Key, bool IDX>
 __device__ void block_network(Key* keys, uint16_t* idx, uint32_t s) {
@@ -298,11 +355,13 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
 
   // A bin of more than NET/2 keys at [o, o + sz): listed for a wavefront up
-  // to WAVE_NET keys, otherwise queued for another binning round.
-  auto push_big = [&](uint32_t o, uint32_t sz) {
+  // to WAVE_NET keys, otherwise queued for another binning round.  A list
+  // entry is o << 17 | cinfo | sz, cinfo being the counting-sort information
+  // of the binning that made the bin (see count_info).
+  auto push_big = [&](uint32_t o, uint32_t sz, uint32_t cinfo) {
     if (sz <= WAVE_NET) {
       const uint32_t slot = atomicAdd(&s_nmid, 1u);
-      if (slot < MIDCAP) s_mid[slot] = (o << 16) | sz;
+      if (slot < MIDCAP) s_mid[slot] = (o << 17) | cinfo | sz;
       else s_fallback = 1;
     } else {
       const uint32_t slot = atomicAdd(&s_fat_tail, 1u);
@@ -323,7 +382,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   // The list of each class is built without per-bin atomics: a bin's place
   // is its rank among the wavefront's bins of that class (ballots) after the
   // wavefront's base (one counter update per wavefront and class).
-  auto sort_bins = [&](uint32_t o, uint32_t nbins) {
+  auto sort_bins = [&](uint32_t o, uint32_t nbins, uint32_t cinfo) {
     constexpr uint32_t BPT = (MAXBINS + NT - 1) / NT;   // bins per thread
     uint32_t cls_of[BPT], rk[BPT];
     if (tid < 2) s_ccnt[tid] = 0;
@@ -337,7 +396,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
         const uint32_t sz = s_cnt[b];
         if (sz > 1) {
           cls_of[q] = sz <= NET / 4 ? 0u : (sz <= NET / 2 ? 1u : 3u);
-          if (cls_of[q] == 3) push_big(o + s_off[b], sz);
+          if (cls_of[q] == 3) push_big(o + s_off[b], sz, cinfo);
         }
       }
       const uint64_t m0 = __ballot(cls_of[q] == 0), m1 = __ballot(cls_of[q] == 1);
@@ -375,12 +434,19 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     const uint32_t m0 = s_mdone, m1 = s_nmid < MIDCAP ? s_nmid : MIDCAP;
     if (!s_fallback) {
       for (uint32_t q = m0 + (NT / 64 - 1 - wave); q < m1; q += NT / 64) {
-        const uint32_t ent = s_mid[q], mo = ent >> 16, ms = ent & 0xFFFFu;
+        const uint32_t ent = s_mid[q], mo = ent >> 17, ms = ent & 0xFFu;
+        const uint32_t cu = (ent >> 8) & 7u, cm = (ent >> 11) & 63u;
         bool same = true;
         for (uint32_t i = lane; i < ms; i += 64) same = same && keq(keys[mo + i], keys[mo]);
         if (__all(same)) continue;
-        if (ms <= 64) wave_reg_network<T, IDX, 1>(keys + mo, idxb + mo, ms);
-        else wave_reg_network<T, IDX, 2>(keys + mo, idxb + mo, ms);
+        if (cu) {   // at most 64 possible values: counting sort by value
+          if (ms <= 64) wave_count_sort<T, IDX, 1>(keys + mo, idxb + mo, ms, cu - 1, cm);
+          else wave_count_sort<T, IDX, 2>(keys + mo, idxb + mo, ms, cu - 1, cm);
+        } else if (ms <= 64) {
+          wave_reg_network<T, IDX, 1>(keys + mo, idxb + mo, ms);
+        } else {
+          wave_reg_network<T, IDX, 2>(keys + mo, idxb + mo, ms);
+        }
       }
     }
     __syncthreads();
@@ -463,7 +529,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     }
     __syncthreads();
     // 4. Bins by size class.
-    sort_bins(0, nbins);
+    sort_bins(0, nbins, count_info(ush, mn));
   }
 
   // 5. Re-binning rounds, one queued bin [o, o + s) at a time by the whole
@@ -537,7 +603,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     __syncthreads();
     for (uint32_t j = tid; j < nsub; j += NT) s_cnt[j] = s_off[j + 1] - s_off[j];   // sizes
     __syncthreads();
-    sort_bins(o, nsub);
+    sort_bins(o, nsub, count_info(ush2, mn2));
   }
 
   // 6. (Bins of NET/2 .. WAVE_NET keys were sorted with their size classes.)

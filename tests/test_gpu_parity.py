@@ -34,6 +34,46 @@ def test_lds_tier(sorter, kind):
         assert_parity(gpu_sort(sorter, a, kind), a, kind)
 
 
+def _narrow_dup_input(kind: str, n: int, pairs: int, gap: int, seed: int) -> np.ndarray:
+    """n elements whose keys take 2 * pairs values: for i < pairs, base +
+    128 i and base + 128 i + gap, each element picking one at random.  Over
+    a span of 128 * pairs values the binning of a single LDS-tier task puts
+    both values of a pair into one bin of a few dozen to about 130 keys (a
+    bin spanning at most 64 possible values)."""
+    x = synth.stream(seed, n)
+    i = (x % np.uint64(pairs)).astype(np.uint64)
+    v = i * np.uint64(128) + ((x >> np.uint64(32)) & np.uint64(1)) * np.uint64(gap)
+    if kind == "u32":
+        return (v + np.uint64(0x9000_0000)).astype(np.uint32)
+    if kind == "u64":
+        return v + np.uint64(0x1234_5678_9000_0000)
+    if kind == "f64":   # positive doubles: the bit pattern orders them
+        return (v + np.uint64(0x4100_0000_0000_0000)).view(np.float64)
+    if kind == "pair":
+        out = np.empty((n, 2), dtype=np.uint64)
+        out[:, 0] = v + np.uint64(0x1234_5678_9000_0000)
+        out[:, 1] = np.arange(n, dtype=np.uint64)
+        return out
+    out = synth.gen_rec100("uniform", n, seed)     # payload and index from the generator
+    out[:, 0:8] = np.frombuffer(bytes([0x5A, 1, 2, 3, 4, 5, 6, 7]), dtype=np.uint8)
+    out[:, 8:10] = v.astype(">u2").view(np.uint8).reshape(n, 2)
+    return out
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_lds_tier_narrow_duplicate_bins(sorter, kind):
+    """Bins of 17 to about 130 keys holding two values within a window of
+    at most 64 values (what duplicate-heavy inputs such as TwoDup give the
+    LDS tier): they are sorted by the wavefront counting sort, those above
+    the wavefront limit by another binning round."""
+    n = {"pair": 4000, "rec100": 1000}.get(kind, 4000)
+    gap = 5 if kind == "rec100" else 3
+    for pairs in (16, 32, 64):
+        a = _narrow_dup_input(kind, n, pairs, gap, 4242 + pairs)
+        log(f"lds narrow dup {kind} pairs={pairs}")
+        assert_parity(gpu_sort(sorter, a, kind, params=ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)), a, kind)
+
+
 @pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
 def test_lds_tier_sorted_reverse_repeated(sorter, kind):
     """Sorted and reverse inputs whose last keys sit in a partly filled
