@@ -31,6 +31,8 @@
 namespace ips {
 
 constexpr uint32_t WAVE_NET = 128;    // largest bin sorted by one wavefront's network
+constexpr uint32_t WAVE_CNT = 512;    // largest bin sorted by one wavefront's counting sort (keys only;
+                                      // half that with indices, for registers)
 constexpr uint32_t FATCAP = 128;      // bins waiting to be binned again (each > WAVE_NET keys)
 constexpr uint32_t FAT_ROUNDS = 1024; // re-binning rounds per task before the fallback
 
@@ -207,10 +209,10 @@ __device__ void wave_reg_network(typename T::Key* keys, uint16_t* idx, uint32_t 
 // Counting-sort information of a binning with shift ush from image mn: a
 // bin spans at most 2^ush consecutive images, so for ush <= 6 a key's rank
 // inside its bin is (image - mn) mod 2^ush, and only mn mod 64 is needed.
-// Bits 8-10: ush + 1 (0: no counting sort), bits 11-16: mn mod 64.
+// Bits 0-2: ush + 1 (0: no counting sort), bits 3-8: mn mod 64.
 template <class Img>
 __device__ __forceinline__ uint32_t count_info(uint32_t ush, Img mn) {
-  return ush <= 6 ? (((ush + 1) << 8) | (((uint32_t)mn & 63u) << 11)) : 0u;
+  return ush <= 6 ? ((ush + 1) | (((uint32_t)mn & 63u) << 3)) : 0u;
 }
 
 // One wavefront sorts keys[0, s) (s <= 64 R, R per lane) whose images lie
@@ -334,6 +336,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   __shared__ uint32_t s_ccnt[2];
   constexpr uint32_t MIDCAP = MAXBINS / 2;   // > CAP / (NET/2 + 1): never overflows
   __shared__ uint32_t s_mid[MIDCAP];         // (offset << 16) | size, for the wavefronts
+  __shared__ uint16_t s_midc[MIDCAP];        // and its counting-sort information
   __shared__ uint32_t s_fat_o[FATCAP], s_fat_s[FATCAP];
   __shared__ uint32_t s_wsum[NT / 64];
   __shared__ uint32_t s_nmid, s_mdone, s_fat_head, s_fat_tail, s_fallback;
@@ -355,13 +358,14 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   }
 
   // A bin of more than NET/2 keys at [o, o + sz): listed for a wavefront up
-  // to WAVE_NET keys, otherwise queued for another binning round.  A list
-  // entry is o << 17 | cinfo | sz, cinfo being the counting-sort information
-  // of the binning that made the bin (see count_info).
+  // to WAVE_NET keys (WAVE_CNT keys when it spans at most 64 values),
+  // otherwise queued for another binning round.  A list entry is
+  // o << 16 | sz, beside cinfo, the counting-sort information of the
+  // binning that made the bin (see count_info).
   auto push_big = [&](uint32_t o, uint32_t sz, uint32_t cinfo) {
-    if (sz <= WAVE_NET) {
+    if (sz <= WAVE_NET || (cinfo && sz <= (IDX ? WAVE_CNT / 2 : WAVE_CNT))) {
       const uint32_t slot = atomicAdd(&s_nmid, 1u);
-      if (slot < MIDCAP) s_mid[slot] = (o << 17) | cinfo | sz;
+      if (slot < MIDCAP) { s_mid[slot] = (o << 16) | sz; s_midc[slot] = (uint16_t)cinfo; }
       else s_fallback = 1;
     } else {
       const uint32_t slot = atomicAdd(&s_fat_tail, 1u);
@@ -434,14 +438,16 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     const uint32_t m0 = s_mdone, m1 = s_nmid < MIDCAP ? s_nmid : MIDCAP;
     if (!s_fallback) {
       for (uint32_t q = m0 + (NT / 64 - 1 - wave); q < m1; q += NT / 64) {
-        const uint32_t ent = s_mid[q], mo = ent >> 17, ms = ent & 0xFFu;
-        const uint32_t cu = (ent >> 8) & 7u, cm = (ent >> 11) & 63u;
+        const uint32_t ent = s_mid[q], mo = ent >> 16, ms = ent & 0xFFFFu;
+        const uint32_t ci = s_midc[q], cu = ci & 7u, cm = (ci >> 3) & 63u;
         bool same = true;
         for (uint32_t i = lane; i < ms; i += 64) same = same && keq(keys[mo + i], keys[mo]);
         if (__all(same)) continue;
         if (cu) {   // at most 64 possible values: counting sort by value
           if (ms <= 64) wave_count_sort<T, IDX, 1>(keys + mo, idxb + mo, ms, cu - 1, cm);
-          else wave_count_sort<T, IDX, 2>(keys + mo, idxb + mo, ms, cu - 1, cm);
+          else if (ms <= 128) wave_count_sort<T, IDX, 2>(keys + mo, idxb + mo, ms, cu - 1, cm);
+          else if (IDX || ms <= 256) wave_count_sort<T, IDX, 4>(keys + mo, idxb + mo, ms, cu - 1, cm);
+          else wave_count_sort<T, IDX, IDX ? 4 : 8>(keys + mo, idxb + mo, ms, cu - 1, cm);
         } else if (ms <= 64) {
           wave_reg_network<T, IDX, 1>(keys + mo, idxb + mo, ms);
         } else {
