@@ -1061,7 +1061,7 @@ k_permute(BatchArgs a) {
         const uint32_t nch = cs ? (npl + cs - 1) / cs : 0;
         const uint64_t m = low_mask64(nch);
         if (npl) {
-          const uint64_t seen = use_mask ? at_load64(fm) : *reinterpret_cast<volatile uint64_t*>(fm);
+          const uint64_t seen = use_mask ? at_load64(fm) : *fm;
           const uint64_t fr = ~seen & m;
           if (cs == 1 || !use_mask) {
             uint32_t ch = probe % nch;
