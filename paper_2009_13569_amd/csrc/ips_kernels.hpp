@@ -1270,7 +1270,8 @@ __global__ void __launch_bounds__(CLN_THREADS) k_cleanup_a(BatchArgs a) {
 // block, and the partial buffer blocks of every stripe - fill the bucket's
 // free positions: its head [start_j, d_j b) and its tail after its blocks.
 template <class T>
-__device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t max_w, uint64_t* s_off) {
+__device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t part, uint32_t parts,
+                               uint32_t max_w, uint64_t* s_off) {
   constexpr int DW = T::DW;
   const uint32_t m = a.cln_map[item];
   const uint32_t tix = m >> 10, j = m & 1023u;
@@ -1323,7 +1324,7 @@ __device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t max_w
   const uint32_t* spill = reinterpret_cast<const uint32_t*>(a.spill + tk.spill_off) + (uint64_t)j * b * DW;
   const uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
   const uint8_t* slot0 = a.slots + tk.slot_off;
-  for (uint64_t e = threadIdx.x; e < total; e += CLN_THREADS) {
+  for (uint64_t e = (uint64_t)part * CLN_THREADS + threadIdx.x; e < total; e += (uint64_t)parts * CLN_THREADS) {
     uint32_t lo = 0, hi = W + 2;     // segment: largest i with s_off[i] <= e
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) / 2;
@@ -1347,13 +1348,19 @@ __device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t max_w
 }
 
 // One workgroup per bucket item (task, bucket); with device-planned counts
-// the grid loops over the step's items.
+// the grid loops over the step's items.  When the grid has several
+// workgroups per item (few large buckets), each item is split into up to
+// CLN_PARTS parts: every part computes the bucket's leftover offsets and
+// copies every parts-th run of CLN_THREADS elements.
+constexpr uint32_t CLN_PARTS = 16;
 template <class T>
 __global__ void __launch_bounds__(CLN_THREADS) k_cleanup_b(BatchArgs a, uint32_t max_w) {
   extern __shared__ uint64_t s_off[];   // max_w + 3 entries
   const uint32_t count = a.devplan ? a.ctrl[CTRL_NCLN] : gridDim.x;
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    cleanup_b_item<T>(a, item, max_w, s_off);
+  uint32_t parts = count ? gridDim.x / count : 1u;
+  parts = parts < 1u ? 1u : (parts > CLN_PARTS ? CLN_PARTS : parts);
+  for (uint32_t x = blockIdx.x; x < count * parts; x += gridDim.x) {
+    cleanup_b_item<T>(a, x / parts, x % parts, parts, max_w, s_off);
     __syncthreads();
   }
 }
