@@ -129,7 +129,8 @@ def main() -> int:
     sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
     ref_sum = pristine.view(torch.int64).sum()
     for c in copies:
-        v = c.view(torch.int64) ^ sign if kind == "u64" else c.view(torch.int32).to(torch.int64) ^ (1 << 31)
+        # order as unsigned: u64 keys with the sign bit flipped, u32 keys widened without sign extension
+        v = c.view(torch.int64) ^ sign if kind == "u64" else c.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
         assert bool((v[1:] >= v[:-1]).all()), "output not sorted"
         assert int(c.view(torch.int64).sum() if kind == "u64" else c.view(torch.int32).to(torch.int64).sum()) == \
             int(ref_sum if kind == "u64" else pristine.view(torch.int32).to(torch.int64).sum()), "multiset changed"
