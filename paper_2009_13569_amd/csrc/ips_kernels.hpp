@@ -1086,8 +1086,8 @@ k_permute(BatchArgs a) {
           const uint32_t sr = plb + q;
           // piece metadata loads are issued before the pointer update so that
           // their latencies overlap
-          const uint32_t cap = __builtin_nontemporal_load(&pc[sr]);
-          const int32_t rin = __builtin_nontemporal_load(&pr[sr]);
+          const uint32_t cap = pc[sr];
+          const int32_t rin = pr[sr];
           const uint64_t wv = at_add64(&word[(uint64_t)sr * PWORD_STRIDE], 1ull << 32);
           const uint32_t w = (uint32_t)(wv >> 32);
           r2 = (uint32_t)rin;
