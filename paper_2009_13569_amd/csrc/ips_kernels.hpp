@@ -276,14 +276,31 @@ k_sample(BatchArgs a, uint64_t seed) {
   }
   __syncthreads();
   lds_bitonic_keys(s_smp, P);
-  if (threadIdx.x == 0) {
-    uint32_t u = 0;
-    for (uint32_t i = 0; i + 1 < kp; ++i) {
-      Key s = s_smp[(i + 1) * alpha - 1];
-      if (u > 0 && keq(s, s_spl[u - 1])) continue;
-      s_spl[u++] = s;
+  // Splitter i (i < kp - 1) is sample (i + 1) alpha - 1; a splitter equal to
+  // the one before it is dropped (the sample is sorted, so equal splitters
+  // are adjacent).  Thread i keeps or drops splitter i; the kept ones are
+  // packed in order by a ballot prefix count.
+  {
+    static_assert(MAX_K <= SMP_THREADS, "one splitter per thread");
+    __shared__ uint32_t s_wkeep[SMP_THREADS / 64];
+    const uint32_t i = threadIdx.x, lane = i & 63, wave = i >> 6;
+    bool keep = false;
+    Key sp = s_smp[0];
+    if (i + 1 < kp) {
+      sp = s_smp[(i + 1) * alpha - 1];
+      keep = i == 0 || !keq(sp, s_smp[i * alpha - 1]);
     }
-    s_u = u;
+    const uint64_t bm = __ballot(keep);
+    if (lane == 0) s_wkeep[wave] = (uint32_t)__popcll(bm);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < SMP_THREADS / 64; ++w) {
+      const uint32_t c = s_wkeep[w];
+      before += w < wave ? c : 0u;
+      total += c;
+    }
+    if (keep) s_spl[before + lanes_below(bm)] = sp;
+    if (i == 0) s_u = total;
   }
   __syncthreads();
   const uint32_t u = s_u;
