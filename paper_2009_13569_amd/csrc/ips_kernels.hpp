@@ -649,9 +649,9 @@ k_classify(BatchArgs a) {
     const uint32_t consumed = (ts + TILE < slen) ? ts + TILE : slen;
     // Per-bucket tile states of the elements, read together (kept in
     // registers when there are at most 8 elements per thread).
-    constexpr int NST = EPT <= 8 ? EPT : 1;
+    constexpr int NST = EPT <= 12 ? EPT : 1;
     uint2 stv[NST];
-    if constexpr (EPT <= 8) {
+    if constexpr (EPT <= 12) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) stv[i] = s_fn[bk[i]];
     }
@@ -659,7 +659,7 @@ k_classify(BatchArgs a) {
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint2 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
+        const uint2 st = (EPT <= 12) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.x) {
           st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
@@ -689,7 +689,7 @@ k_classify(BatchArgs a) {
     for (int i = 0; i < EPT; ++i) {
       const uint32_t idx = ts + (uint32_t)i * NT + tid;
       if (full || idx < slen) {
-        const uint2 st = (EPT <= 8) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
+        const uint2 st = (EPT <= 12) ? stv[i < NST ? i : 0] : s_fn[bk[i]];
         const uint32_t blk = bd.div(sl[i]), o = sl[i] - blk * b;
         if (blk == st.y && blk > st.x) st_elem<DW>(buf + bk[i] * bstride + o * DW, cur[i]);
       }

@@ -38,7 +38,7 @@ __device__ __forceinline__ uint64_t ord_to_f64(uint64_t k) {
 }
 
 struct TU32 {
-  static constexpr int DW = 1, KDW = 1, CODE = 1, EPT = 16;
+  static constexpr int DW = 1, KDW = 1, CODE = 1, EPT = 12;
   static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
   using Key = uint32_t;
   __device__ static Key key(uint32_t w0, uint32_t, uint32_t) { return w0; }
