@@ -1364,21 +1364,111 @@ __device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t part,
   }
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same cleanup of one bucket item by one wavefront, for a task of at
+// most CLN_WAVE_W stripes: lane s scans stripe s's leftovers (a lane-shuffle
+// prefix sum), the offsets go to this wavefront's s_offw, and the lanes copy
+// the elements.
+constexpr uint32_t CLN_WAVE_W = 61;
+template <class T>
+__device__ void cleanup_b_item_wave(const BatchArgs& a, uint32_t item, uint64_t* s_offw) {
+  constexpr int DW = T::DW;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t m = a.cln_map[item];
+  const uint32_t tix = m >> 10, j = m & 1023u;
+  const PTask& tk = a.tasks[tix];
+  const BucketGeo g = bucket_geo(a, tk, j);
+  const uint32_t b = tk.b, W = tk.W;
+  const uint64_t hend = ((uint64_t)g.d * b < g.end) ? (uint64_t)g.d * b : g.end;
+  const uint64_t hlen = hend - g.start;
+  const uint64_t tlen = (g.F < g.end) ? g.end - g.F : 0;
+  const uint64_t sp = (g.count > 0 && !g.ovf && g.F > g.end) ? g.F - g.end : 0;
+  const uint64_t head = sp + (g.ovf ? b : 0);
+  const uint64_t loc = lane < W ? a.wg_left[(uint64_t)(tk.wg_base + lane) * MAX_NB + j] : 0;
+  uint64_t inc = loc;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = (uint64_t)__shfl_up((long long)inc, o, 64);
+    if ((int)lane >= o) inc += y;
+  }
+  if (lane < W) s_offw[3 + lane] = head + inc;
+  if (lane == 0) { s_offw[0] = 0; s_offw[1] = sp; s_offw[2] = head; }
+  wave_sync();
+  const uint64_t total = s_offw[2 + W];
+  if (total != hlen + tlen) {
+    if (lane == 0) dev_error(a.ctrl, DE_CLEANUP_COUNT, tix, j);
+    wave_sync();
+    return;
+  }
+  uint32_t* gd = a.data + tk.l * DW;
+  const uint32_t* spill = reinterpret_cast<const uint32_t*>(a.spill + tk.spill_off) + (uint64_t)j * b * DW;
+  const uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
+  const uint8_t* slot0 = a.slots + tk.slot_off;
+  for (uint64_t e = lane; e < total; e += 64) {
+    uint32_t lo = 0, hi = W + 2;     // segment: largest i with s_offw[i] <= e
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) / 2;
+      if (s_offw[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t k = e - s_offw[lo];
+    const uint32_t* src;
+    if (lo == 0) src = spill + k * DW;
+    else if (lo == 1) src = ovf + k * DW;
+    else src = reinterpret_cast<const uint32_t*>(slot0 + (uint64_t)(lo - 2) * tk.slot_bytes) +
+               ((uint64_t)j * b + k) * DW;
+    const uint64_t dst = (e < hlen) ? g.start + e : g.F + (e - hlen);
+    if (dst < g.start || dst >= g.end) {
+      dev_error(a.ctrl, DE_CLN_RANGE, tix, j);
+      continue;
+    }
+    uint32_t w[DW];
+    ld_elem<DW>(src, w);
+    st_elem<DW>(gd + dst * DW, w);
+  }
+  wave_sync();   // s_offw is read before the next item writes it
+}
+
 // One workgroup per bucket item (task, bucket); with device-planned counts
 // the grid loops over the step's items.  When the grid has several
 // workgroups per item (few large buckets), each item is split into up to
 // CLN_PARTS parts: every part computes the bucket's leftover offsets and
-// copies every parts-th run of CLN_THREADS elements.
+// copies every parts-th run of CLN_THREADS elements.  Otherwise a workgroup
+// takes its items four at a time, one per wavefront when all four tasks
+// have at most CLN_WAVE_W stripes (small tasks of a deep level), else one
+// after the other with the whole workgroup.
 constexpr uint32_t CLN_PARTS = 16;
 template <class T>
 __global__ void __launch_bounds__(CLN_THREADS) k_cleanup_b(BatchArgs a, uint32_t max_w) {
   extern __shared__ uint64_t s_off[];   // max_w + 3 entries
+  constexpr uint32_t NWV = CLN_THREADS / 64;
+  __shared__ uint64_t s_offw[NWV][CLN_WAVE_W + 3];
   const uint32_t count = a.devplan ? a.ctrl[CTRL_NCLN] : gridDim.x;
   uint32_t parts = count ? gridDim.x / count : 1u;
   parts = parts < 1u ? 1u : (parts > CLN_PARTS ? CLN_PARTS : parts);
-  for (uint32_t x = blockIdx.x; x < count * parts; x += gridDim.x) {
-    cleanup_b_item<T>(a, x / parts, x % parts, parts, max_w, s_off);
-    __syncthreads();
+  if (parts > 1) {
+    for (uint32_t x = blockIdx.x; x < count * parts; x += gridDim.x) {
+      cleanup_b_item<T>(a, x / parts, x % parts, parts, max_w, s_off);
+      __syncthreads();
+    }
+    return;
+  }
+  const uint32_t wave = threadIdx.x >> 6;
+  for (uint32_t x0 = blockIdx.x * NWV; x0 < count; x0 += gridDim.x * NWV) {
+    const uint32_t item = x0 + wave;
+    bool small = true;
+    if (item < count) small = a.tasks[a.cln_map[item] >> 10].W <= CLN_WAVE_W;
+    if (__syncthreads_and(small ? 1 : 0)) {
+      if (item < count) cleanup_b_item_wave<T>(a, item, s_offw[wave]);
+    } else {
+      for (uint32_t q = 0; q < NWV && x0 + q < count; ++q) {
+        cleanup_b_item<T>(a, x0 + q, 0, 1, max_w, s_off);
+        __syncthreads();
+      }
+    }
   }
 }
 
