@@ -320,8 +320,12 @@ struct LdsTier {
 };
 
 // Sorts LDS-tier task number `ti` of the list.
+// `pf`: thread 0 loads descriptor lt[nxt] of the workgroup's next task into
+// *s_t (free once every thread has read the current one), the load issued
+// before this task's key loads and stored after them.
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
-__device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint32_t* ctrl, uint32_t tid) {
+__device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32_t* ctrl, uint32_t tid,
+                              const LTask* lt, uint32_t nxt, bool pf, LTask* s_t) {
   using LT = LdsTier<T, NT, E, NET>;
   using Key = typename T::Key;
   using Img = decltype(bin_image(Key()));
@@ -344,14 +348,16 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idxb = reinterpret_cast<uint16_t*>(keys + CAP);
   uint32_t* stage = reinterpret_cast<uint32_t*>(idxb + CAP);
-  const LTask t = lt[ti];
   const uint32_t n = t.n, lane = tid & 63, wave = tid >> 6;
-  if (n > CAP) {
-    if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
+  const bool pf0 = pf && tid == 0;
+  if (n > CAP || n < 2) {
+    if (tid == 0 && n > CAP) dev_error(ctrl, DE_LDST, ti, n);
+    if (pf0) *s_t = lt[nxt];
     return;
   }
-  if (n < 2) return;
   uint32_t* gd = data + t.l * DW;
+  LTask nt = t;
+  if (pf0) nt = lt[nxt];
   if (tid == 0) { s_nmid = 0; s_mdone = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
   if constexpr (IDX) {   // records: staged in LDS, gathered at the store
     for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
@@ -497,6 +503,7 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
     mx = b2 > mx ? b2 : mx;
   }
   if (lane == 0) { s_min[wave] = mn; s_max[wave] = mx; }
+  if (pf0) *s_t = nt;
   for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
   __syncthreads();
   mn = s_min[0];
@@ -636,36 +643,48 @@ __device__ void lds_tier_task(const LTask* lt, uint32_t ti, uint32_t* data, uint
 // One workgroup per task of the list (cnt == nullptr: the grid is the
 // list).  With a device count `cnt` (at most cnt_cap) the workgroups claim
 // tasks from the counter `pop` (zero at launch) until the list is used up,
-// so that long and short tasks balance as with one workgroup per task; the
-// claim of the next task is issued before the current task's key loads and
-// waits with them.
+// so that long and short tasks balance as with one workgroup per task.
+// Claims run one task ahead: while a task is sorted, the next one is
+// already claimed and its descriptor is loading (issued before the task's
+// key loads, so it waits with them), and the claim after it is in flight.
 template <class T, uint32_t NT, uint32_t E, uint32_t NET>
 __global__ void __launch_bounds__(NT, (NT <= 512 ? 4 : 1))
 k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap,
            uint32_t* pop) {
-  __shared__ uint32_t s_next;
+  __shared__ uint32_t s_next, s_after;
+  __shared__ LTask s_t;
   uint32_t count, ti;
   if (cnt) {
     if (!ctrl[CTRL_LDSRUN]) return;          // device-planned step that defers the lists
     count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
-    if (threadIdx.x == 0) s_next = atomicAdd(pop, 1u);
-    __syncthreads();
-    ti = s_next;
+    if (threadIdx.x == 0) {
+      const uint32_t c0 = atomicAdd(pop, 1u);
+      s_after = atomicAdd(pop, 1u);
+      s_next = c0;
+      if (c0 < count) s_t = lt[c0];
+    }
   } else {
     ti = blockIdx.x;
     count = ti + 1;
+    if (threadIdx.x == 0) { s_next = ti; s_t = lt[ti]; }
   }
+  __syncthreads();
+  ti = s_next;
   while (ti < count) {
-    __syncthreads();   // every thread has read s_next
+    const LTask t = s_t;
+    __syncthreads();   // every thread has read s_next and s_t
     // The thread index is made opaque on every pass so that the compiler
     // recomputes the many addresses derived from it inside the loop instead
     // of keeping them all live across it (which costs registers).
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    uint32_t nxt = count;   // the grid's own task only, without a device count
-    if (cnt && tid == 0) nxt = atomicAdd(pop, 1u);
-    lds_tier_task<T, NT, E, NET>(lt, ti, data, ctrl, tid);
-    if (tid == 0) s_next = nxt;
+    uint32_t nxt = count, after = count;   // the grid's own task only, without a device count
+    if (cnt && tid == 0) {
+      nxt = s_after;                       // claimed during the previous task
+      after = atomicAdd(pop, 1u);
+    }
+    lds_tier_task<T, NT, E, NET>(t, ti, data, ctrl, tid, lt, nxt, cnt && nxt < count, &s_t);
+    if (tid == 0) { s_next = nxt; s_after = after; }
     __syncthreads();
     ti = s_next;
   }
