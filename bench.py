@@ -43,9 +43,11 @@ def main() -> int:
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-radix", action="store_true", help="skip the radix-path measurement")
-    ap.add_argument("--workload", default="sort", choices=["sort", "batch", "serve"],
+    ap.add_argument("--workload", default="sort", choices=["sort", "batch", "serve", "sweep"],
                     help="sort: one 2^28-key array (default); batch: 4096 arrays of 2^8..2^22 keys; "
-                         "serve: a Poisson trace of mixed-type requests of 2^10..2^26 elements")
+                         "serve: a Poisson trace of mixed-type requests of 2^10..2^26 elements; "
+                         "sweep: every generator at 2^28 for u64 and u32, and the wider elements "
+                         "(f64 and Pair at 2^27, 100-byte records at 2^24)")
     ap.add_argument("--arrays", type=int, default=4096, help="batch: number of arrays")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
@@ -70,6 +72,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
     import torch
@@ -394,6 +398,107 @@ def _seg_sorted_and_sum(t, offs):
     starts = starts[(starts > 0) & (starts < t.numel())]
     ok[starts - 1] = True              # boundaries between segments are not compared
     return bool(ok.all()), int(t.sum())
+
+
+SWEEP_DISTS = ("uniform", "exponential", "rootdup", "twodup", "eightdup", "almostsorted", "sorted",
+               "reversesorted", "zero", "zipf")
+
+
+def _sorted_and_fingerprint(t, kind):
+    """Non-decreasing in the library's key order, and the sum of the int64
+    (int32 for records) bit patterns as a multiset fingerprint, on the device."""
+    import torch
+    if kind == "u64":
+        v = t.view(torch.int64) ^ (-(1 << 63))
+        return bool((v[1:] >= v[:-1]).all()), int(t.view(torch.int64).sum())
+    if kind == "u32":
+        v = t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        return bool((v[1:] >= v[:-1]).all()), int(v.sum())
+    if kind == "f64":   # the generators emit neither NaN nor -0.0
+        return bool((t[1:] >= t[:-1]).all()), int(t.view(torch.int64).sum())
+    if kind == "pair":
+        v = t[:, 0] ^ (-(1 << 63))
+        return bool((v[1:] >= v[:-1]).all()), int(t.sum())
+    # 100-byte records: key bytes 0..9, unsigned lexicographic
+    b = t[:, :10].to(torch.int64)
+    hi = torch.zeros(t.shape[0], dtype=torch.int64, device=t.device)
+    for i in range(8):
+        hi = hi | (b[:, i] << (56 - 8 * i))
+    hi = hi ^ (-(1 << 63))
+    lo = (b[:, 8] << 8) | b[:, 9]
+    ok = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] >= lo[:-1]))
+    return bool(ok.all()), int(t.view(torch.int32).to(torch.int64).sum())
+
+
+def bench_sweep(args) -> int:
+    """Every generator at n = 2^28 for u64 and u32 keys (samplesort and
+    IPS2Ra), then the wider elements: f64 (Uniform, Exponential) and Pair
+    (Uniform, RootDup) at 2^27, 100-byte records (Uniform and RootDup keys) at
+    2^24.  Each case: one warmup and `steps` sorts of a pristine device copy
+    (the copy untimed), timed with HIP events; the output is checked on the
+    device (key order and an unchanged fingerprint)."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+
+    dev = torch.device("cuda:0")
+    steps = max(1, min(args.steps, 5))
+    cases = [(k, d, 28, a) for k in ("u64", "u32") for d in SWEEP_DISTS for a in ("samplesort", "radix")]
+    cases += [("f64", "uniform", 27, "samplesort"), ("f64", "exponential", 27, "samplesort"),
+              ("pair", "uniform", 27, "samplesort"), ("pair", "rootdup", 27, "samplesort"),
+              ("pair", "uniform", 27, "radix"), ("pair", "rootdup", 27, "radix"),
+              ("rec100", "uniform", 24, "samplesort"), ("rec100", "rootdup", 24, "samplesort")]
+    sorter = ips.Sorter(0)
+    rows = []
+    for kind, dist, lg, algo in cases:
+        n = 1 << lg
+        seed = synth.seed_for(2 if lg == 28 else 3, SWEEP_DISTS.index(dist))
+        if kind == "rec100":
+            src = torch.from_numpy(synth.gen_rec100(dist, n, seed)).to(dev)
+        else:
+            src = sd.generate(kind, dist, n, seed, dev)
+        _, fp = _sorted_and_fingerprint(src, kind) if kind in ("u32", "u64", "f64", "pair") else (None, None)
+        if fp is None:
+            fp = int(src.view(torch.int32).to(torch.int64).sum())
+        work = torch.empty_like(src)
+        ws = sorter.workspace(ips.workspace_bytes(n, kind, algo, sorter.params_for(n, kind, algo, False)))
+        times = []
+        for r in range(steps + 1):
+            work.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sorter.sort_(work, algo=algo, kind=kind, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1))
+        ok, fp2 = _sorted_and_fingerprint(work, kind)
+        assert ok and fp2 == fp, f"{kind} {dist} 2^{lg} {algo}: output not sorted or multiset changed"
+        ms = float(np.median(times))
+        st = sorter.stats()
+        row = {"kind": kind, "dist": dist, "log2n": lg, "algo": algo, "ms": round(ms, 3),
+               "Gelems_per_s": round(n / (ms * 1e-3) / 1e9, 2), "levels": int(st.levels),
+               "detected": int(st.detected)}
+        rows.append(row)
+        log(f"{kind:6s} {dist:13s} 2^{lg} {algo:10s} {ms:8.3f} ms {row['Gelems_per_s']:7.2f} Gelem/s "
+            f"levels {row['levels']}")
+        del src, work
+        torch.cuda.empty_cache()
+    rand = [r["Gelems_per_s"] for r in rows if r["kind"] == "u64" and r["algo"] == "samplesort"
+            and r["dist"] not in ("sorted", "reversesorted", "zero")]
+    gm = float(np.exp(np.mean(np.log(rand))))
+    out = {"metric": "Gkeys/s, geometric mean of u64 samplesort over the seven unsorted generators at 2^28",
+           "value": round(gm, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "mixed (u64, u32, f64, pair, 100-byte records)",
+           "data": "synthetic: the paper's generators, SplitMix64-seeded (records generated on the host)",
+           "config": {"workload": "generator sweep at 2^28 (u64, u32) and wider elements (f64, Pair at "
+                                  "2^27; 100-byte records at 2^24)"},
+           "cases": rows}
+    print(json.dumps(out))
+    return 0
 
 
 def bench_batch(args) -> int:
