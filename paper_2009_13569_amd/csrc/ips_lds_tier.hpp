@@ -360,7 +360,22 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   if (pf0) nt = lt[nxt];
   if (tid == 0) { s_nmid = 0; s_mdone = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
   if constexpr (IDX) {   // records: staged in LDS, gathered at the store
-    for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
+    // SU dwords per lane are loaded before any is stored, so their loads overlap
+    constexpr uint32_t SU = 8;
+    const uint32_t tot = n * DW;
+    for (uint32_t x0 = tid; x0 < tot; x0 += NT * SU) {
+      uint32_t v[SU];
+#pragma unroll
+      for (uint32_t u = 0; u < SU; ++u) {
+        const uint32_t x = x0 + u * NT;
+        v[u] = x < tot ? gd[x] : 0u;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < SU; ++u) {
+        const uint32_t x = x0 + u * NT;
+        if (x < tot) stage[x] = v[u];
+      }
+    }
   }
 
   // A bin of more than NET/2 keys at [o, o + sz): listed for a wavefront up
@@ -627,9 +642,23 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
 
   // 7. Store.
   if constexpr (IDX) {
-    for (uint32_t x = tid; x < n * DW; x += NT) {
-      const uint32_t i = x / DW, d = x - i * DW;
-      gd[x] = stage[(uint32_t)idxb[i] * DW + d];
+    constexpr uint32_t SU = 8;
+    const uint32_t tot = n * DW;
+    for (uint32_t x0 = tid; x0 < tot; x0 += NT * SU) {
+      uint32_t v[SU];
+#pragma unroll
+      for (uint32_t u = 0; u < SU; ++u) {
+        const uint32_t x = x0 + u * NT;
+        if (x < tot) {
+          const uint32_t i = x / DW, d = x - i * DW;
+          v[u] = stage[(uint32_t)idxb[i] * DW + d];
+        }
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < SU; ++u) {
+        const uint32_t x = x0 + u * NT;
+        if (x < tot) gd[x] = v[u];
+      }
     }
   } else {
     for (uint32_t i = tid; i < n; i += NT) {
