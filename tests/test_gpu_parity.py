@@ -74,6 +74,44 @@ def test_lds_tier_narrow_duplicate_bins(sorter, kind):
         assert_parity(gpu_sort(sorter, a, kind, params=ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)), a, kind)
 
 
+def _keyed(kind: str, v: np.ndarray, seed: int) -> np.ndarray:
+    """Elements of `kind` whose keys are base + v, in key order of v (v <
+    2^16 for records, whose key ends in v as two bytes); records get their
+    payload from the generator."""
+    n = v.size
+    v = v.astype(np.uint64)
+    if kind == "u32":
+        return (v + np.uint64(0x9000_0000)).astype(np.uint32)
+    if kind == "u64":
+        return v + np.uint64(0x1234_5678_9000_0000)
+    if kind == "f64":   # positive doubles: the bit pattern orders them
+        return (v + np.uint64(0x4100_0000_0000_0000)).view(np.float64)
+    if kind == "pair":
+        out = np.empty((n, 2), dtype=np.uint64)
+        out[:, 0] = v + np.uint64(0x1234_5678_9000_0000)
+        out[:, 1] = np.arange(n, dtype=np.uint64)
+        return out
+    out = synth.gen_rec100("uniform", n, seed)
+    out[:, 0:8] = np.frombuffer(bytes([0x5A, 1, 2, 3, 4, 5, 6, 7]), dtype=np.uint8)
+    out[:, 8:10] = v.astype(">u2").view(np.uint8).reshape(n, 2)
+    return out
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_lds_tier_clustered_bins(sorter, kind):
+    """Keys in narrow clusters spread over a wide range: the binning of one
+    LDS-tier task gives bins of 17 to about 100 keys holding many values
+    (wider than the counting sort's 64), sorted by the wavefront register
+    network with one or two keys per lane."""
+    n, clusters, width, spacing = {"rec100": (1000, 12, 300, 3000)}.get(kind, (4000, 48, 150, 1400))
+    for seed in (11, 12):
+        x = synth.stream(seed, 2 * n)
+        v = (x[0::2] % np.uint64(clusters)) * np.uint64(spacing) + (x[1::2] % np.uint64(width))
+        a = _keyed(kind, v, seed)
+        log(f"lds clustered {kind} seed={seed}")
+        assert_parity(gpu_sort(sorter, a, kind, params=ips.make_params(flags=ips.FLAG_NO_SORTED_CHECK)), a, kind)
+
+
 @pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair"])
 def test_lds_tier_sorted_reverse_repeated(sorter, kind):
     """Sorted and reverse inputs whose last keys sit in a partly filled
