@@ -1967,7 +1967,16 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   const uint32_t nwg = act ? ((uint32_t)ng + gpw - 1) / gpw : 0;   // ng <= NB / 4 fits 32 bits
   const uint32_t piece_cap = act ? 2 * nb + 2 + W + NB / c.cmax + 1 : 0;
   uint64_t t_wg, t_slot, t_spill, t_flag, t_piece, t_bucket, t_pwg, t_cln;
-  const uint64_t e_wg = block_incl_scan64<PLAN_THREADS>(act ? W : 0, s_w, &t_wg) - (act ? W : 0);
+  // Classification workgroups: the tasks whose stripes are longer than S
+  // take the first indices (workgroups start roughly in index order, so the
+  // longest start first and the shorter ones fill the end of the launch).
+  const bool lng = act && (uint64_t)W * S < p.n;
+  uint64_t t_wl, t_ws;
+  const uint64_t e_wl = block_incl_scan64<PLAN_THREADS>(lng ? W : 0, s_w, &t_wl) - (lng ? W : 0);
+  const uint64_t e_ws = block_incl_scan64<PLAN_THREADS>((act && !lng) ? W : 0, s_w, &t_ws) -
+                        ((act && !lng) ? W : 0);
+  const uint64_t e_wg = lng ? e_wl : t_wl + e_ws;
+  t_wg = t_wl + t_ws;
   const uint64_t e_slot = block_incl_scan64<PLAN_THREADS>(act ? W * slot_bytes : 0, s_w, &t_slot) -
                           (act ? W * slot_bytes : 0);
   const uint64_t e_spill = block_incl_scan64<PLAN_THREADS>(slot_bytes, s_w, &t_spill) - slot_bytes;
