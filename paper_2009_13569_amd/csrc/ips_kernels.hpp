@@ -1549,13 +1549,24 @@ __global__ void __launch_bounds__(256) k_reverse(uint32_t* data, uint64_t n) {
 template <class T>
 __global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n, uint32_t* ctrl) {
   constexpr int DW = T::DW;
+  constexpr int U = 8;   // loads in flight per lane
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
   uint64_t mn = ~0ull, mx = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    uint32_t w[DW];
-    ld_elem<DW>(data + i * DW, w);
-    const uint64_t k = T::rkey(key_of<T>(w));
-    mn = k < mn ? k : mn;
-    mx = k > mx ? k : mx;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += stride * U) {
+    uint32_t w[U][DW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = i0 + (uint64_t)u * stride;
+      if (i < n) ld_elem<DW>(data + i * DW, w[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + (uint64_t)u * stride < n) {
+        const uint64_t k = T::rkey(key_of<T>(w[u]));
+        mn = k < mn ? k : mn;
+        mx = k > mx ? k : mx;
+      }
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const uint64_t a = (uint64_t)__shfl_xor((long long)mn, o, 64);
