@@ -296,6 +296,24 @@ def _pmc_rows(folder: str):
     return rows
 
 
+def _from_root(path: str) -> str:
+    """A path as written in a command run from /tmp: relative paths are taken
+    from the repository root, $R."""
+    return path if os.path.isabs(path) else "$R/" + path
+
+
+def traffic_commands(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_write_dir: str) -> list:
+    """The counter runs that fill the four folders, and the summary command."""
+    runs = [("FETCH_SIZE", fetch_dir, "--steps 2 --warmup 1 --no-cpu --no-radix"),
+            ("WRITE_SIZE", write_dir, "--steps 2 --warmup 1 --no-cpu --no-radix"),
+            ("FETCH_SIZE", cal_fetch_dir, "--calib-copy"),
+            ("WRITE_SIZE", cal_write_dir, "--calib-copy")]
+    lines = [f"rocprofv3 --pmc {c} --output-format csv -d {_from_root(d)} -o p -- python3 $R/bench.py {a}"
+             for c, d, a in runs]
+    lines.append(f"python3 bench.py --traffic-summary {fetch_dir} {write_dir} {cal_fetch_dir} {cal_write_dir}")
+    return lines
+
+
 def traffic_summary(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_write_dir: str) -> int:
     """Mean FETCH_SIZE / WRITE_SIZE per dispatch of each sort kernel, scaled by
     the factor that maps the same counter of the calibration copy onto its
@@ -325,16 +343,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_writ
              "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one pass per counter (repo root, `cd /tmp`",
              "and `TMPDIR=/tmp` first, R = repo root):", "",
              "```",
-             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_FETCH_SIZE -o p -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-radix",
-             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_WRITE_SIZE -o p -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-radix",
-             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/cal_FETCH_SIZE -o p -- "
-             "python3 $R/bench.py --calib-copy",
-             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/cal_WRITE_SIZE -o p -- "
-             "python3 $R/bench.py --calib-copy",
-             "python3 bench.py --traffic-summary gpurun_out/pmc_FETCH_SIZE gpurun_out/pmc_WRITE_SIZE "
-             "gpurun_out/cal_FETCH_SIZE gpurun_out/cal_WRITE_SIZE",
+             *traffic_commands(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir),
              "```", "",
              "Each counter is scaled by the factor that maps the same counter of the plain 1 GiB",
              "device-to-device copy (`__amd_rocclr_copyBuffer`) onto its 1 GiB read and 1 GiB written.", "",
@@ -357,9 +366,11 @@ def kernel_stats_summary(csv_path: str) -> int:
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort\n")
+    folder = os.path.dirname(csv_path)
+    prefix = os.path.basename(csv_path)[:-len("_kernel_stats.csv")]
     print("Command (`cd /tmp`, `TMPDIR=/tmp`, R = repo root): `rocprofv3 --kernel-trace --stats --output-format csv "
-          "-d $R/gpurun_out/ktrace -o kt -- python3 $R/bench.py --steps 3 --warmup 1 --no-cpu --no-radix`; "
-          "table from `python3 bench.py --kernel-stats-summary gpurun_out/ktrace/kt_kernel_stats.csv`.\n")
+          f"-d {_from_root(folder)} -o {prefix} -- python3 $R/bench.py --steps 3 --warmup 1 --no-cpu --no-radix`; "
+          f"table from `python3 bench.py --kernel-stats-summary {csv_path}`.\n")
     print("6 sorts (1 warmup, 3 timed, 2 timed per kernel for the per-level table) plus the bench's own "
           "copies and checks; durations in microseconds.\n")
     print("| kernel | calls | total us | avg us | % |")
