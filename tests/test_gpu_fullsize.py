@@ -1,0 +1,109 @@
+"""Bit-exact parity at the full benchmark sizes: 2^28 u64 and u32 keys of all
+ten generators (samplesort and IPS2Ra), 2^27 doubles and Pair records, 2^24
+100-byte records.  The sort runs through the C ABI with the parameters the
+benchmark uses; the digest of its sorted key sequence must equal the digest
+of the oracle's sorted keys of the same input (tests/golden/fullsize.py
+writes those from the oracle alone).  Records must also keep their multiset:
+Pair values and record payload bytes 10..17 hold each element's input
+index, so the output values must be a permutation of 0..n-1 and every
+output record must equal the input record its index names.
+
+The small configuration (2^20 u64 Uniform keys, k = 256, 2 KiB blocks,
+alpha = 4, n0 = 16) is compared with the oracle element by element."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2009_13569_amd as ips
+from golden import fullsize as fs
+from gpu_util import assert_parity, log
+
+pytestmark = pytest.mark.gpu
+
+with open(fs.OUT) as _f:
+    GOLD = json.load(_f)["cases"]
+
+
+@pytest.fixture(scope="module")
+def sorter():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ips.Sorter(0)
+
+
+def _device_input(c, dev):
+    """The case's input as a device tensor (integer kinds as signed bit
+    patterns of the same width; the library is told the kind)."""
+    import torch
+    import synth
+    import synth.device as sd
+    n = 1 << c["log2n"]
+    kind, dist = c["kind"], c["dist"]
+    if kind in ("u32", "u64", "pair") or (kind == "f64" and dist == "uniform"):
+        return sd.generate(kind, dist, n, synth.seed_for(c["config"], c["array"]), dev)
+    return torch.from_numpy(fs.generate(c)).to(dev)   # f64 Exponential (host log1p), records
+
+
+def _key_digest(t, kind):
+    """fs.digest of the key bytes of a sorted device array."""
+    k = t[:, 0] if kind == "pair" else t[:, :10] if kind == "rec100" else t
+    host = np.ascontiguousarray(k.contiguous().cpu().numpy())
+    return fs.digest(memoryview(host).cast("B"), threads=16)
+
+
+def _check_records(out, inp, kind):
+    """Output indices form a permutation and each output record is the
+    input record its index names (exact multiset equality)."""
+    import torch
+    n = out.shape[0]
+    if kind == "pair":
+        ix = out[:, 1].view(torch.int64)
+    else:
+        ix = out[:, 10:18].contiguous().view(torch.int64).reshape(n)
+    assert int(ix.min()) >= 0 and int(ix.max()) < n, "index out of range"
+    seen = torch.zeros(n, dtype=torch.int32, device=out.device)
+    seen.index_add_(0, ix, torch.ones(n, dtype=torch.int32, device=out.device))
+    assert bool((seen == 1).all()), "payload indices are not a permutation"
+    assert bool((inp.index_select(0, ix) == out).all()), "a record changed"
+
+
+CASES = [(name, algo) for name, c in sorted(GOLD.items())
+         for algo in (("samplesort", "radix") if c["kind"] != "rec100" else ("samplesort",))]
+
+
+@pytest.mark.parametrize("name,algo", CASES, ids=[f"{n}-{a}" for n, a in CASES])
+def test_fullsize_digest(sorter, name, algo):
+    import torch
+    c = GOLD[name]
+    kind = c["kind"]
+    dev = torch.device("cuda:0")
+    log(f"fullsize {name} {algo}: generating")
+    src = _device_input(c, dev)
+    work = src.clone()
+    log(f"fullsize {name} {algo}: sorting {work.shape[0]} elements")
+    sorter.sort_(work, algo=algo, kind=kind)
+    torch.cuda.synchronize()
+    log(f"fullsize {name} {algo}: digest")
+    assert _key_digest(work, kind) == c["digest"], f"{name} {algo}: sorted keys differ from the oracle's"
+    if kind in ("pair", "rec100"):
+        _check_records(work, src, kind)
+    del src, work
+    torch.cuda.empty_cache()
+
+
+def test_small_config_elementwise(sorter):
+    """2^20 u64 Uniform keys with k = 256, 2 KiB blocks (buffer blocks in the
+    workspace), n0 = 16 and the root's alpha = 4, element by element."""
+    import synth
+    a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
+    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
+    import torch
+    t = torch.from_numpy(a).cuda()
+    sorter.sort_(t, params=p)
+    torch.cuda.synchronize()
+    ri = sorter.root_info()
+    assert (ri.alpha, ri.k_prime, ri.block_elems) == (4, 256, 256)
+    assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))

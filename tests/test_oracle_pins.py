@@ -110,19 +110,72 @@ def test_sort_matches_library_sort(kind, n):
             assert np.array_equal(s, np.sort(a, kind="stable"))
 
 
-def test_sort_brute_force_tiny():
-    # Every permutation of distinct keys and every sequence over {0,1,2} for
-    # n <= 6: the sorted output is the unique non-decreasing arrangement.
-    for n in range(0, 7):
-        base = np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 >> 3)
-        for perm in itertools.permutations(range(n)):
-            a = base[list(perm)]
-            assert np.array_equal(oracle.sort(a, "u64"), np.sort(base))
+def _oracle_sort_segments(arr, kind, n):
+    """The oracle run in place on every consecutive n-element segment."""
+    import ctypes
+    L, D = oracle.lib(), oracle.ELEM_BYTES[kind]
+    base = arr.ctypes.data
+    for off in range(0, arr.shape[0], n):
+        assert L.oracle_sort(ctypes.c_void_p(base + off * D), n, oracle.TYPES[kind]) == 0
+    return arr
+
+
+def _key_list(a, kind):
+    """Keys as comparable Python values: integers (f64: the bit pattern,
+    whose order is checked against the hand-ordered list) or bytes."""
+    if kind == "f64":
+        return a.view(np.uint64).tolist()
+    if kind == "pair":
+        return a[:, 0].tolist()
+    if kind == "rec100":
+        return [bytes(r[:10]) for r in a]
+    return a.tolist()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_sort_brute_force_tiny(kind):
+    """Every permutation of n <= 8 distinct keys and every sequence of n <= 8
+    keys over three values (tests/bruteforce_cases.py).  A permutation must
+    come out as the keys in their listed (hand-ordered) order; a sequence
+    must come out non-decreasing in the listed order with its multiset
+    unchanged; pair values and record payloads must still name an input
+    element with the same key."""
+    import bruteforce_cases as bc
+    vals = bc.key_values(kind)
+    if kind in ("u32", "u64", "pair", "rec100"):
+        assert vals == sorted(vals)          # library order agrees with the listed order
+    else:                                    # the listed doubles follow the golden totalOrder list
+        gold = [int(r[0], 16) for r in _lines("f64_total_order.txt")]
+        assert [gold.index(v) for v in vals] == sorted(gold.index(v) for v in vals)
+    tri = bc.tri_values(kind)
+    rank = {v: i for i, v in enumerate(tri)}
+    for n in range(1, bc.NMAX + 1):
+        inp = bc.build(kind, bc.permutation_seqs(kind, n))
+        out = _oracle_sort_segments(inp.copy(), kind, n)
+        want = vals[:n]
+        keys = _key_list(out, kind)
+        assert all(keys[o:o + n] == want for o in range(0, len(keys), n)), (kind, n)
+        if kind in ("pair", "rec100"):
+            ix = (out[:, 1] if kind == "pair" else out[:, 10:18].copy().view("<u8")[:, 0]).astype(np.int64)
+            assert np.array_equal(np.sort(ix), np.arange(inp.shape[0]))
+            assert np.array_equal(out, inp[ix])            # whole records moved intact
+            assert all(set(ix[o:o + n] // n) == {o // n} for o in range(0, len(ix), n))
+        seqs = bc.ternary_seqs(kind, n)
+        inp = bc.build(kind, seqs)
+        out = _oracle_sort_segments(inp.copy(), kind, n)
+        keys = _key_list(out, kind)
+        for i, sq in enumerate(seqs):
+            got = keys[i * n:(i + 1) * n]
+            r = [rank[x] for x in got]
+            assert r == sorted(r) and Counter(got) == Counter(sq), (kind, sq, got)
+
+
+def test_sort_brute_force_multiset_u32():
+    """Sequences over {0, 1, 2} against Python's sorted (library)."""
+    for n in range(0, 8):
         for seq in itertools.product(range(3), repeat=n):
             a = np.array(seq, dtype=np.uint32)
-            s = oracle.sort(a, "u32")
-            assert all(s[i] <= s[i + 1] for i in range(n - 1))
-            assert Counter(s.tolist()) == Counter(seq)
+            assert oracle.sort(a, "u32").tolist() == sorted(seq)
 
 
 def test_pair_sort_values_are_indices():
@@ -263,6 +316,37 @@ def test_radix_digit_info_hand_values():
     assert oracle.radix_digit_info(np.full(5, 7, dtype=np.uint32), "u32")["all_equal"]
     h = oracle.radix_histogram(rd, "u64", 2, 8)
     assert np.array_equal(h, np.full(256, 4096, dtype=np.uint64))
+
+
+def test_radix_key_of_doubles():
+    """The unsigned image of a double used by the radix variant keeps IEEE
+    754 totalOrder.  Hand values: +0.0 maps to 0x8000000000000000 and -0.0 to
+    0x7FFFFFFFFFFFFFFF, so their highest differing bit is 63 and the top
+    digit is 0x80 and 0x7F; +inf (0xFFF0...) and +NaN (0xFFF8...) differ
+    first at bit 51; -inf maps to 0x000F... and -1.0 to 0x400F..., first
+    differing at bit 62.  Order: for each consecutive pair x < y of the
+    golden totalOrder list, the array [x, x, y] puts both x into digit 0 of
+    the one-bit digit at their highest differing bit."""
+    f = lambda *bits: np.array(bits, dtype=np.uint64).view(np.float64)
+    z = f(0x0000000000000000, 0x8000000000000000)
+    assert oracle.radix_digit_info(z, "f64") == {"shift": 56, "width": 8, "all_equal": False}
+    h = oracle.radix_histogram(z, "f64", 56, 8)
+    assert h[0x80] == 1 and h[0x7F] == 1 and int(h.sum()) == 2
+    inf_nan = f(0x7FF0000000000000, 0x7FF8000000000000)
+    assert oracle.radix_digit_info(inf_nan, "f64") == {"shift": 44, "width": 8, "all_equal": False}
+    h = oracle.radix_histogram(inf_nan, "f64", 44, 8)
+    assert h[0x00] == 1 and h[0x80] == 1
+    neg = f(0xFFF0000000000000, 0xBFF0000000000000)            # -inf, -1.0
+    assert oracle.radix_digit_info(neg, "f64") == {"shift": 55, "width": 8, "all_equal": False}
+    h = oracle.radix_histogram(neg, "f64", 55, 8)
+    assert h[0x00] == 1 and h[0x80] == 1
+    assert oracle.radix_digit_info(f(0x7FF8000000000001, 0x7FF8000000000001), "f64")["all_equal"]
+    gold = [int(r[0], 16) for r in _lines("f64_total_order.txt")]
+    for x, y in zip(gold, gold[1:]):
+        a = f(x, x, y)
+        d = oracle.radix_digit_info(a, "f64")
+        top = d["shift"] + d["width"] - 1
+        assert oracle.radix_histogram(a, "f64", top, 1).tolist() == [2, 1], (hex(x), hex(y))
 
 
 def test_count_less_matches_searchsorted():
