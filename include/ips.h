@@ -18,10 +18,17 @@
  *    device memory while sorting; extra memory comes from the caller's
  *    workspace, sized by ips_workspace_bytes.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *    Work is enqueued on it; the sort entry points also synchronize with it
- *    between recursion levels (the host plans each level from the bucket
- *    sizes of the previous one), so they return only when the data is
- *    sorted.
+ *    Work is enqueued on it.  The partitioning steps are planned on the
+ *    device from a task queue in the workspace; the host enqueues rounds of
+ *    steps and synchronizes with the stream between rounds to read the
+ *    queue's head and tail (and once after the sorted-input check), so the
+ *    sort entry points return only when the data is sorted.  With
+ *    IPS_FLAG_HOST_PLAN the host instead plans every batch of a recursion
+ *    level from read-back bucket sizes.
+ *  - After IPS_E_DEVICE the contents of the array are unspecified (a kernel
+ *    stopped part-way through moving blocks); after any other error code
+ *    the array is unchanged unless the error came from a HIP call made
+ *    after the first kernel launch.
  *  - Return values are IPS_OK (0) or a negative IPS_E_* code; arguments are
  *    validated before any HIP call.  ips_status_string names every code.
  *  - The sort is unstable: records with equal keys may end in any order.
@@ -52,6 +59,8 @@ extern "C" {
 #define IPS_E_DEVICE (-7)          /* a kernel reported an internal consistency error;
                                       see ips_last_device_error */
 #define IPS_E_NO_DEVICE (-8)       /* no usable gfx950 device */
+#define IPS_E_SCRATCH (-9)         /* ips_sort_keys_noalloc: the call needs more than
+                                      the static scratch (or pinned staging) holds */
 
 /* Element types.  Keys: u32, u64, f64 (ordered by IEEE 754 totalOrder, so
  * -0.0 < +0.0 and NaNs sort to the ends by sign).  Records (Section 7 of the
@@ -130,8 +139,12 @@ typedef struct ips_ctx ips_ctx;
 
 /* Create a context on HIP device `device` (the "sorter object" of
  * Section 7.6: it keeps host-side state and pinned staging buffers between
- * calls; it holds no device memory).  Errors: IPS_E_INVALID_ARG for a null
- * `out`, IPS_E_NO_DEVICE, IPS_E_HIP. */
+ * calls; it holds no device memory).  Creation allocates 8 MiB of pinned
+ * host staging (grown later by calls that need more, except the
+ * allocation-free entry point) and, for the first context on a device,
+ * takes that device's address of the static scratch of
+ * ips_sort_keys_noalloc (the current device is restored afterwards).
+ * Errors: IPS_E_INVALID_ARG for a null `out`, IPS_E_NO_DEVICE, IPS_E_HIP. */
 int ips_ctx_create(ips_ctx** out, int device);
 
 /* Destroy a context (NULL is accepted). */
@@ -152,6 +165,31 @@ int ips_workspace_bytes(uint64_t n, int elem_type, int algo,
 int ips_sort_keys(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type,
                   int algo, void* d_ws, size_t ws_bytes,
                   const ips_params* params, void* stream);
+
+/* Allocation-free variant of ips_sort_keys, for callers that cannot
+ * allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same sort, same kernels and the same
+ * arguments except the workspace: the scratch is a static device array of
+ * 64 MiB inside the library (one copy per GPU, held until the process ends;
+ * its address is taken when the first context on a GPU is created), and
+ * the pinned host staging is the buffer the context allocated when it was
+ * created.  The call allocates no device or pinned host memory and creates
+ * no events or graphs.
+ *  - Limit: calls whose workspace (ips_workspace_bytes with the same
+ *    arguments) exceeds 64 MiB are rejected with IPS_E_SCRATCH before any
+ *    HIP call.  With the default parameters that admits up to 2^23 u64 or
+ *    f64 keys and 2^24 u32 keys.
+ *  - IPS_FLAG_PROFILE and IPS_FLAG_GRAPH are rejected (IPS_E_INVALID_ARG):
+ *    both would create HIP objects.
+ *  - Every call on one GPU shares that GPU's scratch, which keeps the last
+ *    call's contents (the sort initialises what it needs).  Calls that
+ *    overlap in time on one GPU (other threads, other streams, other
+ *    contexts) race on it and must be serialized by the caller.
+ *  - Like ips_sort_keys, the call synchronizes with `stream` between
+ *    rounds of steps and returns when the keys are sorted.
+ * Errors: as ips_sort_keys, plus IPS_E_SCRATCH. */
+int ips_sort_keys_noalloc(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, int algo,
+                          const ips_params* params, void* stream);
 
 /* Sort n records in place at device pointer d_recs (array of structures).
  * Records move as whole records; only the key is compared. */

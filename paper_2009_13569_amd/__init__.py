@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 IPS_OK = 0
 STATUS = {0: "IPS_OK", -1: "IPS_E_INVALID_ARG", -2: "IPS_E_UNSUPPORTED", -3: "IPS_E_WORKSPACE",
           -4: "IPS_E_MISALIGNED", -5: "IPS_E_TOO_LARGE", -6: "IPS_E_HIP", -7: "IPS_E_DEVICE",
-          -8: "IPS_E_NO_DEVICE"}
+          -8: "IPS_E_NO_DEVICE", -9: "IPS_E_SCRATCH"}
 TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5}
 ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100}
 ALGOS = {"samplesort": 0, "radix": 1}
@@ -45,7 +45,8 @@ EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments",
            "ips_batch_workspace_bytes", "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace",
            "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
-           "ips_last_device_error", "ips_status_string", "ips_abi_version", "ips_tuned_params"]
+           "ips_last_device_error", "ips_status_string", "ips_abi_version", "ips_tuned_params",
+           "ips_sort_keys_noalloc"]
 SERVE_BATCH = 0
 SERVE_FIFO = 1
 
@@ -113,6 +114,7 @@ _lib.ips_ctx_destroy.argtypes = [_vp]
 _lib.ips_workspace_bytes.argtypes = [_u64, _i32, _i32, ctypes.POINTER(Params), ctypes.POINTER(_sz)]
 _lib.ips_sort_keys.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_sort_pairs.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
+_lib.ips_sort_keys_noalloc.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Params), _vp]
 _lib.ips_segments_workspace_bytes.argtypes = [_u64, ctypes.POINTER(Segment), ctypes.c_uint32, _i32, _i32,
                                               ctypes.POINTER(Params), ctypes.POINTER(_sz)]
 _lib.ips_sort_segments.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Segment), ctypes.c_uint32,
@@ -138,7 +140,7 @@ for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_batch_workspace_bytes",
            "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace", "ips_get_root_info",
            "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
-           "ips_abi_version", "ips_tuned_params"):
+           "ips_abi_version", "ips_tuned_params", "ips_sort_keys_noalloc"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -312,6 +314,27 @@ class Sorter:
         if rc != IPS_OK:
             raise IpsError(rc, "ips_sort", f"(hip={_lib.ips_last_hip_error(self._h)}, "
                                            f"device={hex(_lib.ips_last_device_error(self._h))})")
+        return t
+
+    def sort_noalloc_(self, t, algo: str = "samplesort", params: Params | None = None, kind: str | None = None,
+                      stream=None):
+        """Sort keys (u32/u64/f64) in place with ips_sort_keys_noalloc: the
+        library's static per-GPU scratch instead of a workspace tensor."""
+        import torch
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensor must be a contiguous GPU tensor")
+        kind = kind or kind_of(t)
+        if kind not in ("u32", "u64", "f64"):
+            raise ValueError("the allocation-free entry point sorts keys only")
+        n = t.shape[0]
+        params = self.params_for(n, kind, algo, False, params)
+        if stream is None:
+            stream = torch.cuda.current_stream(t.device)
+        rc = _lib.ips_sort_keys_noalloc(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ALGOS[algo],
+                                        ctypes.byref(params), ctypes.c_void_p(stream.cuda_stream))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_sort_keys_noalloc", f"(hip={_lib.ips_last_hip_error(self._h)}, "
+                                                        f"device={hex(_lib.ips_last_device_error(self._h))})")
         return t
 
     def sort_segments_(self, t, offsets, sizes, algo: str = "samplesort", params: Params | None = None,

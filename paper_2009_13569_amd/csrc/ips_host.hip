@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -263,8 +264,28 @@ struct HTask {
 
 }  // namespace
 
+// Scratch of ips_sort_keys_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (in host code the name is only a stand-in); its device
+// address on each GPU is taken once with hipGetSymbolAddress when the first
+// context on that GPU is created, and that address is used everywhere.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Pinned staging every context allocates when it is created: enough for the
+// largest plan of any call whose workspace fits the static scratch (at most
+// TB_MAX tasks, WB_MAX classification workgroups, 2^18 + 2 TB_MAX + 16
+// permutation workgroups and TB_MAX * MAX_NB LDS-tier tasks), so that the
+// allocation-free entry point never needs a larger buffer.
+constexpr size_t PIN_PREALLOC_BYTES = (size_t)8 << 20;
+
 struct ips_ctx {
   int device = 0;
+  bool noalloc = false;      // inside ips_sort_keys_noalloc: never allocate
+  void* scratch = nullptr;   // this device's address of `scratch`
   int last_hip = 0;
   int last_dev = 0;
   ips_root_info root;
@@ -338,6 +359,7 @@ hipError_t timed(ips_ctx* ctx, hipStream_t st, uint32_t row, uint32_t ph, uint64
 
 int ensure_pinned(ips_ctx* ctx, size_t bytes) {
   if (ctx->pin_bytes >= bytes) return IPS_OK;
+  if (ctx->noalloc) return IPS_E_SCRATCH;
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   ctx->pin = nullptr;
   ctx->pin_bytes = 0;
@@ -1395,6 +1417,9 @@ const char* ips_status_string(int s) {
     case IPS_E_HIP: return "IPS_E_HIP: HIP runtime error";
     case IPS_E_DEVICE: return "IPS_E_DEVICE: kernel consistency error";
     case IPS_E_NO_DEVICE: return "IPS_E_NO_DEVICE: no usable device";
+    case IPS_E_SCRATCH:
+      return "IPS_E_SCRATCH: the call needs more than the 64 MiB static scratch (or the context's pinned "
+             "staging) of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -1409,6 +1434,31 @@ int ips_ctx_create(ips_ctx** out, int device) {
   c->device = device;
   std::memset(&c->root, 0, sizeof(c->root));
   std::memset(&c->stats, 0, sizeof(c->stats));
+  if (device >= MAX_DEVICES) { delete c; return IPS_E_NO_DEVICE; }
+  {
+    // Once per device, with that device current: the device address of the
+    // allocation-free entry point's scratch array.
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      int prev = 0;
+      hipError_t e = hipGetDevice(&prev);
+      if (e == hipSuccess) e = hipSetDevice(device);
+      void* ptr = nullptr;
+      if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess && e2 != hipSuccess) e = e2;
+      if (e != hipSuccess || !ptr) {
+        delete c;
+        return IPS_E_HIP;
+      }
+      g_scratch_ptr[device] = ptr;
+    }
+    c->scratch = g_scratch_ptr[device];
+  }
+  if (int e = ensure_pinned(c, PIN_PREALLOC_BYTES)) {
+    delete c;
+    return e;
+  }
   *out = c;
   return IPS_OK;
 }
@@ -1441,6 +1491,26 @@ int ips_sort_keys(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, int algo
                   size_t ws_bytes, const ips_params* params, void* stream) {
   if (key_type != IPS_U32 && key_type != IPS_U64 && key_type != IPS_F64) return IPS_E_INVALID_ARG;
   return sort_impl(ctx, d_keys, n, key_type, algo, d_ws, ws_bytes, params, stream);
+}
+
+int ips_sort_keys_noalloc(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, int algo,
+                          const ips_params* params, void* stream) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  if (key_type != IPS_U32 && key_type != IPS_U64 && key_type != IPS_F64) return IPS_E_INVALID_ARG;
+  if (params && (params->flags & (IPS_FLAG_PROFILE | IPS_FLAG_GRAPH))) return IPS_E_INVALID_ARG;
+  Cfg c;
+  if (int e = make_cfg(n, key_type, algo, params, &c)) return e;
+  if (n >= (1ull << 31) * (uint64_t)block_elems(c, max_nb(c))) return IPS_E_TOO_LARGE;
+  if (n >= 2) {
+    Layout L;
+    plan(n, c, &L);
+    if (L.total > NOALLOC_SCRATCH_BYTES) return IPS_E_SCRATCH;
+  }
+  if (!ctx->scratch) return IPS_E_HIP;
+  ctx->noalloc = true;
+  const int rc = sort_impl(ctx, d_keys, n, key_type, algo, ctx->scratch, NOALLOC_SCRATCH_BYTES, params, stream);
+  ctx->noalloc = false;
+  return rc;
 }
 
 int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type, int algo, void* d_ws,

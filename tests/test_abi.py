@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_abi_version_and_status_strings():
     assert ips.lib().ips_abi_version() == 1
-    for code in range(-8, 1):
+    for code in range(-9, 1):
         assert ips.lib().ips_status_string(code).decode().startswith("IPS_")
 
 
@@ -74,6 +74,7 @@ def test_sort_rejects_bad_arguments_before_hip():
     # wrong type codes for each entry point
     assert L.ips_sort_keys(None, fake, 10, 4, 0, fake, 1 << 20, None, None) == -1
     assert L.ips_sort_pairs(None, fake, 10, 2, 0, fake, 1 << 20, None, None) == -1
+    assert L.ips_sort_keys_noalloc(None, fake, 10, 2, 0, None, None) == -1
 
 
 def test_ctx_create_null_out():
