@@ -99,11 +99,15 @@ def test_small_config_elementwise(sorter):
     workspace), n0 = 16 and the root's alpha = 4, element by element."""
     import synth
     a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
-    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
     import torch
+    p1 = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_LEVEL1_ONLY)
+    t = torch.from_numpy(a).cuda()
+    sorter.sort_(t, params=p1)              # the root step alone: its parameters
+    torch.cuda.synchronize()
+    ri = sorter.root_info()
+    assert (ri.valid, ri.alpha, ri.k_prime, ri.m, ri.block_elems) == (1, 4, 256, 1024, 256)
+    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
     t = torch.from_numpy(a).cuda()
     sorter.sort_(t, params=p)
     torch.cuda.synchronize()
-    ri = sorter.root_info()
-    assert (ri.alpha, ri.k_prime, ri.block_elems) == (4, 256, 256)
     assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))
