@@ -16,10 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5}
-ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100}
+TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5, "quartet": 6}
+ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100, "quartet": 32}
 _DT = {"u32": np.uint32, "u64": np.uint64, "f64": np.float64,
-       "pair": np.uint64, "rec100": np.uint8}
+       "pair": np.uint64, "rec100": np.uint8, "quartet": np.uint64}
 
 _lib = None
 
@@ -76,6 +76,8 @@ def _check(a: np.ndarray, kind: str) -> np.ndarray:
         raise TypeError("pair arrays are (n, 2)")
     if kind == "rec100" and (a.ndim != 2 or a.shape[1] != 100):
         raise TypeError("rec100 arrays are (n, 100)")
+    if kind == "quartet" and (a.ndim != 2 or a.shape[1] != 4):
+        raise TypeError("quartet arrays are (n, 4)")
     return a
 
 
@@ -89,8 +91,10 @@ def mulhi64(a: int, b: int) -> int:
 
 
 def key_less(kind: str, a: np.ndarray, b: np.ndarray) -> bool:
-    a = _check(a.reshape((1,) + a.shape) if kind in ("pair", "rec100") and a.ndim == 1 else np.atleast_1d(a), kind)
-    b = _check(b.reshape((1,) + b.shape) if kind in ("pair", "rec100") and b.ndim == 1 else np.atleast_1d(b), kind)
+    a = _check(a.reshape((1,) + a.shape) if kind in ("pair", "rec100", "quartet") and a.ndim == 1
+               else np.atleast_1d(a), kind)
+    b = _check(b.reshape((1,) + b.shape) if kind in ("pair", "rec100", "quartet") and b.ndim == 1
+               else np.atleast_1d(b), kind)
     return bool(lib().oracle_key_less(TYPES[kind], _ptr(a), _ptr(b)))
 
 
@@ -136,7 +140,8 @@ def sample_step(a: np.ndarray, kind: str, l: int = 0, n: int | None = None, k: i
 
 
 def classify(e: np.ndarray, kind: str, splitters: np.ndarray, K: int, eq: bool) -> int:
-    e = _check(e.reshape((1,) + e.shape) if kind in ("pair", "rec100") and e.ndim == 1 else np.atleast_1d(e), kind)
+    e = _check(e.reshape((1,) + e.shape) if kind in ("pair", "rec100", "quartet") and e.ndim == 1
+               else np.atleast_1d(e), kind)
     s = _check(splitters, kind)
     return int(lib().oracle_classify(TYPES[kind], _ptr(e), _ptr(s), K, int(eq)))
 
@@ -183,5 +188,6 @@ def check_partition(a: np.ndarray, kind: str, splitters: np.ndarray, K: int, eq:
 
 def count_less(a: np.ndarray, kind: str, v: np.ndarray, or_equal: bool = False) -> int:
     a = _check(a, kind)
-    v = _check(v.reshape((1,) + v.shape) if kind in ("pair", "rec100") and v.ndim == 1 else np.atleast_1d(v), kind)
+    v = _check(v.reshape((1,) + v.shape) if kind in ("pair", "rec100", "quartet") and v.ndim == 1
+               else np.atleast_1d(v), kind)
     return int(lib().oracle_count_less(_ptr(a), _n(a, kind), TYPES[kind], _ptr(v), int(or_equal)))

@@ -19,6 +19,7 @@ size_t oracle_elem_bytes(int type) {
     case 3: return 8;
     case 4: return 16;
     case 5: return 100;
+    case 6: return 32;
     default: return 0;
   }
 }
@@ -53,7 +54,9 @@ static int f64_total_less(uint64_t a, uint64_t b) {
 /* Strict key order of the element types.  Pair compares only its key
  * (value is payload, Section 7); rec100 compares the first ten bytes
  * lexicographically as unsigned bytes (Algorithm 4 read with unsigned
- * char, the memcmp order). */
+ * char, the memcmp order); Quartet compares its three 64-bit key words
+ * a, b, c (bytes 0, 8, 16) lexicographically, the fourth word being
+ * payload (Algorithm 3). */
 int oracle_key_less(int type, const void* a, const void* b) {
   switch (type) {
     case 1: return rd32(a) < rd32(b);
@@ -65,6 +68,15 @@ int oracle_key_less(int type, const void* a, const void* b) {
       const unsigned char* y = (const unsigned char*)b;
       for (int i = 0; i < 10; ++i)
         if (x[i] != y[i]) return x[i] < y[i];
+      return 0;
+    }
+    case 6: {
+      const unsigned char* x = (const unsigned char*)a;
+      const unsigned char* y = (const unsigned char*)b;
+      for (int w = 0; w < 3; ++w) {
+        const uint64_t u = rd64(x + 8 * w), v = rd64(y + 8 * w);
+        if (u != v) return u < v;
+      }
       return 0;
     }
     default: return 0;

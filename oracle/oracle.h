@@ -8,7 +8,8 @@
  * Element types (codes shared by value only, not by header):
  *   1 u32, 2 u64, 3 f64 (IEEE-754 totalOrder), 4 pair (u64 key at byte 0,
  *   u64 value at byte 8), 5 rec100 (100-byte record, key = bytes 0..9
- *   compared as unsigned bytes).
+ *   compared as unsigned bytes), 6 quartet (32 bytes: u64 key words a, b,
+ *   c at bytes 0, 8, 16 compared lexicographically, u64 value at byte 24).
  */
 #ifndef IPS_ORACLE_H
 #define IPS_ORACLE_H

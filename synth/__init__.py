@@ -202,8 +202,27 @@ def gen_rec100(dist: str, n: int, seed: int) -> np.ndarray:
     return out
 
 
+def gen_quartet(dist: str, n: int, seed: int) -> np.ndarray:
+    """(n, 4) uint64: key words a, b, c and the original index.  Uniform:
+    three independent uniform words.  Other distributions: a from the
+    integer distribution and b, c derived from a (b = a >> 1, c = a ^
+    0x5555...), so that equal a means an equal key and the distribution's
+    duplicates reach the comparison of all three words."""
+    out = np.empty((n, 4), dtype=np.uint64)
+    if dist == "uniform":
+        x = stream(seed, 3 * n)
+        out[:, 0], out[:, 1], out[:, 2] = x[0::3], x[1::3], x[2::3]
+    else:
+        a = gen_u64(dist, n, seed)
+        out[:, 0] = a
+        out[:, 1] = a >> np.uint64(1)
+        out[:, 2] = a ^ np.uint64(0x5555555555555555)
+    out[:, 3] = np.arange(n, dtype=np.uint64)
+    return out
+
+
 def generate(kind: str, dist: str, n: int, seed: int) -> np.ndarray:
-    """kind in {u32, u64, f64, pair, rec100}."""
+    """kind in {u32, u64, f64, pair, rec100, quartet}."""
     if kind == "u64":
         return gen_u64(dist, n, seed)
     if kind == "u32":
@@ -214,6 +233,8 @@ def generate(kind: str, dist: str, n: int, seed: int) -> np.ndarray:
         return gen_pair(dist, n, seed)
     if kind == "rec100":
         return gen_rec100(dist, n, seed)
+    if kind == "quartet":
+        return gen_quartet(dist, n, seed)
     raise ValueError(kind)
 
 

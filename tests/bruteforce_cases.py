@@ -41,21 +41,32 @@ def _rec_key(i: int) -> bytes:
 
 _REC_TRI = [bytes([0x00] * 10), bytes([0x7F] + [0xFF] * 9), bytes([0x80] + [0x00] * 9)]
 
+# Quartet keys (a, b, c), increasing lexicographically, each differing from
+# the one before in a different word (Algorithm 3).
+_M = 0xFFFFFFFFFFFFFFFF
+_QUARTET = [(0, 0, 0), (0, 0, 1), (0, 0, 1 << 63), (0, 1, 0), (0, 1 << 63, 0), (1, 0, 0), (1 << 63, 0, 0),
+            (_M, _M, _M)]
+_QUARTET_TRI = [(0, 0, _M), (0, 1, 0), (1, 0, 0)]
+
 
 def key_values(kind: str) -> list:
+    if kind == "quartet":
+        return _QUARTET
     return {"u32": _U32, "u64": _U64, "f64": _F64, "pair": _U64}.get(kind) or [_rec_key(i) for i in range(8)]
 
 
 def tri_values(kind: str) -> list:
+    if kind == "quartet":
+        return _QUARTET_TRI
     return _TRI.get(kind) or _REC_TRI
 
 
 def build(kind: str, keyseqs: list[list], base_index: int = 0) -> np.ndarray:
     """One array per key sequence, concatenated: keys given as integers
-    (bit patterns for f64) or 10-byte strings (records).  Pair values and
-    record payloads (bytes 10..17, little endian) hold the element's
-    position in the concatenation plus base_index; the rest of a record's
-    payload is a fixed pattern."""
+    (bit patterns for f64), 10-byte strings (records) or (a, b, c) triples
+    (Quartet).  Pair and Quartet values and record payloads (bytes 10..17,
+    little endian) hold the element's position in the concatenation plus
+    base_index; the rest of a record's payload is a fixed pattern."""
     flat = [k for s in keyseqs for k in s]
     n = len(flat)
     if kind == "u32":
@@ -65,6 +76,12 @@ def build(kind: str, keyseqs: list[list], base_index: int = 0) -> np.ndarray:
     if kind == "f64":
         return np.array(flat, dtype=np.uint64).view(np.float64)
     idx = np.arange(base_index, base_index + n, dtype=np.uint64)
+    if kind == "quartet":
+        out = np.empty((n, 4), dtype=np.uint64)
+        if n:
+            out[:, :3] = np.array(flat, dtype=np.uint64).reshape(n, 3)
+        out[:, 3] = idx
+        return out
     if kind == "pair":
         out = np.empty((n, 2), dtype=np.uint64)
         out[:, 0] = np.array(flat, dtype=np.uint64)

@@ -3,7 +3,7 @@
 The configurations measured at full size (2^28 u64 and u32 keys of every
 generator, 2^27 doubles and Pair records, 2^24 100-byte records) are far too
 large to store sorted outputs for.  This module defines those inputs (the
-generator, size and seed of each), a digest of a sorted key sequence, and a
+generator, size and seed of each; also 2^27 Quartets), a digest of a sorted key sequence, and a
 writer that sorts every input with the CPU oracle and stores the digests in
 ``fullsize_digests.json`` next to this file.  The GPU tests generate the same
 inputs, sort them with the HIP library and compare digests, so every stored
@@ -17,7 +17,8 @@ The digest is SHA-256 (FIPS 180-4) over the concatenation of the byte count
 (8 bytes, little endian) and the SHA-256 of each consecutive 64 MiB chunk of
 the key bytes; the chunks are hashed in parallel threads.  Key bytes are the
 array itself for u32, u64 and f64 (f64 by its bit pattern), column 0 (the
-u64 key) for Pair, and bytes 0..9 of every record for 100-byte records.
+u64 key) for Pair, bytes 0..9 of every record for 100-byte records, and the
+key words a, b, c (columns 0..2) of every Quartet.
 """
 from __future__ import annotations
 
@@ -49,6 +50,7 @@ def cases() -> list[dict]:
     out += [dict(kind="f64", dist=d, log2n=27, config=3, array=DISTS.index(d)) for d in ("uniform", "exponential")]
     out += [dict(kind="pair", dist=d, log2n=27, config=3, array=DISTS.index(d)) for d in ("uniform", "rootdup")]
     out += [dict(kind="rec100", dist=d, log2n=24, config=3, array=DISTS.index(d)) for d in ("uniform", "rootdup")]
+    out += [dict(kind="quartet", dist="uniform", log2n=27, config=3, array=DISTS.index("uniform"))]
     return out
 
 
@@ -74,6 +76,8 @@ def key_bytes(a: np.ndarray, kind: str) -> memoryview:
         return memoryview(np.ascontiguousarray(a[:, 0])).cast("B")
     if kind == "rec100":
         return memoryview(np.ascontiguousarray(a[:, :10])).cast("B")
+    if kind == "quartet":
+        return memoryview(np.ascontiguousarray(a[:, :3])).cast("B")
     raise ValueError(kind)
 
 

@@ -67,7 +67,7 @@ def test_adaptive_k_against_real_valued_formula():
         assert oracle.adaptive_k(n, k, n0) == max(2, min(k, want)), n
 
 
-KINDS = ["u32", "u64", "f64", "pair", "rec100"]
+KINDS = ["u32", "u64", "f64", "pair", "rec100", "quartet"]
 
 
 def _keys(a, kind):
@@ -78,6 +78,8 @@ def _keys(a, kind):
         return [float(x) for x in a]
     if kind == "pair":
         return [int(x) for x in a[:, 0]]
+    if kind == "quartet":
+        return [tuple(int(v) for v in r[:3]) for r in a]
     return [bytes(r[:10]) for r in a]
 
 
@@ -92,6 +94,8 @@ def _gen(kind, dist, n, seed):
         return synth.gen_f64("uniform" if dist not in ("exponential",) else dist, n, seed)
     if kind == "rec100":
         return synth.gen_rec100("rootdup" if dist == "rootdup" else "uniform", n, seed)
+    if kind == "quartet":
+        return synth.gen_quartet(dist, n, seed)
     if kind == "u32" and dist == "twodup" or kind == "u32" and dist == "eightdup":
         return synth.gen_u32(dist, n, seed)
     return synth.generate(kind, dist, n, seed)
@@ -129,6 +133,8 @@ def _key_list(a, kind):
         return a[:, 0].tolist()
     if kind == "rec100":
         return [bytes(r[:10]) for r in a]
+    if kind == "quartet":
+        return [tuple(int(v) for v in r[:3]) for r in a]
     return a.tolist()
 
 
@@ -142,7 +148,7 @@ def test_sort_brute_force_tiny(kind):
     element with the same key."""
     import bruteforce_cases as bc
     vals = bc.key_values(kind)
-    if kind in ("u32", "u64", "pair", "rec100"):
+    if kind in ("u32", "u64", "pair", "rec100", "quartet"):
         assert vals == sorted(vals)          # library order agrees with the listed order
     else:                                    # the listed doubles follow the golden totalOrder list
         gold = [int(r[0], 16) for r in _lines("f64_total_order.txt")]
@@ -155,8 +161,9 @@ def test_sort_brute_force_tiny(kind):
         want = vals[:n]
         keys = _key_list(out, kind)
         assert all(keys[o:o + n] == want for o in range(0, len(keys), n)), (kind, n)
-        if kind in ("pair", "rec100"):
-            ix = (out[:, 1] if kind == "pair" else out[:, 10:18].copy().view("<u8")[:, 0]).astype(np.int64)
+        if kind in ("pair", "rec100", "quartet"):
+            ix = (out[:, 1] if kind == "pair" else out[:, 3] if kind == "quartet"
+                  else out[:, 10:18].copy().view("<u8")[:, 0]).astype(np.int64)
             assert np.array_equal(np.sort(ix), np.arange(inp.shape[0]))
             assert np.array_equal(out, inp[ix])            # whole records moved intact
             assert all(set(ix[o:o + n] // n) == {o // n} for o in range(0, len(ix), n))
@@ -356,3 +363,15 @@ def test_count_less_matches_searchsorted():
         x = np.array([v], dtype=np.uint64)
         assert oracle.count_less(a, "u64", x) == int(np.searchsorted(s, v, "left"))
         assert oracle.count_less(a, "u64", x, True) == int(np.searchsorted(s, v, "right"))
+
+
+def test_quartet_order_is_lexicographic():
+    """Algorithm 3: a decides, then b, then c; the fourth word is payload."""
+    rng = np.random.default_rng(12)
+    a = rng.integers(0, 4, size=(4000, 4), dtype=np.uint64)   # many ties in every word
+    a[:, 3] = np.arange(4000, dtype=np.uint64)
+    s = oracle.sort(a, "quartet")
+    assert [tuple(r[:3]) for r in s.tolist()] == sorted(tuple(r[:3]) for r in a.tolist())
+    assert np.array_equal(a[s[:, 3].astype(np.int64)], s)
+    big = np.array([[1, 0, 0, 0], [0, 0xFFFFFFFFFFFFFFFF, 0, 1], [0, 0, 0xFFFFFFFFFFFFFFFF, 2]], dtype=np.uint64)
+    assert oracle.sort(big, "quartet")[:, 3].tolist() == [2, 1, 0]
