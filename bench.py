@@ -8,8 +8,11 @@ timed region is exactly K back-to-back sorts bracketed by device
 synchronizations.  Every launch is timed with HIP events on the sort's
 stream (library profiling flag) to give per-level and per-kernel HBM
 rates; the dominant kernel's rate is reported against the 8 TB/s peak.
-The CPU baseline is the oracle's single-threaded merge sort on a 2^24-key
-sample of the same distribution.
+The output of every timed sort is checked on the device (order and a
+multiset fingerprint), and the first copy's sorted keys against the
+oracle's digest of the same input (tests/golden/fullsize_digests.json).
+The CPU baseline is the oracle's single-threaded merge sort on a bounded
+sample (the first 2^25 keys) of the same input.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -43,11 +46,12 @@ def main() -> int:
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-radix", action="store_true", help="skip the radix-path measurement")
-    ap.add_argument("--workload", default="sort", choices=["sort", "batch", "serve", "sweep"],
+    ap.add_argument("--workload", default="sort", choices=["sort", "batch", "serve", "sweep", "oop"],
                     help="sort: one 2^28-key array (default); batch: 4096 arrays of 2^8..2^22 keys; "
                          "serve: a Poisson trace of mixed-type requests of 2^10..2^26 elements; "
                          "sweep: every generator at 2^28 for u64 and u32, and the wider elements "
-                         "(f64 and Pair at 2^27, 100-byte records at 2^24)")
+                         "(f64 and Pair at 2^27, 100-byte records at 2^24); "
+                         "oop: the out-of-place partitioning step (ablation) against the in-place one")
     ap.add_argument("--arrays", type=int, default=4096, help="batch: number of arrays")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
@@ -57,9 +61,13 @@ def main() -> int:
                     help="turn four rocprofv3 --pmc output folders into the traffic summary (markdown)")
     ap.add_argument("--kernel-stats-summary", metavar="CSV",
                     help="print a rocprofv3 kernel_stats.csv as a markdown table")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="turn rocprofv3 --pmc output folders into a per-kernel counter table (markdown)")
     args = ap.parse_args()
     if args.kernel_stats_summary:
         return kernel_stats_summary(args.kernel_stats_summary)
+    if args.counter_summary:
+        return counter_summary(args.counter_summary)
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary)
     if args.calib_copy:
@@ -74,6 +82,8 @@ def main() -> int:
         return bench_serve(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "oop":
+        return bench_oop(args)
 
     import numpy as np
     import torch
@@ -86,7 +96,7 @@ def main() -> int:
     D = ips.ELEM_BYTES[kind]
     log(f"generating {kind} {args.dist} n=2^{args.log2n}")
     t0 = time.time()
-    host = synth.generate(kind, args.dist, n, synth.seed_for(2, 0))
+    host = synth.generate(kind, args.dist, n, synth.seed_for(2, SWEEP_DISTS.index(args.dist)))
     log(f"  {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     pristine = torch.from_numpy(host).to(dev)
@@ -97,6 +107,11 @@ def main() -> int:
     params = ips.make_params(flags=prof_flags)
     ws = sorter.workspace(ips.workspace_bytes(n, kind, "samplesort", sorter.params_for(n, kind, params=params)))
     log(f"workspace {ws.numel() / 2**20:.1f} MiB for {n * D / 2**30:.2f} GiB of data")
+    tp = sorter.params_for(n, kind, params=ips.make_params())
+    cap = tp.lds_task_max or ips.LDS_CAP[kind]
+    run_params = {"k": tp.k or 256, "block_bytes": tp.block_bytes or "LDS budget / buckets",
+                  "n0": tp.n0, "lds_task_max": cap, "piece_blocks": tp.piece_blocks or 1024,
+                  "perm_groups": tp.perm_groups or 131072}
 
     # Warmup steps, timing every kernel, pick the dominant kernel.
     prof_all = ips.make_params(flags=ips.FLAG_PROFILE)
@@ -138,6 +153,17 @@ def main() -> int:
         assert bool((v[1:] >= v[:-1]).all()), "output not sorted"
         assert int(c.view(torch.int64).sum() if kind == "u64" else c.view(torch.int32).to(torch.int64).sum()) == \
             int(ref_sum if kind == "u64" else pristine.view(torch.int32).to(torch.int64).sum()), "multiset changed"
+    gold, fsmod = _golden_digests()
+    gcase = (gold or {}).get(f"{kind}-{args.dist}-2p{args.log2n}")
+
+    def digest_equal(t):
+        if gcase is None:
+            return None
+        h = np.ascontiguousarray(t.cpu().numpy())
+        ok = fsmod.digest(memoryview(h).cast("B"), threads=16) == gcase["digest"]
+        assert ok, "sorted keys differ from the oracle's"
+        return ok
+    parity = {"samplesort": digest_equal(copies[0])}
 
     # Per level, from two more sorts (outside the timed region) that time
     # every kernel: algorithmic bytes 4 D n' per partitioning level
@@ -204,23 +230,25 @@ def main() -> int:
         v = copies[0].view(torch.int64) ^ sign if kind == "u64" else None
         if v is not None:
             assert bool((v[1:] >= v[:-1]).all()), "radix output not sorted"
+        parity["radix"] = digest_equal(copies[0])
 
     cpu = None
     if not args.no_cpu:
-        import numpy as np
-
         import oracle
-        ns = 1 << 24
-        sample = synth.generate(kind, args.dist, ns, synth.seed_for(2, 0))
+        # A bounded sample of the same input (its first 2^25 keys, about 10 s
+        # of single-threaded work per run), two runs.
+        ns = min(n, 1 << 25)
+        sample = np.ascontiguousarray(host[:ns])
         times = []
-        for r in range(4):
+        for r in range(2):
             t0 = time.perf_counter()
             oracle.sort(sample, kind)
             times.append(time.perf_counter() - t0)
-        med = float(np.median(times[1:]))
-        cpu = {"value": round(ns / med / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"2^24 {kind} {args.dist} keys, single-threaded merge sort, 4 runs, first dropped, "
-                         f"median {med:.2f} s"}
+        mean = sum(times) / len(times)
+        cpu = {"value": round(ns / mean / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "host_cores": os.cpu_count(),
+               "sample": f"the first 2^{ns.bit_length() - 1} keys of the benchmark's {kind} {args.dist} input, "
+                         f"the oracle's single-threaded merge sort, 2 runs, mean {mean:.2f} s"}
         log(f"cpu oracle: {cpu['value']} Gkeys/s")
 
     out = {
@@ -236,13 +264,18 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": kind,
         "data": "synthetic: SplitMix64-seeded keys, resident in HBM before the timed region",
-        "config": {"workload": f"{kind} {args.dist} n=2^{args.log2n}, IPS4o samplesort (k=256, n0=16)",
+        "config": {"workload": f"{kind} {args.dist} n=2^{args.log2n}, IPS4o samplesort: at most "
+                               f"{run_params['k']} buckets per step, buckets of at most {cap} keys sorted "
+                               f"in the LDS tier (no n0 insertion-sort base case: k' is the smallest power "
+                               f"of two giving mean buckets of at most {cap // 4} keys), blocks sized for one "
+                               f"LDS buffer block per bucket",
                    "n": n, "kind": kind, "algo": "samplesort", "dist": args.dist,
-                   "workspace_bytes": int(ws.numel())},
+                   "params": run_params, "workspace_bytes": int(ws.numel())},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "levels": levels,
         "radix": radix,
+        "oracle_digest_equal": parity,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -361,6 +394,60 @@ def traffic_summary(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_writ
     return 0
 
 
+CU_NUM = 256
+XCD_NUM = 8
+
+
+def counter_summary(folders: list) -> int:
+    """Per kernel (sort kernels of KERNEL_NAMES), the mean of every counter
+    per dispatch over the rocprofv3 --pmc folders given, and the ratios that
+    say what bounds the kernel: resident waves per CU (4 SQ_WAVE_CYCLES per
+    GUI-active cycle and CU), the fraction of wave time spent waiting for
+    memory (SQ_WAIT_ANY) or for an instruction dependency (SQ_WAIT_INST_ANY),
+    memory instructions per wave, L2 hit rate and atomics per dispatch."""
+    per = {}
+    for folder in folders:
+        for r in _pmc_rows(folder):
+            for short, pat in KERNEL_NAMES.items():
+                if pat in r["Kernel_Name"]:
+                    key = (short, r["Counter_Name"])
+                    per.setdefault(key, {}).setdefault((folder, r.get("Dispatch_Id", r.get("Correlation_Id"))), 0.0)
+                    per[key][(folder, r.get("Dispatch_Id", r.get("Correlation_Id")))] += float(r["Counter_Value"])
+    kernels = sorted({k for k, _ in per}, key=list(KERNEL_NAMES).index)
+    counters = sorted({c for _, c in per})
+    mean = {(k, c): sum(v.values()) / len(v) for (k, c), v in per.items()}
+    disp = {k: max(len(v) for (kk, _), v in per.items() if kk == k) for k in kernels}
+    lines = ["| counter (mean per dispatch) | " + " | ".join(kernels) + " |",
+             "|---|" + "---|" * len(kernels)]
+    lines.append("| dispatches | " + " | ".join(str(disp[k]) for k in kernels) + " |")
+    for c in counters:
+        lines.append(f"| {c} | " + " | ".join(f"{mean[(k, c)]:.4g}" if (k, c) in mean else "-" for k in kernels) + " |")
+
+    def ratio(k, a, b, scale=1.0):
+        if (k, a) in mean and (k, b) in mean and mean[(k, b)]:
+            return f"{scale * mean[(k, a)] / mean[(k, b)]:.3g}"
+        return "-"
+    # SQ_WAVE_CYCLES counts wave-cycles in units of four cycles, and rocprofv3
+    # reports GRBM_GUI_ACTIVE summed over the XCDs (8 on this part), so the
+    # mean number of resident waves per CU is 4 * 8 * SQ_WAVE_CYCLES /
+    # (GRBM_GUI_ACTIVE * CU_NUM).
+    derived = [("resident waves per CU (of 32)",
+                lambda k: ratio(k, "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE", 4.0 * XCD_NUM / CU_NUM)),
+               ("wave time waiting for memory", lambda k: ratio(k, "SQ_WAIT_ANY", "SQ_WAVE_CYCLES")),
+               ("wave time waiting on a dependency", lambda k: ratio(k, "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")),
+               ("vector memory reads per wave", lambda k: ratio(k, "SQ_INSTS_VMEM_RD", "SQ_WAVES")),
+               ("vector memory writes per wave", lambda k: ratio(k, "SQ_INSTS_VMEM_WR", "SQ_WAVES")),
+               ("LDS bank-conflict cycles per LDS instruction", lambda k: ratio(k, "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS")),
+               ("L2 hits / (hits + misses)", lambda k: (
+                   f"{mean[(k, 'TCC_HIT_sum')] / (mean[(k, 'TCC_HIT_sum')] + mean[(k, 'TCC_MISS_sum')]):.3g}"
+                   if (k, "TCC_HIT_sum") in mean and (k, "TCC_MISS_sum") in mean else "-"))]
+    lines += ["", "| derived | " + " | ".join(kernels) + " |", "|---|" + "---|" * len(kernels)]
+    for name, f in derived:
+        lines.append(f"| {name} | " + " | ".join(f(k) for k in kernels) + " |")
+    print("\n".join(lines))
+    return 0
+
+
 def kernel_stats_summary(csv_path: str) -> int:
     """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
     import csv
@@ -430,6 +517,10 @@ def _sorted_and_fingerprint(t, kind):
     if kind == "pair":
         v = t[:, 0] ^ (-(1 << 63))
         return bool((v[1:] >= v[:-1]).all()), int(t.sum())
+    if kind == "quartet":     # (a, b, c) lexicographic
+        a, b, c = (t[:, i] ^ (-(1 << 63)) for i in range(3))
+        ok = (a[1:] > a[:-1]) | ((a[1:] == a[:-1]) & ((b[1:] > b[:-1]) | ((b[1:] == b[:-1]) & (c[1:] >= c[:-1]))))
+        return bool(ok.all()), int(t.sum())
     # 100-byte records: key bytes 0..9, unsigned lexicographic
     b = t[:, :10].to(torch.int64)
     hi = torch.zeros(t.shape[0], dtype=torch.int64, device=t.device)
@@ -441,13 +532,32 @@ def _sorted_and_fingerprint(t, kind):
     return bool(ok.all()), int(t.view(torch.int32).to(torch.int64).sum())
 
 
+def _golden_digests():
+    """The oracle's digests of the full-size inputs (written by
+    tests/golden/fullsize.py from the oracle alone) and that module's digest
+    function, or (None, None) when the file is absent."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "fullsize.py")
+    if not os.path.exists(path):
+        return None, None
+    spec = importlib.util.spec_from_file_location("fullsize_golden", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not os.path.exists(mod.OUT):
+        return None, None
+    with open(mod.OUT) as f:
+        return json.load(f)["cases"], mod
+
+
 def bench_sweep(args) -> int:
     """Every generator at n = 2^28 for u64 and u32 keys (samplesort and
     IPS2Ra), then the wider elements: f64 (Uniform, Exponential) and Pair
-    (Uniform, RootDup) at 2^27, 100-byte records (Uniform and RootDup keys) at
-    2^24.  Each case: one warmup and `steps` sorts of a pristine device copy
-    (the copy untimed), timed with HIP events; the output is checked on the
-    device (key order and an unchanged fingerprint)."""
+    (Uniform, RootDup) at 2^27 with both algorithms, Quartets (Uniform) at
+    2^27, 100-byte records (Uniform and RootDup keys) at 2^24.  Each case: one
+    warmup and `steps` sorts of a pristine device copy (the copy untimed),
+    timed with HIP events; the output is checked on the device (key order and
+    an unchanged fingerprint) and, where the oracle's digest of the same
+    input exists, the digest of the sorted keys must equal it."""
     import torch
 
     import paper_2009_13569_amd as ips
@@ -457,20 +567,22 @@ def bench_sweep(args) -> int:
     dev = torch.device("cuda:0")
     steps = max(1, min(args.steps, 5))
     cases = [(k, d, 28, a) for k in ("u64", "u32") for d in SWEEP_DISTS for a in ("samplesort", "radix")]
-    cases += [("f64", "uniform", 27, "samplesort"), ("f64", "exponential", 27, "samplesort"),
-              ("pair", "uniform", 27, "samplesort"), ("pair", "rootdup", 27, "samplesort"),
-              ("pair", "uniform", 27, "radix"), ("pair", "rootdup", 27, "radix"),
+    cases += [(k, d, 27, a) for k, d in (("f64", "uniform"), ("f64", "exponential"), ("pair", "uniform"),
+                                          ("pair", "rootdup")) for a in ("samplesort", "radix")]
+    cases += [("quartet", "uniform", 27, "samplesort"),
               ("rec100", "uniform", 24, "samplesort"), ("rec100", "rootdup", 24, "samplesort")]
+    gold, fsmod = _golden_digests()
     sorter = ips.Sorter(0)
     rows = []
     for kind, dist, lg, algo in cases:
         n = 1 << lg
         seed = synth.seed_for(2 if lg == 28 else 3, SWEEP_DISTS.index(dist))
-        if kind == "rec100":
-            src = torch.from_numpy(synth.gen_rec100(dist, n, seed)).to(dev)
+        if kind in ("rec100", "quartet") or (kind == "f64" and dist != "uniform"):
+            # host generators (f64 Exponential takes the host's log1p, as the oracle's input does)
+            src = torch.from_numpy(synth.generate(kind, dist, n, seed)).to(dev)
         else:
             src = sd.generate(kind, dist, n, seed, dev)
-        _, fp = _sorted_and_fingerprint(src, kind) if kind in ("u32", "u64", "f64", "pair") else (None, None)
+        _, fp = _sorted_and_fingerprint(src, kind) if kind != "rec100" else (None, None)
         if fp is None:
             fp = int(src.view(torch.int32).to(torch.int64).sum())
         work = torch.empty_like(src)
@@ -489,9 +601,18 @@ def bench_sweep(args) -> int:
         assert ok and fp2 == fp, f"{kind} {dist} 2^{lg} {algo}: output not sorted or multiset changed"
         ms = float(np.median(times))
         st = sorter.stats()
+        g = (gold or {}).get(f"{kind}-{dist}-2p{lg}")
+        digest_ok = None
+        if g is not None:
+            key = {"pair": lambda: work[:, 0], "rec100": lambda: work[:, :10],
+                   "quartet": lambda: work[:, :3]}.get(kind, lambda: work)()
+            host = np.ascontiguousarray(key.contiguous().cpu().numpy())
+            digest_ok = fsmod.digest(memoryview(host).cast("B"), threads=16) == g["digest"]
+            assert digest_ok, f"{kind} {dist} 2^{lg} {algo}: sorted keys differ from the oracle's"
+            del host
         row = {"kind": kind, "dist": dist, "log2n": lg, "algo": algo, "ms": round(ms, 3),
                "Gelems_per_s": round(n / (ms * 1e-3) / 1e9, 2), "levels": int(st.levels),
-               "detected": int(st.detected)}
+               "detected": int(st.detected), "oracle_digest_equal": digest_ok}
         rows.append(row)
         log(f"{kind:6s} {dist:13s} 2^{lg} {algo:10s} {ms:8.3f} ms {row['Gelems_per_s']:7.2f} Gelem/s "
             f"levels {row['levels']}")
@@ -509,6 +630,80 @@ def bench_sweep(args) -> int:
                                   "2^27; 100-byte records at 2^24)"},
            "cases": rows}
     print(json.dumps(out))
+    return 0
+
+
+def bench_oop(args) -> int:
+    """The paper's in-place partitioning step against super scalar
+    samplesort's out-of-place one (oracle array, distribution into a second
+    array) on the same input (u64 Uniform 2^28 by default), with the same
+    sampling, tree and LDS-tier base case: whole-sort time over `steps`
+    sorts of pristine copies (HIP events), and per level the partitioning
+    kernels' time (library profiling, one extra sort each) beside the
+    algorithmic bytes of the level: 4 D n' in place, (3 D + 2 o) n' out of
+    place (o = 1-byte oracle entries with at most 256 buckets, 2 above)."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+
+    n = 1 << args.log2n
+    kind = args.kind
+    D = ips.ELEM_BYTES[kind]
+    dev = torch.device("cuda:0")
+    src = sd.generate(kind, args.dist, n, synth.seed_for(2, 0), dev)
+    work = torch.empty_like(src)
+    tmp = torch.empty(2 * n * D + (1 << 20), dtype=torch.uint8, device=dev)   # second array + oracle
+    sorter = ips.Sorter(0)
+    steps = max(1, args.steps)
+    res = {}
+    for name in ("in_place", "out_of_place"):
+        def run(params=None):
+            if name == "in_place":
+                sorter.sort_(work, kind=kind, params=params)
+            else:
+                sorter.sort_oop_(work, kind=kind, params=params, tmp=tmp)
+        work.copy_(src)
+        run()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            work.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ok, _ = _sorted_and_fingerprint(work, kind)
+        assert ok, f"{name}: output not sorted"
+        work.copy_(src)
+        run(ips.make_params(flags=ips.FLAG_PROFILE | (ips.FLAG_NO_SORTED_CHECK if name == "in_place" else 0)))
+        torch.cuda.synchronize()
+        levels = []
+        for row, ph in sorted((k, v) for k, v in sorter.profile().items() if k != "outside"):
+            part = {p: round(v[0], 4) for p, v in ph.items() if p != "lds_sort"}
+            el = ph.get("classify", (0, 0, 0))[1]
+            ms = sum(part.values())
+            if not el:
+                continue
+            alg = 4 * D * el if name == "in_place" else (3 * D + 2) * el
+            levels.append({"level": row, "elems": int(el), "partition_ms": round(ms, 4), "kernels_ms": part,
+                           "algorithmic_bytes": int(alg), "GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+                           "lds_ms": round(ph.get("lds_sort", (0, 0, 0))[0], 4)})
+        res[name] = {"ms_per_sort": round(float(np.median(times)), 3),
+                     "Gkeys_per_s": round(n / (float(np.median(times)) * 1e-3) / 1e9, 2), "levels": levels}
+        log(f"{name}: {res[name]['ms_per_sort']} ms/sort; levels " +
+            ", ".join(f"{x['level']}: {x['partition_ms']} ms {x['GBps']} GB/s" for x in levels))
+    out = {"metric": f"ms per sort, {kind} {args.dist} n=2^{args.log2n}, out-of-place partitioning step (ablation)",
+           "value": res["out_of_place"]["ms_per_sort"], "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": 1,
+           "ms_per_step": res["out_of_place"]["ms_per_sort"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": kind, "data": "synthetic: SplitMix64-seeded keys resident in HBM",
+           "config": {"workload": f"{kind} {args.dist} n=2^{args.log2n}: in-place IPS4o step vs super scalar "
+                                  f"samplesort's out-of-place step, same tree and base case"},
+           "runs": res}
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -542,7 +737,10 @@ def bench_batch(args) -> int:
     res = {}
     gstream = torch.cuda.Stream()
     gparams = ips.make_params(flags=ips.FLAG_GRAPH)
-    for mode in ("batched", "batched_graph", "per_array"):
+    untuned = ips.Sorter(0, tuning=None)
+    ws0 = untuned.workspace(ips.segments_workspace_bytes(total, segs, nseg, "u64", "samplesort",
+                                                         untuned.params_for(total, "u64", batched=True)))
+    for mode in ("batched", "batched_defaults", "batched_graph", "per_array"):
         times = []
         for step in range(args.warmup + args.steps):
             work.copy_(pristine)
@@ -550,6 +748,8 @@ def bench_batch(args) -> int:
             t0 = time.perf_counter()
             if mode == "batched":
                 sorter.sort_segments_(work, offs.tolist(), sizes.tolist(), kind="u64", ws=ws)
+            elif mode == "batched_defaults":   # the library defaults instead of the tuning table
+                untuned.sort_segments_(work, offs.tolist(), sizes.tolist(), kind="u64", ws=ws0)
             elif mode == "batched_graph":   # steps replayed from a captured HIP graph
                 with torch.cuda.stream(gstream):
                     sorter.sort_segments_(work, offs.tolist(), sizes.tolist(), params=gparams, kind="u64",
@@ -574,6 +774,7 @@ def bench_batch(args) -> int:
         "config": {"workload": f"{len(sizes)} u64 arrays, log-uniform sizes in [2^8, 2^22], "
                                f"Uniform/TwoDup/AlmostSorted", "keys": total},
         "graph_replay": res["batched_graph"],
+        "untuned_defaults": res["batched_defaults"],
         "per_array_calls": res["per_array"],
         "tuning": [e for e in sorter.tuning if e.get("batched")],
         "speedup_vs_per_array": round(res["per_array"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
@@ -587,7 +788,10 @@ def bench_serve(args) -> int:
     element type uniform over u32/u64/f64/Pair, distribution uniform over
     the paper's ten), data resident in HBM at arrival; continuous batching
     under an HBM budget against one call per request, at offered loads
-    0.5 and 0.8 of the per-request service rate."""
+    0.5, 0.8 and 2.0 (saturated) of the per-request service rate.  Latency
+    runs from a request's arrival to the host seeing it finished;
+    throughput is all elements over the time from the first arrival to the
+    last completion."""
     import torch
 
     import paper_2009_13569_amd as ips
@@ -628,7 +832,7 @@ def bench_serve(args) -> int:
     mean_svc = float(svc.mean())
     log(f"mean service time alone {mean_svc * 1e3:.3f} ms (total {svc.sum():.2f} s)")
     out_runs = {}
-    for rho in (0.5, 0.8):
+    for rho in (0.5, 0.8, 2.0):   # 2.0: arrivals faster than one call per request can serve
         rate = rho / mean_svc
         arr = synth.poisson_arrivals(N, rate, synth.seed_for(5, 1))
         arr -= arr[0]
@@ -657,11 +861,12 @@ def bench_serve(args) -> int:
                     w = v.to(torch.int64) ^ (-(1 << 63)) if k != "u32" else v.to(torch.int64) & 0xFFFFFFFF
                     assert bool((w[1:] >= w[:-1]).all())
             lat = np.array([r["done_s"] - a for r, a in zip(res, arr)])
-            span = max(r["done_s"] for r in res)
+            span = max(r["done_s"] for r in res)   # from the first arrival (time 0) to the last completion
             key = f"rho{rho}_{name}"
             out_runs[key] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
                              "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
                              "Gelems_per_s": round(int(sizes.sum()) / span / 1e9, 3),
+                             "makespan_s": round(span, 4),
                              "batches": len({r["batch"] for r in res})}
             log(f"{key}: {out_runs[key]}")
     best = out_runs["rho0.8_batched"]

@@ -66,13 +66,15 @@ extern "C" {
  * -0.0 < +0.0 and NaNs sort to the ends by sign).  Records (Section 7 of the
  * paper): IPS_PAIR_U64_U64 is 16 bytes, a u64 key at byte 0 and a u64 value
  * at byte 8; IPS_REC100 is 100 bytes whose key is bytes 0..9 compared
- * lexicographically as unsigned bytes (memcmp order, Algorithm 4). */
+ * lexicographically as unsigned bytes (memcmp order, Algorithm 4);
+ * IPS_QUARTET is 32 bytes, three u64 key words a, b, c at bytes 0, 8, 16
+ * compared lexicographically (Algorithm 3) and a u64 value at byte 24. */
 typedef enum { IPS_U32 = 1, IPS_U64 = 2, IPS_F64 = 3 } ips_key_type;
-typedef enum { IPS_PAIR_U64_U64 = 4, IPS_REC100 = 5 } ips_rec_type;
+typedef enum { IPS_PAIR_U64_U64 = 4, IPS_REC100 = 5, IPS_QUARTET = 6 } ips_rec_type;
 
 /* IPS_SAMPLESORT: IPS4o.  IPS_RADIX: IPS2Ra (unsigned integer keys; the
  * f64 key is mapped to its order-preserving unsigned image; not available
- * for IPS_REC100). */
+ * for IPS_REC100 and IPS_QUARTET). */
 typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
 
 /* Flags of ips_params. */
@@ -118,6 +120,8 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *  seed         seed of the sampling stream (default 0)
  *  perm_groups  target number of block-permutation groups (swap buffers) per
  *               batch (default 131072)
+ *  perm_wg      workgroup size of the block permutation: 128, 256 or 512
+ *               threads (default 256)
  *  profile_mask with IPS_FLAG_PROFILE: bit (1 << IPS_PH_x) selects the phases
  *               whose launches are timed (0 = all phases).  Every timed
  *               launch adds two event records to the stream.
@@ -132,7 +136,8 @@ typedef struct {
   uint64_t seed;
   uint32_t perm_groups;
   uint32_t profile_mask;
-  uint32_t reserved[2];
+  uint32_t perm_wg;
+  uint32_t reserved;   /* must be 0 */
 } ips_params;
 
 typedef struct ips_ctx ips_ctx;
@@ -150,7 +155,7 @@ int ips_ctx_create(ips_ctx** out, int device);
 /* Destroy a context (NULL is accepted). */
 int ips_ctx_destroy(ips_ctx* ctx);
 
-/* Workspace bytes needed to sort n elements of `elem_type` (1..5) with
+/* Workspace bytes needed to sort n elements of `elem_type` (1..6) with
  * `algo` and `params` (nullable).  Pure host computation, no HIP call.
  * The size is O(k * b) per workgroup of the largest batch plus O(n / b)
  * words of block flags.  Errors: IPS_E_INVALID_ARG, IPS_E_UNSUPPORTED,
@@ -191,6 +196,28 @@ int ips_sort_keys(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type,
 int ips_sort_keys_noalloc(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, int algo,
                           const ips_params* params, void* stream);
 
+/* Out-of-place ablation: the partitioning step of super scalar samplesort
+ * (Sanders and Winkel), which the paper re-implements on its framework
+ * (Section 7) and compares with its in-place step by I/O volume (appendix,
+ * "Comparing the I/O Volume"), run with the same sampling, decision tree,
+ * start table and LDS-tier base case as ips_sort_keys/ips_sort_pairs with
+ * IPS_SAMPLESORT.  Each level classifies every element into an oracle
+ * array (one byte per element, two when a step has more than 256 buckets),
+ * sums the bucket sizes, and distributes the elements into the other of
+ * two arrays; a level moves 3 D + 2 o bytes per element instead of 4 D.
+ * The sorted result ends in d_data.  It needs a second device buffer d_tmp
+ * of tmp_bytes (the element array plus the oracle, 256-byte aligned, owned
+ * by the caller, contents garbage afterwards) besides the workspace; both
+ * sizes come from ips_oop_workspace_bytes.  elem_type is any of 1..6; no
+ * sorted-input detection; IPS_FLAG_LEVEL1_ONLY, IPS_FLAG_GRAPH,
+ * IPS_FLAG_HOST_PLAN and IPS_FLAG_GLOBAL_BUFFERS are rejected.  n must be
+ * below 2^32.  Errors: as ips_sort_keys; IPS_E_WORKSPACE also for a short
+ * d_tmp. */
+int ips_oop_workspace_bytes(uint64_t n, int elem_type, const ips_params* params, size_t* ws_bytes,
+                            size_t* tmp_bytes);
+int ips_sort_oop(ips_ctx* ctx, void* d_data, uint64_t n, int elem_type, void* d_tmp, size_t tmp_bytes,
+                 void* d_ws, size_t ws_bytes, const ips_params* params, void* stream);
+
 /* Sort n records in place at device pointer d_recs (array of structures).
  * Records move as whole records; only the key is compared. */
 int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type,
@@ -214,7 +241,7 @@ int ips_segments_workspace_bytes(uint64_t n_total, const ips_segment* segs,
 /* Sort each of nseg segments of one device array independently, in place,
  * in one call (batched sorting of many arrays; the paper's problem of
  * Section 2 applied to every segment).  d_data holds n_total elements of
- * elem_type (1..5, keys or records); segs is a HOST array of nseg
+ * elem_type (1..6, keys or records); segs is a HOST array of nseg
  * non-overlapping segments (read during the call only); elements outside
  * every segment are left unchanged.  All segments' partitioning steps of one
  * recursion level run in shared launches (Section 4.2 breadth first);
@@ -301,7 +328,8 @@ int ips_serve_trace(ips_ctx* ctx, ips_request* reqs, uint32_t nreq,
  * buckets), nb (buckets: K, or 2K with equality buckets), splitters[0..K-1]
  * stored as keys (u32 keys widened to u64; f64 as the raw double bits; the
  * 100-byte record key as bytes 0..9 in the first ten bytes of the 16-byte
- * slot).  For IPS_RADIX: radix_shift and radix_width of the root digit.
+ * slot; the Quartet's first two key words a, b, its third word c not
+ * reported).  For IPS_RADIX: radix_shift and radix_width of the root digit.
  * bucket_start[0..nb] are the bucket boundaries (elements) after the step.
  * valid is 0 when the last sort had no root partitioning step (n small,
  * sorted input). */
@@ -360,7 +388,7 @@ int ips_get_profile(ips_ctx* ctx, ips_profile* out);
  * Python package from timings on the GPU; the library stores none.
  * A zero field means "no tuned value" (the default applies). */
 typedef struct {
-  int32_t elem_type;      /* IPS_U32 .. IPS_REC100 */
+  int32_t elem_type;      /* IPS_U32 .. IPS_QUARTET */
   int32_t algo;           /* IPS_SAMPLESORT or IPS_RADIX */
   uint32_t log2n_min;     /* size classes [log2n_min, log2n_max] */
   uint32_t log2n_max;
@@ -371,12 +399,12 @@ typedef struct {
   uint32_t lds_task_max;  /* selects which of the LDS tier's workgroup shapes run */
   uint32_t piece_blocks;
   uint32_t perm_groups;
-  uint32_t reserved;
+  uint32_t perm_wg;       /* workgroup size of the block permutation */
 } ips_tune_entry;
 
 /* Parameters for one call from a tuning table: *out = *base (zeroed when
  * base is NULL), then every field of *out that is zero and tunable (k,
- * block_bytes, n0, lds_task_max, piece_blocks, perm_groups) takes the value
+ * block_bytes, n0, lds_task_max, piece_blocks, perm_groups, perm_wg) takes the value
  * of the first entry of table[0, count) that matches elem_type, algo,
  * batched and floor(log2 n) (n >= 1).  Fields the caller set are kept; flags,
  * seed and profile_mask are never changed.  Pass the same *out to the

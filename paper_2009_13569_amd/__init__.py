@@ -26,8 +26,10 @@ IPS_OK = 0
 STATUS = {0: "IPS_OK", -1: "IPS_E_INVALID_ARG", -2: "IPS_E_UNSUPPORTED", -3: "IPS_E_WORKSPACE",
           -4: "IPS_E_MISALIGNED", -5: "IPS_E_TOO_LARGE", -6: "IPS_E_HIP", -7: "IPS_E_DEVICE",
           -8: "IPS_E_NO_DEVICE", -9: "IPS_E_SCRATCH"}
-TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5}
-ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100}
+TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5, "quartet": 6}
+ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100, "quartet": 32}
+# Largest task the LDS tier sorts by default (elements), per element kind.
+LDS_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
 ALGOS = {"samplesort": 0, "radix": 1}
 FLAG_NO_SORTED_CHECK = 0x1
 FLAG_EQ_ON = 0x2
@@ -46,7 +48,7 @@ EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_batch_workspace_bytes", "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace",
            "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
            "ips_last_device_error", "ips_status_string", "ips_abi_version", "ips_tuned_params",
-           "ips_sort_keys_noalloc"]
+           "ips_sort_keys_noalloc", "ips_oop_workspace_bytes", "ips_sort_oop"]
 SERVE_BATCH = 0
 SERVE_FIFO = 1
 
@@ -56,7 +58,7 @@ class Params(ctypes.Structure):
                 ("lds_task_max", ctypes.c_uint32), ("piece_blocks", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("perm_groups", ctypes.c_uint32), ("profile_mask", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("perm_wg", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class RootInfo(ctypes.Structure):
@@ -78,10 +80,10 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("elem_type", ctypes.c_int32), ("algo", ctypes.c_int32), ("log2n_min", ctypes.c_uint32),
                 ("log2n_max", ctypes.c_uint32), ("batched", ctypes.c_uint32), ("k", ctypes.c_uint32),
                 ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32), ("lds_task_max", ctypes.c_uint32),
-                ("piece_blocks", ctypes.c_uint32), ("perm_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("piece_blocks", ctypes.c_uint32), ("perm_groups", ctypes.c_uint32), ("perm_wg", ctypes.c_uint32)]
 
 
-TUNE_FIELDS = ("k", "block_bytes", "n0", "lds_task_max", "piece_blocks", "perm_groups")
+TUNE_FIELDS = ("k", "block_bytes", "n0", "lds_task_max", "piece_blocks", "perm_groups", "perm_wg")
 # The table written by `python -m paper_2009_13569_amd.tune` (loaded by Sorter).
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -115,6 +117,8 @@ _lib.ips_workspace_bytes.argtypes = [_u64, _i32, _i32, ctypes.POINTER(Params), c
 _lib.ips_sort_keys.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_sort_pairs.argtypes = [_vp, _vp, _u64, _i32, _i32, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_sort_keys_noalloc.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Params), _vp]
+_lib.ips_oop_workspace_bytes.argtypes = [_u64, _i32, ctypes.POINTER(Params), ctypes.POINTER(_sz), ctypes.POINTER(_sz)]
+_lib.ips_sort_oop.argtypes = [_vp, _vp, _u64, _i32, _vp, _sz, _vp, _sz, ctypes.POINTER(Params), _vp]
 _lib.ips_segments_workspace_bytes.argtypes = [_u64, ctypes.POINTER(Segment), ctypes.c_uint32, _i32, _i32,
                                               ctypes.POINTER(Params), ctypes.POINTER(_sz)]
 _lib.ips_sort_segments.argtypes = [_vp, _vp, _u64, _i32, _i32, ctypes.POINTER(Segment), ctypes.c_uint32,
@@ -140,7 +144,8 @@ for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments", "ips_batch_workspace_bytes",
            "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace", "ips_get_root_info",
            "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
-           "ips_abi_version", "ips_tuned_params", "ips_sort_keys_noalloc"):
+           "ips_abi_version", "ips_tuned_params", "ips_sort_keys_noalloc", "ips_oop_workspace_bytes",
+           "ips_sort_oop"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -156,11 +161,11 @@ def lib() -> ctypes.CDLL:
 
 
 def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0,
-                perm_groups=0, profile_phases=None) -> Params:
+                perm_groups=0, profile_phases=None, perm_wg=0) -> Params:
     """profile_phases: names from PHASES to time with FLAG_PROFILE (None: all)."""
     p = Params()
     p.k, p.block_bytes, p.n0, p.lds_task_max, p.piece_blocks = k, block_bytes, n0, lds_task_max, piece_blocks
-    p.flags, p.seed, p.perm_groups = flags, seed, perm_groups
+    p.flags, p.seed, p.perm_groups, p.perm_wg = flags, seed, perm_groups, perm_wg
     p.profile_mask = 0 if profile_phases is None else sum(1 << PHASES.index(x) for x in profile_phases)
     return p
 
@@ -232,13 +237,15 @@ def tuned_params(table, count: int, n: int, kind: str, algo: str = "samplesort",
 
 def kind_of(t) -> str:
     """Element kind of a torch tensor: 1-D uint32/uint64/float64 keys, (n, 2)
-    64-bit pairs, or (n, 100) uint8 records."""
+    64-bit pairs, (n, 4) 64-bit Quartets, or (n, 100) uint8 records."""
     import torch
     if t.dim() == 1:
         return {torch.uint32: "u32", torch.int32: "u32", torch.uint64: "u64", torch.int64: "u64",
                 torch.float64: "f64"}[t.dtype]
     if t.dim() == 2 and t.shape[1] == 2 and t.dtype in (torch.uint64, torch.int64):
         return "pair"
+    if t.dim() == 2 and t.shape[1] == 4 and t.dtype in (torch.uint64, torch.int64):
+        return "quartet"
     if t.dim() == 2 and t.shape[1] == 100 and t.dtype == torch.uint8:
         return "rec100"
     raise TypeError(f"unsupported tensor {tuple(t.shape)} {t.dtype}")
@@ -335,6 +342,34 @@ class Sorter:
         if rc != IPS_OK:
             raise IpsError(rc, "ips_sort_keys_noalloc", f"(hip={_lib.ips_last_hip_error(self._h)}, "
                                                         f"device={hex(_lib.ips_last_device_error(self._h))})")
+        return t
+
+    def sort_oop_(self, t, params: Params | None = None, kind: str | None = None, stream=None, tmp=None):
+        """Sort tensor `t` with the out-of-place partitioning step (the
+        ablation ips_sort_oop); the result ends in `t`.  `tmp`: a uint8 device
+        tensor of at least the second-array bytes (allocated when None)."""
+        import torch
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensor must be a contiguous GPU tensor")
+        kind = kind or kind_of(t)
+        n = t.shape[0]
+        if params is None:
+            params = Params()
+        wsb, tmpb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        rc = _lib.ips_oop_workspace_bytes(n, TYPES[kind], ctypes.byref(params), ctypes.byref(wsb), ctypes.byref(tmpb))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_oop_workspace_bytes")
+        ws = self.workspace(wsb.value)
+        if tmp is None or tmp.numel() < tmpb.value:
+            tmp = torch.empty(max(tmpb.value, 256), dtype=torch.uint8, device=t.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(t.device)
+        rc = _lib.ips_sort_oop(self._h, ctypes.c_void_p(t.data_ptr()), n, TYPES[kind], ctypes.c_void_p(tmp.data_ptr()),
+                               tmp.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(params),
+                               ctypes.c_void_p(stream.cuda_stream))
+        if rc != IPS_OK:
+            raise IpsError(rc, "ips_sort_oop", f"(hip={_lib.ips_last_hip_error(self._h)}, "
+                                               f"device={hex(_lib.ips_last_device_error(self._h))})")
         return t
 
     def sort_segments_(self, t, offsets, sizes, algo: str = "samplesort", params: Params | None = None,

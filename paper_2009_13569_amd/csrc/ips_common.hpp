@@ -30,7 +30,7 @@ constexpr int PERM_RD = IPS_PERM_RD;
 constexpr uint32_t PWORD_STRIDE = IPS_PWORD_STRIDE;
 constexpr uint32_t MAX_PLACE_PIECES = IPS_MAX_PLACE_PIECES;
 constexpr uint32_t CLS_THREADS = 1024;
-constexpr uint32_t PERM_THREADS = 256;
+constexpr uint32_t PERM_THREADS = 256;   // default workgroup size of the block permutation
 constexpr uint32_t SMP_THREADS = 1024;
 constexpr uint32_t CLN_THREADS = 256;
 constexpr uint32_t LDST_THREADS = 512;
@@ -51,6 +51,10 @@ enum CtrlSlot : uint32_t {
   CTRL_LDSEL = 16,     // children of a batch: u64 elements per LDS-tier variant (16..21)
   CTRL_LDSPOP = 22,    // LDS-tier tasks claimed per variant (22..24), zeroed with NLDS..LDSEL
   CTRL_LDSRUN = 25,    // device-planned step: 1 when this step's LDS-tier launches sort the lists
+  // serving: per-request completion counters (all zero: off)
+  CTRL_SEGLO = 26,     // u64 device address of the requests' first elements, ascending (26..27)
+  CTRL_SEGDONE = 28,   // u64 device address of the per-request counters of finished elements (28..29)
+  CTRL_NSEG = 30,      // number of requests in the table
   // device-planned execution (queue of tasks, per-step counts, statistics)
   CTRL_QHEAD = 64,     // next task to take from the queue
   CTRL_QTAIL = 65,     // end of the queued tasks
@@ -58,7 +62,7 @@ enum CtrlSlot : uint32_t {
   CTRL_NWG = 67,       // classification workgroups of the step
   CTRL_NPWG = 68,      // permutation workgroups of the step
   CTRL_NCLN = 69,      // buckets of the step (cleanup items)
-  CTRL_NFLAGS = 70,    // block flags of the step
+  CTRL_RSV70 = 70,     // unused
   CTRL_MAXW = 71,      // largest stripe count of the step
   CTRL_SPOP = 72,      // stripe length the step's tasks were chosen for (u64: 72..73)
   CTRL_STEPS = 74,     // statistics: partitioning steps (tasks)
@@ -77,7 +81,7 @@ enum DevErr : uint32_t {
   DE_CLS_INPLACE = 1,     // classification write past the consumed region
   DE_PIECES = 2,          // more pointer pieces than planned
   DE_PLACE = 3,           // no free slot found for a block
-  DE_WAIT = 4,            // reader flag never set
+  DE_WAIT = 4,            // a slot's reader never finished
   DE_CLEANUP_COUNT = 5,   // elements to place != free positions
   DE_SAMPLE = 6,          // sample too large
   DE_PERM_RANGE = 7,      // block position outside the task
@@ -89,7 +93,7 @@ enum DevErr : uint32_t {
 };
 
 // Result of the sampling phase of one step (Section 4.1) or the digit of a
-// radix step.  Keys live in 16-byte slots so that every key type fits.
+// radix step.  Keys live in 24-byte slots so that every key type fits.
 constexpr uint32_t CHILD_WGS = 1024;   // workgroups of the children kernel (at most)
 constexpr uint32_t LDS_DEFER_TASKS = 16384;   // device-planned steps: LDS-tier lists run from this many tasks
 constexpr uint32_t START_BITS = 12;   // start-node table: 2^12 entries
@@ -103,8 +107,8 @@ struct StepRec {
   uint32_t K, logK, eq, nb, u, alpha, kp, m;
   uint32_t shift, width, radix, tshift;
   uint64_t tbase;            // start-node table: key image of s_0 and shift
-  uint64_t tree[MAX_K][2];   // tree[1..K-1], breadth-first order
-  uint64_t spl[MAX_K][2];    // sorted splitters s_0..s_{K-1}, s_{K-1} = s_{K-2}
+  uint64_t tree[MAX_K][3];   // tree[1..K-1], breadth-first order
+  uint64_t spl[MAX_K][3];    // sorted splitters s_0..s_{K-1}, s_{K-1} = s_{K-2}
   uint16_t tstart[1u << START_BITS];   // start-table entries (tree node or first bucket and span), by key prefix
 };
 
@@ -113,7 +117,6 @@ struct PTask {
   uint64_t l, n;             // element offset and size
   uint64_t slot_off;         // byte offset of stripe 0's buffer slot (slots contiguous)
   uint64_t spill_off;        // byte offset of the per-bucket spill area
-  uint64_t flag_off;         // index of the first u32 block flag
   uint32_t level, tflags;    // recursion depth; TF_* bits
   uint32_t b, NB, W, wg_base;        // block elements, blocks, stripes, first WG
   uint32_t nb, K, logK, eq;          // buckets of the step
@@ -167,9 +170,9 @@ struct ChildArgs {
 // Workspace budgets and parameters of the device-planned execution (the
 // same rules the host applies when it plans a batch).
 struct PlanCfg {
-  uint64_t SB, SPB, FB, PB, slot_max;
+  uint64_t SB, SPB, PB, slot_max;
   uint32_t TB, WB, PWB, NBE, QCAP, CLNB;
-  uint32_t D, DW, k, n0, cap, cmax, groups, b_req, gbuf, radix, tflags0, wg_target;
+  uint32_t D, DW, k, n0, cap, cmax, groups, b_req, gbuf, radix, tflags0, wg_target, perm_threads, buf_bytes;
 };
 
 // Arguments shared by the kernels of one batch.
@@ -181,15 +184,15 @@ struct BatchArgs {
   const uint32_t* cls_task;   // classification WG -> task
   const uint32_t* perm_task;  // permutation WG -> task
   const uint32_t* cln_map;    // cleanup WG -> (task << 10) | bucket
-  uint32_t* wg_nfull;         // [WG][MAX_NB] full blocks flushed per bucket
-  uint32_t* wg_left;          // [WG][MAX_NB] elements left in the buffer
+  uint32_t* wg_nfull;         // [WG][nbs] full blocks flushed per bucket
+  uint32_t* wg_left;          // [WG][nbs] elements left in the buffer
   uint32_t* wg_F;             // [WG] full blocks at the stripe front
-  uint64_t* wg_min;           // [WG][MAX_K] radix: min key per bucket
+  uint64_t* wg_min;           // [WG][nbs] radix: min key per bucket
   uint64_t* wg_max;
+  uint32_t nbs;               // row length of the per-workgroup bucket arrays (>= any task's nb)
   uint8_t* slots;             // stripe buffer slots
   uint8_t* spill;             // spill areas
   uint32_t* ovf;              // [task][MAX_BLOCK_BYTES/4] overflow blocks
-  uint32_t* flags;            // block read flags
   uint64_t* b_start;          // [bucket_base + j], j = 0..nb (task-relative)
   uint32_t* b_count;          // blocks of bucket j
   uint32_t* b_d;              // first block of bucket j
@@ -198,7 +201,10 @@ struct BatchArgs {
   uint64_t* b_min;            // radix: min/max key of bucket j
   uint64_t* b_max;
   uint64_t* b_full;           // bit i: placement piece plb + i of bucket j is full
-  uint64_t* p_word;           // pieces: packed (w << 32) | (r + PTR_BIAS)
+  uint64_t* p_word;           // pieces, PWORD_STRIDE words each: [0] packed (w << 32) | (r + PTR_BIAS);
+                              // [1] reader state: low half the claimed blocks whose reads have
+                              // finished, high half 1 + the first claimed block once no
+                              // more claims can succeed (0 before)
   uint32_t* p_a;              // first block of the piece
   uint32_t* p_c;              // end block (exclusive) of the piece
   int32_t* p_rinit;           // last unprocessed block at the start (a-1: none)

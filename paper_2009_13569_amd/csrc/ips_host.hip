@@ -11,15 +11,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
+#include <deque>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/ips.h"
 #include "ips_common.hpp"
 #include "ips_launch.hpp"
+#include "ips_oop.hpp"
 
 using namespace ips;
 
@@ -39,6 +43,8 @@ struct Cfg {
   uint64_t seed;
   uint32_t b_req;   // requested block elements (0 = automatic)
   uint32_t groups;  // permutation groups per batch
+  uint32_t perm_threads;   // workgroup size of the block permutation
+  uint32_t buf_bytes;      // LDS of the classification's buffer blocks
 };
 
 uint32_t elem_bytes(int t) {
@@ -48,6 +54,7 @@ uint32_t elem_bytes(int t) {
     case 3: return 8;
     case 4: return 16;
     case 5: return 100;
+    case 6: return 32;
     default: return 0;
   }
 }
@@ -59,6 +66,7 @@ const Launchers* launchers_for(int t) {
     case 3: return launchers_f64();
     case 4: return launchers_pair();
     case 5: return launchers_rec100();
+    case 6: return launchers_quartet();
     default: return nullptr;
   }
 }
@@ -80,7 +88,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   const uint32_t D = elem_bytes(type);
   if (!D) return IPS_E_INVALID_ARG;
   if (algo != IPS_SAMPLESORT && algo != IPS_RADIX) return IPS_E_INVALID_ARG;
-  if (algo == IPS_RADIX && type == 5) return IPS_E_UNSUPPORTED;
+  if (algo == IPS_RADIX && (type == 5 || type == 6)) return IPS_E_UNSUPPORTED;
   ips_params z;
   std::memset(&z, 0, sizeof(z));
   if (!p) p = &z;
@@ -99,6 +107,10 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   c->cmax = p->piece_blocks ? p->piece_blocks : 1024;
   c->groups = p->perm_groups ? p->perm_groups : GRP_TARGET;
   if (c->groups > (1u << 20)) return IPS_E_INVALID_ARG;
+  c->perm_threads = p->perm_wg ? p->perm_wg : PERM_THREADS;
+  c->buf_bytes = launchers_for(type)->buf_bytes;
+  if (c->perm_threads != 128 && c->perm_threads != 256 && c->perm_threads != 512) return IPS_E_INVALID_ARG;
+  if (p->reserved) return IPS_E_INVALID_ARG;
   c->seed = p->seed;
   c->b_req = 0;
   if (p->block_bytes) {
@@ -150,7 +162,7 @@ uint32_t block_elems(const Cfg& c, uint32_t nb) {
   const uint32_t bmax = std::max<uint32_t>(1, MAX_BLOCK_BYTES / c.D);
   if (c.gbuf) return std::min(bmax, std::max<uint32_t>(1, c.b_req));
   // LDS holds nb buffers of b elements (plus BUF_PAD_DW dwords of padding each)
-  uint32_t b = std::max<uint32_t>(1, BUF_LDS_BYTES / (nb * c.D));
+  uint32_t b = std::max<uint32_t>(1, c.buf_bytes / (nb * c.D));
   b = std::min(b, bmax);
   if (c.b_req) b = std::min(b, c.b_req);
   return b;
@@ -158,11 +170,22 @@ uint32_t block_elems(const Cfg& c, uint32_t nb) {
 
 uint32_t max_nb(const Cfg& c) { return c.radix ? MAX_K : 2 * c.k; }
 
+// Buckets of any step of a sort of at most n elements: radix steps have at
+// most 2^8; a samplesort task of n' elements has at most 2 k'(n') (equality
+// buckets double K <= k'), and the default k' rule grows with n' (the
+// paper's rule does not, so it is bounded by k).
+uint32_t plan_nb(const Cfg& c, uint64_t n) {
+  if (c.radix) return MAX_K;
+  if (c.n0) return 2 * c.k;
+  return 2 * task_kprime(c, n);
+}
+
 struct Layout {
   uint32_t TB, WB, PWB, LTB, NBE;   // tasks, cls WGs, perm WGs, LDS tasks, bucket entries
   uint32_t NXB;                     // next-level tasks one batch can produce
   uint32_t QCAP;                    // task queue of the device-planned execution
-  uint64_t SB, SPB, FB, PB;         // slot bytes, spill bytes, flag words, pieces
+  uint32_t NBS;                     // buckets per step at most (row length of per-WG arrays)
+  uint64_t SB, SPB, PB;             // slot bytes, spill bytes, pieces
   uint64_t slot_max;
   size_t off[40];
   size_t total;
@@ -170,60 +193,84 @@ struct Layout {
 
 enum Region {
   R_CTRL, R_TASKS, R_RECS, R_CLS, R_PERM, R_CLN, R_NFULL, R_LEFT, R_F, R_WMIN, R_WMAX, R_SLOTS,
-  R_SPILL, R_OVF, R_FLAGS, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
+  R_SPILL, R_OVF, R_BSTART, R_BCOUNT, R_BD, R_BPLB, R_BPLE, R_BMIN, R_BMAX, R_PWORD,
   R_PA, R_PC, R_PR, R_PCUM, R_TNP, R_TUP, R_LT, R_BFULL, R_PFCNT, R_LTC, R_NEXT, R_QUEUE, R_STEPEL, R_COUNT
 };
 
+// Workspace plan of a sort of n elements (Section 5.1: O(k b) extra memory
+// per thread; here per workgroup).  Every region is either per task (O(k)
+// words: step records, bucket tables, pieces, one overflow block and one
+// spill area of one buffer block per bucket), per workgroup (O(k) counters
+// and, for the stripes' buffer blocks saved after classification, one
+// buffer block per bucket = the LDS budget), or bounded by the number of
+// tasks and workgroups of one step.  The step's task and workgroup budgets
+// (TB <= 512 tasks, WB <= 2048 workgroups) are constants, so for large n the
+// workspace no longer grows with n; for small n the budgets shrink with the
+// data (a single task never needs more slots than a quarter of its data
+// plus one buffer block per bucket).
 void plan(uint64_t n, const Cfg& c, Layout* L) {
-  const uint64_t nbm = max_nb(c);
-  const uint32_t bmin = block_elems(c, (uint32_t)nbm);
+  const uint32_t nbm = plan_nb(c, n);
+  const uint32_t bmin = block_elems(c, nbm);
   uint64_t slot_max = 0;
   for (uint32_t nb = 2; nb <= nbm; nb *= 2)
     slot_max = std::max<uint64_t>(slot_max, ((uint64_t)nb * block_elems(c, nb) * c.D + 255) & ~255ull);
-  const uint64_t tasks_ub = n / ((uint64_t)c.cap + 1) + 1;
+  // Tasks of one step: every queued partitioning task holds more than cap
+  // elements, so at most n / (cap + 1) of them exist at once.
+  const uint64_t tasks_ub = std::max<uint64_t>(1, n / ((uint64_t)c.cap + 1));
   L->TB = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(TB_MAX, tasks_ub),
-                                       std::max<uint64_t>(64, n * c.D / (256 * 1024)));
+                                       std::max<uint64_t>(16, n * c.D / (256 * 1024)));
   L->WB = (uint32_t)std::min<uint64_t>(std::min<uint32_t>(WB_MAX, WG_TARGET + L->TB),
                                        L->TB + n * c.D / 65536 + 16);
+  L->NBS = nbm;
   L->slot_max = slot_max;
-  // Budgets scale with the data: a batch holds as many tasks as fit, and any
-  // single task fits (its slots need at most max(slot, n D / 2 + W * 256)).
-  const uint64_t data_budget = n * c.D / 4 + 4 * slot_max + (uint64_t)WG_TARGET * 256;
-  L->SB = std::min<uint64_t>((uint64_t)(WG_TARGET + L->TB) * slot_max, data_budget);
-  L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, std::max<uint64_t>(slot_max, data_budget));
-  L->FB = n / bmin + L->TB + 1;
-  // Pieces: a task with k' buckets (2k' with equality buckets) has at most
-  // 4k' + 3 + W + NB / cmax of them.  Under the default k' rule k' is below
-  // 8 n' / cap (or 2), so a samplesort batch needs at most 32 n / cap + 13
-  // per task besides the stripe and chunk terms (radix steps always have up
-  // to 256 buckets).
+  // Buffer slots: one buffer block per bucket per stripe, and any single task
+  // fits (a task has at most n D / (4 nb b) stripes, so its slots need at
+  // most max(one slot, n D / 4 + 256 per stripe of rounding)).
+  const uint64_t data_budget = std::max<uint64_t>(slot_max, n * c.D / 4 + (uint64_t)L->WB * 256);
+  L->SB = std::min<uint64_t>((uint64_t)L->WB * slot_max, data_budget);
+  L->SPB = std::min<uint64_t>((uint64_t)L->TB * slot_max, data_budget);
+  // Pieces: a task with nb buckets has at most 2 nb + 3 + W + NB / cmax of
+  // them.  Under the default k' rule k' is below 8 n' / cap (or 2), so a
+  // samplesort batch needs at most 32 n / cap + 13 per task besides the
+  // stripe and chunk terms (radix steps always have up to 256 buckets).
   uint64_t pb_buckets = (uint64_t)L->TB * (2 * nbm + 3);
   if (!c.n0 && !c.radix) pb_buckets = std::min<uint64_t>(pb_buckets, 32 * n / c.cap + 13ull * L->TB);
-  L->PB = pb_buckets + L->WB + L->FB / c.cmax + 16;
-  L->PWB = c.groups / 4 + 2 * L->TB + 16;
-  L->NBE = L->TB * (uint32_t)(nbm + 1);
-  // LDS-tier children of one batch: at most 2k' (equality buckets) per task;
-  // under the default k' rule k' < 8 n' / cap (or 2), so a batch has fewer
-  // than 16 n / cap + 4 TB of them.
-  uint64_t ltb = (uint64_t)L->TB * nbm;
-  if (!c.n0 && !c.radix) ltb = std::min<uint64_t>(ltb, 16 * n / c.cap + 4ull * L->TB);
-  L->LTB = (uint32_t)ltb + 1;
+  // Chunk pieces: a bucket's range is cut every max(cmax, its blocks / 32)
+  // blocks, so at most 64 times per bucket (its range exceeds its own full
+  // blocks by at most one block per stripe), and never more than the blocks
+  // of the step divided by cmax.
+  L->PB = pb_buckets + L->WB + std::min<uint64_t>(n / bmin / c.cmax + L->TB, 64ull * nbm * L->TB) + 16;
+  // Permutation workgroups: a task of NB blocks gets at most NB / 4 groups
+  // (or one) of max(4, b DW / 4) lanes at most; a workgroup of NT threads
+  // holds NT / lanes groups, so one step needs at most
+  // min(groups * 64 / NT, n / (NT bmin) + n DW / (16 NT)) workgroups plus two
+  // per task.
+  const uint64_t NT = c.perm_threads;
+  const uint64_t pw_data = n / (NT * bmin) + n * c.DW / (16 * NT) + 1;
+  L->PWB = (uint32_t)(std::min<uint64_t>(c.groups * 64 / NT, pw_data) + 2ull * L->TB + 16);
+  // Buckets of one step: at most 2k' (equality buckets) per task; under the
+  // default k' rule k' < 8 n' / cap (or 2), and the tasks of a step are
+  // disjoint, so a step has fewer than 16 n / cap + 4 TB of them.  These
+  // bound the bucket tables, the cleanup items and the LDS-tier children.
+  uint64_t nbe = (uint64_t)L->TB * nbm;
+  if (!c.n0 && !c.radix) nbe = std::min<uint64_t>(nbe, 16 * n / c.cap + 4ull * L->TB);
+  L->NBE = (uint32_t)(nbe + L->TB);
+  L->LTB = (uint32_t)nbe + 1;
   size_t sz[R_COUNT];
   sz[R_CTRL] = CTRL_WORDS * 4;
   sz[R_TASKS] = (size_t)L->TB * sizeof(PTask);
-  sz[R_RECS] = (size_t)L->TB * sizeof(StepRec);
+  sz[R_RECS] = c.radix ? 0 : (size_t)L->TB * sizeof(StepRec);   // radix steps take no sample
   sz[R_CLS] = (size_t)L->WB * 4;
   sz[R_PERM] = (size_t)L->PWB * 4;
-  sz[R_CLN] = (size_t)L->TB * nbm * 4;
-  sz[R_NFULL] = (size_t)L->WB * MAX_NB * 4;
-  sz[R_LEFT] = (size_t)L->WB * MAX_NB * 4;
+  sz[R_CLN] = (size_t)L->NBE * 4;
+  sz[R_NFULL] = (size_t)L->WB * nbm * 4;
+  sz[R_LEFT] = (size_t)L->WB * nbm * 4;
   sz[R_F] = (size_t)L->WB * 4;
-  sz[R_WMIN] = c.radix ? (size_t)L->WB * MAX_K * 8 : 0;
+  sz[R_WMIN] = c.radix ? (size_t)L->WB * nbm * 8 : 0;
   sz[R_WMAX] = sz[R_WMIN];
   sz[R_SLOTS] = L->SB;
   sz[R_SPILL] = L->SPB;
   sz[R_OVF] = (size_t)L->TB * MAX_BLOCK_BYTES;
-  sz[R_FLAGS] = L->FB * 4;
   sz[R_BSTART] = (size_t)L->NBE * 8;
   sz[R_BCOUNT] = (size_t)L->NBE * 4;
   sz[R_BD] = (size_t)L->NBE * 4;
@@ -385,6 +432,7 @@ struct Run {
   uint8_t* h_rb;      // readback
   size_t rb_bytes;
   uint32_t* h_ctrl;
+  uint32_t lds_min = LDS_DEFER_TASKS;   // device-planned steps: LDS-tier lists run from this many tasks
 };
 
 template <class P>
@@ -467,7 +515,7 @@ hipError_t launch_lds_lists(Run& r, const ChildArgs& ca, const uint32_t (&cnt)[3
 
 // Upper bounds of one task's resources before its step is sampled.
 struct Need {
-  uint64_t wg, slot, spill, flags, pieces;
+  uint64_t wg, slot, spill, pieces;
 };
 
 Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
@@ -478,10 +526,9 @@ Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
   nd.slot = std::min<uint64_t>(nd.wg * r.L.slot_max,
                                std::max<uint64_t>(r.L.slot_max, t.n * r.c.D / 4 + nd.wg * 256));
   nd.spill = r.L.slot_max;
-  const uint32_t bmin = block_elems(r.c, max_nb(r.c));
-  nd.flags = t.n / bmin + 1;
-  const uint64_t nbt = r.c.radix ? MAX_K : 2ull * task_kprime(r.c, t.n);   // buckets at most
-  nd.pieces = 2 * nbt + 3 + nd.wg + nd.flags / r.c.cmax + 1;
+  const uint32_t nbt = r.c.radix ? MAX_K : 2 * task_kprime(r.c, t.n);   // buckets at most
+  const uint32_t bmin = block_elems(r.c, nbt);
+  nd.pieces = 2ull * nbt + 3 + nd.wg + (t.n / bmin + 1) / r.c.cmax + 1;
   return nd;
 }
 
@@ -539,7 +586,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     blocks_sum += NBv[t];
   }
   uint32_t wg = 0, pwg = 0, maxW = 1, cln = 0;
-  uint64_t slot_off = 0, spill_off = 0, flag_off = 0;
+  uint64_t slot_off = 0, spill_off = 0;
   uint32_t piece = 0, bucket = 0;
   uint32_t* h_cls = r.h_maps;
   uint32_t* h_perm = h_cls + r.L.WB;
@@ -595,8 +642,6 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     slot_off += (uint64_t)p.W * p.slot_bytes;
     p.spill_off = spill_off;
     spill_off += p.slot_bytes;
-    p.flag_off = flag_off;
-    flag_off += NB;
     p.piece_base = piece;
     p.piece_cap = 2 * nb + 2 + p.W + NB / c.cmax + 1;   // chunks are never smaller than cmax
     piece += p.piece_cap;
@@ -608,7 +653,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.glanes = gl;
     uint64_t ng = std::max<uint64_t>(1, std::min<uint64_t>(NB / 4, (uint64_t)c.groups * NB / std::max<uint64_t>(1, blocks_sum)));
     p.ngrp = (uint32_t)ng;
-    const uint32_t gpw = PERM_THREADS / gl;
+    const uint32_t gpw = c.perm_threads / gl;
     const uint32_t nwg = (uint32_t)((ng + gpw - 1) / gpw);
     p.pwg_base = pwg;
     for (uint32_t x = 0; x < nwg; ++x) h_perm[pwg + x] = t;
@@ -616,8 +661,8 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     for (uint32_t j = 0; j < nb; ++j) h_cln[cln++] = (t << 10) | j;
     if (!c.gbuf) max_dyn = std::max<size_t>(max_dyn, (size_t)nb * (b * c.DW + BUF_PAD_DW) * 4);
   }
-  if (wg > r.L.WB || pwg > r.L.PWB || slot_off > r.L.SB || spill_off > r.L.SPB || flag_off > r.L.FB ||
-      piece > r.L.PB || bucket > r.L.NBE || cln > r.L.TB * max_nb(c)) {
+  if (wg > r.L.WB || pwg > r.L.PWB || slot_off > r.L.SB || spill_off > r.L.SPB || max_nb_batch > r.L.NBS ||
+      piece > r.L.PB || bucket > r.L.NBE || cln > r.L.NBE) {
     ctx->last_dev = 0x100;
     return IPS_E_DEVICE;
   }
@@ -633,9 +678,8 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
                     [&] { return c.L->classify(r.a, wg, (uint32_t)max_dyn, c.gbuf, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, bel,
                     [&] { return launch_boundaries(r.a, T, max_nb_batch, c.cmax, r.st); }));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, bel,
-                    [&] { return launch_fill32(r.a.flags, flag_off, 0u, r.st); }));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, bel, [&] { return c.L->permute(r.a, pwg, r.st); }));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, bel,
+                    [&] { return c.L->permute(r.a, pwg, c.perm_threads, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, bel, [&] { return c.L->cleanup_a(r.a, T, r.st); }));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, bel,
                     [&] { return c.L->cleanup_b(r.a, cln, maxW, r.st); }));
@@ -688,16 +732,19 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     ri.n = p.n;
     for (uint32_t j2 = 0; j2 <= p.nb && j2 < 513; ++j2) ri.bucket_start[j2] = h_root[j2];
     if (!c.radix) {
-      std::vector<uint64_t> spl((size_t)p.K * 2);
+      std::vector<uint64_t> spl((size_t)p.K * 3);
       HIPCHK(ctx, hipMemcpy(spl.data(), &d_recs[0].spl[0][0], spl.size() * 8, hipMemcpyDeviceToHost));
       for (uint32_t q = 0; q < p.K && q < 256; ++q) {
-        uint64_t k0 = spl[2 * q], k1 = spl[2 * q + 1];
+        uint64_t k0 = spl[3 * q], k1 = spl[3 * q + 1];
         if (c.type == 3) k0 = (k0 >> 63) ? (k0 & ~(1ull << 63)) : ~k0;   // ordered image -> bits
         if (c.type == 5) {
           uint8_t* d = ri.splitters[q];
           for (int x = 0; x < 8; ++x) d[x] = (uint8_t)(k0 >> (56 - 8 * x));
           d[8] = (uint8_t)(k1 >> 8);
           d[9] = (uint8_t)k1;
+        } else if (c.type == 6) {   // the Quartet's first two key words (a, b)
+          std::memcpy(ri.splitters[q], &k0, 8);
+          std::memcpy(ri.splitters[q] + 8, &k1, 8);
         } else {
           std::memcpy(ri.splitters[q], &k0, 8);
         }
@@ -811,7 +858,7 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   HIPCHK(ctx, hipSetDevice(ctx->device));
   // Pinned staging: tasks | maps | LDS tasks | readback | ctrl | extra.
   const size_t b_tasks = (size_t)r.L.TB * sizeof(PTask);
-  const size_t b_maps = ((size_t)r.L.WB + r.L.PWB + (size_t)r.L.TB * max_nb(r.c)) * 4;
+  const size_t b_maps = ((size_t)r.L.WB + r.L.PWB + (size_t)r.L.NBE) * 4;
   const size_t b_lt = (size_t)r.L.LTB * sizeof(LTask);
   // readback: sampling headers, or next-level tasks (first half) and the
   // root step's bucket starts (second half)
@@ -844,7 +891,7 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   a.slots = wsp<uint8_t>(r, R_SLOTS);
   a.spill = wsp<uint8_t>(r, R_SPILL);
   a.ovf = wsp<uint32_t>(r, R_OVF);
-  a.flags = wsp<uint32_t>(r, R_FLAGS);
+  a.nbs = r.L.NBS;
   a.b_start = wsp<uint64_t>(r, R_BSTART);
   a.b_count = wsp<uint32_t>(r, R_BCOUNT);
   a.b_d = wsp<uint32_t>(r, R_BD);
@@ -912,15 +959,14 @@ int level_loop(Run& r, std::vector<HTask> cur, const std::vector<LTask>& lds_roo
     size_t i = 0;
     while (i < cur.size()) {
       std::vector<HTask> bt;
-      Need tot{0, 0, 0, 0, 0};
+      Need tot{0, 0, 0, 0};
       while (i < cur.size() && bt.size() < r.L.TB) {
         Need nd = task_need(r, cur[i], level_elems);
         if (!bt.empty() && (tot.wg + nd.wg > r.L.WB || tot.slot + nd.slot > r.L.SB ||
-                            tot.spill + nd.spill > r.L.SPB || tot.flags + nd.flags > r.L.FB ||
-                            tot.pieces + nd.pieces > r.L.PB))
+                            tot.spill + nd.spill > r.L.SPB || tot.pieces + nd.pieces > r.L.PB))
           break;
         tot.wg += nd.wg; tot.slot += nd.slot; tot.spill += nd.spill;
-        tot.flags += nd.flags; tot.pieces += nd.pieces;
+        tot.pieces += nd.pieces;
         bt.push_back(cur[i++]);
       }
       if (int e = run_batch(r, bt, level_elems, next, record_root && level == 0)) return e;
@@ -947,30 +993,26 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
   a.devplan = 1;
   a.step = step;
   const uint32_t row = std::min<uint32_t>(step, IPS_MAX_LEVELS - 1);
-  const uint32_t nbm = max_nb(c);
+  const uint32_t nbm = r.L.NBS;
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_SAMPLE, 0, [&] {
            hipError_t e = launch_plan_pop(a, pc, r.st);
            if (e != hipSuccess || c.radix) return e;
            return c.L->sample(a, r.L.TB, c.seed, r.st);
          }, 0));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, 0, [&] {
-           hipError_t e = launch_plan_geom(a, pc, r.st);
-           if (e != hipSuccess) return e;
-           return launch_fill32_cnt(a.flags, a.ctrl + CTRL_NFLAGS, (uint32_t)std::min<uint64_t>(r.L.FB, 0xFFFFFFFFu),
-                                    0u, r.st);
-         }, 0));
-  const size_t dyn = c.gbuf ? 0 : (size_t)BUF_LDS_BYTES + (size_t)MAX_NB * BUF_PAD_DW * 4;
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, 0, [&] { return launch_plan_geom(a, pc, r.st); }, 0));
+  const size_t dyn = c.gbuf ? 0 : (size_t)c.buf_bytes + (size_t)MAX_NB * BUF_PAD_DW * 4;
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, 0,
                     [&] { return c.L->classify(a, r.L.WB, (uint32_t)dyn, c.gbuf, r.st); }, 0));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0,
                     [&] { return launch_boundaries(a, r.L.TB, nbm, c.cmax, r.st); }, 0));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, 0, [&] { return c.L->permute(a, r.L.PWB, r.st); }, 0));
+  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, 0,
+                    [&] { return c.L->permute(a, r.L.PWB, c.perm_threads, r.st); }, 0));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, 0, [&] { return c.L->cleanup_a(a, r.L.TB, r.st); }, 0));
   const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
                     [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
   HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
-  HIPCHK(ctx, launch_lds_decide(a.ctrl, LDS_DEFER_TASKS, r.L.LTB, r.st));
+  HIPCHK(ctx, launch_lds_decide(a.ctrl, r.lds_min, r.L.LTB, r.st));
   for (uint32_t v = 0; v < 3; ++v) {
     if (v && c.L->lds_caps[v] == c.L->lds_caps[v - 1]) continue;
     const uint32_t grid = (uint32_t)std::min<uint64_t>(ca.lt_cap, 2048);
@@ -980,6 +1022,28 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
   }
   HIPCHK(ctx, launch_lds_reset(a.ctrl, r.st));
   return IPS_OK;
+}
+
+// Budgets of the device planner and the children lists of device-planned
+// steps (lists of two steps' capacity).
+void plan_cfg(const Run& r, PlanCfg* pcp, ChildArgs* cap) {
+  const Cfg& c = r.c;
+  PlanCfg& pc = *pcp;
+  pc.SB = r.L.SB; pc.SPB = r.L.SPB; pc.PB = r.L.PB; pc.slot_max = r.L.slot_max;
+  pc.TB = r.L.TB; pc.WB = r.L.WB; pc.PWB = r.L.PWB; pc.NBE = r.L.NBE; pc.QCAP = r.L.QCAP;
+  pc.CLNB = r.L.NBE;
+  pc.D = c.D; pc.DW = c.DW; pc.k = c.k; pc.n0 = c.n0; pc.cap = c.cap; pc.cmax = c.cmax;
+  pc.groups = c.groups; pc.b_req = c.b_req; pc.gbuf = c.gbuf ? 1 : 0; pc.radix = c.radix ? 1 : 0;
+  pc.tflags0 = 0; pc.wg_target = WG_TARGET; pc.perm_threads = c.perm_threads; pc.buf_bytes = c.buf_bytes;
+  ChildArgs& ca = *cap;
+  LTask* d_ltc = reinterpret_cast<LTask*>(r.ws + r.L.off[R_LTC]);
+  for (uint32_t v = 0; v < 3; ++v) {
+    ca.lt[v] = d_ltc + (size_t)v * 2 * r.L.LTB;
+    ca.caps[v] = std::min(c.cap, c.L->lds_caps[v]);
+  }
+  ca.next = reinterpret_cast<CTask*>(r.ws + r.L.off[R_NEXT]);
+  ca.lt_cap = 2 * r.L.LTB;
+  ca.next_cap = r.L.NXB;
 }
 
 int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask>& lds_roots) {
@@ -1009,21 +1073,8 @@ int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask
   HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_QTAIL, 1, (uint32_t)roots.size(), r.st));
   HIPCHK(ctx, launch_fill32(reinterpret_cast<uint32_t*>(r.a.step_el), MAX_STEPS_RECORDED * 8, 0u, r.st));
   PlanCfg pc;
-  pc.SB = r.L.SB; pc.SPB = r.L.SPB; pc.FB = r.L.FB; pc.PB = r.L.PB; pc.slot_max = r.L.slot_max;
-  pc.TB = r.L.TB; pc.WB = r.L.WB; pc.PWB = r.L.PWB; pc.NBE = r.L.NBE; pc.QCAP = r.L.QCAP;
-  pc.CLNB = r.L.TB * max_nb(c);
-  pc.D = c.D; pc.DW = c.DW; pc.k = c.k; pc.n0 = c.n0; pc.cap = c.cap; pc.cmax = c.cmax;
-  pc.groups = c.groups; pc.b_req = c.b_req; pc.gbuf = c.gbuf ? 1 : 0; pc.radix = c.radix ? 1 : 0;
-  pc.tflags0 = 0; pc.wg_target = WG_TARGET;
   ChildArgs ca;
-  LTask* d_ltc = wsp<LTask>(r, R_LTC);
-  for (uint32_t v = 0; v < 3; ++v) {
-    ca.lt[v] = d_ltc + (size_t)v * 2 * r.L.LTB;
-    ca.caps[v] = std::min(c.cap, c.L->lds_caps[v]);
-  }
-  ca.next = wsp<CTask>(r, R_NEXT);
-  ca.lt_cap = 2 * r.L.LTB;
-  ca.next_cap = r.L.NXB;
+  plan_cfg(r, &pc, &ca);
   HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 14, 0u, r.st));   // lists empty, no run pending
   const bool graph = (c.flags & IPS_FLAG_GRAPH) != 0;
   if (graph) ctx->profiling = false;   // no event records inside a captured graph
@@ -1372,6 +1423,657 @@ int batch_impl(ips_ctx* ctx, void* const* ptrs, const uint64_t* ns, uint32_t cou
   return IPS_OK;
 }
 
+// ------------------------------------------------- out-of-place ablation
+//
+// Super scalar samplesort's out-of-place partitioning step (the algorithm the
+// paper re-implements on its framework, Section 7, and compares by I/O
+// volume in its appendix) on the same GPU, with the same sampling, decision
+// tree, start table and LDS-tier base case as the in-place step, as an
+// ablation of the paper's in-place design.  Levels alternate between the
+// input and a second array of the caller; buckets that end in the second
+// array (final ones and LDS-tier tasks of a level that wrote there) are
+// copied back before the LDS tier sorts them in the input, which is where
+// super scalar samplesort copies back after an odd number of levels.
+
+uint64_t oop_tmp_bytes(uint64_t n, uint32_t D) {
+  return ((n * D + 255) & ~255ull) + ((2 * n + 255) & ~255ull);
+}
+
+// Reads `count` entries of a device list through a pinned staging area of
+// `cap` entries (the stream is synchronized for every chunk).
+template <class E>
+int read_list(Run& r, const E* d_list, uint32_t count, E* staging, size_t cap, std::vector<E>* out) {
+  for (uint32_t done = 0; done < count;) {
+    const uint32_t cnt = (uint32_t)std::min<size_t>(count - done, cap);
+    HIPCHK(r.ctx, hipMemcpyAsync(staging, d_list + done, (size_t)cnt * sizeof(E), hipMemcpyDeviceToHost, r.st));
+    HIPCHK(r.ctx, hipStreamSynchronize(r.st));
+    out->insert(out->end(), staging, staging + cnt);
+    done += cnt;
+  }
+  return IPS_OK;
+}
+
+int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_bytes, void* ws, size_t ws_bytes,
+             const ips_params* params, void* stream) {
+  ips_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  if (p.flags & (IPS_FLAG_LEVEL1_ONLY | IPS_FLAG_GRAPH | IPS_FLAG_HOST_PLAN | IPS_FLAG_GLOBAL_BUFFERS))
+    return IPS_E_INVALID_ARG;
+  if (n >= (1ull << 32)) return IPS_E_TOO_LARGE;
+  Run r;
+  int rc = setup_run(ctx, r, d, n, n, type, IPS_SAMPLESORT, ws, ws_bytes, 0, &p, stream, 0, nullptr);
+  if (rc || n < 2) return rc;
+  const Cfg& c = r.c;
+  if (!tmp || tmp_bytes < oop_tmp_bytes(n, c.D)) return IPS_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(tmp) % 256) return IPS_E_MISALIGNED;
+  if (n <= c.cap) {
+    std::vector<LTask> lt(1);
+    lt[0].l = 0; lt[0].n = (uint32_t)n; lt[0].pad = 0;
+    return level_loop(r, {}, lt, true);
+  }
+  uint32_t* A = r.data;
+  uint32_t* B = static_cast<uint32_t*>(tmp);
+  OopArgs o;
+  o.oracle = static_cast<uint8_t*>(tmp) + ((n * c.D + 255) & ~255ull);
+  o.tasks = r.a.tasks;
+  o.recs = r.a.recs;
+  o.wg_task = r.a.cls_task;
+  o.cnt = r.a.wg_nfull;
+  o.b_start = r.a.b_start;
+  o.nbs = r.L.NBS;
+  LTask* d_lds = wsp<LTask>(r, R_LTC);
+  LTask* d_copy = d_lds + r.L.LTB;
+  CTask* d_next = wsp<CTask>(r, R_NEXT);
+  struct Hdr { uint32_t K, logK, eq, nb, u, alpha, kp, m; };
+  std::vector<HTask> cur(1);
+  cur[0].l = 0; cur[0].n = n; cur[0].level = 0; cur[0].shift = 0; cur[0].width = 0;
+  cur[0].tflags = (c.flags & IPS_FLAG_EQ_ON) ? TF_EQ_ON : (c.flags & IPS_FLAG_EQ_OFF) ? TF_EQ_OFF : 0u;
+  uint32_t level = 0;
+  while (!cur.empty()) {
+    const bool to_b = (level % 2) == 0;
+    uint32_t* src = to_b ? A : B;
+    uint32_t* dst = to_b ? B : A;
+    uint64_t level_elems = 0;
+    for (const HTask& t : cur) level_elems += t.n;
+    const uint64_t S = std::max<uint64_t>(16384, level_elems / WG_TARGET);   // stripe length
+    std::vector<HTask> next;
+    std::vector<LTask> lds, copy;
+    const uint32_t row = std::min<uint32_t>(level, IPS_MAX_LEVELS - 1);
+    for (size_t i = 0; i < cur.size();) {
+      // a batch: as many tasks as the task, workgroup and bucket budgets hold
+      uint32_t T = 0, wsum = 0, nbsum = 0;
+      while (i + T < cur.size() && T < r.L.TB) {
+        const HTask& t = cur[i + T];
+        const uint32_t w = (uint32_t)std::min<uint64_t>(WG_TARGET, (t.n + S - 1) / S);
+        const uint32_t nbt = 2 * task_kprime(c, t.n) + 1;
+        if (T && (wsum + w > r.L.WB || nbsum + nbt > r.L.NBE)) break;
+        wsum += w;
+        nbsum += nbt;
+        ++T;
+      }
+      for (uint32_t t = 0; t < T; ++t) {
+        PTask& q = r.h_tasks[t];
+        std::memset(&q, 0, sizeof(q));
+        q.l = cur[i + t].l;
+        q.n = cur[i + t].n;
+        q.level = cur[i + t].level;
+        q.tflags = cur[i + t].tflags;
+        q.kp = task_kprime(c, q.n);
+      }
+      BatchArgs a = r.a;
+      a.data = src;
+      HIPCHK(ctx, hipMemcpyAsync(wsp<PTask>(r, R_TASKS), r.h_tasks, T * sizeof(PTask), hipMemcpyHostToDevice, r.st));
+      HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_SAMPLE, 0, [&] { return c.L->sample(a, T, c.seed, r.st); }));
+      HIPCHK(ctx, hipMemcpy2DAsync(r.h_rb, sizeof(Hdr), r.a.recs, sizeof(StepRec), sizeof(Hdr), T,
+                                   hipMemcpyDeviceToHost, r.st));
+      if (int e = read_ctrl(r)) return e;
+      const Hdr* hdr = reinterpret_cast<const Hdr*>(r.h_rb);
+      uint32_t wg = 0, bucket = 0;
+      uint64_t bel = 0;
+      uint32_t* h_cls = r.h_maps;
+      for (uint32_t t = 0; t < T; ++t) {
+        PTask& q = r.h_tasks[t];
+        q.K = hdr[t].K; q.logK = hdr[t].logK; q.eq = hdr[t].eq; q.nb = hdr[t].nb;
+        if (q.nb > r.L.NBS) { ctx->last_dev = 0x105; return IPS_E_DEVICE; }
+        q.W = (uint32_t)std::min<uint64_t>(WG_TARGET, (q.n + S - 1) / S);
+        q.wg_base = wg;
+        for (uint32_t x = 0; x < q.W; ++x) h_cls[wg + x] = t;
+        wg += q.W;
+        q.bucket_base = bucket;
+        bucket += q.nb + 1;
+        bel += q.n;
+      }
+      if (wg > r.L.WB || bucket > r.L.NBE) { ctx->last_dev = 0x106; return IPS_E_DEVICE; }
+      HIPCHK(ctx, hipMemcpyAsync(wsp<PTask>(r, R_TASKS), r.h_tasks, T * sizeof(PTask), hipMemcpyHostToDevice, r.st));
+      HIPCHK(ctx, hipMemcpyAsync(const_cast<uint32_t*>(r.a.cls_task), h_cls, wg * 4, hipMemcpyHostToDevice, r.st));
+      o.src = src;
+      o.dst = dst;
+      HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, bel, [&] { return c.L->oop_classify(o, wg, r.st); }));
+      HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, bel, [&] { return launch_oop_scan(o, T, r.st); }));
+      HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, bel, [&] { return c.L->oop_distribute(o, wg, r.st); }));
+      HIPCHK(ctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 4, 0u, r.st));
+      HIPCHK(ctx, launch_oop_children(o, T, r.a.ctrl, d_next, r.L.NXB, d_lds, d_copy, r.L.LTB, c.cap,
+                                      to_b ? 1u : 0u, r.st));
+      if (int e = read_ctrl(r)) return e;
+      const uint32_t nnext = r.h_ctrl[CTRL_NNEXT], nlds = r.h_ctrl[CTRL_NLDS], ncopy = r.h_ctrl[CTRL_NLDS + 1];
+      if (nnext > r.L.NXB || nlds > r.L.LTB || ncopy > r.L.LTB) { ctx->last_dev = 0x107; return IPS_E_DEVICE; }
+      std::vector<CTask> ch;
+      if (int e = read_list(r, d_next, nnext, reinterpret_cast<CTask*>(r.h_rb), r.rb_bytes / sizeof(CTask), &ch))
+        return e;
+      for (const CTask& q : ch) {
+        HTask h;
+        h.l = q.l; h.n = q.n; h.level = q.level; h.tflags = q.tflags; h.shift = 0; h.width = 0;
+        next.push_back(h);
+      }
+      if (int e = read_list(r, d_lds, nlds, r.h_lt, r.L.LTB, &lds)) return e;
+      if (int e = read_list(r, d_copy, ncopy, r.h_lt, r.L.LTB, &copy)) return e;
+      ctx->stats.steps += T;
+      ctx->stats.batches += 1;
+      ctx->stats.partitioned_elems += bel;
+      i += T;
+    }
+    // buckets that stay in the second array come back first
+    uint64_t cel = 0;
+    for (const LTask& t : copy) cel += t.n;
+    for (size_t done = 0; done < copy.size();) {
+      const size_t cnt = std::min<size_t>(copy.size() - done, r.L.LTB);
+      std::memcpy(r.h_lt, copy.data() + done, cnt * sizeof(LTask));
+      LTask* d_lt = wsp<LTask>(r, R_LT);
+      HIPCHK(ctx, hipMemcpyAsync(d_lt, r.h_lt, cnt * sizeof(LTask), hipMemcpyHostToDevice, r.st));
+      HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, cel,
+                        [&] { return c.L->copy_ranges(d_lt, (uint32_t)cnt, B, A, r.st); }));
+      HIPCHK(ctx, hipStreamSynchronize(r.st));   // the staging is reused
+      done += cnt;
+    }
+    for (const LTask& t : lds) ctx->stats.lds_elems += t.n;
+    if (!lds.empty())
+      if (int e = launch_lds_tasks(r, lds, row)) return e;
+    std::sort(next.begin(), next.end(), [](const HTask& x, const HTask& y) { return x.l < y.l; });
+    cur.swap(next);
+    ctx->stats.levels = ++level;
+    ctx->prof.levels = std::min<uint32_t>(level, IPS_MAX_LEVELS);
+  }
+  return read_ctrl(r);
+}
+
+// ------------------------------------------------------------------ serving
+//
+// Continuous batching (no paper passage; the closest analogue is the reuse
+// of a preallocated sorter object, Section 7.6).  Requests are grouped into
+// lanes by element type and algorithm; each lane owns a slice of the
+// workspace planned for its share of the HBM budget, its own stream and its
+// own pinned staging, and runs device-planned steps over one task queue.
+// Between two rounds of a lane (a round is a few steps followed by an
+// asynchronous read-back of the control block and of the per-request
+// counters), arrived requests are admitted in arrival order while the lane's
+// elements in flight stay within its plan and all request data plus the
+// lanes' workspaces stays within the budget: requests larger than the LDS
+// tier become root tasks at the tail of the running queue, smaller ones are
+// sorted by the LDS tier at the start of the next round.  The kernels add
+// the elements of every final bucket and every finished LDS-tier task to the
+// counter of the request they belong to, so a request completes at the first
+// read-back that shows all its elements final.  Lanes run on separate
+// streams, so the work of requests of different types overlaps on the GPU,
+// and requests of one type share the launches of every step.
+
+struct SLane {
+  int type = 0, algo = 0;
+  uint32_t D = 0;
+  ips_ctx* lctx = nullptr;
+  Run r;
+  PlanCfg pc;
+  ChildArgs ca;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  uintptr_t base = 0;
+  uint64_t span = 0, n_plan = 0, inflight = 0;
+  size_t ws_off = 0, ws_bytes = 0;
+  std::vector<uint32_t> reqs;      // requests of the lane, by address (request table order)
+  std::vector<uint32_t> seg_of;    // request id -> table index (indexed by position in reqs)
+  uint64_t* d_seglo = nullptr;
+  uint64_t* d_done = nullptr;
+  uint64_t* h_done = nullptr;
+  uint64_t* h_seglo = nullptr;
+  uint32_t* h_words = nullptr;     // staging of control words
+  SegItem* h_items = nullptr;
+  SegItem* d_items = nullptr;
+  uint64_t *d_mn = nullptr, *d_mx = nullptr, *h_mn = nullptr, *h_mx = nullptr;
+  uint64_t items_cap = 0;
+  std::deque<uint32_t> waiting;
+  std::vector<uint32_t> active;
+  std::vector<LTask> lt_new;
+  std::vector<CTask> roots_new;
+  uint32_t qhead = 0, qtail = 0, rounds = 0;
+  bool busy = false, ready = false;
+  int err = IPS_OK;
+};
+
+constexpr uint32_t SERVE_STEPS = 1;   // steps per round of a lane (arrivals are admitted between rounds)
+
+struct LaneExtra {
+  size_t o_seglo, o_done, o_items, o_mn, o_mx, total;
+};
+
+LaneExtra lane_extra(uint64_t nseg, uint64_t items) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  LaneExtra e;
+  e.o_seglo = 0;
+  e.o_done = al(nseg * 8);
+  e.o_items = e.o_done + al(nseg * 8);
+  e.o_mn = e.o_items + al(items * sizeof(SegItem));
+  e.o_mx = e.o_mn + al(nseg * 8);
+  e.total = e.o_mx + al(nseg * 8);
+  return e;
+}
+
+// Scan chunks of the radix roots admitted at once: every root holds more
+// than cap elements, and all of them together at most n_plan.
+uint64_t lane_items(uint64_t n_plan, uint32_t cap) { return n_plan / SEG_CHUNK + n_plan / ((uint64_t)cap + 1) + 2; }
+
+// Elements a lane holds in flight at most: its share of half the budget.
+uint64_t lane_plan_elems(uint64_t budget, uint32_t lanes, uint32_t D) {
+  return std::max<uint64_t>(2, budget / (2ull * std::max<uint32_t>(1, lanes) * D));
+}
+
+size_t lane_ws_bytes(int type, int algo, uint64_t n_plan, uint64_t nseg, const ips_params* params, int* rc) {
+  Cfg c;
+  *rc = make_cfg(n_plan, type, algo, params, &c);
+  if (*rc) return 0;
+  Layout L;
+  plan(n_plan, c, &L);
+  return ((L.total + lane_extra(nseg, lane_items(n_plan, c.cap)).total) + 255) & ~(size_t)255;
+}
+
+void lane_fail(SLane& L, ips_request* reqs, int rc, double now, uint32_t* done_cnt) {
+  for (uint32_t id : L.active) {
+    reqs[id].status = rc;
+    reqs[id].done_s = now;
+    reqs[id].detail = rc == IPS_E_DEVICE ? L.lctx->last_dev : rc == IPS_E_HIP ? L.lctx->last_hip : 0;
+    ++*done_cnt;
+  }
+  L.active.clear();
+  L.inflight = 0;
+  L.err = rc;
+}
+
+// Sets up a lane: context, stream, event, workspace slice, request table.
+int lane_init(SLane& L, ips_ctx* ctx, ips_request* reqs, uint8_t* ws, const ips_params* params) {
+  L.lctx = new (std::nothrow) ips_ctx();
+  if (!L.lctx) return IPS_E_INVALID_ARG;
+  L.lctx->device = ctx->device;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+  HIPCHK(ctx, hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+  const uint64_t nseg = L.reqs.size();
+  Cfg c0;
+  if (int e = make_cfg(L.n_plan, L.type, L.algo, params, &c0)) return e;
+  const uint64_t items = lane_items(L.n_plan, c0.cap);
+  L.items_cap = items;
+  const LaneExtra ex = lane_extra(nseg, items);
+  ips_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  p.flags = (p.flags | IPS_FLAG_NO_SORTED_CHECK) & ~(uint32_t)(IPS_FLAG_PROFILE | IPS_FLAG_GRAPH | IPS_FLAG_HOST_PLAN);
+  const size_t pin_extra = ex.total + 256;
+  uint8_t* hx = nullptr;
+  int rc = setup_run(L.lctx, L.r, reinterpret_cast<void*>(L.base), L.span, L.n_plan, L.type, L.algo,
+                     ws + L.ws_off, L.ws_bytes, ex.total, &p, L.st, pin_extra, &hx);
+  if (rc) return rc;
+  if (!hx) return IPS_E_INVALID_ARG;
+  Run& r = L.r;
+  r.lds_min = 1;   // every step sorts the LDS-tier children it produced (latency)
+  uint8_t* wx = r.ws + r.L.total;
+  L.d_seglo = reinterpret_cast<uint64_t*>(wx + ex.o_seglo);
+  L.d_done = reinterpret_cast<uint64_t*>(wx + ex.o_done);
+  L.d_items = reinterpret_cast<SegItem*>(wx + ex.o_items);
+  L.d_mn = reinterpret_cast<uint64_t*>(wx + ex.o_mn);
+  L.d_mx = reinterpret_cast<uint64_t*>(wx + ex.o_mx);
+  L.h_seglo = reinterpret_cast<uint64_t*>(hx + ex.o_seglo);
+  L.h_done = reinterpret_cast<uint64_t*>(hx + ex.o_done);
+  L.h_items = reinterpret_cast<SegItem*>(hx + ex.o_items);
+  L.h_mn = reinterpret_cast<uint64_t*>(hx + ex.o_mn);
+  L.h_mx = reinterpret_cast<uint64_t*>(hx + ex.o_mx);
+  L.h_words = reinterpret_cast<uint32_t*>(hx + ex.total);
+  for (uint64_t i = 0; i < nseg; ++i)
+    L.h_seglo[i] = (reinterpret_cast<uintptr_t>(reqs[L.reqs[i]].d_data) - L.base) / L.D;
+  HIPCHK(L.lctx, hipMemcpyAsync(L.d_seglo, L.h_seglo, nseg * 8, hipMemcpyHostToDevice, L.st));
+  HIPCHK(L.lctx, launch_fill32(reinterpret_cast<uint32_t*>(L.d_done), 2 * nseg, 0u, L.st));
+  const uint64_t lo = reinterpret_cast<uintptr_t>(L.d_seglo), dn = reinterpret_cast<uintptr_t>(L.d_done);
+  L.h_words[0] = (uint32_t)lo; L.h_words[1] = (uint32_t)(lo >> 32);
+  L.h_words[2] = (uint32_t)dn; L.h_words[3] = (uint32_t)(dn >> 32);
+  L.h_words[4] = (uint32_t)nseg;
+  HIPCHK(L.lctx, hipMemcpyAsync(r.a.ctrl + CTRL_SEGLO, L.h_words, 5 * 4, hipMemcpyHostToDevice, L.st));
+  HIPCHK(L.lctx, launch_fill32(r.a.ctrl + CTRL_QHEAD, 2, 0u, L.st));
+  HIPCHK(L.lctx, launch_fill32(reinterpret_cast<uint32_t*>(r.a.step_el), MAX_STEPS_RECORDED * 8, 0u, L.st));
+  HIPCHK(L.lctx, launch_fill32(r.a.ctrl + CTRL_NLDS, 14, 0u, L.st));
+  plan_cfg(r, &L.pc, &L.ca);
+  HIPCHK(L.lctx, hipStreamSynchronize(L.st));   // the staging of the table is reused below
+  L.ready = true;
+  return IPS_OK;
+}
+
+// Admission of one request into an idle lane (returns false when it must
+// wait).  Radix roots need their key range first: collected here and
+// resolved by lane_resolve_radix.
+bool lane_admit(SLane& L, ips_request& q, uint32_t id, std::vector<uint32_t>& radix_new) {
+  if (L.inflight + q.n > L.n_plan) return false;
+  L.inflight += q.n;
+  const uint64_t l = (reinterpret_cast<uintptr_t>(q.d_data) - L.base) / L.D;
+  L.active.push_back(id);
+  if (q.n <= L.r.c.cap) {
+    LTask t;
+    t.l = l;
+    t.n = (uint32_t)q.n;
+    t.pad = 0;
+    L.lt_new.push_back(t);
+  } else if (L.r.c.radix) {
+    radix_new.push_back(id);
+  } else {
+    CTask t;
+    t.l = l; t.n = q.n; t.level = 0; t.tflags = 0; t.shift = 0; t.width = 0;
+    L.roots_new.push_back(t);
+  }
+  return true;
+}
+
+// Key ranges of newly admitted radix requests (one batched scan, waited
+// for: the lane is idle), then their root tasks.  Requests whose keys are
+// all equal are finished at once.
+int lane_resolve_radix(SLane& L, ips_request* reqs, const std::vector<uint32_t>& ids, double now,
+                       uint32_t* done_cnt) {
+  if (ids.empty()) return IPS_OK;
+  Run& r = L.r;
+  uint64_t ni = 0;
+  for (uint32_t q = 0; q < ids.size(); ++q) {
+    const ips_request& rq = reqs[ids[q]];
+    const uint64_t l = (reinterpret_cast<uintptr_t>(rq.d_data) - L.base) / L.D;
+    for (uint64_t o = 0; o < rq.n; o += SEG_CHUNK) {
+      if (ni >= L.items_cap) return IPS_E_INVALID_ARG;
+      SegItem it;
+      it.l = l + o;
+      it.n = (uint32_t)std::min<uint64_t>(SEG_CHUNK, rq.n - o);
+      it.seg = q;
+      it.first = o == 0;
+      it.pad = 0;
+      L.h_items[ni++] = it;
+    }
+  }
+  const uint32_t m = (uint32_t)ids.size();
+  HIPCHK(L.lctx, hipMemcpyAsync(L.d_items, L.h_items, ni * sizeof(SegItem), hipMemcpyHostToDevice, L.st));
+  HIPCHK(L.lctx, launch_fill32(reinterpret_cast<uint32_t*>(L.d_mn), 2 * m, 0xFFFFFFFFu, L.st));
+  HIPCHK(L.lctx, launch_fill32(reinterpret_cast<uint32_t*>(L.d_mx), 2 * m, 0u, L.st));
+  HIPCHK(L.lctx, r.c.L->seg_minmax(L.d_items, (uint32_t)ni, r.data, L.d_mn, L.d_mx, L.st));
+  HIPCHK(L.lctx, hipMemcpyAsync(L.h_mn, L.d_mn, m * 8, hipMemcpyDeviceToHost, L.st));
+  HIPCHK(L.lctx, hipMemcpyAsync(L.h_mx, L.d_mx, m * 8, hipMemcpyDeviceToHost, L.st));
+  HIPCHK(L.lctx, hipStreamSynchronize(L.st));
+  for (uint32_t q = 0; q < m; ++q) {
+    ips_request& rq = reqs[ids[q]];
+    HTask h;
+    const uint64_t l = (reinterpret_cast<uintptr_t>(rq.d_data) - L.base) / L.D;
+    if (!make_root(r.c, l, rq.n, L.h_mn[q], L.h_mx[q], &h)) {   // all keys equal: sorted
+      rq.status = IPS_OK;
+      rq.done_s = now;
+      L.inflight -= rq.n;
+      L.active.erase(std::find(L.active.begin(), L.active.end(), ids[q]));
+      ++*done_cnt;
+      continue;
+    }
+    CTask t;
+    t.l = h.l; t.n = h.n; t.level = 0; t.tflags = h.tflags; t.shift = h.shift; t.width = h.width;
+    L.roots_new.push_back(t);
+  }
+  return IPS_OK;
+}
+
+// One round of an idle lane: the new small requests through the LDS tier,
+// the new roots onto the queue, SERVE_STEPS device-planned steps, and the
+// asynchronous read-back of the control block and the request counters.
+int lane_launch(SLane& L) {
+  Run& r = L.r;
+  if (!L.lt_new.empty()) {
+    if (int e = launch_lds_tasks(r, L.lt_new, 0)) return e;
+    L.lt_new.clear();
+  }
+  if (!L.roots_new.empty()) {
+    if ((uint64_t)(L.qtail - L.qhead) + L.roots_new.size() > r.L.QCAP) return IPS_E_DEVICE;
+    CTask* h = reinterpret_cast<CTask*>(r.h_rb);
+    const size_t chunk = r.rb_bytes / sizeof(CTask);
+    size_t done = 0;
+    while (done < L.roots_new.size()) {
+      const size_t cnt = std::min(chunk, L.roots_new.size() - done);
+      std::memcpy(h, L.roots_new.data() + done, cnt * sizeof(CTask));
+      // ring positions qtail .. qtail + cnt - 1 (modulo the capacity): at most two copies
+      const uint32_t p0 = L.qtail % r.L.QCAP;
+      const size_t first = std::min<size_t>(cnt, r.L.QCAP - p0);
+      HIPCHK(L.lctx, hipMemcpyAsync(r.a.queue + p0, h, first * sizeof(CTask), hipMemcpyHostToDevice, L.st));
+      if (first < cnt)
+        HIPCHK(L.lctx, hipMemcpyAsync(r.a.queue, h + first, (cnt - first) * sizeof(CTask), hipMemcpyHostToDevice,
+                                      L.st));
+      L.qtail += (uint32_t)cnt;
+      done += cnt;
+      if (done < L.roots_new.size()) HIPCHK(L.lctx, hipStreamSynchronize(L.st));   // staging reused
+    }
+    L.roots_new.clear();
+    HIPCHK(L.lctx, launch_fill32(r.a.ctrl + CTRL_QTAIL, 1, L.qtail, L.st));
+  }
+  for (uint32_t s = 0; s < SERVE_STEPS; ++s)
+    if (int e = enqueue_step(r, L.pc, L.ca, MAX_STEPS_RECORDED)) return e;
+  HIPCHK(L.lctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, L.st));
+  HIPCHK(L.lctx, hipMemcpyAsync(L.h_done, L.d_done, L.reqs.size() * 8, hipMemcpyDeviceToHost, L.st));
+  HIPCHK(L.lctx, hipEventRecord(L.ev, L.st));
+  L.busy = true;
+  ++L.rounds;
+  return IPS_OK;
+}
+
+// Checks a busy lane; after its round finished, completes the requests whose
+// elements are all final.  Returns an error code of the round, if any.
+int lane_poll(SLane& L, ips_request* reqs, double now, uint64_t* data_bytes, uint32_t* done_cnt) {
+  if (!L.busy) return IPS_OK;
+  const hipError_t q = hipEventQuery(L.ev);
+  if (q == hipErrorNotReady) return IPS_OK;
+  L.busy = false;
+  if (q != hipSuccess) { L.lctx->last_hip = (int)q; return IPS_E_HIP; }
+  if (int e = check_dev_error(L.r)) return e;
+  L.qhead = L.r.h_ctrl[CTRL_QHEAD];
+  L.qtail = L.r.h_ctrl[CTRL_QTAIL];
+  std::vector<uint32_t> still;
+  for (uint32_t id : L.active) {
+    const uint32_t pos = L.seg_of[id];
+    if (L.h_done[pos] >= reqs[id].n) {
+      reqs[id].status = IPS_OK;
+      reqs[id].done_s = now;
+      L.inflight -= reqs[id].n;
+      *data_bytes -= reqs[id].n * (uint64_t)L.D;
+      ++*done_cnt;
+    } else {
+      still.push_back(id);
+    }
+  }
+  L.active.swap(still);
+  // An empty queue runs every pending LDS-tier task within the round, so
+  // work left over then is a broken invariant, not a reason to spin.
+  if (!L.active.empty() && L.qhead == L.qtail && L.lt_new.empty() && L.roots_new.empty()) {
+    L.lctx->last_dev = 0x104;
+    return IPS_E_DEVICE;
+  }
+  return IPS_OK;
+}
+
+using SClock = std::chrono::steady_clock;
+double s_since(SClock::time_point t0) { return std::chrono::duration<double>(SClock::now() - t0).count(); }
+
+int serve_lanes_plan(const ips_request* reqs, uint32_t nreq, uint64_t budget, const ips_params* params,
+                     std::vector<SLane>* lanes_out, size_t* total_ws) {
+  std::vector<SLane>& lanes = *lanes_out;
+  lanes.clear();
+  *total_ws = 0;
+  std::vector<std::pair<int, int>> keys;
+  for (uint32_t i = 0; i < nreq; ++i) {
+    const std::pair<int, int> k(reqs[i].elem_type, reqs[i].algo);
+    if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+  }
+  lanes.resize(keys.size());
+  for (size_t g = 0; g < keys.size(); ++g) {
+    SLane& L = lanes[g];
+    L.type = keys[g].first;
+    L.algo = keys[g].second;
+    L.D = elem_bytes(L.type);
+    if (!L.D) return IPS_E_INVALID_ARG;
+    L.n_plan = lane_plan_elems(budget, (uint32_t)keys.size(), L.D);
+    uintptr_t lo = ~(uintptr_t)0, hi = 0;
+    for (uint32_t i = 0; i < nreq; ++i) {
+      if (reqs[i].elem_type != L.type || reqs[i].algo != L.algo || reqs[i].n < 2) continue;
+      const uintptr_t p = reinterpret_cast<uintptr_t>(reqs[i].d_data);
+      lo = std::min(lo, p);
+      hi = std::max<uintptr_t>(hi, p + reqs[i].n * L.D);
+      L.reqs.push_back(i);
+    }
+    if (L.reqs.empty()) { L.base = 0; L.span = 0; continue; }
+    L.base = lo;
+    L.span = (hi - lo + L.D - 1) / L.D;
+    std::sort(L.reqs.begin(), L.reqs.end(), [&](uint32_t a, uint32_t b) { return reqs[a].d_data < reqs[b].d_data; });
+    int rc = IPS_OK;
+    L.ws_off = *total_ws;
+    L.ws_bytes = lane_ws_bytes(L.type, L.algo, L.n_plan, L.reqs.size(), params, &rc);
+    if (rc) return rc;
+    *total_ws += L.ws_bytes;
+  }
+  return IPS_OK;
+}
+
+int serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_serve_config* cfg, void* d_ws,
+                     size_t ws_bytes, const ips_params* params) {
+  std::vector<SLane> lanes;
+  size_t total_ws = 0;
+  if (int e = serve_lanes_plan(reqs, nreq, cfg->hbm_budget, params, &lanes, &total_ws)) return e;
+  if (total_ws > ws_bytes) return IPS_E_WORKSPACE;
+  if (nreq && !d_ws) return IPS_E_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return IPS_E_MISALIGNED;
+  std::vector<int32_t> lane_of(nreq, -1);
+  for (size_t g = 0; g < lanes.size(); ++g) {
+    SLane& L = lanes[g];
+    L.seg_of.assign(nreq, 0);
+    for (uint32_t pos = 0; pos < L.reqs.size(); ++pos) {
+      L.seg_of[L.reqs[pos]] = pos;
+      lane_of[L.reqs[pos]] = (int32_t)g;
+    }
+  }
+  int first_error = IPS_OK;
+  int rc = IPS_OK;
+  std::vector<uint32_t> order(nreq);
+  for (uint32_t i = 0; i < nreq; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+  uint32_t next = 0, done = 0, round_id = 0;
+  uint64_t data_bytes = 0;
+  const SClock::time_point t0 = SClock::now();
+  while (rc == IPS_OK && done < nreq) {
+    double now = s_since(t0);
+    // arrivals go to their lane's queue (empty requests finish at once)
+    while (next < nreq && reqs[order[next]].arrival_s <= now) {
+      const uint32_t id = order[next++];
+      ips_request& q = reqs[id];
+      const int g = lane_of[id];
+      if (q.n < 2 || g < 0) {
+        q.start_s = q.done_s = now;
+        q.status = IPS_OK;
+        ++done;
+        continue;
+      }
+      SLane& L = lanes[(size_t)g];
+      if (q.n > L.n_plan || (reinterpret_cast<uintptr_t>(q.d_data) - L.base) % L.D) {
+        q.start_s = q.done_s = now;
+        q.status = q.n > L.n_plan ? IPS_E_WORKSPACE : IPS_E_MISALIGNED;
+        if (first_error == IPS_OK) first_error = q.status;
+        ++done;
+        continue;
+      }
+      if (L.err) {
+        q.start_s = q.done_s = now;
+        q.status = L.err;
+        ++done;
+        continue;
+      }
+      L.waiting.push_back(id);
+    }
+    bool any_busy = false;
+    for (SLane& L : lanes) {
+      if (!L.ready) {   // a lane is set up when its first request can be admitted
+        if (L.waiting.empty() || L.err) continue;
+        const int e = lane_init(L, ctx, reqs, static_cast<uint8_t*>(d_ws), params);
+        if (e) {
+          L.err = e;
+          if (first_error == IPS_OK) first_error = e;
+          for (uint32_t id : L.waiting) { reqs[id].status = e; reqs[id].start_s = reqs[id].done_s = now; ++done; }
+          L.waiting.clear();
+          continue;
+        }
+      }
+      const int e = lane_poll(L, reqs, now, &data_bytes, &done);
+      if (e) {
+        data_bytes -= L.inflight * L.D;
+        lane_fail(L, reqs, e, now, &done);
+        if (first_error == IPS_OK) first_error = e;
+        for (uint32_t id : L.waiting) { reqs[id].status = e; reqs[id].start_s = reqs[id].done_s = now; ++done; }
+        L.waiting.clear();
+        continue;
+      }
+      if (L.busy) { any_busy = true; continue; }
+      // admission in arrival order while the lane's plan and the budget hold
+      now = s_since(t0);
+      std::vector<uint32_t> radix_new;
+      uint32_t admitted = 0;
+      while (!L.waiting.empty() && !(cfg->max_batch && admitted >= cfg->max_batch)) {
+        ips_request& q = reqs[L.waiting.front()];
+        const uint64_t bytes = q.n * (uint64_t)L.D;
+        if (data_bytes + bytes + total_ws > cfg->hbm_budget && !L.active.empty()) break;
+        if (!lane_admit(L, q, L.waiting.front(), radix_new)) break;
+        q.start_s = now;
+        q.batch = round_id;
+        data_bytes += bytes;
+        L.waiting.pop_front();
+        ++admitted;
+      }
+      int e2 = lane_resolve_radix(L, reqs, radix_new, now, &done);
+      if (!e2 && !L.active.empty()) {
+        e2 = lane_launch(L);
+        ++round_id;
+        any_busy = any_busy || L.busy;
+      }
+      if (e2) {
+        data_bytes -= L.inflight * L.D;
+        lane_fail(L, reqs, e2, now, &done);
+        if (first_error == IPS_OK) first_error = e2;
+      }
+    }
+    if (!any_busy && done < nreq) {
+      // idle: sleep until the next arrival
+      if (next < nreq) {
+        const double left = reqs[order[next]].arrival_s - s_since(t0);
+        if (left > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(left - 1e-4));
+      }
+    } else if (any_busy) {
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
+  for (SLane& L : lanes) {
+    if (L.st) {
+      (void)hipStreamSynchronize(L.st);
+      (void)hipStreamDestroy(L.st);
+    }
+    if (L.ev) (void)hipEventDestroy(L.ev);
+    if (L.lctx) {
+      for (hipEvent_t e : L.lctx->ev_pool) (void)hipEventDestroy(e);
+      if (L.lctx->pin) (void)hipHostFree(L.lctx->pin);
+      delete L.lctx;
+    }
+  }
+  if (rc) return rc;
+  return first_error;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1398,6 +2100,7 @@ int ips_tuned_params(const ips_tune_entry* table, uint32_t count, uint64_t n, in
     if (!p.lds_task_max) p.lds_task_max = e.lds_task_max;
     if (!p.piece_blocks) p.piece_blocks = e.piece_blocks;
     if (!p.perm_groups) p.perm_groups = e.perm_groups;
+    if (!p.perm_wg) p.perm_wg = e.perm_wg;
     *out = p;
     return 1;
   }
@@ -1513,9 +2216,27 @@ int ips_sort_keys_noalloc(ips_ctx* ctx, void* d_keys, uint64_t n, int key_type, 
   return rc;
 }
 
+int ips_oop_workspace_bytes(uint64_t n, int elem_type, const ips_params* params, size_t* ws_bytes,
+                            size_t* tmp_bytes) {
+  if (!ws_bytes || !tmp_bytes) return IPS_E_INVALID_ARG;
+  *ws_bytes = 0;
+  *tmp_bytes = 0;
+  if (n >= (1ull << 32)) return IPS_E_TOO_LARGE;
+  if (int e = ips_workspace_bytes(n, elem_type, IPS_SAMPLESORT, params, ws_bytes)) return e;
+  if (n >= 2) *tmp_bytes = oop_tmp_bytes(n, elem_bytes(elem_type));
+  return IPS_OK;
+}
+
+int ips_sort_oop(ips_ctx* ctx, void* d_data, uint64_t n, int elem_type, void* d_tmp, size_t tmp_bytes,
+                 void* d_ws, size_t ws_bytes, const ips_params* params, void* stream) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  if (!elem_bytes(elem_type)) return IPS_E_INVALID_ARG;
+  return oop_impl(ctx, d_data, n, elem_type, d_tmp, tmp_bytes, d_ws, ws_bytes, params, stream);
+}
+
 int ips_sort_pairs(ips_ctx* ctx, void* d_recs, uint64_t n, int rec_type, int algo, void* d_ws,
                    size_t ws_bytes, const ips_params* params, void* stream) {
-  if (rec_type != IPS_PAIR_U64_U64 && rec_type != IPS_REC100) return IPS_E_INVALID_ARG;
+  if (rec_type != IPS_PAIR_U64_U64 && rec_type != IPS_REC100 && rec_type != IPS_QUARTET) return IPS_E_INVALID_ARG;
   return sort_impl(ctx, d_recs, n, rec_type, algo, d_ws, ws_bytes, params, stream);
 }
 
@@ -1545,6 +2266,21 @@ size_t ips_internal_ws_bound(uint64_t n, uint64_t nseg, int type, int algo, cons
   Layout L;
   plan(n, c, &L);
   return L.total + seg_extra_bytes(c, n, nseg);
+}
+
+// Continuous-batching replay of a trace and its workspace (ips_serve.hip).
+__attribute__((visibility("hidden")))
+int ips_internal_serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_serve_config* cfg,
+                                  void* d_ws, size_t ws_bytes, const ips_params* params) {
+  if (!ctx) return IPS_E_INVALID_ARG;
+  return serve_continuous(ctx, reqs, nreq, cfg, d_ws, ws_bytes, params);
+}
+
+__attribute__((visibility("hidden")))
+int ips_internal_serve_ws(const ips_request* reqs, uint32_t nreq, uint64_t budget, const ips_params* params,
+                          size_t* out) {
+  std::vector<SLane> lanes;
+  return serve_lanes_plan(reqs, nreq, budget, params, &lanes, out);
 }
 
 int ips_sort_batch(ips_ctx* ctx, void* const* d_ptrs, const uint64_t* ns, uint32_t count,

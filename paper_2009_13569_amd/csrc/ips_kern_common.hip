@@ -2,6 +2,7 @@
 #define IPS_COMMON_KERNELS 1
 #include "ips_kernels.hpp"
 #include "ips_launch.hpp"
+#include "ips_oop.hpp"
 
 namespace ips {
 
@@ -54,6 +55,21 @@ hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n,
   if (!max_n) return hipSuccess;
   uint32_t g = (max_n + 255) / 256 < 4096 ? (max_n + 255) / 256 : 4096;
   hipLaunchKernelGGL(k_fill32_cnt, dim3(g), dim3(256), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_oop_scan(const OopArgs& a, uint32_t nt, hipStream_t st) {
+  if (!nt) return hipSuccess;
+  hipLaunchKernelGGL(k_oop_scan, dim3(nt), dim3(MAX_NB), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_oop_children(const OopArgs& a, uint32_t nt, uint32_t* ctrl, CTask* next, uint32_t next_cap,
+                               LTask* lds, LTask* copy, uint32_t list_cap, uint32_t cap, uint32_t to_second,
+                               hipStream_t st) {
+  if (!nt) return hipSuccess;
+  hipLaunchKernelGGL(k_oop_children, dim3(nt), dim3(256), 0, st, a, ctrl, next, next_cap, lds, copy, list_cap,
+                     cap, to_second);
   return hipGetLastError();
 }
 

@@ -4,6 +4,9 @@
 #include "ips_kernels.hpp"
 #include "ips_launch.hpp"
 #include "ips_lds_tier.hpp"
+#include "ips_oop.hpp"
+
+#include <type_traits>
 
 namespace ips {
 
@@ -27,6 +30,10 @@ template <> struct LdsShape<TPair> {
 template <> struct LdsShape<TRec100> {
   static constexpr uint32_t N0 = 256, E0 = 4, N1 = 256, E1 = 4, N2 = 256, E2 = 4, NET = 16;
 };
+// The Quartet's tier is the bitonic kernel (capacities 512, 1024, 2048).
+template <> struct LdsShape<TQuartet> {
+  static constexpr uint32_t N0 = 256, E0 = 2, N1 = 256, E1 = 4, N2 = 256, E2 = 8, NET = 32;
+};
 
 template <class T>
 struct LaunchImpl {
@@ -44,7 +51,7 @@ struct LaunchImpl {
     if (!attr_done) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_classify<T, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(BUF_LDS_BYTES + MAX_NB * BUF_PAD_DW * 4));
+                                (int)(T::BUF_BYTES + MAX_NB * BUF_PAD_DW * 4));
       attr_done = true;
     }
     if (gbuf)
@@ -53,9 +60,13 @@ struct LaunchImpl {
       hipLaunchKernelGGL((k_classify<T, false>), dim3(nwg), dim3(CLS_THREADS), dyn, st, a);
     return hipGetLastError();
   }
-  static hipError_t permute(const BatchArgs& a, uint32_t nwg, hipStream_t st) {
+  // Workgroups of 128, 256 or 512 threads (the tuning table picks one).
+  static hipError_t permute(const BatchArgs& a, uint32_t nwg, uint32_t threads, hipStream_t st) {
     if (!nwg) return hipSuccess;
-    hipLaunchKernelGGL((k_permute<T>), dim3(nwg), dim3(PERM_THREADS), 0, st, a);
+    if (threads == 128) hipLaunchKernelGGL((k_permute<T, 128>), dim3(nwg), dim3(128), 0, st, a);
+    else if (threads == 512) hipLaunchKernelGGL((k_permute<T, 512>), dim3(nwg), dim3(512), 0, st, a);
+    else if (threads == 256) hipLaunchKernelGGL((k_permute<T, 256>), dim3(nwg), dim3(256), 0, st, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
   }
   static hipError_t cleanup_a(const BatchArgs& a, uint32_t nt, hipStream_t st) {
@@ -72,6 +83,27 @@ struct LaunchImpl {
   template <uint32_t N, uint32_t E>
   static hipError_t lds_launch(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl,
                                const uint32_t* cnt, uint32_t cnt_cap, uint32_t* pop, hipStream_t st) {
+    if constexpr (std::is_same_v<T, TQuartet>) {
+      constexpr uint32_t C = N * E;
+      static bool qattr = false;
+      static uint32_t qres = 0;
+      const size_t dyn = lds_bitonic_bytes<T, C>();
+      if (!qattr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lds_bitonic<T, C>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_lds_bitonic<T, C>),
+                                                         256, dyn) == hipSuccess &&
+            per_cu > 0 && cus > 0)
+          qres = (uint32_t)(per_cu * cus);
+        qattr = true;
+      }
+      if (cnt && qres && nt > qres) nt = qres;
+      hipLaunchKernelGGL((k_lds_bitonic<T, C>), dim3(nt), dim3(256), dyn, st, lt, data, ctrl, cnt, cnt_cap, pop);
+      return hipGetLastError();
+    } else {
     static bool attr_done = false;
     static uint32_t resident = 0;   // workgroups of this kernel the device holds at once
     const size_t dyn = LdsTier<T, N, E, SH::NET>::lds_bytes();
@@ -94,6 +126,7 @@ struct LaunchImpl {
     hipLaunchKernelGGL((k_lds_tier<T, N, E, SH::NET>), dim3(nt), dim3(N), dyn, st, lt, data, ctrl, cnt,
                        cnt_cap, pop);
     return hipGetLastError();
+    }
   }
   // nt workgroups; with `cnt` (a device count) they claim the list's tasks
   // through the variant's counter ctrl[CTRL_LDSPOP + variant] (zero at launch).
@@ -154,11 +187,28 @@ struct LaunchImpl {
     hipLaunchKernelGGL((k_seg_reverse<T::DW>), dim3(nitems), dim3(256), 0, st, items, data);
     return hipGetLastError();
   }
+  static hipError_t oop_classify(const OopArgs& a, uint32_t nwg, hipStream_t st) {
+    if (!nwg) return hipSuccess;
+    hipLaunchKernelGGL((k_oop_classify<T>), dim3(nwg), dim3(OOP_THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t oop_distribute(const OopArgs& a, uint32_t nwg, hipStream_t st) {
+    if (!nwg) return hipSuccess;
+    hipLaunchKernelGGL((k_oop_distribute<T>), dim3(nwg), dim3(OOP_THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+  static hipError_t copy_ranges(const LTask* list, uint32_t count, const uint32_t* from, uint32_t* to,
+                                hipStream_t st) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL((k_copy_ranges<T::DW>), dim3(count), dim3(256), 0, st, list, from, to);
+    return hipGetLastError();
+  }
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
-        CAP2, {CAP0, CAP1, CAP2}, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
-        &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax, &seg_order, &seg_reverse};
+        CAP2, {CAP0, CAP1, CAP2}, T::BUF_BYTES, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
+        &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax, &seg_order, &seg_reverse,
+        &oop_classify, &oop_distribute, &copy_ranges};
     return &t;
   }
 };

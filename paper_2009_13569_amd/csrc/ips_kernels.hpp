@@ -34,6 +34,24 @@ __device__ __forceinline__ void at_store32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Serving: `cnt` elements starting at element l of the data are in their
+// final place; they are counted for the request that holds element l (the
+// requests' first elements are listed in ascending order).
+__device__ __forceinline__ void seg_done_add(const uint32_t* ctrl, uint64_t l, uint64_t cnt) {
+  const uint32_t nseg = ctrl[CTRL_NSEG];
+  if (!nseg) return;
+  const uint64_t* lo = reinterpret_cast<const uint64_t*>((uint64_t)ctrl[CTRL_SEGLO] |
+                                                         ((uint64_t)ctrl[CTRL_SEGLO + 1] << 32));
+  unsigned long long* done = reinterpret_cast<unsigned long long*>((uint64_t)ctrl[CTRL_SEGDONE] |
+                                                                   ((uint64_t)ctrl[CTRL_SEGDONE + 1] << 32));
+  uint32_t a = 0, b = nseg;   // the last request whose first element is <= l
+  while (b - a > 1) {
+    const uint32_t m = (a + b) >> 1;
+    if (lo[m] <= l) a = m; else b = m;
+  }
+  atomicAdd(&done[a], (unsigned long long)cnt);
+}
+
 __device__ __forceinline__ void dev_error(uint32_t* ctrl, uint32_t code, uint32_t x,
                                           uint32_t y) {
   if (atomicCAS(&ctrl[CTRL_ERR], 0u, code) == 0u) {
@@ -163,8 +181,7 @@ struct BlockDiv {
 
 template <class T>
 __device__ __forceinline__ typename T::Key key_of(const uint32_t (&w)[T::DW]) {
-  constexpr int D = T::DW;
-  return T::key(w[0], w[D > 1 ? 1 : 0], w[D > 2 ? 2 : 0]);
+  return T::key_w(w);
 }
 
 // Branchless decision tree (Definitions and Preliminaries, Algorithm 1):
@@ -702,11 +719,11 @@ k_classify(BatchArgs a) {
   __syncthreads();
   for (uint32_t j = tid; j < nb; j += NT) {
     const uint32_t nfull = s_fn[j].y;
-    a.wg_nfull[(uint64_t)wg * MAX_NB + j] = nfull;
-    a.wg_left[(uint64_t)wg * MAX_NB + j] = s_cnt[j] - nfull * b;
+    a.wg_nfull[(uint64_t)wg * a.nbs + j] = nfull;
+    a.wg_left[(uint64_t)wg * a.nbs + j] = s_cnt[j] - nfull * b;
     if (radix && j < MAX_K) {
-      a.wg_min[(uint64_t)wg * MAX_K + j] = s_mn[j];
-      a.wg_max[(uint64_t)wg * MAX_K + j] = s_mx[j];
+      a.wg_min[(uint64_t)wg * a.nbs + j] = s_mn[j];
+      a.wg_max[(uint64_t)wg * a.nbs + j] = s_mx[j];
     }
   }
   if (tid == 0) a.wg_F[wg] = s_wpos;
@@ -771,11 +788,11 @@ __global__ void __launch_bounds__(512) k_bucket_sums(BatchArgs a, uint32_t group
   const bool radix = (tk.tflags & TF_RADIX) != 0;
   uint64_t full = 0, left = 0, mn = ~0ull, mx = 0;
   for (uint32_t s = lane; s < W; s += 64) {
-    const uint64_t o = (uint64_t)(wg0 + s) * MAX_NB + j;
+    const uint64_t o = (uint64_t)(wg0 + s) * a.nbs + j;
     full += a.wg_nfull[o];
     left += a.wg_left[o];
     if (radix) {
-      const uint64_t om = (uint64_t)(wg0 + s) * MAX_K + j;
+      const uint64_t om = (uint64_t)(wg0 + s) * a.nbs + j;
       const uint64_t x = a.wg_min[om], y = a.wg_max[om];
       mn = x < mn ? x : mn;
       mx = y > mx ? y : mx;
@@ -894,6 +911,7 @@ __global__ void __launch_bounds__(512) k_boundaries(BatchArgs a, uint32_t cmax) 
                      a.p_cum[p] = cu;
                      a.p_fcnt[p] = 0;
                      a.p_word[(uint64_t)p * PWORD_STRIDE] = ((uint64_t)c0 << 32) | (uint64_t)((uint32_t)ri + PTR_BIAS);
+                     a.p_word[(uint64_t)p * PWORD_STRIDE + 1] = 0;
                      cu += (uint32_t)(ri - (int32_t)c0 + 1);
                      ++p;
                      if (place) ple = p;
@@ -914,15 +932,26 @@ __device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t lane) {
 
 
 template <class T>
-__device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[PERM_RD], uint32_t lbase,
+__device__ __forceinline__ uint32_t block_bucket(const uint32_t (&dat)[PERM_RD], uint32_t lbase, uint32_t glanes,
                                                  const typename T::Key* tree,
                                                  const typename T::Key* spl, uint32_t logK,
                                                  uint32_t eq, bool radix, uint32_t shift,
                                                  uint32_t rmask) {
-  const uint32_t w0 = shfl32(dat[0], lbase);
-  const uint32_t w1 = (T::KDW > 1) ? shfl32(dat[0], lbase + 1) : 0u;
-  const uint32_t w2 = (T::KDW > 2) ? shfl32(dat[0], lbase + 2) : 0u;
-  return bucket_of<T>(T::key(w0, w1, w2), tree, spl, logK, eq, radix, shift, rmask);
+  // dword x of the block is register x / glanes of lane lbase + x % glanes
+  // (glanes >= 4, so the first element's KDW <= 6 key dwords are in
+  // registers 0 and 1)
+  static_assert(T::KDW <= 8, "key dwords beyond the first two registers of a group");
+  uint32_t w[T::KDW];
+#pragma unroll
+  for (int x = 0; x < T::KDW; ++x) {
+    if constexpr (T::KDW <= 4) {
+      w[x] = shfl32(dat[0], lbase + x);
+    } else {
+      const uint32_t q = (uint32_t)x >= glanes, l = q ? (uint32_t)x - glanes : (uint32_t)x;
+      w[x] = shfl32(q ? dat[1] : dat[0], lbase + l);
+    }
+  }
+  return bucket_of<T>(T::key_w(w), tree, spl, logK, eq, radix, shift, rmask);
 }
 
 // Waits until every load into `v` has returned (an opaque use of each
@@ -941,15 +970,24 @@ __device__ __forceinline__ void wait_regs(const uint32_t (&v)[PERM_RD]) {
 // first element, and reserves the next slot w of a piece of the destination
 // bucket: an unprocessed block there is swapped out (or skipped if it is
 // already correct), an empty slot is written.  A slot that another group
-// is still reading (w > r but w <= the piece's initial r) is written only
-// after that reader has set the block's flag (the paper's reader guard).
+// may still be reading (w > r but w <= the piece's initial r) is written
+// only after every read of a block claimed from that piece has finished:
+// the paper's reader counter of a bucket, kept per piece in the word next
+// to the pointer word.  Its low half counts finished reads; its high half
+// is set, by whichever operation takes the piece's last unprocessed block
+// (a claim with r = w or a swap with w = r), to 1 + the first block that
+// claims took (claims take blocks from the initial r downward, so blocks
+// [first, r_init] are exactly the claimed ones, and no later claim can
+// succeed).  A waiting writer proceeds once the count reaches
+// r_init - first + 1, so the reader state is one word per piece,
+// O(k + stripes) per task, not one flag per block.
 //
 // Every iteration first issues the pointer operations of all groups of the
 // wavefront together, then all block loads together, so that one iteration
 // costs about one atomic and one load latency whatever mix of states the
 // groups are in.
-template <class T>
-__global__ void __launch_bounds__(PERM_THREADS)
+template <class T, uint32_t NT>
+__global__ void __launch_bounds__(NT)
 k_permute(BatchArgs a) {
   using Key = typename T::Key;
   __shared__ Key s_tree[MAX_K];
@@ -964,12 +1002,12 @@ k_permute(BatchArgs a) {
   const uint32_t rmask = low_mask32(tk.width);
   if (!radix) {
     const StepRec* rec = a.recs + tix;
-    for (uint32_t i = threadIdx.x; i < tk.K; i += PERM_THREADS) {
+    for (uint32_t i = threadIdx.x; i < tk.K; i += NT) {
       s_tree[i] = T::from_slot(rec->tree[i]);
       s_spl[i] = T::from_slot(rec->spl[i]);
     }
   }
-  for (uint32_t j = threadIdx.x; j < tk.nb; j += PERM_THREADS) {
+  for (uint32_t j = threadIdx.x; j < tk.nb; j += NT) {
     const uint32_t lo = a.b_plb[tk.bucket_base + j] - tk.piece_base;
     s_plb[j] = lo;
     s_npl[j] = a.b_ple[tk.bucket_base + j] - tk.piece_base - lo;
@@ -979,7 +1017,7 @@ k_permute(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t gl = lane & (GL - 1);
   const uint32_t lbase = lane - gl;
-  const uint32_t gid = (blockIdx.x - tk.pwg_base) * (PERM_THREADS / GL) + threadIdx.x / GL;
+  const uint32_t gid = (blockIdx.x - tk.pwg_base) * (NT / GL) + threadIdx.x / GL;
   const uint32_t b = tk.b, NB = tk.NB;
   const uint32_t BDW = b * T::DW;
   uint32_t* gd = a.data + tk.l * T::DW;
@@ -991,7 +1029,6 @@ k_permute(BatchArgs a) {
   const uint32_t* pc = a.p_c + pb;
   const int32_t* pr = a.p_rinit + pb;
   const uint32_t* pcum = a.p_cum + pb;
-  uint32_t* flags = a.flags + tk.flag_off;
   const uint32_t bb = tk.bucket_base;
   const bool partial = (tk.n % b) != 0;
   uint32_t* ovf = a.ovf + (uint64_t)tix * (MAX_BLOCK_BYTES / 4);
@@ -1049,16 +1086,21 @@ k_permute(BatchArgs a) {
     if (__all(mode == DONE)) break;
     PSTAT(st_loop);
     // 1. Pointer operations of every group (leader lanes).
-    uint32_t r0 = NONE, r1 = 0, r2 = 0;   // CLAIM: r0 = P; PLACE: r0 = w (NONE: piece full), r1 = r,
-                                          // r2 = the piece's initial r; WAIT: r0 = flag
+    uint32_t r0 = NONE, r1 = 0, r2 = 0;   // CLAIM: r0 = P, r1 = 1 if P = w; PLACE: r0 = w (NONE: piece full), r1 = r,
+                                          // r2 = the piece's initial r; WAIT: r0 = 1 once the slot's reads are done
     if (gl == 0) {
       if (mode == CLAIM) {
         // Decrementing r of an exhausted piece is harmless (r only moves
         // further below w), so each attempt is one read-modify-write.
         while (src < src_end) {
-          const uint64_t wv = at_add64(&word[(uint64_t)src * PWORD_STRIDE], ~0ull);
+          const uint64_t wv = at_add64(&word[src * PWORD_STRIDE], ~0ull);
           const int32_t w = (int32_t)(wv >> 32), r = (int32_t)((uint32_t)wv - PTR_BIAS);
-          if (r >= w) { r0 = (uint32_t)r; PSTAT(st_claim_ok); break; }
+          if (r >= w) {
+            r0 = (uint32_t)r;
+            r1 = r == w;   // the piece's last unprocessed block: blocks [w, r_init] were claimed
+            PSTAT(st_claim_ok);
+            break;
+          }
           PSTAT(st_claim_fail);
           ++src;
         }
@@ -1105,12 +1147,14 @@ k_permute(BatchArgs a) {
           // their latencies overlap
           const uint32_t cap = pc[sr];
           const int32_t rin = pr[sr];
-          const uint64_t wv = at_add64(&word[(uint64_t)sr * PWORD_STRIDE], 1ull << 32);
+          const uint64_t wv = at_add64(&word[sr * PWORD_STRIDE], 1ull << 32);
           const uint32_t w = (uint32_t)(wv >> 32);
           r2 = (uint32_t)rin;
           if (w < cap) {
             r0 = w;
             r1 = (uint32_t)((int32_t)((uint32_t)wv - PTR_BIAS));
+            if (r0 == r1)   // this swap takes the last unprocessed block: [w + 1, r_init] were claimed
+              (void)at_add64(&word[sr * PWORD_STRIDE + 1], (uint64_t)(w + 2) << 32);
             if (w + 1 == cap) {            // this placement filled the piece
               if (cs == 1) {
                 atomicOr((unsigned long long*)fm, bit64(q));
@@ -1126,7 +1170,11 @@ k_permute(BatchArgs a) {
           }
         }
       } else if (mode == WAIT) {
-        r0 = at_load32(&flags[wpos]);
+        // the waited slot lies in placement piece cur_q of the held block's bucket
+        const uint32_t sr = s_plb[dest] + cur_q;
+        const uint64_t v = at_load64(&word[sr * PWORD_STRIDE + 1]);
+        const uint32_t first1 = (uint32_t)(v >> 32), done = (uint32_t)v;   // 1 + first claimed block
+        r0 = (first1 != 0 && (uint64_t)done + first1 >= (uint64_t)(uint32_t)pr[sr] + 2) ? 1u : 0u;
       }
     }
     r0 = shfl32(r0, lbase);
@@ -1160,7 +1208,7 @@ k_permute(BatchArgs a) {
       } else if ((int32_t)r0 <= (int32_t)r1) {
         ld = r0;                                   // unprocessed: swap candidate
       } else if ((int32_t)r0 <= (int32_t)r2) {
-        wpos = r0;                                 // being read by another group
+        wpos = r0;                                 // maybe still being read by another group
         spin = 0;
         mode = WAIT;
         PSTAT(st_wait);
@@ -1188,16 +1236,19 @@ k_permute(BatchArgs a) {
       }
       wait_regs(tmp);
       if (mode == CLAIM) {
-        if (gl == 0) at_store32(&flags[ld], 1u);
+        // This read has finished; a claim that took the piece's last
+        // unprocessed block also publishes 1 + the first claimed block (its
+        // own), which waiting writers need together with this read anyway.
+        if (gl == 0) (void)at_add64(&word[src * PWORD_STRIDE + 1], 1ull + (r1 ? (uint64_t)(ld + 1) << 32 : 0ull));
 #pragma unroll
         for (int q = 0; q < PERM_RD; ++q) dat[q] = tmp[q];
-        dest = block_bucket<T>(dat, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        dest = block_bucket<T>(dat, lbase, GL, s_tree, s_spl, logK, eq, radix, shift, rmask);
         probe = gid * 0x9E3779B1u + dest * 0x85EBCA6Bu;
         use_mask = false;
         fails = 0;
         mode = PLACE;
       } else {
-        const uint32_t d2 = block_bucket<T>(tmp, lbase, s_tree, s_spl, logK, eq, radix, shift, rmask);
+        const uint32_t d2 = block_bucket<T>(tmp, lbase, GL, s_tree, s_spl, logK, eq, radix, shift, rmask);
         if (d2 == dest) {
           PSTAT(st_skip);                          // already in its bucket
         } else {
@@ -1312,7 +1363,7 @@ __device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t part,
     const uint32_t s0 = tid * per;
     uint64_t loc = 0;
     for (uint32_t i = 0; i < per; ++i)
-      if (s0 + i < W) loc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * MAX_NB + j];
+      if (s0 + i < W) loc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * a.nbs + j];
     uint64_t inc = loc;
     for (int o = 1; o < 64; o <<= 1) {
       const uint64_t y = (uint64_t)__shfl_up((long long)inc, o, 64);
@@ -1325,7 +1376,7 @@ __device__ void cleanup_b_item(const BatchArgs& a, uint32_t item, uint32_t part,
     for (uint32_t w = 0; w < wave; ++w) acc += s_ws[w];
     for (uint32_t i = 0; i < per; ++i) {
       if (s0 + i < W) {
-        acc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * MAX_NB + j];
+        acc += a.wg_left[(uint64_t)(tk.wg_base + s0 + i) * a.nbs + j];
         s_off[3 + s0 + i] = acc;
       }
     }
@@ -1389,7 +1440,7 @@ __device__ void cleanup_b_item_wave(const BatchArgs& a, uint32_t item, uint64_t*
   const uint64_t tlen = (g.F < g.end) ? g.end - g.F : 0;
   const uint64_t sp = (g.count > 0 && !g.ovf && g.F > g.end) ? g.F - g.end : 0;
   const uint64_t head = sp + (g.ovf ? b : 0);
-  const uint64_t loc = lane < W ? a.wg_left[(uint64_t)(tk.wg_base + lane) * MAX_NB + j] : 0;
+  const uint64_t loc = lane < W ? a.wg_left[(uint64_t)(tk.wg_base + lane) * a.nbs + j] : 0;
   uint64_t inc = loc;
   for (int o = 1; o < 64; o <<= 1) {
     const uint64_t y = (uint64_t)__shfl_up((long long)inc, o, 64);
@@ -1702,6 +1753,7 @@ __global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint
       const Child ch = child_of(a, c, tk, j);
       if (ch.dest < 4) atomicAdd(&s_n[ch.dest], 1u);
       if (ch.dest < 3) atomicAdd(&s_el[ch.dest], (unsigned long long)ch.sz);
+      if (ch.dest == 4 && ch.sz) seg_done_add(a.ctrl, tk.l + ch.s0, ch.sz);   // final bucket
     }
   }
   __syncthreads();
@@ -1794,7 +1846,7 @@ __device__ uint32_t dev_block_elems(const PlanCfg& c, uint32_t nb) {
     const uint32_t b = c.b_req ? c.b_req : 1;
     return b < bmax ? b : bmax;
   }
-  uint32_t b = BUF_LDS_BYTES / (nb * c.D);
+  uint32_t b = c.buf_bytes / (nb * c.D);
   if (!b) b = 1;
   if (b > bmax) b = bmax;
   if (c.b_req && c.b_req < b) b = c.b_req;
@@ -1851,7 +1903,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
     if (Sw > S) S = Sw;
   }
   // resource needs of the task (upper bounds, as the host estimates them)
-  uint64_t nw = 0, nslot = 0, nspill = 0, nflags = 0, npieces = 0;
+  uint64_t nw = 0, nslot = 0, nspill = 0, npieces = 0;
   if (t < cand) {
     const uint64_t wub = (q.n + S - 1) / S;
     nw = wub < c.wg_target ? wub : c.wg_target;
@@ -1860,21 +1912,18 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
     nslot = nw * c.slot_max;
     if (nslot > (s2 > c.slot_max ? s2 : c.slot_max)) nslot = s2 > c.slot_max ? s2 : c.slot_max;
     nspill = c.slot_max;
-    const uint32_t nbm = c.radix ? MAX_K : 2 * c.k;
-    const uint32_t bmin = dev_block_elems(c, nbm);
-    nflags = q.n / bmin + 1;
-    const uint64_t nbt = c.radix ? MAX_K : 2ull * dev_kprime(c, q.n);
-    npieces = 2 * nbt + 3 + nw + nflags / c.cmax + 1;
+    const uint32_t nbt = c.radix ? MAX_K : 2 * dev_kprime(c, q.n);   // buckets at most
+    const uint32_t bmin = dev_block_elems(c, nbt);
+    npieces = 2ull * nbt + 3 + nw + (q.n / bmin + 1) / c.cmax + 1;
   }
-  uint64_t tw, tsl, tsp, tfl, tpc;
+  uint64_t tw, tsl, tsp, tpc;
   const uint64_t pw = block_incl_scan64<PLAN_THREADS>(nw, s_w, &tw);
   const uint64_t psl = block_incl_scan64<PLAN_THREADS>(nslot, s_w, &tsl);
   const uint64_t psp = block_incl_scan64<PLAN_THREADS>(nspill, s_w, &tsp);
-  const uint64_t pfl = block_incl_scan64<PLAN_THREADS>(nflags, s_w, &tfl);
   const uint64_t ppc = block_incl_scan64<PLAN_THREADS>(npieces, s_w, &tpc);
   if (t == 0) s_take = cand;
   __syncthreads();
-  const bool fits = pw <= c.WB && psl <= c.SB && psp <= c.SPB && pfl <= c.FB && ppc <= c.PB;
+  const bool fits = pw <= c.WB && psl <= c.SB && psp <= c.SPB && ppc <= c.PB;
   if (t < cand && t > 0 && !fits) atomicMin(&s_take, t);
   __syncthreads();
   const uint32_t T = s_take;
@@ -1910,7 +1959,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
 
 // Geometry of the step's tasks after sampling: blocks, stripes (about one
 // WG_TARGET-th of the batch each, fewer while the budgets are exceeded),
-// buffer slots, spill areas, block flags, pieces, permutation groups and the
+// buffer slots, spill areas, pieces, permutation groups and the
 // workgroup-to-task maps of the later kernels.
 __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg c) {
   __shared__ uint64_t s_w[PLAN_THREADS / 64];
@@ -1920,7 +1969,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   if (T == 0) {
     if (t == 0) {
       a.ctrl[CTRL_NWG] = 0; a.ctrl[CTRL_NPWG] = 0; a.ctrl[CTRL_NCLN] = 0;
-      a.ctrl[CTRL_NFLAGS] = 0; a.ctrl[CTRL_MAXW] = 0;
+      a.ctrl[CTRL_MAXW] = 0;
     }
     return;
   }
@@ -1974,10 +2023,10 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
     if (ng > NB / 4) ng = NB / 4;
     if (!ng) ng = 1;
   }
-  const uint32_t gpw = PERM_THREADS / gl;
+  const uint32_t gpw = c.perm_threads / gl;
   const uint32_t nwg = act ? ((uint32_t)ng + gpw - 1) / gpw : 0;   // ng <= NB / 4 fits 32 bits
   const uint32_t piece_cap = act ? 2 * nb + 2 + W + NB / c.cmax + 1 : 0;
-  uint64_t t_wg, t_slot, t_spill, t_flag, t_piece, t_bucket, t_pwg, t_cln;
+  uint64_t t_wg, t_slot, t_spill, t_piece, t_bucket, t_pwg, t_cln;
   // Classification workgroups: the tasks whose stripes are longer than S
   // take the first indices (workgroups start roughly in index order, so the
   // longest start first and the shorter ones fill the end of the launch).
@@ -1991,7 +2040,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   const uint64_t e_slot = block_incl_scan64<PLAN_THREADS>(act ? W * slot_bytes : 0, s_w, &t_slot) -
                           (act ? W * slot_bytes : 0);
   const uint64_t e_spill = block_incl_scan64<PLAN_THREADS>(slot_bytes, s_w, &t_spill) - slot_bytes;
-  const uint64_t e_flag = block_incl_scan64<PLAN_THREADS>(NB, s_w, &t_flag) - NB;
   const uint64_t e_piece = block_incl_scan64<PLAN_THREADS>(piece_cap, s_w, &t_piece) - piece_cap;
   const uint64_t e_bucket = block_incl_scan64<PLAN_THREADS>(act ? nb + 1 : 0, s_w, &t_bucket) - (act ? nb + 1 : 0);
   const uint64_t e_pwg = block_incl_scan64<PLAN_THREADS>(nwg, s_w, &t_pwg) - nwg;
@@ -2003,7 +2051,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   }
   if (t == 0) s_ok = 1;
   __syncthreads();
-  if (t == 0 && (t_wg > c.WB || t_pwg > c.PWB || t_slot > c.SB || t_spill > c.SPB || t_flag > c.FB ||
+  if (t == 0 && (t_wg > c.WB || t_pwg > c.PWB || t_slot > c.SB || t_spill > c.SPB ||
                  t_piece > c.PB || t_bucket > c.NBE || t_cln > c.CLNB)) {
     s_ok = 0;
     dev_error(a.ctrl, DE_PLAN, (uint32_t)T, (uint32_t)t_wg);
@@ -2013,7 +2061,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
   if (!s_ok) {
     if (t == 0) {
       a.ctrl[CTRL_T] = 0; a.ctrl[CTRL_NWG] = 0; a.ctrl[CTRL_NPWG] = 0; a.ctrl[CTRL_NCLN] = 0;
-      a.ctrl[CTRL_NFLAGS] = 0;
     }
     return;
   }
@@ -2022,7 +2069,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
     q.nb = nb; q.K = K; q.logK = logK; q.eq = eq;
     q.b = b; q.NB = NB; q.W = W; q.wg_base = (uint32_t)e_wg;
     q.slot_bytes = (uint32_t)slot_bytes; q.slot_off = e_slot;
-    q.spill_off = e_spill; q.flag_off = e_flag;
+    q.spill_off = e_spill;
     q.piece_base = (uint32_t)e_piece; q.piece_cap = piece_cap;
     q.bucket_base = (uint32_t)e_bucket;
     q.glanes = gl; q.ngrp = (uint32_t)ng; q.pwg_base = (uint32_t)e_pwg;
@@ -2049,7 +2096,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_geom(BatchArgs a, PlanCfg
     a.ctrl[CTRL_NWG] = (uint32_t)t_wg;
     a.ctrl[CTRL_NPWG] = (uint32_t)t_pwg;
     a.ctrl[CTRL_NCLN] = (uint32_t)t_cln;
-    a.ctrl[CTRL_NFLAGS] = (uint32_t)t_flag;
   }
 }
 

@@ -8,6 +8,8 @@
 
 namespace ips {
 
+struct OopArgs;
+
 struct Launchers {
   int code;
   uint32_t dw;            // dwords per element
@@ -15,9 +17,10 @@ struct Launchers {
   bool keys_only, radix_ok;
   uint32_t lds_cap;       // LDS-tier capacity (elements)
   uint32_t lds_caps[3];   // capacities of the three LDS-tier variants (ascending)
+  uint32_t buf_bytes;     // LDS of the classification's buffer blocks
   hipError_t (*sample)(const BatchArgs&, uint32_t ntask, uint64_t seed, hipStream_t);
   hipError_t (*classify)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, bool gbuf, hipStream_t);
-  hipError_t (*permute)(const BatchArgs&, uint32_t nwg, hipStream_t);
+  hipError_t (*permute)(const BatchArgs&, uint32_t nwg, uint32_t threads, hipStream_t);
   hipError_t (*cleanup_a)(const BatchArgs&, uint32_t ntask, hipStream_t);
   hipError_t (*cleanup_b)(const BatchArgs&, uint32_t nwg, uint32_t max_w, hipStream_t);
   hipError_t (*lds_sort)(const LTask*, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
@@ -31,6 +34,10 @@ struct Launchers {
   hipError_t (*seg_order)(const SegItem* items, uint32_t nitems, const uint32_t* data,
                           uint32_t* flags, hipStream_t);
   hipError_t (*seg_reverse)(const RevItem* items, uint32_t nitems, uint32_t* data, hipStream_t);
+  // out-of-place partitioning step (ablation)
+  hipError_t (*oop_classify)(const OopArgs&, uint32_t nwg, hipStream_t);
+  hipError_t (*oop_distribute)(const OopArgs&, uint32_t nwg, hipStream_t);
+  hipError_t (*copy_ranges)(const LTask* list, uint32_t count, const uint32_t* from, uint32_t* to, hipStream_t);
 };
 
 const Launchers* launchers_u32();
@@ -38,6 +45,7 @@ const Launchers* launchers_u64();
 const Launchers* launchers_f64();
 const Launchers* launchers_pair();
 const Launchers* launchers_rec100();
+const Launchers* launchers_quartet();
 
 hipError_t launch_boundaries(const BatchArgs&, uint32_t ntask, uint32_t max_nb, uint32_t cmax,
                              hipStream_t);
@@ -48,5 +56,9 @@ hipError_t launch_children(const BatchArgs&, const ChildArgs&, uint32_t ntask, h
 hipError_t launch_plan_pop(const BatchArgs&, const PlanCfg&, hipStream_t);
 hipError_t launch_plan_geom(const BatchArgs&, const PlanCfg&, hipStream_t);
 hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n, uint32_t v, hipStream_t);
+hipError_t launch_oop_scan(const OopArgs&, uint32_t ntask, hipStream_t);
+hipError_t launch_oop_children(const OopArgs&, uint32_t ntask, uint32_t* ctrl, CTask* next, uint32_t next_cap,
+                               LTask* lds, LTask* copy, uint32_t list_cap, uint32_t cap, uint32_t to_second,
+                               hipStream_t);
 
 }  // namespace ips

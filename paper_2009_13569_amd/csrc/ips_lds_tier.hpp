@@ -489,7 +489,7 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
       const uint32_t i = e * NT + tid;
       if (i < n) {
         const uint32_t* r = stage + i * DW;
-        k[e] = T::key(r[0], r[DW > 1 ? 1 : 0], r[DW > 2 ? 2 : 0]);
+        k[e] = T::key_w(r);
       }
     }
   } else {
@@ -713,10 +713,93 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt,
       after = atomicAdd(pop, 1u);
     }
     lds_tier_task<T, NT, E, NET>(t, ti, data, ctrl, tid, lt, nxt, cnt && nxt < count, &s_t);
-    if (tid == 0) { s_next = nxt; s_after = after; }
+    if (tid == 0) {
+      s_next = nxt;
+      s_after = after;
+      seg_done_add(ctrl, t.l, t.n);   // serving: the task's elements are final
+    }
     __syncthreads();
     ti = s_next;
   }
+}
+
+// LDS tier of the Quartet, whose 192-bit keys the binning above has no
+// image for: the task's records are staged in LDS, (key, index) pairs
+// padded to a power of two are sorted by a bitonic network in LDS, and the
+// records are written back in key order from the stage.  Same calling
+// convention as k_lds_tier (a list, or claims from a device count).
+template <class T, uint32_t CAP>
+__global__ void __launch_bounds__(256)
+k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap,
+              uint32_t* pop) {
+  using Key = typename T::Key;
+  constexpr uint32_t NT = 256;
+  constexpr int DW = T::DW;
+  extern __shared__ __align__(16) uint8_t s_raw[];
+  Key* keys = reinterpret_cast<Key*>(s_raw);
+  uint16_t* idx = reinterpret_cast<uint16_t*>(keys + CAP);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(idx + CAP);
+  __shared__ uint32_t s_next;
+  __shared__ LTask s_t;
+  uint32_t count;
+  if (cnt) {
+    if (!ctrl[CTRL_LDSRUN]) return;
+    count = *cnt < cnt_cap ? *cnt : cnt_cap;
+  } else {
+    count = gridDim.x;   // one workgroup per task of the list
+  }
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t it = 0;; ++it) {
+    if (tid == 0) {
+      const uint32_t nx = cnt ? atomicAdd(pop, 1u) : (it == 0 ? blockIdx.x : count);
+      s_next = nx;
+      if (nx < count) s_t = lt[nx];
+    }
+    __syncthreads();
+    const uint32_t ti = s_next;
+    if (ti >= count) break;
+    const LTask t = s_t;
+    const uint32_t n = t.n;
+    if (n > CAP) {
+      if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
+    } else if (n >= 2) {
+      uint32_t* gd = data + t.l * DW;
+      for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
+      __syncthreads();
+      uint32_t P = 1;
+      while (P < n) P <<= 1;
+      for (uint32_t i = tid; i < P; i += NT) {
+        keys[i] = i < n ? T::key_w(stage + i * DW) : T::kmax();
+        idx[i] = (uint16_t)(i < n ? i : 0xFFFFu);
+      }
+      __syncthreads();
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t i = tid; i < P / 2; i += NT) {
+            const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
+            const bool up = (lo & k) == 0;
+            const Key x = keys[lo], y = keys[hi];
+            const uint16_t ix = idx[lo], iy = idx[hi];
+            // (key, index) order: padding (index 0xFFFF) sorts last among equal keys
+            const bool gt = kless(y, x) || (keq(x, y) && iy < ix);
+            if (gt == up) { keys[lo] = y; keys[hi] = x; idx[lo] = iy; idx[hi] = ix; }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t x = tid; x < n * DW; x += NT) {
+        const uint32_t i = x / DW, d = x - i * DW;
+        gd[x] = stage[idx[i] * DW + d];
+      }
+    }
+    if (tid == 0) seg_done_add(ctrl, t.l, t.n);   // serving: the task's elements are final
+    __syncthreads();   // LDS reused by the next task; s_next read by every thread
+  }
+}
+
+template <class T, uint32_t CAP>
+constexpr size_t lds_bitonic_bytes() {
+  return (size_t)CAP * sizeof(typename T::Key) + (size_t)CAP * 2 + (size_t)CAP * T::DW * 4;
 }
 
 }  // namespace ips

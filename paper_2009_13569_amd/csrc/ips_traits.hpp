@@ -6,7 +6,12 @@
 // (negative: all bits flipped; positive: sign bit set); Pair compares its
 // u64 key at byte 0; the 100-byte record compares bytes 0..9 as unsigned
 // bytes (Algorithm 4 of the paper with unsigned char), i.e. as a big-endian
-// 80-bit integer.
+// 80-bit integer; the Quartet compares its three u64 key words a, b, c
+// lexicographically (Algorithm 3), its fourth word being payload.
+//
+// key_w(w) builds the key from the first KDW dwords of an element; BUF_BYTES
+// is the LDS the classification's buffer blocks may take (the rest of the
+// 160 KiB holds the decision tree, whose keys are largest for the Quartet).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,6 +24,10 @@ struct K80 {
   uint32_t pad;
 };
 
+struct K192 {
+  uint64_t a, b, c;
+};
+
 __device__ __forceinline__ bool kless(uint32_t a, uint32_t b) { return a < b; }
 __device__ __forceinline__ bool kless(uint64_t a, uint64_t b) { return a < b; }
 __device__ __forceinline__ bool kless(const K80& a, const K80& b) {
@@ -29,6 +38,12 @@ __device__ __forceinline__ bool keq(uint64_t a, uint64_t b) { return a == b; }
 __device__ __forceinline__ bool keq(const K80& a, const K80& b) {
   return a.hi == b.hi && a.lo == b.lo;
 }
+__device__ __forceinline__ bool kless(const K192& x, const K192& y) {
+  return x.a < y.a || (x.a == y.a && (x.b < y.b || (x.b == y.b && x.c < y.c)));
+}
+__device__ __forceinline__ bool keq(const K192& x, const K192& y) { return x.a == y.a && x.b == y.b && x.c == y.c; }
+
+constexpr uint32_t BUF_BYTES_DEFAULT = 128u * 1024u;
 
 __device__ __forceinline__ uint64_t f64_to_ord(uint64_t b) {
   return (b >> 63) ? ~b : (b | (1ull << 63));
@@ -40,8 +55,10 @@ __device__ __forceinline__ uint64_t ord_to_f64(uint64_t k) {
 struct TU32 {
   static constexpr int DW = 1, KDW = 1, CODE = 1, EPT = 12;
   static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  static constexpr uint32_t BUF_BYTES = BUF_BYTES_DEFAULT;
   using Key = uint32_t;
   __device__ static Key key(uint32_t w0, uint32_t, uint32_t) { return w0; }
+  __device__ static Key key_w(const uint32_t* w) { return w[0]; }
   __device__ static Key kmax() { return 0xFFFFFFFFu; }
   __device__ static uint64_t rkey(Key k) { return k; }
   __device__ static void from_key(Key k, uint32_t* w) { w[0] = k; }
@@ -58,10 +75,12 @@ struct TU32 {
 struct TU64 {
   static constexpr int DW = 2, KDW = 2, CODE = 2, EPT = 8;
   static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  static constexpr uint32_t BUF_BYTES = BUF_BYTES_DEFAULT;
   using Key = uint64_t;
   __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
     return (uint64_t)w0 | ((uint64_t)w1 << 32);
   }
+  __device__ static Key key_w(const uint32_t* w) { return key(w[0], w[1], 0); }
   __device__ static Key kmax() { return ~0ull; }
   __device__ static uint64_t rkey(Key k) { return k; }
   __device__ static void from_key(Key k, uint32_t* w) { w[0] = (uint32_t)k; w[1] = (uint32_t)(k >> 32); }
@@ -76,10 +95,12 @@ struct TU64 {
 struct TF64 {
   static constexpr int DW = 2, KDW = 2, CODE = 3, EPT = 8;
   static constexpr bool KEYS_ONLY = true, RADIX_OK = true;
+  static constexpr uint32_t BUF_BYTES = BUF_BYTES_DEFAULT;
   using Key = uint64_t;
   __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
     return f64_to_ord((uint64_t)w0 | ((uint64_t)w1 << 32));
   }
+  __device__ static Key key_w(const uint32_t* w) { return key(w[0], w[1], 0); }
   __device__ static Key kmax() { return ~0ull; }
   __device__ static uint64_t rkey(Key k) { return k; }
   __device__ static void from_key(Key k, uint32_t* w) {
@@ -97,10 +118,12 @@ struct TF64 {
 struct TPair {
   static constexpr int DW = 4, KDW = 2, CODE = 4, EPT = 4;
   static constexpr bool KEYS_ONLY = false, RADIX_OK = true;
+  static constexpr uint32_t BUF_BYTES = BUF_BYTES_DEFAULT;
   using Key = uint64_t;
   __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t) {
     return (uint64_t)w0 | ((uint64_t)w1 << 32);
   }
+  __device__ static Key key_w(const uint32_t* w) { return key(w[0], w[1], 0); }
   __device__ static Key kmax() { return ~0ull; }
   __device__ static uint64_t rkey(Key k) { return k; }
   __device__ static Key from_slot(const uint64_t* s) { return s[0]; }
@@ -114,6 +137,7 @@ struct TPair {
 struct TRec100 {
   static constexpr int DW = 25, KDW = 3, CODE = 5, EPT = 1;
   static constexpr bool KEYS_ONLY = false, RADIX_OK = false;
+  static constexpr uint32_t BUF_BYTES = BUF_BYTES_DEFAULT;
   using Key = K80;
   __device__ static Key key(uint32_t w0, uint32_t w1, uint32_t w2) {
     K80 k;
@@ -122,6 +146,7 @@ struct TRec100 {
     k.pad = 0;
     return k;
   }
+  __device__ static Key key_w(const uint32_t* w) { return key(w[0], w[1], w[2]); }
   __device__ static Key kmax() { K80 k; k.hi = ~0ull; k.lo = 0xFFFFu; k.pad = 0; return k; }
   __device__ static uint64_t rkey(Key) { return 0; }
   __device__ static Key from_slot(const uint64_t* s) {
@@ -131,6 +156,29 @@ struct TRec100 {
   __device__ static uint64_t img(Key k) { return k.hi; }
   __device__ static Key lo_of(uint64_t x) { K80 k; k.hi = x; k.lo = 0; k.pad = 0; return k; }
   __device__ static Key hi_of(uint64_t x) { K80 k; k.hi = x; k.lo = 0xFFFFu; k.pad = 0; return k; }
+  static constexpr uint64_t IMG_MAX = ~0ull;
+};
+
+// Quartet: 32 bytes, key words a, b, c at bytes 0, 8, 16, payload at 24.
+struct TQuartet {
+  static constexpr int DW = 8, KDW = 6, CODE = 6, EPT = 2;
+  static constexpr bool KEYS_ONLY = false, RADIX_OK = false;
+  static constexpr uint32_t BUF_BYTES = 120u * 1024u;
+  using Key = K192;
+  __device__ static Key key_w(const uint32_t* w) {
+    K192 k;
+    k.a = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    k.b = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    k.c = (uint64_t)w[4] | ((uint64_t)w[5] << 32);
+    return k;
+  }
+  __device__ static Key kmax() { K192 k; k.a = ~0ull; k.b = ~0ull; k.c = ~0ull; return k; }
+  __device__ static uint64_t rkey(Key) { return 0; }
+  __device__ static Key from_slot(const uint64_t* s) { K192 k; k.a = s[0]; k.b = s[1]; k.c = s[2]; return k; }
+  __device__ static void to_slot(Key k, uint64_t* s) { s[0] = k.a; s[1] = k.b; s[2] = k.c; }
+  __device__ static uint64_t img(Key k) { return k.a; }
+  __device__ static Key lo_of(uint64_t x) { K192 k; k.a = x; k.b = 0; k.c = 0; return k; }
+  __device__ static Key hi_of(uint64_t x) { K192 k; k.a = x; k.b = ~0ull; k.c = ~0ull; return k; }
   static constexpr uint64_t IMG_MAX = ~0ull;
 };
 

@@ -55,15 +55,53 @@ def test_workspace_validation():
     assert rc == -1
 
 
-@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100"])
-def test_workspace_is_small_relative_to_data(kind):
-    # O(k b) per workgroup of a batch: well below the data for large arrays.
-    for n, frac in ((1 << 24, 1.0), (1 << 28, 0.35)):
-        ws = ips.workspace_bytes(n, kind)
-        assert ws < n * ips.ELEM_BYTES[kind] * frac, (n, ws)
-    n = 1 << 24
-    gb = ips.workspace_bytes(n, kind, params=ips.make_params(flags=ips.FLAG_GLOBAL_BUFFERS))
-    assert gb > 0
+# LDS-tier capacities (elements) of the element types: every queued
+# partitioning task holds more than this many elements.
+_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
+
+
+def _ws_bound(n, kind, gbuf=False):
+    """The in-place workspace bound (Section 5.1: O(k b) extra memory per
+    thread), with the step's budgets of at most 2048 workgroups and 512
+    tasks: per workgroup one buffer block per bucket (k b D: the 128 KiB LDS
+    budget, or k = 512 buckets of 2 KiB blocks with the buffers in the
+    workspace) plus O(k) counters; per task one spill area of the same size,
+    the step record (splitters, tree, start table) and O(k) bucket, piece and
+    child entries.  Two terms grow with n, both by well under 0.1 % of the
+    data: the task queue (32 bytes per cap elements: every queued task holds
+    more than cap) and the permutation's pointer pieces (52 bytes per 1024
+    blocks of at least 256 bytes)."""
+    D = ips.ELEM_BYTES[kind]
+    kbd = 512 * 2048 if gbuf else 128 << 10
+    per_wg = kbd + 512 * 24 + 16
+    per_task = kbd + 24 * 1024 + 512 * 400
+    return (2048 * per_wg + 512 * per_task + 40 * (n // _CAP[kind] + 512) + 64 * (n * D // (256 << 10))
+            + (1 << 20))
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100", "quartet"])
+def test_workspace_in_place_bound(kind):
+    D = ips.ELEM_BYTES[kind]
+    top = {"rec100": 31, "quartet": 33}.get(kind, 34)          # n below 2^31 blocks
+    for lg in range(10, top + 1):
+        n = 1 << lg
+        for algo in ("samplesort", "radix"):
+            if algo == "radix" and kind in ("rec100", "quartet"):
+                continue
+            ws = ips.workspace_bytes(n, kind, algo)
+            assert ws <= _ws_bound(n, kind), (kind, algo, lg, ws)
+            # below the data itself from 2^16 elements (samplesort) and 2^20
+            # (radix: 256 buckets per step whatever the task size)
+            if lg >= (16 if algo == "samplesort" else 20):
+                assert ws < n * D, (kind, algo, lg, ws / (n * D))
+        gb = ips.workspace_bytes(n, kind, params=ips.make_params(flags=ips.FLAG_GLOBAL_BUFFERS))
+        assert gb <= _ws_bound(n, kind, gbuf=True), (kind, lg, gb)
+    # beyond the budgets only the two small terms grow (and the list of next
+    # tasks of one step, up to 32 bytes x 512 tasks x 512 buckets)
+    w28 = ips.workspace_bytes(1 << 28, kind)
+    w34 = ips.workspace_bytes(1 << top, kind)
+    dn = (1 << top) - (1 << 28)
+    assert w34 - w28 <= 40 * (dn // _CAP[kind]) + 64 * (dn * D // (256 << 10)) + 32 * 512 * 512, (w28, w34)
 
 
 def test_sort_rejects_bad_arguments_before_hip():

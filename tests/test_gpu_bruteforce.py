@@ -16,7 +16,7 @@ from gpu_util import keys_of, log
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["u32", "u64", "f64", "pair", "rec100"]
+KINDS = ["u32", "u64", "f64", "pair", "rec100", "quartet"]
 
 
 @pytest.fixture(scope="module")
@@ -53,8 +53,11 @@ def _check(out, inp, ref, offs, kind, what):
         bad = np.nonzero((ko != kr).reshape(ko.shape[0], -1).any(axis=1))[0]
         seg = np.searchsorted(offs, bad[0], side="right") - 1
         raise AssertionError(f"{what}: {bad.size} keys differ, first at element {bad[0]} (segment {seg})")
-    if kind in ("pair", "rec100"):
-        ix = (out[:, 1] if kind == "pair" else out[:, 10:18].copy().view("<u8")[:, 0]).astype(np.int64)
+    if kind in ("pair", "rec100", "quartet"):
+        if kind == "rec100":
+            ix = out[:, 10:18].copy().view("<u8")[:, 0].astype(np.int64)
+        else:
+            ix = out[:, {"pair": 1, "quartet": 3}[kind]].astype(np.int64)
         assert np.array_equal(np.sort(ix), np.arange(inp.shape[0])), f"{what}: payload indices not a permutation"
         assert np.array_equal(out, inp[ix]), f"{what}: a record changed"
         seg_of = np.repeat(np.arange(offs.size), np.diff(np.append(offs, inp.shape[0])))
@@ -100,7 +103,7 @@ def test_brute_force_graph_and_sorted_check(sorter, kind):
         pg = ips.make_params(k=2, block_bytes=ips.ELEM_BYTES[kind], n0=1, lds_task_max=1,
                              flags=ips.FLAG_GRAPH | ips.FLAG_NO_SORTED_CHECK)
         _run(sorter, kind, "samplesort", pg, f"{kind} samplesort graph")
-        if kind != "rec100":
+        if kind not in ("rec100", "quartet"):
             pr = ips.make_params(lds_task_max=1, flags=ips.FLAG_GRAPH)
             _run(sorter, kind, "radix", pr, f"{kind} radix graph")
     stream.synchronize()

@@ -36,14 +36,14 @@ def _sort(sorter, a, kind, algo, flags, stream=None):
 MODES = [("device", 0), ("host", ips.FLAG_HOST_PLAN), ("graph", ips.FLAG_GRAPH)]
 
 
-@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100"])
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100", "quartet"])
 def test_plan_modes_agree(sorter, kind):
     import torch
     stream = torch.cuda.Stream()
-    n = 60_000 if kind == "rec100" else 700_001
+    n = {"rec100": 60_000, "quartet": 200_003}.get(kind, 700_001)
     for dist in ("uniform", "twodup", "zero") if kind != "rec100" else ("uniform", "rootdup"):
         a = generate(kind, dist, n, 13)
-        algos = ["samplesort"] + (["radix"] if kind != "rec100" else [])
+        algos = ["samplesort"] + (["radix"] if kind not in ("rec100", "quartet") else [])
         for algo in algos:
             for name, fl in MODES:
                 log(f"plan mode {name} {kind} {dist} {algo}")

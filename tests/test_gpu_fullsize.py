@@ -1,11 +1,11 @@
 """Bit-exact parity at the full benchmark sizes: 2^28 u64 and u32 keys of all
-ten generators (samplesort and IPS2Ra), 2^27 doubles and Pair records, 2^24
-100-byte records.  The sort runs through the C ABI with the parameters the
+ten generators (samplesort and IPS2Ra), 2^27 doubles, Pair records and
+Quartets, 2^24 100-byte records.  The sort runs through the C ABI with the parameters the
 benchmark uses; the digest of its sorted key sequence must equal the digest
 of the oracle's sorted keys of the same input (tests/golden/fullsize.py
 writes those from the oracle alone).  Records must also keep their multiset:
-Pair values and record payload bytes 10..17 hold each element's input
-index, so the output values must be a permutation of 0..n-1 and every
+Pair values, Quartet word 3 and record payload bytes 10..17 hold each
+element's input index, so the output values must be a permutation of 0..n-1 and every
 output record must equal the input record its index names.
 
 The small configuration (2^20 u64 Uniform keys, k = 256, 2 KiB blocks,
@@ -49,7 +49,7 @@ def _device_input(c, dev):
 
 def _key_digest(t, kind):
     """fs.digest of the key bytes of a sorted device array."""
-    k = t[:, 0] if kind == "pair" else t[:, :10] if kind == "rec100" else t
+    k = {"pair": lambda: t[:, 0], "rec100": lambda: t[:, :10], "quartet": lambda: t[:, :3]}.get(kind, lambda: t)()
     host = np.ascontiguousarray(k.contiguous().cpu().numpy())
     return fs.digest(memoryview(host).cast("B"), threads=16)
 
@@ -59,8 +59,8 @@ def _check_records(out, inp, kind):
     input record its index names (exact multiset equality)."""
     import torch
     n = out.shape[0]
-    if kind == "pair":
-        ix = out[:, 1].view(torch.int64)
+    if kind in ("pair", "quartet"):
+        ix = out[:, 1 if kind == "pair" else 3].view(torch.int64)
     else:
         ix = out[:, 10:18].contiguous().view(torch.int64).reshape(n)
     assert int(ix.min()) >= 0 and int(ix.max()) < n, "index out of range"
@@ -71,7 +71,7 @@ def _check_records(out, inp, kind):
 
 
 CASES = [(name, algo) for name, c in sorted(GOLD.items())
-         for algo in (("samplesort", "radix") if c["kind"] != "rec100" else ("samplesort",))]
+         for algo in (("samplesort", "radix") if c["kind"] not in ("rec100", "quartet") else ("samplesort",))]
 
 
 @pytest.mark.parametrize("name,algo", CASES, ids=[f"{n}-{a}" for n, a in CASES])
@@ -88,7 +88,7 @@ def test_fullsize_digest(sorter, name, algo):
     torch.cuda.synchronize()
     log(f"fullsize {name} {algo}: digest")
     assert _key_digest(work, kind) == c["digest"], f"{name} {algo}: sorted keys differ from the oracle's"
-    if kind in ("pair", "rec100"):
+    if kind in ("pair", "rec100", "quartet"):
         _check_records(work, src, kind)
     del src, work
     torch.cuda.empty_cache()

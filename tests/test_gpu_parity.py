@@ -15,7 +15,21 @@ from gpu_util import assert_parity, generate, gpu_sort, log
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["u32", "u64", "f64", "pair", "rec100"]
+KINDS = ["u32", "u64", "f64", "pair", "rec100", "quartet"]
+
+
+def _quartet_of(v: np.ndarray) -> np.ndarray:
+    """Quartets whose (a, b, c) keys are ordered as v: a fixed, v split over
+    the top bits of b and c (so that neighbouring keys differ in c and keys
+    far apart in b), the value the position."""
+    n = v.size
+    v = v.astype(np.uint64)
+    out = np.empty((n, 4), dtype=np.uint64)
+    out[:, 0] = np.uint64(0x5A01_0203_0405_0607)
+    out[:, 1] = v >> np.uint64(6)
+    out[:, 2] = ((v & np.uint64(63)) << np.uint64(58)) | np.uint64(0x1234)
+    out[:, 3] = np.arange(n, dtype=np.uint64)
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +41,7 @@ def sorter():
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_lds_tier(sorter, kind):
-    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}[kind]
+    cap = ips.LDS_CAP[kind]
     for n in sorted({2, 3, 17, 33, 1000, cap // 4, cap // 4 + 1, cap // 2, cap // 2 + 1, cap - 1, cap}):
         a = generate(kind, "uniform", n, 100 + n)
         log(f"lds {kind} n={n}")
@@ -54,6 +68,8 @@ def _narrow_dup_input(kind: str, n: int, pairs: int, gap: int, seed: int) -> np.
         out[:, 0] = v + np.uint64(0x1234_5678_9000_0000)
         out[:, 1] = np.arange(n, dtype=np.uint64)
         return out
+    if kind == "quartet":
+        return _quartet_of(v)
     out = synth.gen_rec100("uniform", n, seed)     # payload and index from the generator
     out[:, 0:8] = np.frombuffer(bytes([0x5A, 1, 2, 3, 4, 5, 6, 7]), dtype=np.uint8)
     out[:, 8:10] = v.astype(">u2").view(np.uint8).reshape(n, 2)
@@ -91,6 +107,8 @@ def _keyed(kind: str, v: np.ndarray, seed: int) -> np.ndarray:
         out[:, 0] = v + np.uint64(0x1234_5678_9000_0000)
         out[:, 1] = np.arange(n, dtype=np.uint64)
         return out
+    if kind == "quartet":
+        return _quartet_of(v)
     out = synth.gen_rec100("uniform", n, seed)
     out[:, 0:8] = np.frombuffer(bytes([0x5A, 1, 2, 3, 4, 5, 6, 7]), dtype=np.uint8)
     out[:, 8:10] = v.astype(">u2").view(np.uint8).reshape(n, 2)
@@ -138,12 +156,13 @@ DISTS = {
     "f64": ["uniform", "exponential"],
     "pair": ["uniform", "rootdup"],
     "rec100": ["uniform", "rootdup"],
+    "quartet": ["uniform", "rootdup", "eightdup"],
 }
 
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_samplesort_parity(sorter, kind):
-    nbig = {"rec100": 40_000}.get(kind, 300_001)
+    nbig = {"rec100": 40_000, "quartet": 150_001}.get(kind, 300_001)
     for dist in DISTS[kind]:
         for n in (20_011, nbig):
             a = generate(kind, dist, n, 7)
@@ -178,13 +197,14 @@ def _level1(sorter, a, kind, params, algo="samplesort"):
     return out, ri
 
 
-LDS_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}
+LDS_CAP = ips.LDS_CAP
 
 
 @pytest.mark.parametrize("kind,n,gbuf,n0", [("u64", 1 << 20, True, 16), ("u64", 1 << 20, False, 16),
                                             ("u32", 300_001, False, 16), ("f64", 200_003, False, 16),
                                             ("pair", 100_003, False, 16), ("rec100", 30_011, False, 16),
-                                            ("u64", 300_001, False, 0), ("rec100", 30_011, False, 0)])
+                                            ("u64", 300_001, False, 0), ("rec100", 30_011, False, 0),
+                                            ("quartet", 100_003, False, 16), ("quartet", 60_011, False, 0)])
 def test_level1_exact(sorter, kind, n, gbuf, n0):
     """The root step's sample, splitters, equality-bucket flag and bucket
     boundaries equal the oracle's, and every element lies in its bucket.
@@ -211,6 +231,8 @@ def test_level1_exact(sorter, kind, n, gbuf, n0):
             got = bytes(ri.splitters[i])
             if kind == "rec100":
                 assert got[:10] == bytes(spl[i][:10]), i
+            elif kind == "quartet":      # words a and b are reported
+                assert got == np.ascontiguousarray(spl[i][:2]).tobytes(), i
             elif kind == "u32":
                 assert int.from_bytes(got[:8], "little") == int(spl[i]), i
             else:
@@ -257,7 +279,7 @@ def test_brute_force_tiny(sorter, k, bb):
                     assert np.array_equal(gpu_sort(sorter, a, "u64", params=p), np.sort(a)), seq
 
 
-@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_edge_cases(sorter, kind):
     rng = np.random.default_rng(11)
     p1 = ips.make_params(lds_task_max=1, flags=ips.FLAG_NO_SORTED_CHECK)
@@ -327,6 +349,8 @@ def _as_kind(u, kind):
         return (u >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     if kind == "pair":
         return np.stack([u, np.arange(n, dtype=np.uint64)], axis=1)
+    if kind == "quartet":       # u in word b, a shared, c a function of u
+        return np.stack([np.full(n, 7, dtype=np.uint64), u, ~u, np.arange(n, dtype=np.uint64)], axis=1)
     r = synth.gen_rec100("uniform", n, 5)
     r[:, 0:2] = 0
     r[:, 2:10] = u.astype(">u8").view(np.uint8).reshape(n, 8)
@@ -338,7 +362,7 @@ def test_lds_tier_fallbacks(sorter, kind):
     """Bins above the register-network size, above the wavefront limit, few
     distinct keys and all-equal keys inside single LDS-tier tasks."""
     rng = np.random.default_rng(21)
-    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024}[kind]
+    cap = ips.LDS_CAP[kind]
     for name in ("clustered", "mid_cluster", "three_values", "all_equal"):
         for n in sorted({cap // 2 + 7, cap}):
             a = _as_kind(_pattern_u64(name, n, rng), kind)
@@ -360,13 +384,13 @@ def test_presorted_inputs_through_partitioning(sorter, kind):
                 assert_parity(gpu_sort(sorter, a, kind, algo=algo, params=p), a, kind)
 
 
-@pytest.mark.parametrize("kind", ["u32", "u64", "pair", "rec100"])
+@pytest.mark.parametrize("kind", ["u32", "u64", "pair", "rec100", "quartet"])
 def test_block_sizes(kind):
     """Every block size the parameters allow (which sets how many lanes move
     one block in the permutation: 4 to 64) sorts like the oracle, on inputs
     that need two partitioning levels.  2 KiB blocks need global buffers."""
     s = ips.Sorter(0, tuning=None)
-    n = {"u32": 3_000_017, "u64": 2_100_001, "pair": 600_011, "rec100": 120_007}[kind]
+    n = {"u32": 3_000_017, "u64": 2_100_001, "pair": 600_011, "rec100": 120_007, "quartet": 300_007}[kind]
     a = generate(kind, "uniform", n, 4242)
     ref = oracle.sort(a, kind)
     for bb in (128, 256, 512, 1024, 2048):

@@ -49,9 +49,9 @@ def _check(out, data, offs, sizes, kind):
 MIXED = [0, 1, 2, 17, 1000, 16384, 16385, 40_000, 3, 150_001, 9000, 70_000]
 
 
-@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100"])
+@pytest.mark.parametrize("kind", ["u32", "u64", "f64", "pair", "rec100", "quartet"])
 def test_segments_mixed_sizes(sorter, kind):
-    sizes = [s for s in MIXED if kind != "rec100" or s <= 40_000]
+    sizes = [s for s in MIXED if kind not in ("rec100", "quartet") or s <= 40_000]
     offs, total = _layout(sizes, gap=5)
     data = generate(kind, "uniform", total, 31)
     log(f"segments {kind} samplesort sizes={sizes}")

@@ -83,6 +83,11 @@ def test_serve_trace_results_equal_alone(sorter, policy):
         assert nb == len(tens)
         starts = [res[i]["start_s"] for i in np.argsort(arrivals, kind="stable")]
         assert starts == sorted(starts)
+    else:
+        # continuous batching: some request was admitted while another one
+        # (possibly of another element type) was still being sorted
+        iv = sorted((r["start_s"], r["done_s"]) for r in res)
+        assert any(iv[j][0] < iv[i][1] for i in range(len(iv)) for j in range(i + 1, len(iv))), iv[:5]
     lat = np.array([r["done_s"] - arrivals[i] for i, r in enumerate(res)])
     log(f"  batches={nb} p50={np.percentile(lat, 50) * 1e3:.2f} ms p99={np.percentile(lat, 99) * 1e3:.2f} ms")
 
@@ -100,3 +105,27 @@ def test_serve_rejects_request_over_budget(sorter):
     assert np.array_equal(tens[2].cpu().numpy().view(np.uint64), big)     # untouched
     for i in (0, 1, 3):
         assert_parity(tens[i].cpu().numpy(), inputs[i], "u64")
+
+
+def test_serve_requests_arriving_mid_flight_equal_alone(sorter):
+    """Large requests keep the queues busy while small and large requests of
+    every type keep arriving: each result must still equal the oracle's sort
+    of that request alone, and later arrivals must be admitted before the
+    first large requests finish."""
+    import torch
+    kinds = ["u64", "u32", "f64", "pair"]
+    # the first four need more than one round of steps (two partitioning levels)
+    specs = [(kinds[i % 4], 1 << 23 if i < 4 else int(3000 + 977 * i), ("uniform", "twodup", "zipf")[i % 3])
+             for i in range(24)]
+    inputs = [generate(k, d, n, 300 + i) for i, (k, n, d) in enumerate(specs)]
+    tens = [_to_dev(a) for a in inputs]
+    arrivals = [0.0] * 4 + [0.0001 * (i + 1) for i in range(20)]
+    torch.cuda.synchronize()
+    res, rc = sorter.serve_trace(tens, arrivals, hbm_budget=1 << 30, policy=ips.SERVE_BATCH)
+    torch.cuda.synchronize()
+    assert rc == 0, rc
+    for i, (a, t, r) in enumerate(zip(inputs, tens, res)):
+        assert r["status"] == 0, (i, r)
+        assert_parity(t.cpu().numpy(), a, specs[i][0])
+    first_done = min(res[i]["done_s"] for i in range(4))
+    assert any(res[i]["start_s"] < first_done for i in range(4, 24)), "no request admitted mid-flight"
