@@ -134,7 +134,8 @@ enum TaskFlags : uint32_t { TF_EQ_ON = 1u, TF_EQ_OFF = 2u, TF_RADIX = 4u };
 // A task of the LDS tier: sorted entirely inside one workgroup's LDS.
 struct LTask {
   uint64_t l;
-  uint32_t n, pad;
+  uint32_t n;
+  uint32_t req;   // serving: index of the task's request in the request table (else 0)
 };
 
 // A chunk of one segment of a batched call (ips_sort_segments): elements

@@ -1174,7 +1174,7 @@ int sort_impl(ips_ctx* ctx, void* d, uint64_t n, int type, int algo, void* ws, s
     std::vector<LTask> lt(1);
     lt[0].l = 0;
     lt[0].n = (uint32_t)n;
-    lt[0].pad = 0;
+    lt[0].req = 0;
     return level_loop(r, {}, lt, true);
   }
   if (r.c.flags & (IPS_FLAG_LEVEL1_ONLY | IPS_FLAG_HOST_PLAN))
@@ -1249,7 +1249,7 @@ int segments_impl(ips_ctx* ctx, void* d, uint64_t n_total, int type, int algo,
     LTask q;
     q.l = segs[i].offset;
     q.n = (uint32_t)segs[i].n;
-    q.pad = 0;
+    q.req = 0;
     lt.push_back(q);
   }
   const bool check = !(r.c.flags & IPS_FLAG_NO_SORTED_CHECK);
@@ -1469,7 +1469,7 @@ int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_
   if (reinterpret_cast<uintptr_t>(tmp) % 256) return IPS_E_MISALIGNED;
   if (n <= c.cap) {
     std::vector<LTask> lt(1);
-    lt[0].l = 0; lt[0].n = (uint32_t)n; lt[0].pad = 0;
+    lt[0].l = 0; lt[0].n = (uint32_t)n; lt[0].req = 0;
     return level_loop(r, {}, lt, true);
   }
   uint32_t* A = r.data;
@@ -1765,7 +1765,7 @@ bool lane_admit(SLane& L, ips_request& q, uint32_t id, std::vector<uint32_t>& ra
     LTask t;
     t.l = l;
     t.n = (uint32_t)q.n;
-    t.pad = 0;
+    t.req = L.seg_of[id];   // the request's entry in the lane's table
     L.lt_new.push_back(t);
   } else if (L.r.c.radix) {
     radix_new.push_back(id);

@@ -37,20 +37,23 @@ __device__ __forceinline__ void at_store32(uint32_t* p, uint32_t v) {
 // Serving: `cnt` elements starting at element l of the data are in their
 // final place; they are counted for the request that holds element l (the
 // requests' first elements are listed in ascending order).
-__device__ __forceinline__ void seg_done_add(const uint32_t* ctrl, uint64_t l, uint64_t cnt) {
-  const uint32_t nseg = ctrl[CTRL_NSEG];
-  if (!nseg) return;
+// Serving: the request whose elements start at or before element l (the
+// last entry of the ascending table of first elements that is <= l).
+__device__ __forceinline__ uint32_t seg_find(const uint32_t* ctrl, uint32_t nseg, uint64_t l) {
   const uint64_t* lo = reinterpret_cast<const uint64_t*>((uint64_t)ctrl[CTRL_SEGLO] |
                                                          ((uint64_t)ctrl[CTRL_SEGLO + 1] << 32));
-  unsigned long long* done = reinterpret_cast<unsigned long long*>((uint64_t)ctrl[CTRL_SEGDONE] |
-                                                                   ((uint64_t)ctrl[CTRL_SEGDONE + 1] << 32));
-  uint32_t a = 0, b = nseg;   // the last request whose first element is <= l
+  uint32_t a = 0, b = nseg;
   while (b - a > 1) {
     const uint32_t m = (a + b) >> 1;
     if (lo[m] <= l) a = m; else b = m;
   }
-  atomicAdd(&done[a], (unsigned long long)cnt);
+  return a;
 }
+__device__ __forceinline__ unsigned long long* seg_done_ptr(const uint32_t* ctrl) {
+  return reinterpret_cast<unsigned long long*>((uint64_t)ctrl[CTRL_SEGDONE] |
+                                               ((uint64_t)ctrl[CTRL_SEGDONE + 1] << 32));
+}
+
 
 __device__ __forceinline__ void dev_error(uint32_t* ctrl, uint32_t code, uint32_t x,
                                           uint32_t y) {
@@ -1741,6 +1744,7 @@ __device__ __forceinline__ Child child_of(const BatchArgs& a, const ChildArgs& c
 // tasks (device-planned steps read it from the control block).
 __global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint32_t ntask) {
   const uint32_t T = a.devplan ? a.ctrl[CTRL_T] : ntask;
+  const uint32_t nseg = a.ctrl[CTRL_NSEG];
   __shared__ uint32_t s_n[4], s_base[4], s_pos[4];
   __shared__ unsigned long long s_el[3];
   const uint32_t tid = threadIdx.x;
@@ -1753,7 +1757,8 @@ __global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint
       const Child ch = child_of(a, c, tk, j);
       if (ch.dest < 4) atomicAdd(&s_n[ch.dest], 1u);
       if (ch.dest < 3) atomicAdd(&s_el[ch.dest], (unsigned long long)ch.sz);
-      if (ch.dest == 4 && ch.sz) seg_done_add(a.ctrl, tk.l + ch.s0, ch.sz);   // final bucket
+      if (ch.dest == 4 && ch.sz && nseg)   // serving: a final bucket's elements are done
+        atomicAdd(&seg_done_ptr(a.ctrl)[seg_find(a.ctrl, nseg, tk.l + ch.s0)], (unsigned long long)ch.sz);
     }
   }
   __syncthreads();
@@ -1781,7 +1786,7 @@ __global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint
           LTask t;
           t.l = tk.l + ch.s0;
           t.n = (uint32_t)ch.sz;
-          t.pad = 0;
+          t.req = nseg ? seg_find(a.ctrl, nseg, t.l) : 0u;   // serving: the task's request
           c.lt[ch.dest][q] = t;
         } else {
           dev_error(a.ctrl, DE_CLN_RANGE, ti, q);

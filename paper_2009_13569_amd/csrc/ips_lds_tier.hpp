@@ -683,6 +683,11 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt,
   __shared__ uint32_t s_next, s_after;
   __shared__ LTask s_t;
   uint32_t count, ti;
+  // Serving: a finished task adds its elements to its request's counter
+  // (the table is read here, before any store, so that no wait at a task's
+  // end is tied to its stores).
+  const uint32_t nseg = ctrl[CTRL_NSEG];
+  unsigned long long* const seg_done = nseg ? seg_done_ptr(ctrl) : nullptr;
   if (cnt) {
     if (!ctrl[CTRL_LDSRUN]) return;          // device-planned step that defers the lists
     count = *cnt < cnt_cap ? *cnt : cnt_cap;   // a list never holds more than cnt_cap
@@ -716,7 +721,7 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt,
     if (tid == 0) {
       s_next = nxt;
       s_after = after;
-      seg_done_add(ctrl, t.l, t.n);   // serving: the task's elements are final
+      if (seg_done) atomicAdd(&seg_done[t.req], (unsigned long long)t.n);   // serving: elements final
     }
     __syncthreads();
     ti = s_next;
@@ -749,6 +754,8 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
     count = gridDim.x;   // one workgroup per task of the list
   }
   const uint32_t tid = threadIdx.x;
+  const uint32_t nseg = ctrl[CTRL_NSEG];
+  unsigned long long* const seg_done = nseg ? seg_done_ptr(ctrl) : nullptr;
   for (uint32_t it = 0;; ++it) {
     if (tid == 0) {
       const uint32_t nx = cnt ? atomicAdd(pop, 1u) : (it == 0 ? blockIdx.x : count);
@@ -792,7 +799,7 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
         gd[x] = stage[idx[i] * DW + d];
       }
     }
-    if (tid == 0) seg_done_add(ctrl, t.l, t.n);   // serving: the task's elements are final
+    if (tid == 0 && seg_done) atomicAdd(&seg_done[t.req], (unsigned long long)t.n);   // serving
     __syncthreads();   // LDS reused by the next task; s_next read by every thread
   }
 }

@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) k_oop_children(OopArgs a, uint32_t* ctrl,
       continue;
     }
     LTask t;
-    t.l = tk.l + s0; t.n = (uint32_t)sz; t.pad = 0;
+    t.l = tk.l + s0; t.n = (uint32_t)sz; t.req = 0;
     if (sz >= 2 && !eqb) {
       const uint32_t q = atomicAdd(&ctrl[CTRL_NLDS], 1u);
       if (q < list_cap) lds[q] = t;
