@@ -179,25 +179,7 @@ def main() -> int:
                 a = prof_sum.setdefault(row, {}).setdefault(ph, [0.0, 0, 0])
                 a[0] += ms; a[1] += el; a[2] += la
         del x
-    levels = []
-    for row in sorted(k for k in prof_sum if k != "outside"):
-        ph = prof_sum[row]
-        part = ["sample", "classify", "boundaries", "flags", "permute", "cleanup_a", "cleanup_b"]
-        ms = sum(ph[p][0] for p in part if p in ph) / extra
-        el = ph.get("classify", [0, 0, 0])[1] / extra
-        rec = {"level": row, "elems": int(el), "ms": round(ms, 4)}
-        if el and ms:
-            gbs = 4 * D * el / (ms * 1e-3) / 1e9
-            rec.update({"GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
-        if "lds_sort" in ph:
-            lms = ph["lds_sort"][0] / extra
-            lel = ph["lds_sort"][1] / extra
-            rec["lds_ms"] = round(lms, 4)
-            rec["lds_elems"] = int(lel)
-            if lms:
-                rec["lds_GBps"] = round(2 * D * lel / (lms * 1e-3) / 1e9, 1)
-        rec["kernels_ms"] = {p: round(v[0] / extra, 4) for p, v in ph.items()}
-        levels.append(rec)
+    levels = level_table(prof_sum, D, extra)
     # Dominant kernel, from its HIP-event timings inside the timed region.
     dms, delems, dla = dsum
     bytes_per_elem = {"classify": 2 * D, "permute": 2 * D, "lds_sort": 2 * D, "sorted_check": D,
@@ -231,6 +213,35 @@ def main() -> int:
         if v is not None:
             assert bool((v[1:] >= v[:-1]).all()), "radix output not sorted"
         parity["radix"] = digest_equal(copies[0])
+
+        # IPS2Ra with classification fused into the permutation (exact bucket
+        # sizes from a histogram pass): the same K sorts, then two profiled
+        # sorts for its per-level table.
+        for c in copies:
+            c.copy_(pristine)
+        fp = ips.make_params(flags=ips.FLAG_FUSED)
+        x = pristine.clone()
+        sorter.sort_(x, algo="radix", params=fp)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for c in copies:
+            sorter.sort_(c, algo="radix", params=fp)
+        torch.cuda.synchronize()
+        fel = time.perf_counter() - f0
+        parity["radix_fused"] = digest_equal(copies[0])
+        fsum: dict = {}
+        fpp = ips.make_params(flags=ips.FLAG_FUSED | ips.FLAG_PROFILE)
+        for _ in range(extra):
+            x = pristine.clone()
+            sorter.sort_(x, algo="radix", params=fpp)
+            for row, phases in sorter.profile().items():
+                for ph, (ms, el, la) in phases.items():
+                    acc = fsum.setdefault(row, {}).setdefault(ph, [0.0, 0, 0])
+                    acc[0] += ms; acc[1] += el; acc[2] += la
+            del x
+        radix["fused"] = {"value": round(n * steps / fel / 1e9, 3), "ms_per_step": round(fel / steps * 1e3, 3),
+                          "levels": level_table(fsum, D, extra)}
+        log(f"radix fused: {fel / steps * 1e3:.2f} ms/step, {radix['fused']['value']:.2f} Gkeys/s")
 
     cpu = None
     if not args.no_cpu:
@@ -279,6 +290,40 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def level_table(prof_sum: dict, D: int, runs: int) -> list:
+    """Per recursion level, from summed per-kernel timings of `runs` sorts:
+    the partitioning kernels' time and the level's rate in the in-place
+    step's algorithmic bytes, 4 D n' (classification and permutation each
+    read and write every element once), against the 8 TB/s peak; the LDS
+    tier's time and rate at 2 D per element.  For the fused radix step the
+    level's own algorithmic bytes, 3 D n' (histogram read, one read and one
+    write), are reported beside it."""
+    levels = []
+    part = ["sample", "classify", "boundaries", "flags", "permute", "cleanup_a", "cleanup_b", "histogram", "fused"]
+    for row in sorted(k for k in prof_sum if k != "outside"):
+        ph = prof_sum[row]
+        ms = sum(ph[p][0] for p in part if p in ph) / runs
+        el = max(ph.get("classify", [0, 0, 0])[1], ph.get("histogram", [0, 0, 0])[1]) / runs
+        rec = {"level": row, "elems": int(el), "ms": round(ms, 4)}
+        if el and ms:
+            gbs = 4 * D * el / (ms * 1e-3) / 1e9
+            rec.update({"GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            if "fused" in ph:
+                own = 3 * D * el / (ms * 1e-3) / 1e9
+                rec.update({"own_bytes_per_elem": 3 * D, "own_GBps": round(own, 1),
+                            "own_frac": round(own / HBM_PEAK_GBS, 4)})
+        if "lds_sort" in ph:
+            lms = ph["lds_sort"][0] / runs
+            lel = ph["lds_sort"][1] / runs
+            rec["lds_ms"] = round(lms, 4)
+            rec["lds_elems"] = int(lel)
+            if lms:
+                rec["lds_GBps"] = round(2 * D * lel / (lms * 1e-3) / 1e9, 1)
+        rec["kernels_ms"] = {p: round(v[0] / runs, 4) for p, v in ph.items()}
+        levels.append(rec)
+    return levels
 
 
 # --------------------------------------------------------------- traffic
@@ -518,6 +563,7 @@ def _sorted_and_fingerprint(t, kind):
         v = t[:, 0] ^ (-(1 << 63))
         return bool((v[1:] >= v[:-1]).all()), int(t.sum())
     if kind == "quartet":     # (a, b, c) lexicographic
+        t = t.view(torch.int64)
         a, b, c = (t[:, i] ^ (-(1 << 63)) for i in range(3))
         ok = (a[1:] > a[:-1]) | ((a[1:] == a[:-1]) & ((b[1:] > b[:-1]) | ((b[1:] == b[:-1]) & (c[1:] >= c[:-1]))))
         return bool(ok.all()), int(t.sum())

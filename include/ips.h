@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define IPS_ABI_VERSION 1
+#define IPS_ABI_VERSION 2
 
 /* Status codes. */
 #define IPS_OK 0
@@ -100,6 +100,16 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
                                           workspace instead of LDS, so that block_bytes
                                           may exceed the LDS budget (e.g. 2 KiB blocks
                                           with 256 buckets) */
+#define IPS_FLAG_FUSED 0x100u         /* IPS_RADIX only: run every partitioning step
+                                          with exact bucket sizes and classification
+                                          fused into the block permutation (Section 8,
+                                          future work): a digit histogram pass, then
+                                          one pass that reads every element once and
+                                          writes it once to its final position.
+                                          IPS_E_UNSUPPORTED with IPS_SAMPLESORT,
+                                          IPS_FLAG_HOST_PLAN, IPS_FLAG_LEVEL1_ONLY or
+                                          IPS_FLAG_GLOBAL_BUFFERS; IPS_E_TOO_LARGE for
+                                          n >= 2^31 - 2^16 elements */
 
 /* Tuning and test parameters.  A zero field selects the default.
  *  k            maximum number of buckets per step (power of two, 2..256;
@@ -157,8 +167,10 @@ int ips_ctx_destroy(ips_ctx* ctx);
 
 /* Workspace bytes needed to sort n elements of `elem_type` (1..6) with
  * `algo` and `params` (nullable).  Pure host computation, no HIP call.
- * The size is O(k * b) per workgroup of the largest batch plus O(n / b)
- * words of block flags.  Errors: IPS_E_INVALID_ARG, IPS_E_UNSUPPORTED,
+ * The size is O(k * b * element size) per workgroup of the largest step
+ * plus O(k) words per task of that step (Section 5.1), and two terms that
+ * grow with n by well under 0.1% of the data (the task queue and the
+ * permutation's pointer pieces).  Errors: IPS_E_INVALID_ARG, IPS_E_UNSUPPORTED,
  * IPS_E_TOO_LARGE. */
 int ips_workspace_bytes(uint64_t n, int elem_type, int algo,
                         const ips_params* params, size_t* out_bytes);
@@ -363,11 +375,13 @@ int ips_get_stats(ips_ctx* ctx, ips_stats* out);
  * elems the elements of the tasks those launches covered, launches the
  * number of launches. */
 #define IPS_MAX_LEVELS 16
-#define IPS_PHASES 11
+#define IPS_PHASES 13
 enum {
   IPS_PH_SORTED_CHECK = 0, IPS_PH_MINMAX = 1, IPS_PH_SAMPLE = 2, IPS_PH_CLASSIFY = 3,
   IPS_PH_BOUNDARIES = 4, IPS_PH_FLAGS = 5, IPS_PH_PERMUTE = 6, IPS_PH_CLEANUP_A = 7,
-  IPS_PH_CLEANUP_B = 8, IPS_PH_LDS_SORT = 9, IPS_PH_REVERSE = 10
+  IPS_PH_CLEANUP_B = 8, IPS_PH_LDS_SORT = 9, IPS_PH_REVERSE = 10,
+  IPS_PH_HISTOGRAM = 11,   /* IPS_FLAG_FUSED: digit histogram of a step */
+  IPS_PH_FUSED = 12        /* IPS_FLAG_FUSED: classification fused with the permutation */
 };
 typedef struct {
   uint32_t levels, pad;

@@ -39,9 +39,10 @@ FLAG_GLOBAL_BUFFERS = 0x10
 FLAG_PROFILE = 0x20
 FLAG_GRAPH = 0x40
 FLAG_HOST_PLAN = 0x80
+FLAG_FUSED = 0x100
 MAX_LEVELS = 16
 PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags", "permute",
-          "cleanup_a", "cleanup_b", "lds_sort", "reverse"]
+          "cleanup_a", "cleanup_b", "lds_sort", "reverse", "histogram", "fused"]
 
 EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
            "ips_sort_pairs", "ips_segments_workspace_bytes", "ips_sort_segments",

@@ -45,7 +45,12 @@ struct Cfg {
   uint32_t groups;  // permutation groups per batch
   uint32_t perm_threads;   // workgroup size of the block permutation
   uint32_t buf_bytes;      // LDS of the classification's buffer blocks
+  bool fused;              // radix steps with classification fused into the permutation
 };
+
+// Largest task of the fused radix step: its pointer words hold element
+// positions in 31 bits.
+constexpr uint64_t FUSED_MAX_N = (1ull << 31) - (1ull << 16);
 
 uint32_t elem_bytes(int t) {
   switch (t) {
@@ -120,7 +125,13 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     c->b_req = paper_block(D);
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
-  if (p->flags & ~0xFFu) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0x1FFu) return IPS_E_INVALID_ARG;
+  c->fused = (p->flags & IPS_FLAG_FUSED) != 0;
+  if (c->fused) {
+    if (!c->radix || !launchers_for(type)->fhist) return IPS_E_UNSUPPORTED;
+    if (c->gbuf || (p->flags & (IPS_FLAG_HOST_PLAN | IPS_FLAG_LEVEL1_ONLY))) return IPS_E_UNSUPPORTED;
+    if (n > FUSED_MAX_N) return IPS_E_TOO_LARGE;
+  }
   if (p->profile_mask >> IPS_PHASES) return IPS_E_INVALID_ARG;
   c->L = nullptr;
   return IPS_OK;
@@ -916,6 +927,9 @@ int setup_run(ips_ctx* ctx, Run& r, void* d, uint64_t n, uint64_t n_plan, int ty
   a.step_el = wsp<uint64_t>(r, R_STEPEL);
   // Control block: errors and flags cleared; min = all ones, max = 0.
   HIPCHK(ctx, launch_fill32(a.ctrl, CTRL_WORDS, 0u, r.st));
+  // Fused radix steps add their histograms to the bucket counters (each
+  // step zeroes the counters it used).
+  if (r.c.fused) HIPCHK(ctx, launch_fill32(a.b_count, r.L.NBE, 0u, r.st));
   HIPCHK(ctx, launch_fill32(a.ctrl + CTRL_MINMAX, 2, 0xFFFFFFFFu, r.st));
   return IPS_OK;
 }
@@ -1001,16 +1015,24 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
          }, 0));
   HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FLAGS, 0, [&] { return launch_plan_geom(a, pc, r.st); }, 0));
   const size_t dyn = c.gbuf ? 0 : (size_t)c.buf_bytes + (size_t)MAX_NB * BUF_PAD_DW * 4;
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, 0,
-                    [&] { return c.L->classify(a, r.L.WB, (uint32_t)dyn, c.gbuf, r.st); }, 0));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0,
-                    [&] { return launch_boundaries(a, r.L.TB, nbm, c.cmax, r.st); }, 0));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, 0,
-                    [&] { return c.L->permute(a, r.L.PWB, c.perm_threads, r.st); }, 0));
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, 0, [&] { return c.L->cleanup_a(a, r.L.TB, r.st); }, 0));
-  const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
-  HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
-                    [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
+  if (c.fused) {
+    // exact bucket sizes, then classification fused with the permutation
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_HISTOGRAM, 0, [&] { return c.L->fhist(a, r.L.WB, r.st); }, 0));
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0, [&] { return launch_fscan(a, r.L.TB, r.st); }, 0));
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FUSED, 0,
+                      [&] { return c.L->fused(a, r.L.WB, (uint32_t)dyn, r.st); }, 0));
+  } else {
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, 0,
+                      [&] { return c.L->classify(a, r.L.WB, (uint32_t)dyn, c.gbuf, r.st); }, 0));
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0,
+                      [&] { return launch_boundaries(a, r.L.TB, nbm, c.cmax, r.st); }, 0));
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_PERMUTE, 0,
+                      [&] { return c.L->permute(a, r.L.PWB, c.perm_threads, r.st); }, 0));
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_A, 0, [&] { return c.L->cleanup_a(a, r.L.TB, r.st); }, 0));
+    const uint32_t cln_grid = (uint32_t)std::min<uint64_t>((uint64_t)r.L.TB * nbm, 16384);
+    HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLEANUP_B, 0,
+                      [&] { return c.L->cleanup_b(a, cln_grid, r.L.WB, r.st); }, 0));
+  }
   HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
   HIPCHK(ctx, launch_lds_decide(a.ctrl, r.lds_min, r.L.LTB, r.st));
   for (uint32_t v = 0; v < 3; ++v) {

@@ -3,6 +3,7 @@
 #include "ips_kernels.hpp"
 #include "ips_launch.hpp"
 #include "ips_oop.hpp"
+#include "ips_fused.hpp"
 
 namespace ips {
 
@@ -61,6 +62,12 @@ hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n,
 hipError_t launch_oop_scan(const OopArgs& a, uint32_t nt, hipStream_t st) {
   if (!nt) return hipSuccess;
   hipLaunchKernelGGL(k_oop_scan, dim3(nt), dim3(MAX_NB), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fscan(const BatchArgs& a, uint32_t nt, hipStream_t st) {
+  if (!nt) return hipSuccess;
+  hipLaunchKernelGGL(k_fscan, dim3(nt), dim3(MAX_K), 0, st, a, nt);
   return hipGetLastError();
 }
 

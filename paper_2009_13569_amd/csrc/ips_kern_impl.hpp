@@ -5,6 +5,7 @@
 #include "ips_launch.hpp"
 #include "ips_lds_tier.hpp"
 #include "ips_oop.hpp"
+#include "ips_fused.hpp"
 
 #include <type_traits>
 
@@ -203,12 +204,37 @@ struct LaunchImpl {
     hipLaunchKernelGGL((k_copy_ranges<T::DW>), dim3(count), dim3(256), 0, st, list, from, to);
     return hipGetLastError();
   }
+  static hipError_t fhist(const BatchArgs& a, uint32_t nwg, hipStream_t st) {
+    if constexpr (T::RADIX_OK) {
+      if (!nwg) return hipSuccess;
+      hipLaunchKernelGGL((k_fhist<T>), dim3(nwg), dim3(CLS_THREADS), 0, st, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  static hipError_t fused(const BatchArgs& a, uint32_t nwg, uint32_t dyn, hipStream_t st) {
+    if constexpr (T::RADIX_OK) {
+      static bool attr_done = false;
+      if (!attr_done) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(T::BUF_BYTES + MAX_NB * BUF_PAD_DW * 4));
+        attr_done = true;
+      }
+      if (!nwg) return hipSuccess;
+      hipLaunchKernelGGL((k_fused<T>), dim3(nwg), dim3(CLS_THREADS), dyn, st, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   static const Launchers* table() {
     static const Launchers t = {
         T::CODE, (uint32_t)T::DW, (uint32_t)sizeof(typename T::Key), T::KEYS_ONLY, T::RADIX_OK,
         CAP2, {CAP0, CAP1, CAP2}, T::BUF_BYTES, &sample_, &classify, &permute, &cleanup_a, &cleanup_b, &lds_sort,
         &sorted_sample, &sorted_check, &reverse, &minmax, &seg_minmax, &seg_order, &seg_reverse,
-        &oop_classify, &oop_distribute, &copy_ranges};
+        &oop_classify, &oop_distribute, &copy_ranges, &fhist, &fused};
     return &t;
   }
 };

@@ -34,11 +34,9 @@ __device__ __forceinline__ void at_store32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Serving: `cnt` elements starting at element l of the data are in their
-// final place; they are counted for the request that holds element l (the
-// requests' first elements are listed in ascending order).
-// Serving: the request whose elements start at or before element l (the
-// last entry of the ascending table of first elements that is <= l).
+// Serving: the request that holds element l of the data (the last entry of
+// the ascending table of the requests' first elements that is <= l), and
+// the per-request counters of elements in their final place.
 __device__ __forceinline__ uint32_t seg_find(const uint32_t* ctrl, uint32_t nseg, uint64_t l) {
   const uint64_t* lo = reinterpret_cast<const uint64_t*>((uint64_t)ctrl[CTRL_SEGLO] |
                                                          ((uint64_t)ctrl[CTRL_SEGLO + 1] << 32));

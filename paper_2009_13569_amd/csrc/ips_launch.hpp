@@ -38,6 +38,10 @@ struct Launchers {
   hipError_t (*oop_classify)(const OopArgs&, uint32_t nwg, hipStream_t);
   hipError_t (*oop_distribute)(const OopArgs&, uint32_t nwg, hipStream_t);
   hipError_t (*copy_ranges)(const LTask* list, uint32_t count, const uint32_t* from, uint32_t* to, hipStream_t);
+  // radix step with classification fused into the permutation (null for
+  // types without a radix key)
+  hipError_t (*fhist)(const BatchArgs&, uint32_t nwg, hipStream_t);
+  hipError_t (*fused)(const BatchArgs&, uint32_t nwg, uint32_t dyn_lds, hipStream_t);
 };
 
 const Launchers* launchers_u32();
@@ -57,6 +61,7 @@ hipError_t launch_plan_pop(const BatchArgs&, const PlanCfg&, hipStream_t);
 hipError_t launch_plan_geom(const BatchArgs&, const PlanCfg&, hipStream_t);
 hipError_t launch_fill32_cnt(uint32_t* p, const uint32_t* count, uint32_t max_n, uint32_t v, hipStream_t);
 hipError_t launch_oop_scan(const OopArgs&, uint32_t ntask, hipStream_t);
+hipError_t launch_fscan(const BatchArgs&, uint32_t ntask, hipStream_t);
 hipError_t launch_oop_children(const OopArgs&, uint32_t ntask, uint32_t* ctrl, CTask* next, uint32_t next_cap,
                                LTask* lds, LTask* copy, uint32_t list_cap, uint32_t cap, uint32_t to_second,
                                hipStream_t);

@@ -65,10 +65,12 @@ def _resolve(field, v, kind):
 
 
 def _descend(measure, kind, cands_all=None):
-    """Coordinate descent from the defaults; returns (best dict, best ms)."""
+    """Coordinate descent from the defaults; returns (best dict, best ms,
+    ms of the defaults)."""
     cands_all = cands_all or CANDIDATES
     cur = {f: 0 for f in cands_all}
     best = measure(cur)
+    base = best
     _log(f"    defaults: {best:.3f} ms")
     for rnd in range(2):
         changed = False
@@ -89,7 +91,7 @@ def _descend(measure, kind, cands_all=None):
                     cur, best, changed = trial, ms, True
         if not changed:
             break
-    return cur, best
+    return cur, best, base
 
 
 def _source(kind: str, n: int, seed: int, dev):
@@ -117,6 +119,7 @@ def _digest(t, kind):
         ok = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] >= lo[:-1]))
         return bool(ok.all()), int(t.view(torch.int32).to(torch.int64).sum())
     if kind == "quartet":     # (a, b, c) lexicographic, as signed images of the unsigned words
+        t = t.view(torch.int64)
         a, b, c = (t[:, i] ^ (-(1 << 63)) for i in range(3))
         ok = (a[1:] > a[:-1]) | ((a[1:] == a[:-1]) & ((b[1:] > b[:-1]) | ((b[1:] == b[:-1]) & (c[1:] >= c[:-1]))))
         return bool(ok.all()), int(t.sum())
@@ -220,8 +223,27 @@ def tune_batch(reps: int, arrays: int = 4096):
         return times[len(times) // 2]
 
     _log(f"  batch: {arrays} u64 arrays, {total} keys")
-    cfg, ms = _descend(measure, "u64")
-    return cfg, ms, total
+    cfg, ms, ms0 = _descend(measure, "u64")
+    return cfg, ms, ms0, total
+
+
+def summary(path: str) -> int:
+    """Markdown table of a tuning table's measurements: per element type,
+    algorithm and size class (and the batched call) the median time with the
+    library defaults and with the tuned parameters."""
+    with open(path) as f:
+        doc = json.load(f)
+    skip = ("kind", "algo", "log2n_min", "log2n_max", "batched")
+    print("| kind | algo | n | defaults ms | tuned ms | speedup | tuned parameters |")
+    print("|---|---|---|---|---|---|---|")
+    for m in doc["measurements"]:
+        n = f"2^{m['log2n']}" if "log2n" in m else f"batch of {m.get('batch_keys')} keys"
+        d0 = m.get("defaults_ms")
+        sp = f"{d0 / m['ms']:.2f}" if d0 else "-"
+        params = ", ".join(f"{k}={v}" for k, v in m["params"].items() if k not in skip) or "(defaults)"
+        print(f"| {m['kind']} | {m.get('algo', 'samplesort')} | {n} | {d0 if d0 is not None else '-'} | "
+              f"{m['ms']} | {sp} | {params} |")
+    return 0
 
 
 def main(argv=None) -> int:
@@ -233,7 +255,10 @@ def main(argv=None) -> int:
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None)
     ap.add_argument("--update", action="store_true", help="keep the existing table's other entries")
+    ap.add_argument("--summary", metavar="TABLE", help="print a tuning table's measurements as markdown and exit")
     args = ap.parse_args(argv)
+    if args.summary:
+        return summary(args.summary)
     sys.path.insert(0, ROOT)
     import torch
 
@@ -249,19 +274,21 @@ def main(argv=None) -> int:
                 continue
             ks = [c for c in classes if c <= MAX_LOG2[kind]]
             for i, c in enumerate(ks):
-                cfg, ms = tune_single(kind, algo, c, args.reps)
+                cfg, ms, ms0 = tune_single(kind, algo, c, args.reps)
                 hi = ks[i + 1] - 1 if i + 1 < len(ks) else 40
                 e = {"kind": kind, "algo": algo, "log2n_min": c, "log2n_max": hi, "batched": 0}
                 e.update({f: int(v) for f, v in cfg.items() if v})
                 entries.append(e)
-                notes.append({"kind": kind, "algo": algo, "log2n": c, "ms": round(ms, 4), "params": e})
+                notes.append({"kind": kind, "algo": algo, "log2n": c, "ms": round(ms, 4),
+                              "defaults_ms": round(ms0, 4), "params": e})
                 torch.cuda.empty_cache()
     if args.batch:
-        cfg, ms, total = tune_batch(args.reps)
+        cfg, ms, ms0, total = tune_batch(args.reps)
         e = {"kind": "u64", "algo": "samplesort", "log2n_min": 0, "log2n_max": 40, "batched": 1}
         e.update({f: int(v) for f, v in cfg.items() if v})
         entries.append(e)
-        notes.append({"kind": "u64", "batch_keys": total, "ms": round(ms, 4), "params": e})
+        notes.append({"kind": "u64", "batch_keys": total, "ms": round(ms, 4), "defaults_ms": round(ms0, 4),
+                      "params": e})
     if args.update and os.path.exists(out):
         with open(out) as f:
             old = json.load(f)

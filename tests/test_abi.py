@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_status_strings():
-    assert ips.lib().ips_abi_version() == 1
+    assert ips.lib().ips_abi_version() == 2
     for code in range(-9, 1):
         assert ips.lib().ips_status_string(code).decode().startswith("IPS_")
 
@@ -258,3 +258,24 @@ def test_tuning_file_entries_are_valid():
         n = 1 << max(int(e["log2n_min"]), 1)
         p = ips.tuned_params(table, cnt, n, e["kind"], e.get("algo", "samplesort"), bool(e.get("batched", 0)))
         assert ips.workspace_bytes(n, e["kind"], e.get("algo", "samplesort"), p) > 0
+
+
+def test_fused_flag_validation():
+    """IPS_FLAG_FUSED is a radix option of device-planned steps: rejected
+    with samplesort, host planning, the root-step-only mode and global
+    buffers, and for more elements than its 31-bit positions hold."""
+    F = ips.FLAG_FUSED
+    assert ips.workspace_bytes(1 << 20, "u64", "radix", ips.make_params(flags=F)) > 0
+    assert ips.workspace_bytes(1 << 20, "pair", "radix", ips.make_params(flags=F)) > 0
+    for kind, algo, extra in (("u64", "samplesort", 0), ("u64", "radix", ips.FLAG_HOST_PLAN),
+                              ("u64", "radix", ips.FLAG_LEVEL1_ONLY), ("u64", "radix", ips.FLAG_GLOBAL_BUFFERS),
+                              ("rec100", "radix", 0)):
+        with pytest.raises(ips.IpsError) as e:
+            ips.workspace_bytes(1 << 20, kind, algo, ips.make_params(flags=F | extra))
+        assert e.value.code == -2, (kind, algo, extra)
+    with pytest.raises(ips.IpsError) as e:
+        ips.workspace_bytes((1 << 31) - (1 << 16) + 1, "u32", "radix", ips.make_params(flags=F))
+    assert e.value.code == -5
+    with pytest.raises(ips.IpsError) as e:
+        ips.workspace_bytes(1000, "u64", "radix", ips.make_params(flags=0x200))
+    assert e.value.code == -1
