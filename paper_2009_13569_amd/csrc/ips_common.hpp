@@ -37,6 +37,8 @@ constexpr uint32_t LDST_THREADS = 512;
 constexpr uint32_t MAX_SAMPLE = 4096;        // padded sample of one step
 constexpr uint32_t DEEP_ALPHA = 16;          // least oversampling below the root
 constexpr uint32_t PTR_BIAS = 0x80000000u;   // bias of the read pointer half
+constexpr uint32_t FUSED_THREADS = 512;             // fused radix step: two workgroups per CU
+constexpr uint32_t FUSED_BUF_BYTES = 64u * 1024u;   // and the LDS buffer blocks of one of them
 
 // Control block at the start of the workspace.
 enum CtrlSlot : uint32_t {

@@ -37,8 +37,9 @@
 
 namespace ips {
 
-constexpr uint32_t FUSED_CLAIMS = 8;                 // claims per tile at most
-constexpr uint32_t FUSED_SEGS = MAX_K + 1 + FUSED_CLAIMS;
+constexpr uint32_t FUSED_CLAIMS = 8;                 // buckets claimed from in parallel
+constexpr uint32_t FUSED_CLAIMS_MAX = 64;            // claims per tile at most
+constexpr uint32_t FUSED_SEGS = MAX_K + 1 + FUSED_CLAIMS_MAX;
 constexpr uint32_t FUSED_DEFER = 0x80000000u;        // segment source: the workgroup's deferral stack
 
 // Positions of a bucket's reader word: low half the claimed elements whose
@@ -131,10 +132,10 @@ __global__ void __launch_bounds__(MAX_K) k_fscan(BatchArgs a, uint32_t ntask) {
 #endif  // IPS_COMMON_KERNELS
 
 template <class T>
-__global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
+__global__ void __launch_bounds__(FUSED_THREADS, 2) k_fused(BatchArgs a) {
   constexpr int DW = T::DW;
   constexpr int EPT = T::EPT;
-  constexpr uint32_t NT = CLS_THREADS;
+  constexpr uint32_t NT = FUSED_THREADS;
   constexpr uint32_t TILE = NT * EPT;
   __shared__ uint32_t s_cnt[MAX_K];       // elements of bucket j taken so far
   __shared__ uint2 s_fn[MAX_K];           // {blocks complete before the tile, after it}
@@ -148,8 +149,8 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
   __shared__ uint32_t s_segsrc[FUSED_SEGS];   // its source (task-relative position, or FUSED_DEFER | stack index)
   __shared__ uint64_t s_segctr;           // (segments << 32) | elements appended by the reservation pass
   __shared__ uint32_t s_ncopy, s_nwait, s_nseg, s_M, s_push, s_pushbase, s_dtop, s_cursor, s_ncl;
-  __shared__ uint16_t s_clj[FUSED_CLAIMS];
-  __shared__ uint32_t s_cll[FUSED_CLAIMS];
+  __shared__ uint16_t s_clj[FUSED_CLAIMS_MAX];
+  __shared__ uint32_t s_cll[FUSED_CLAIMS_MAX];
   extern __shared__ __align__(16) uint32_t s_buf[];
 
   const uint32_t tid = threadIdx.x, wg = blockIdx.x;
@@ -183,6 +184,21 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
 
   uint32_t cur[EPT][DW], nxt[EPT][DW];
   uint32_t M = 0;   // elements in cur (a prefix of the material index space)
+#ifdef IPS_FUSED_STATS
+  // phase cycles seen by thread 0: classify, reserve, serial, load, waits, store; tiles, claims
+  uint64_t fst[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t ft = __builtin_readcyclecounter();
+#define FSTAT(i)                                           \
+  do {                                                     \
+    if (tid == 0) {                                        \
+      const uint64_t t1_ = __builtin_readcyclecounter();   \
+      fst[i] += t1_ - ft;                                  \
+      ft = t1_;                                            \
+    }                                                      \
+  } while (0)
+#else
+#define FSTAT(i) ((void)0)
+#endif
   for (;;) {
     // 1. Classify the tile and take buffer positions.
     uint32_t bk[EPT], sl[EPT];
@@ -201,6 +217,7 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
     }
     if (tid == 0) { s_segctr = 0; s_ncopy = 0; s_nwait = 0; }
     __syncthreads();
+    FSTAT(0);
     // 2. Reservations: per bucket one atomic for the blocks the tile
     // completes; the unread input in them becomes material segments.
     if ((tid & ~63u) < nb) {
@@ -252,64 +269,106 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
       }
     }
     __syncthreads();
+    FSTAT(1);
     // 3. The next tile: swap reads first; beyond a tile they go to the
-    // deferral stack; a short tile takes deferred elements, then claims.
-    if (tid == 0) {
+    // deferral stack; a short tile takes deferred elements, then claims
+    // (wavefront 0: rounds of claims from up to FUSED_CLAIMS buckets at
+    // once, until the tile is full or every bucket's unread input is gone).
+    if (tid < 64) {
+      const uint32_t lane = tid;
       const uint64_t sc = s_segctr;
       uint32_t nseg = (uint32_t)(sc >> 32), Mn = (uint32_t)sc, push = 0, ncl = 0;
-      s_pushbase = s_dtop;
+      uint32_t dtop = s_dtop;
+      const uint32_t pushbase = dtop;
       if (Mn > TILE) {
         push = Mn - TILE;
-        if (s_dtop + push > dcap) {   // cannot happen (at most one buffer block per bucket is deferred)
-          dev_error(a.ctrl, DE_PIECES, tix, s_dtop + push);
+        if (dtop + push > dcap) {   // cannot happen (at most one buffer block per bucket is deferred)
+          if (lane == 0) dev_error(a.ctrl, DE_PIECES, tix, dtop + push);
           push = 0;
         }
-        s_dtop += push;
+        dtop += push;
         Mn = TILE;
       } else {
-        if (s_dtop && Mn < TILE) {
-          const uint32_t pop = s_dtop < TILE - Mn ? s_dtop : TILE - Mn;
-          s_dtop -= pop;
+        if (dtop && Mn < TILE) {
+          const uint32_t pop = dtop < TILE - Mn ? dtop : TILE - Mn;
+          dtop -= pop;
           Mn += pop;
-          s_segend[nseg] = Mn;
-          s_segsrc[nseg] = FUSED_DEFER | s_dtop;
+          if (lane == 0) {
+            s_segend[nseg] = Mn;
+            s_segsrc[nseg] = FUSED_DEFER | dtop;
+          }
           ++nseg;
         }
         uint32_t cursor = s_cursor;
-        while (Mn < TILE && ncl < FUSED_CLAIMS && cursor < nb) {
-          const uint32_t j = cstart + cursor < nb ? cstart + cursor : cstart + cursor - nb;
-          uint64_t* pw = &word[j * PWORD_STRIDE];
-          if (at_load64(pw + 1) >> 32) { ++cursor; continue; }   // no unread input left
+        while (Mn < TILE && cursor < nb && ncl + FUSED_CLAIMS <= FUSED_CLAIMS_MAX) {
           const uint32_t need = TILE - Mn;
-          const uint64_t old = at_add64(pw, 0ull - (uint64_t)need);
-          const uint32_t w = (uint32_t)(old >> 32);
-          const int32_t r = (int32_t)((uint32_t)old - PTR_BIAS);
-          if (r > (int32_t)w) {
-            const uint32_t avail = (uint32_t)r - w;
-            const uint32_t got = avail < need ? avail : need;
-            Mn += got;
-            s_segend[nseg] = Mn;
-            s_segsrc[nseg] = (uint32_t)r - got;
-            ++nseg;
-            s_clj[ncl] = (uint16_t)j;
-            s_cll[ncl] = got;
-            ++ncl;
-            if (avail <= need) {   // the claim took the last unread element: claims stop at w
-              (void)at_add64(pw + 1, (uint64_t)(w + 1) << 32);
-              ++cursor;
+          const uint32_t nl = nb - cursor < FUSED_CLAIMS ? nb - cursor : FUSED_CLAIMS;
+          const uint32_t share = lane < nl ? need / nl + (lane < need % nl ? 1u : 0u) : 0u;
+          uint32_t got = 0, src = 0, j = 0;
+          bool ex = false;
+          if (lane < nl) {
+            j = cstart + cursor + lane;
+            if (j >= nb) j -= nb;
+            uint64_t* pw = &word[j * PWORD_STRIDE];
+            if (at_load64(pw + 1) >> 32) {
+              ex = true;                         // no unread input left
+            } else if (share) {
+              const uint64_t old = at_add64(pw, 0ull - (uint64_t)share);
+              const uint32_t w = (uint32_t)(old >> 32);
+              const int32_t r = (int32_t)((uint32_t)old - PTR_BIAS);
+              if (r > (int32_t)w) {
+                const uint32_t avail = (uint32_t)r - w;
+                got = avail < share ? avail : share;
+                src = (uint32_t)r - got;
+                if (avail <= share) {            // the claim took the last unread element: claims stop at w
+                  (void)at_add64(pw + 1, (uint64_t)(w + 1) << 32);
+                  ex = true;
+                }
+              } else {
+                ex = true;
+              }
             }
-          } else {
-            ++cursor;
           }
+          // lane-ordered segments of this round
+          uint32_t inc = got, incs = got ? 1u : 0u;
+#pragma unroll
+          for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t t0 = (uint32_t)__shfl_up((int)inc, off);
+            const uint32_t t1 = (uint32_t)__shfl_up((int)incs, off);
+            if (lane >= off) { inc += t0; incs += t1; }
+          }
+          if (got) {
+            s_segend[nseg + incs - 1] = Mn + inc;
+            s_segsrc[nseg + incs - 1] = src;
+            s_clj[ncl + incs - 1] = (uint16_t)j;
+            s_cll[ncl + incs - 1] = got;
+          }
+          const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+          const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)incs, 63);
+          Mn += tot;
+          nseg += cnt;
+          ncl += cnt;
+          // the cursor moves past the leading buckets found without unread input
+          const uint64_t exm = __ballot(ex) | ~low_mask64(nl);
+          cursor += exm == ~0ull ? nl : (uint32_t)__builtin_ctzll(~exm);
         }
-        s_cursor = cursor;
+        if (lane == 0) s_cursor = cursor;
       }
-      s_nseg = nseg;
-      s_M = Mn;
-      s_push = push;
-      s_ncl = ncl;
+      if (lane == 0) {
+        s_dtop = dtop;
+        s_pushbase = pushbase;
+        s_nseg = nseg;
+        s_M = Mn;
+        s_push = push;
+        s_ncl = ncl;
+#ifdef IPS_FUSED_STATS
+        fst[6] += 1;
+        fst[7] += ncl;
+#endif
+      }
     }
     __syncthreads();
+    FSTAT(2);
     const uint32_t Mn = s_M, nseg = s_nseg, push = s_push;
     auto src_of = [&](uint32_t m) -> const uint32_t* {
       uint32_t lo = 0, hi = nseg;   // first segment whose end exceeds m
@@ -339,6 +398,7 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
     // is written.
     __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
     __syncthreads();
+    FSTAT(3);
     // 4. Claimed reads finished; then wait until every claimed read of the
     // buckets whose reserved positions were claimed earlier has finished.
     if (tid < s_ncl) (void)at_add64(&word[s_clj[tid] * PWORD_STRIDE + 1], (uint64_t)s_cll[tid]);
@@ -352,6 +412,7 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
       }
     }
     __syncthreads();
+    FSTAT(4);
     // 5. Writes, as in classification: elements of the buffer block that
     // completes go to the LDS buffer, whole blocks of the tile straight to
     // their reserved positions, then the completed buffer blocks are
@@ -372,10 +433,16 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
     }
     __syncthreads();
     {
-      const uint32_t ncp = s_ncopy, tot = ncp * bdw;
-      for (uint32_t x = tid; x < tot; x += NT) {
-        const uint32_t q = x / bdw, e = x - q * bdw;
-        gd[(uint64_t)s_cpos[q] * DW + e] = buf[s_cj[q] * bstride + e];
+      const uint32_t ncp = s_ncopy, wave = tid >> 6, lane = tid & 63;
+      for (uint32_t q = wave; q < ncp; q += NT / 64) {
+        const uint32_t* src = buf + s_cj[q] * bstride;
+        uint32_t* dst = gd + (uint64_t)s_cpos[q] * DW;
+        if constexpr (DW % 2 == 0) {   // 8-byte units (elements of even dwords are 8-byte aligned)
+          for (uint32_t x = lane; x < bdw / 2; x += 64)
+            *reinterpret_cast<uint2*>(dst + 2 * x) = *reinterpret_cast<const uint2*>(src + 2 * x);
+        } else {
+          for (uint32_t x = lane; x < bdw; x += 64) dst[x] = src[x];
+        }
       }
     }
     __syncthreads();
@@ -395,8 +462,16 @@ __global__ void __launch_bounds__(CLS_THREADS) k_fused(BatchArgs a) {
       for (int d = 0; d < DW; ++d) cur[i][d] = nxt[i][d];
     M = Mn;
     __syncthreads();
+    FSTAT(5);
     if (M == 0) break;   // no unread input left in the task and nothing deferred
   }
+#ifdef IPS_FUSED_STATS
+  if (tid == 0) {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + 32);
+    for (int i = 0; i < 8; ++i) atomicAdd(&c[i], (unsigned long long)fst[i]);
+  }
+#endif
+#undef FSTAT
   // Partial buffer blocks: no unread input is left, so the reserved
   // positions were all claimed; they are written once those reads are done.
   const uint32_t wave = tid >> 6, lane = tid & 63;

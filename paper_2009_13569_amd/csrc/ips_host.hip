@@ -131,6 +131,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     if (!c->radix || !launchers_for(type)->fhist) return IPS_E_UNSUPPORTED;
     if (c->gbuf || (p->flags & (IPS_FLAG_HOST_PLAN | IPS_FLAG_LEVEL1_ONLY))) return IPS_E_UNSUPPORTED;
     if (n > FUSED_MAX_N) return IPS_E_TOO_LARGE;
+    c->buf_bytes = FUSED_BUF_BYTES;   // two workgroups of the fused kernel share a CU's LDS
   }
   if (p->profile_mask >> IPS_PHASES) return IPS_E_INVALID_ARG;
   c->L = nullptr;
@@ -1019,8 +1020,9 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
     // exact bucket sizes, then classification fused with the permutation
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_HISTOGRAM, 0, [&] { return c.L->fhist(a, r.L.WB, r.st); }, 0));
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_BOUNDARIES, 0, [&] { return launch_fscan(a, r.L.TB, r.st); }, 0));
+    const size_t fdyn = (size_t)c.buf_bytes + (size_t)MAX_K * BUF_PAD_DW * 4;
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_FUSED, 0,
-                      [&] { return c.L->fused(a, r.L.WB, (uint32_t)dyn, r.st); }, 0));
+                      [&] { return c.L->fused(a, r.L.WB, (uint32_t)fdyn, r.st); }, 0));
   } else {
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_CLASSIFY, 0,
                       [&] { return c.L->classify(a, r.L.WB, (uint32_t)dyn, c.gbuf, r.st); }, 0));
@@ -1671,7 +1673,13 @@ struct SLane {
   int err = IPS_OK;
 };
 
-constexpr uint32_t SERVE_STEPS = 1;   // steps per round of a lane (arrivals are admitted between rounds)
+// Steps per round of a lane: one while requests wait for admission or the
+// lane holds much work (arrivals are admitted between rounds), more for a
+// lightly loaded lane with nothing waiting (fewer host round trips for the
+// few requests in flight).
+constexpr uint32_t SERVE_STEPS = 1;
+constexpr uint32_t SERVE_STEPS_IDLE = 4;
+constexpr uint64_t SERVE_LIGHT_ELEMS = 1ull << 22;
 
 struct LaneExtra {
   size_t o_seglo, o_done, o_items, o_mn, o_mx, total;
@@ -1851,7 +1859,7 @@ int lane_resolve_radix(SLane& L, ips_request* reqs, const std::vector<uint32_t>&
 // One round of an idle lane: the new small requests through the LDS tier,
 // the new roots onto the queue, SERVE_STEPS device-planned steps, and the
 // asynchronous read-back of the control block and the request counters.
-int lane_launch(SLane& L) {
+int lane_launch(SLane& L, uint32_t steps) {
   Run& r = L.r;
   if (!L.lt_new.empty()) {
     if (int e = launch_lds_tasks(r, L.lt_new, 0)) return e;
@@ -1879,7 +1887,7 @@ int lane_launch(SLane& L) {
     L.roots_new.clear();
     HIPCHK(L.lctx, launch_fill32(r.a.ctrl + CTRL_QTAIL, 1, L.qtail, L.st));
   }
-  for (uint32_t s = 0; s < SERVE_STEPS; ++s)
+  for (uint32_t s = 0; s < steps; ++s)
     if (int e = enqueue_step(r, L.pc, L.ca, MAX_STEPS_RECORDED)) return e;
   HIPCHK(L.lctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, L.st));
   HIPCHK(L.lctx, hipMemcpyAsync(L.h_done, L.d_done, L.reqs.size() * 8, hipMemcpyDeviceToHost, L.st));
@@ -2060,7 +2068,9 @@ int serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_s
       }
       int e2 = lane_resolve_radix(L, reqs, radix_new, now, &done);
       if (!e2 && !L.active.empty()) {
-        e2 = lane_launch(L);
+        bool waiting = next < nreq && reqs[order[next]].arrival_s <= s_since(t0);
+        for (const SLane& o : lanes) waiting = waiting || !o.waiting.empty();
+        e2 = lane_launch(L, waiting || L.inflight > SERVE_LIGHT_ELEMS ? SERVE_STEPS : SERVE_STEPS_IDLE);
         ++round_id;
         any_busy = any_busy || L.busy;
       }
@@ -2077,7 +2087,7 @@ int serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_s
         if (left > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(left - 1e-4));
       }
     } else if (any_busy) {
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
     }
   }
   for (SLane& L : lanes) {

@@ -219,11 +219,11 @@ struct LaunchImpl {
       if (!attr_done) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(T::BUF_BYTES + MAX_NB * BUF_PAD_DW * 4));
+                                  (int)(FUSED_BUF_BYTES + MAX_K * BUF_PAD_DW * 4));
         attr_done = true;
       }
       if (!nwg) return hipSuccess;
-      hipLaunchKernelGGL((k_fused<T>), dim3(nwg), dim3(CLS_THREADS), dyn, st, a);
+      hipLaunchKernelGGL((k_fused<T>), dim3(nwg), dim3(FUSED_THREADS), dyn, st, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
