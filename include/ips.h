@@ -110,6 +110,15 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
                                           IPS_FLAG_HOST_PLAN, IPS_FLAG_LEVEL1_ONLY or
                                           IPS_FLAG_GLOBAL_BUFFERS; IPS_E_TOO_LARGE for
                                           n >= 2^31 - 2^16 elements */
+#define IPS_FLAG_INSERTION_BASE 0x200u /* IPS_SAMPLESORT with n0 > 0: the paper's base
+                                          case (Section 4.2): a bucket of at most 2 n0
+                                          elements, or any bucket of a task of at most
+                                          k n0 elements, is sorted by insertion sort
+                                          (one thread per bucket) instead of the LDS
+                                          tier; larger ones are partitioned again.
+                                          The number of tasks grows as n / n0, and the
+                                          workspace with it.  IPS_E_INVALID_ARG when
+                                          n0 = 0, IPS_E_UNSUPPORTED with IPS_RADIX */
 
 /* Tuning and test parameters.  A zero field selects the default.
  *  k            maximum number of buckets per step (power of two, 2..256;

@@ -40,6 +40,7 @@ FLAG_PROFILE = 0x20
 FLAG_GRAPH = 0x40
 FLAG_HOST_PLAN = 0x80
 FLAG_FUSED = 0x100
+FLAG_INSERTION_BASE = 0x200
 MAX_LEVELS = 16
 PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags", "permute",
           "cleanup_a", "cleanup_b", "lds_sort", "reverse", "histogram", "fused"]

@@ -37,6 +37,7 @@ constexpr uint32_t LDST_THREADS = 512;
 constexpr uint32_t MAX_SAMPLE = 4096;        // padded sample of one step
 constexpr uint32_t DEEP_ALPHA = 16;          // least oversampling below the root
 constexpr uint32_t PTR_BIAS = 0x80000000u;   // bias of the read pointer half
+constexpr uint32_t LDS_INSERTION = 3;   // base-case "variant" that sorts list 0 by insertion sort
 constexpr uint32_t FUSED_THREADS = 512;             // fused radix step: two workgroups per CU
 constexpr uint32_t FUSED_BUF_BYTES = 64u * 1024u;   // and the LDS buffer blocks of one of them
 
@@ -168,6 +169,7 @@ struct ChildArgs {
   CTask* next;
   uint32_t caps[3];
   uint32_t lt_cap, next_cap;
+  uint64_t ins_parent;   // insertion-sort base case: every bucket of a task of at most k n0 elements (0: off)
 };
 
 // Workspace budgets and parameters of the device-planned execution (the

@@ -46,6 +46,7 @@ struct Cfg {
   uint32_t perm_threads;   // workgroup size of the block permutation
   uint32_t buf_bytes;      // LDS of the classification's buffer blocks
   bool fused;              // radix steps with classification fused into the permutation
+  bool insertion;          // the paper's base case: insertion sort of buckets of <= 2 n0 elements
 };
 
 // Largest task of the fused radix step: its pointer words hold element
@@ -125,7 +126,13 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     c->b_req = paper_block(D);
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
-  if (p->flags & ~0x1FFu) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0x3FFu) return IPS_E_INVALID_ARG;
+  c->insertion = (p->flags & IPS_FLAG_INSERTION_BASE) != 0;
+  if (c->insertion) {
+    if (c->radix) return IPS_E_UNSUPPORTED;
+    if (!c->n0) return IPS_E_INVALID_ARG;
+    c->cap = std::min<uint32_t>(dcap, 2 * c->n0);   // a task of at most 2 n0 elements is a base case
+  }
   c->fused = (p->flags & IPS_FLAG_FUSED) != 0;
   if (c->fused) {
     if (!c->radix || !launchers_for(type)->fhist) return IPS_E_UNSUPPORTED;
@@ -475,12 +482,17 @@ int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
   std::vector<LTask> lt;
   lt.reserve(lt_in.size());
   size_t bound[4] = {0, 0, 0, 0};
-  for (uint32_t v = 0; v < 3; ++v) {
-    const uint32_t lo = v ? caps[v - 1] : 0;
-    if (v && caps[v] == caps[v - 1]) { bound[v + 1] = lt.size(); continue; }
-    for (const LTask& t : lt_in)
-      if (t.n > lo && t.n <= caps[v]) lt.push_back(t);
-    bound[v + 1] = lt.size();
+  if (r.c.insertion) {   // one list, sorted by insertion sort
+    lt = lt_in;
+    bound[1] = bound[2] = bound[3] = lt.size();
+  } else {
+    for (uint32_t v = 0; v < 3; ++v) {
+      const uint32_t lo = v ? caps[v - 1] : 0;
+      if (v && caps[v] == caps[v - 1]) { bound[v + 1] = lt.size(); continue; }
+      for (const LTask& t : lt_in)
+        if (t.n > lo && t.n <= caps[v]) lt.push_back(t);
+      bound[v + 1] = lt.size();
+    }
   }
   size_t done = 0;
   while (done < lt.size()) {
@@ -495,8 +507,8 @@ int launch_lds_tasks(Run& r, const std::vector<LTask>& lt_in, uint32_t row) {
       uint64_t el = 0;
       for (size_t q = p0; q < p1; ++q) el += lt[q].n;
       HIPCHK(r.ctx, timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el, [&] {
-               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data, v, r.a.ctrl, nullptr,
-                                      0, r.st);
+               return r.c.L->lds_sort(d_lt + (p0 - done), (uint32_t)(p1 - p0), r.data,
+                                      r.c.insertion ? LDS_INSERTION : v, r.a.ctrl, nullptr, 0, r.st);
              }));
     }
     done += cnt;
@@ -515,9 +527,10 @@ hipError_t launch_lds_lists(Run& r, const ChildArgs& ca, const uint32_t (&cnt)[3
                             uint32_t row) {
   for (uint32_t v = 0; v < 3; ++v) {
     if (!cnt[v]) continue;
-    if (v && r.c.L->lds_caps[v] == r.c.L->lds_caps[v - 1]) return hipErrorInvalidValue;
+    if (v && (r.c.insertion || r.c.L->lds_caps[v] == r.c.L->lds_caps[v - 1])) return hipErrorInvalidValue;
     hipError_t e = timed(r.ctx, r.st, row, IPS_PH_LDS_SORT, el[v], [&] {
-      return r.c.L->lds_sort(ca.lt[v], cnt[v], r.data, v, r.a.ctrl, nullptr, 0, r.st);
+      return r.c.L->lds_sort(ca.lt[v], cnt[v], r.data, r.c.insertion ? LDS_INSERTION : v, r.a.ctrl, nullptr, 0,
+                             r.st);
     });
     if (e != hipSuccess) return e;
     r.ctx->stats.lds_tasks += cnt[v];
@@ -707,6 +720,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
   ca.next = wsp<CTask>(r, R_NEXT);
   ca.lt_cap = r.L.LTB;
   ca.next_cap = r.L.NXB;
+  ca.ins_parent = c.insertion ? (uint64_t)c.k * c.n0 : 0;
   CTask* h_next = reinterpret_cast<CTask*>(r.h_rb);
   const uint32_t next_pre = (uint32_t)std::min<size_t>(r.L.NXB, (r.rb_bytes / 2) / sizeof(CTask));
   uint64_t* h_root = reinterpret_cast<uint64_t*>(r.h_rb + r.rb_bytes / 2);
@@ -1038,10 +1052,11 @@ int enqueue_step(Run& r, const PlanCfg& pc, const ChildArgs& ca, uint32_t step) 
   HIPCHK(ctx, launch_children(a, ca, r.L.TB, r.st));
   HIPCHK(ctx, launch_lds_decide(a.ctrl, r.lds_min, r.L.LTB, r.st));
   for (uint32_t v = 0; v < 3; ++v) {
-    if (v && c.L->lds_caps[v] == c.L->lds_caps[v - 1]) continue;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(ca.lt_cap, 2048);
+    if (v && (c.insertion || c.L->lds_caps[v] == c.L->lds_caps[v - 1])) continue;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ca.lt_cap, c.insertion ? (uint64_t)ca.lt_cap : 2048);
     HIPCHK(ctx, timed(ctx, r.st, row, IPS_PH_LDS_SORT, 0, [&] {
-             return c.L->lds_sort(ca.lt[v], grid, r.data, v, a.ctrl, a.ctrl + CTRL_NLDS + v, ca.lt_cap, r.st);
+             return c.L->lds_sort(ca.lt[v], grid, r.data, c.insertion ? LDS_INSERTION : v, a.ctrl,
+                                  a.ctrl + CTRL_NLDS + v, ca.lt_cap, r.st);
            }, 1 + (int)v));
   }
   HIPCHK(ctx, launch_lds_reset(a.ctrl, r.st));
@@ -1068,6 +1083,7 @@ void plan_cfg(const Run& r, PlanCfg* pcp, ChildArgs* cap) {
   ca.next = reinterpret_cast<CTask*>(r.ws + r.L.off[R_NEXT]);
   ca.lt_cap = 2 * r.L.LTB;
   ca.next_cap = r.L.NXB;
+  ca.ins_parent = c.insertion ? (uint64_t)c.k * c.n0 : 0;
 }
 
 int device_loop(Run& r, const std::vector<HTask>& roots, const std::vector<LTask>& lds_roots) {
@@ -1482,7 +1498,8 @@ int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_
   ips_params p;
   if (params) p = *params;
   else std::memset(&p, 0, sizeof(p));
-  if (p.flags & (IPS_FLAG_LEVEL1_ONLY | IPS_FLAG_GRAPH | IPS_FLAG_HOST_PLAN | IPS_FLAG_GLOBAL_BUFFERS))
+  if (p.flags & (IPS_FLAG_LEVEL1_ONLY | IPS_FLAG_GRAPH | IPS_FLAG_HOST_PLAN | IPS_FLAG_GLOBAL_BUFFERS |
+                 IPS_FLAG_FUSED | IPS_FLAG_INSERTION_BASE))
     return IPS_E_INVALID_ARG;
   if (n >= (1ull << 32)) return IPS_E_TOO_LARGE;
   Run r;

@@ -134,6 +134,12 @@ struct LaunchImpl {
   static hipError_t lds_sort(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t variant, uint32_t* ctrl,
                              const uint32_t* cnt, uint32_t cnt_cap, hipStream_t st) {
     if (!nt) return hipSuccess;
+    if (variant == LDS_INSERTION) {   // the paper's insertion-sort base case, one task per thread
+      uint32_t g = (nt + 255) / 256;
+      if (g > 2048) g = 2048;
+      hipLaunchKernelGGL((k_insertion<T>), dim3(g), dim3(256), 0, st, lt, nt, data, ctrl, cnt, cnt_cap);
+      return hipGetLastError();
+    }
     if (variant > 2) return hipErrorInvalidValue;
     uint32_t* pop = cnt ? ctrl + CTRL_LDSPOP + variant : nullptr;
     if (variant == 2) return lds_launch<SH::N2, SH::E2>(lt, nt, data, ctrl, cnt, cnt_cap, pop, st);

@@ -1730,6 +1730,10 @@ __device__ __forceinline__ Child child_of(const BatchArgs& a, const ChildArgs& c
   } else if (ch.sz == tk.n) {
     ch.tflags = TF_EQ_ON;   // no progress without equality buckets
   }
+  if (c.ins_parent) {   // the paper's base-case rule: size <= 2 n0, or the parent <= k n0
+    ch.dest = (ch.sz <= c.caps[0] || tk.n <= c.ins_parent) ? 0u : 3u;
+    return ch;
+  }
   ch.dest = ch.sz <= c.caps[2] ? (ch.sz <= c.caps[0] ? 0u : (ch.sz <= c.caps[1] ? 1u : 2u)) : 3u;
   return ch;
 }

@@ -804,6 +804,41 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
   }
 }
 
+// The paper's base case (Section 4.2): insertion sort of one small task
+// per thread, in place in global memory (the elements of a task of a few
+// dozen elements stay in the caches).  Used with IPS_FLAG_INSERTION_BASE,
+// where a bucket of at most 2 n0 elements, or any bucket of a task of at
+// most k n0 elements, is a base case.  Same calling convention as
+// k_lds_tier (a list of nt tasks, or a device count).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_insertion(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap) {
+  constexpr int DW = T::DW;
+  if (cnt && !ctrl[CTRL_LDSRUN]) return;
+  const uint32_t count = cnt ? (*cnt < cnt_cap ? *cnt : cnt_cap) : nt;
+  const uint32_t nseg = ctrl[CTRL_NSEG];
+  unsigned long long* const seg_done = nseg ? seg_done_ptr(ctrl) : nullptr;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+    const LTask t = lt[i];
+    uint32_t* g = data + t.l * DW;
+    for (uint32_t x = 1; x < t.n; ++x) {
+      uint32_t e[DW];
+      ld_elem<DW>(g + (uint64_t)x * DW, e);
+      const typename T::Key k = T::key_w(e);
+      uint32_t y = x;
+      while (y > 0) {
+        uint32_t p[DW];
+        ld_elem<DW>(g + (uint64_t)(y - 1) * DW, p);
+        if (!kless(k, T::key_w(p))) break;
+        st_elem<DW>(g + (uint64_t)y * DW, p);
+        --y;
+      }
+      st_elem<DW>(g + (uint64_t)y * DW, e);
+    }
+    if (seg_done) atomicAdd(&seg_done[t.req], (unsigned long long)t.n);   // serving
+  }
+}
+
 template <class T, uint32_t CAP>
 constexpr size_t lds_bitonic_bytes() {
   return (size_t)CAP * sizeof(typename T::Key) + (size_t)CAP * 2 + (size_t)CAP * T::DW * 4;

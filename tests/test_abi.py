@@ -277,5 +277,16 @@ def test_fused_flag_validation():
         ips.workspace_bytes((1 << 31) - (1 << 16) + 1, "u32", "radix", ips.make_params(flags=F))
     assert e.value.code == -5
     with pytest.raises(ips.IpsError) as e:
-        ips.workspace_bytes(1000, "u64", "radix", ips.make_params(flags=0x200))
+        ips.workspace_bytes(1000, "u64", "radix", ips.make_params(flags=0x400))
     assert e.value.code == -1
+
+
+def test_insertion_base_validation():
+    I = ips.FLAG_INSERTION_BASE
+    assert ips.workspace_bytes(1 << 20, "u64", params=ips.make_params(n0=16, flags=I)) > 0
+    with pytest.raises(ips.IpsError) as e:
+        ips.workspace_bytes(1 << 20, "u64", params=ips.make_params(flags=I))     # n0 = 0
+    assert e.value.code == -1
+    with pytest.raises(ips.IpsError) as e:
+        ips.workspace_bytes(1 << 20, "u64", "radix", ips.make_params(n0=16, flags=I))
+    assert e.value.code == -2

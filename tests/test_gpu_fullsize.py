@@ -111,3 +111,33 @@ def test_small_config_elementwise(sorter):
     sorter.sort_(t, params=p)
     torch.cuda.synchronize()
     assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))
+
+
+def test_small_config_insertion_base_case(sorter):
+    """The same configuration with the paper's base case: buckets of at most
+    2 n0 = 32 elements, and every bucket of a task of at most k n0 = 4096
+    elements, sorted by insertion sort; everything larger partitioned again
+    (IPS_FLAG_INSERTION_BASE).  Element by element against the oracle, also
+    for records and for inputs with many equal keys."""
+    import synth
+    import torch
+    flags = ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_INSERTION_BASE
+    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=flags)
+    a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
+    t = torch.from_numpy(a).cuda()
+    log("config 1 with insertion-sort base cases")
+    sorter.sort_(t, params=p)
+    torch.cuda.synchronize()
+    assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))
+    st = sorter.stats()
+    assert st.levels >= 3, st.levels   # 2^20 -> 2^12 -> 16: three partitioning levels (k' adapts below)
+    from gpu_util import generate
+    for kind, dist, n in (("u32", "twodup", 300_001), ("pair", "rootdup", 100_003), ("rec100", "uniform", 20_011),
+                          ("quartet", "eightdup", 50_001), ("f64", "exponential", 100_003)):
+        a = generate(kind, dist, n, 31)
+        log(f"insertion base case {kind} {dist} n={n}")
+        q = ips.make_params(n0=16, flags=ips.FLAG_INSERTION_BASE | ips.FLAG_NO_SORTED_CHECK)
+        t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        sorter.sort_(t, params=q, kind=kind)
+        torch.cuda.synchronize()
+        assert_parity(t.cpu().numpy(), a, kind)
