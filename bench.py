@@ -786,6 +786,7 @@ def bench_batch(args) -> int:
     untuned = ips.Sorter(0, tuning=None)
     ws0 = untuned.workspace(ips.segments_workspace_bytes(total, segs, nseg, "u64", "samplesort",
                                                          untuned.params_for(total, "u64", batched=True)))
+    first_out = None
     for mode in ("batched", "batched_defaults", "batched_graph", "per_array"):
         times = []
         for step in range(args.warmup + args.steps):
@@ -808,6 +809,11 @@ def bench_batch(args) -> int:
                 times.append(time.perf_counter() - t0)
         ok, s = _seg_sorted_and_sum(work, offs.tolist())
         assert ok and s == ref_sum, f"{mode}: output not sorted per array or multiset changed"
+        # keys only: every mode's output equals the first one's, array by array and bit for bit
+        if first_out is None:
+            first_out = work.clone()
+        else:
+            assert torch.equal(work, first_out), f"{mode}: output differs from the batched call's"
         ms = 1e3 * float(np.mean(times))
         res[mode] = {"ms_per_step": round(ms, 3), "Gkeys_per_s": round(total / (ms * 1e-3) / 1e9, 3)}
         log(f"{mode}: {ms:.2f} ms/step, {res[mode]['Gkeys_per_s']:.2f} Gkeys/s")
@@ -864,6 +870,17 @@ def bench_serve(args) -> int:
         return [int(t.view(torch.int64).sum()) if t.dtype != torch.int32 else int(t.to(torch.int64).sum())
                 for t in ts]
 
+    def order_fp(ts):
+        """Order-sensitive fingerprint of each request's key sequence: the sum
+        of key_i * (2 i + 1), wrapping in 64 bits (Pair: the key column)."""
+        out = []
+        for t, k in zip(ts, kinds):
+            v = t[:, 0] if k == "pair" else t
+            v = v.to(torch.int64) & 0xFFFFFFFF if k == "u32" else v.view(torch.int64)
+            w = torch.arange(v.numel(), dtype=torch.int64, device=v.device) * 2 + 1
+            out.append(int((v * w).sum()))
+        return out
+
     sorter = ips.Sorter(0)
     budget = int(args.budget_gb * 1e9)
     tens = make()
@@ -874,6 +891,14 @@ def bench_serve(args) -> int:
     if rc != 0:
         log(f"alone pass failed rc={rc} device_error={hex(ips.lib().ips_last_device_error(sorter._h))}")
     assert rc == 0
+    alone = order_fp(tens)   # each request sorted alone
+    for t, k in zip(tens, kinds):
+        v = t[:, 0] if k == "pair" else t
+        if k == "f64":
+            assert bool((v[1:] >= v[:-1]).all())
+        else:
+            w = v.to(torch.int64) ^ (-(1 << 63)) if k != "u32" else v.to(torch.int64) & 0xFFFFFFFF
+            assert bool((w[1:] >= w[:-1]).all())
     svc = np.array([r["done_s"] - r["start_s"] for r in res0])
     mean_svc = float(svc.mean())
     log(f"mean service time alone {mean_svc * 1e3:.3f} ms (total {svc.sum():.2f} s)")
@@ -899,13 +924,8 @@ def bench_serve(args) -> int:
                     f"hip={ips.lib().ips_last_hip_error(sorter._h)} failing={bad[:8]}")
             assert rc == 0, rc
             assert fp(tens) == ref, "multiset changed"
-            for t, k in zip(tens[:: max(1, N // 64)], kinds[:: max(1, N // 64)]):
-                v = t[:, 0] if k == "pair" else t
-                if k == "f64":
-                    assert bool((v[1:] >= v[:-1]).all())
-                else:
-                    w = v.to(torch.int64) ^ (-(1 << 63)) if k != "u32" else v.to(torch.int64) & 0xFFFFFFFF
-                    assert bool((w[1:] >= w[:-1]).all())
+            # every request's key sequence equals its sequence when sorted alone
+            assert order_fp(tens) == alone, "a served result differs from the same request sorted alone"
             lat = np.array([r["done_s"] - a for r, a in zip(res, arr)])
             span = max(r["done_s"] for r in res)   # from the first arrival (time 0) to the last completion
             key = f"rho{rho}_{name}"

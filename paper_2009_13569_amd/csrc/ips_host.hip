@@ -1690,13 +1690,10 @@ struct SLane {
   int err = IPS_OK;
 };
 
-// Steps per round of a lane: one while requests wait for admission or the
-// lane holds much work (arrivals are admitted between rounds), more for a
-// lightly loaded lane with nothing waiting (fewer host round trips for the
-// few requests in flight).
+// Steps per round of a lane (arrivals are admitted between rounds).  A
+// round whose task queue is empty runs no step (only the LDS-tier sorts of
+// newly admitted small requests).
 constexpr uint32_t SERVE_STEPS = 1;
-constexpr uint32_t SERVE_STEPS_IDLE = 4;
-constexpr uint64_t SERVE_LIGHT_ELEMS = 1ull << 22;
 
 struct LaneExtra {
   size_t o_seglo, o_done, o_items, o_mn, o_mx, total;
@@ -1904,6 +1901,7 @@ int lane_launch(SLane& L, uint32_t steps) {
     L.roots_new.clear();
     HIPCHK(L.lctx, launch_fill32(r.a.ctrl + CTRL_QTAIL, 1, L.qtail, L.st));
   }
+  if (L.qhead == L.qtail) steps = 0;   // nothing queued (the host's view is exact between rounds)
   for (uint32_t s = 0; s < steps; ++s)
     if (int e = enqueue_step(r, L.pc, L.ca, MAX_STEPS_RECORDED)) return e;
   HIPCHK(L.lctx, hipMemcpyAsync(r.h_ctrl, r.a.ctrl, CTRL_WORDS * 4, hipMemcpyDeviceToHost, L.st));
@@ -2085,9 +2083,7 @@ int serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_s
       }
       int e2 = lane_resolve_radix(L, reqs, radix_new, now, &done);
       if (!e2 && !L.active.empty()) {
-        bool waiting = next < nreq && reqs[order[next]].arrival_s <= s_since(t0);
-        for (const SLane& o : lanes) waiting = waiting || !o.waiting.empty();
-        e2 = lane_launch(L, waiting || L.inflight > SERVE_LIGHT_ELEMS ? SERVE_STEPS : SERVE_STEPS_IDLE);
+        e2 = lane_launch(L, SERVE_STEPS);
         ++round_id;
         any_busy = any_busy || L.busy;
       }
@@ -2104,7 +2100,9 @@ int serve_continuous(ips_ctx* ctx, ips_request* reqs, uint32_t nreq, const ips_s
         if (left > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(left - 1e-4));
       }
     } else if (any_busy) {
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      // poll the lanes' events again at once (a timed sleep lasts tens of
+      // microseconds on a Linux host, longer than a small request's round)
+      std::this_thread::yield();
     }
   }
   for (SLane& L : lanes) {
