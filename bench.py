@@ -63,7 +63,11 @@ def main() -> int:
                     help="print a rocprofv3 kernel_stats.csv as a markdown table")
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
                     help="turn rocprofv3 --pmc output folders into a per-kernel counter table (markdown)")
+    ap.add_argument("--summary", metavar="JSON",
+                    help="print the JSON line of a run of this script (any workload) as markdown tables")
     args = ap.parse_args()
+    if args.summary:
+        return result_summary(args.summary)
     if args.kernel_stats_summary:
         return kernel_stats_summary(args.kernel_stats_summary)
     if args.counter_summary:
@@ -441,6 +445,77 @@ def traffic_summary(fetch_dir: str, write_dir: str, cal_fetch_dir: str, cal_writ
 
 CU_NUM = 256
 XCD_NUM = 8
+
+
+def result_summary(path: str) -> int:
+    """Markdown tables of one JSON result line of this script."""
+    with open(path) as f:
+        d = json.loads(f.read().strip().splitlines()[-1])
+    out = [f"Metric: {d['metric']}: **{d['value']} {d['unit']}**", ""]
+    if "cases" in d:        # sweep
+        groups = {}
+        for c in d["cases"]:
+            groups.setdefault((c["kind"], c["log2n"]), {}).setdefault(c["dist"], {})[c["algo"]] = c
+        for (kind, lg), dists in groups.items():
+            out += [f"## {kind}, n = 2^{lg}", "",
+                    "| generator | samplesort ms | Gelem/s | levels | IPS2Ra ms | Gelem/s | levels | "
+                    "sorted keys = oracle's |", "|---|---|---|---|---|---|---|---|"]
+            for dist, algos in dists.items():
+                cells, eq = [], []
+                for a in ("samplesort", "radix"):
+                    c = algos.get(a)
+                    cells += [str(c["ms"]), str(c["Gelems_per_s"]), str(c["levels"])] if c else ["-", "-", "-"]
+                    if c:
+                        eq.append({True: "yes", False: "NO", None: "-"}[c.get("oracle_digest_equal")])
+                out.append(f"| {dist} | " + " | ".join(cells) + f" | {', '.join(eq)} |")
+            out.append("")
+    elif "per_array_calls" in d:   # batch
+        out += ["| mode | ms/step | Gkeys/s |", "|---|---|---|",
+                f"| one batched call, tuned table | {d['ms_per_step']} | {d['value']} |",
+                f"| one batched call, library defaults | {d['untuned_defaults']['ms_per_step']} | "
+                f"{d['untuned_defaults']['Gkeys_per_s']} |",
+                f"| batched call as HIP-graph replays | {d['graph_replay']['ms_per_step']} | "
+                f"{d['graph_replay']['Gkeys_per_s']} |",
+                f"| one call per array | {d['per_array_calls']['ms_per_step']} | {d['per_array_calls']['Gkeys_per_s']} |",
+                "", f"Speedup of the batched call over one call per array: {d['speedup_vs_per_array']}x."]
+    elif "runs" in d and any(k.startswith("rho") for k in d["runs"]):   # serve
+        out += ["| offered load | policy | p50 ms | p99 ms | Gelem/s | makespan s | rounds |",
+                "|---|---|---|---|---|---|---|"]
+        for k, r in d["runs"].items():
+            rho, pol = k[3:].split("_", 1)
+            out.append(f"| {rho} | {pol} | {r['p50_ms']} | {r['p99_ms']} | {r['Gelems_per_s']} | {r['makespan_s']} | "
+                       f"{r['batches']} |")
+    elif "runs" in d:   # oop ablation
+        out += ["| step | ms/sort | Gkeys/s |", "|---|---|---|"]
+        for k, r in d["runs"].items():
+            out.append(f"| {k} | {r['ms_per_sort']} | {r['Gkeys_per_s']} |")
+        out += ["", "| step | level | elements | partition ms | algorithmic bytes | GB/s | LDS-tier ms |",
+                "|---|---|---|---|---|---|---|"]
+        for k, r in d["runs"].items():
+            for l in r["levels"]:
+                out.append(f"| {k} | {l['level']} | {l['elems']} | {l['partition_ms']} | {l['algorithmic_bytes']} | "
+                           f"{l['GBps']} | {l.get('lds_ms', '-')} |")
+    else:   # the sort workload
+        def levels_table(levels, title):
+            rows = [f"### {title}", "", "| level | elements | partition ms | GB/s at 4 D n' | fraction of 8 TB/s | "
+                    "own bytes/elem | own GB/s | LDS-tier ms |", "|---|---|---|---|---|---|---|---|"]
+            for l in levels:
+                rows.append(f"| {l['level']} | {l['elems']} | {l['ms']} | {l.get('GBps', '-')} | {l.get('frac', '-')} | "
+                            f"{l.get('own_bytes_per_elem', '-')} | {l.get('own_GBps', '-')} | {l.get('lds_ms', '-')} |")
+            return rows + [""]
+        out += [f"- samplesort: {d['ms_per_step']} ms per sort, {d['value']} Gkeys/s"]
+        if d.get("radix"):
+            out.append(f"- IPS2Ra: {d['radix']['ms_per_step']} ms per sort, {d['radix']['value']} Gkeys/s")
+            if d["radix"].get("fused"):
+                out.append(f"- IPS2Ra with classification fused into the permutation: "
+                           f"{d['radix']['fused']['ms_per_step']} ms per sort, {d['radix']['fused']['value']} Gkeys/s")
+        out += [f"- sorted keys equal the oracle's digest: {d.get('oracle_digest_equal')}",
+                f"- dominant kernel: {d['roofline']}", ""]
+        out += levels_table(d["levels"], "samplesort, per level")
+        if d.get("radix", {}).get("fused"):
+            out += levels_table(d["radix"]["fused"]["levels"], "IPS2Ra fused, per level")
+    print("\n".join(out))
+    return 0
 
 
 def counter_summary(folders: list) -> int:
