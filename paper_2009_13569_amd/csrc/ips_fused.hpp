@@ -42,6 +42,11 @@ constexpr uint32_t FUSED_CLAIMS_MAX = 64;            // claims per tile at most
 constexpr uint32_t FUSED_SEGS = MAX_K + 1 + FUSED_CLAIMS_MAX;
 constexpr uint32_t FUSED_DEFER = 0x80000000u;        // segment source: the workgroup's deferral stack
 
+// Elements per thread of a fused tile: larger tiles than classification's
+// (one reservation atomic per bucket and tile, fewer barriers per element),
+// as far as the registers of four waves per SIMD allow.
+template <class T> struct FusedEpt { static constexpr int value = T::DW == 1 ? 14 : (T::DW == 2 ? 10 : 5); };
+
 // Positions of a bucket's reader word: low half the claimed elements whose
 // reads have finished, high half 1 + the position where claims stopped (0
 // while unread input is left).
@@ -134,7 +139,7 @@ __global__ void __launch_bounds__(MAX_K) k_fscan(BatchArgs a, uint32_t ntask) {
 template <class T>
 __global__ void __launch_bounds__(FUSED_THREADS, 2) k_fused(BatchArgs a) {
   constexpr int DW = T::DW;
-  constexpr int EPT = T::EPT;
+  constexpr int EPT = FusedEpt<T>::value;   // elements per thread and tile
   constexpr uint32_t NT = FUSED_THREADS;
   constexpr uint32_t TILE = NT * EPT;
   __shared__ uint32_t s_cnt[MAX_K];       // elements of bucket j taken so far
