@@ -12,6 +12,11 @@ value comes from the oracle alone.
 Writer (CPU only, about 15 minutes on 8 cores):
 
     python tests/golden/fullsize.py --jobs 4
+    python tests/golden/fullsize.py --batch
+
+The second command adds the batched workload (4096 u64 arrays of 2^8 to
+2^22 keys, the batch benchmark's input): the digest of the concatenation
+of every array sorted by the oracle.
 
 The digest is SHA-256 (FIPS 180-4) over the concatenation of the byte count
 (8 bytes, little endian) and the SHA-256 of each consecutive 64 MiB chunk of
@@ -107,19 +112,65 @@ def _oracle_digest(c: dict) -> tuple[str, dict]:
     return case_name(c), {**c, "digest": d, "gen_s": round(t1 - t0, 1), "oracle_s": round(t2 - t1, 1)}
 
 
+BATCH = dict(name="batch-4096-u64", arrays=4096, lo_log2=8, hi_log2=22, layout_seed=(4, 0), data_seed=(4, 1))
+
+
+def batch_inputs():
+    """The batched workload: sizes and generators of its 4096 u64 arrays and
+    the seed of each (synth.batch_layout and synth.generate_batch's seeds)."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import synth
+    sizes, dists = synth.batch_layout(BATCH["arrays"], BATCH["lo_log2"], BATCH["hi_log2"],
+                                      synth.seed_for(*BATCH["layout_seed"]))
+    seeds = synth.stream(synth.seed_for(*BATCH["data_seed"]), len(sizes))
+    return sizes, dists, seeds
+
+
+def _oracle_batch_digest() -> dict:
+    """Every array of the batched workload sorted by the oracle, the digest
+    of their concatenation (u64 keys)."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import oracle
+    import synth
+    sizes, dists, seeds = batch_inputs()
+    out = np.empty(int(sizes.sum()), dtype=np.uint64)
+    o = 0
+    t0 = time.time()
+    for n, d, sd in zip(sizes.tolist(), dists, seeds.tolist()):
+        out[o:o + n] = oracle.sort(synth.gen_u64(d, n, int(sd)), "u64")
+        o += n
+    t1 = time.time()
+    return {**BATCH, "keys": int(sizes.sum()), "digest": digest(memoryview(out).cast("B"), threads=8),
+            "oracle_s": round(t1 - t0, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--only", default=None, help="comma-separated case names")
+    ap.add_argument("--batch", action="store_true", help="only the batched workload's digest")
     args = ap.parse_args()
+    if args.batch:
+        row = _oracle_batch_digest()
+        with open(OUT) as f:
+            doc = json.load(f)
+        doc["batch"] = row
+        with open(OUT + ".tmp", "w") as f:
+            json.dump(doc, f, indent=1)
+        os.replace(OUT + ".tmp", OUT)
+        print(f"{row['name']}: {row['digest'][:16]}... oracle {row['oracle_s']} s", flush=True)
+        return 0
     sel = cases()
     if args.only:
         want = set(args.only.split(","))
         sel = [c for c in sel if case_name(c) in want]
-    old = {}
+    old, batch = {}, None
     if os.path.exists(OUT):
         with open(OUT) as f:
-            old = json.load(f).get("cases", {})
+            prev = json.load(f)
+        old, batch = prev.get("cases", {}), prev.get("batch")
     res = dict(old)
     # largest first so that the pool's tail is short
     sel.sort(key=lambda c: -(c["log2n"] + (1 if c["kind"] in ("u64", "pair", "f64") else 0)))
@@ -131,7 +182,8 @@ def main() -> int:
                 json.dump({"writer": "python tests/golden/fullsize.py --jobs 4",
                            "digest": "sha256(le64(bytes) || sha256(chunk_0) || ... ), 64 MiB chunks of the "
                                      "sorted key bytes",
-                           "cases": dict(sorted(res.items()))}, f, indent=1)
+                           "cases": dict(sorted(res.items())), **({"batch": batch} if batch else {})}, f,
+                          indent=1)
             os.replace(OUT + ".tmp", OUT)
     return 0
 

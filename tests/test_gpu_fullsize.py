@@ -141,3 +141,37 @@ def test_small_config_insertion_base_case(sorter):
         sorter.sort_(t, params=q, kind=kind)
         torch.cuda.synchronize()
         assert_parity(t.cpu().numpy(), a, kind)
+
+
+with open(fs.OUT) as _f:
+    GOLD_BATCH = json.load(_f).get("batch")
+
+
+@pytest.mark.skipif(GOLD_BATCH is None, reason="no oracle digest of the batched workload")
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_workload_digest(sorter, graph):
+    """The batched workload at full size (4096 u64 arrays of 2^8 to 2^22
+    keys, 1.79 G keys), as one ips_sort_segments call, and as replays of a
+    captured graph of device-planned steps: the concatenation of the sorted
+    arrays must equal the oracle's (digest)."""
+    import torch
+    import synth.device as sd
+    sizes, dists, seeds = fs.batch_inputs()
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    assert total == GOLD_BATCH["keys"]
+    log(f"batch workload digest graph={graph}: generating {total} keys")
+    t = torch.empty(total, dtype=torch.int64, device="cuda")
+    for o, n, d, s in zip(offs.tolist(), sizes.tolist(), dists, seeds.tolist()):
+        t[o:o + n] = sd.gen_u64(d, n, int(s), "cuda")
+    stream = torch.cuda.Stream()
+    p = ips.make_params(flags=ips.FLAG_GRAPH if graph else 0)
+    log(f"batch workload digest graph={graph}: sorting")
+    with torch.cuda.stream(stream):
+        sorter.sort_segments_(t, offs.tolist(), sizes.tolist(), params=p, kind="u64", stream=stream)
+    stream.synchronize()
+    host = np.ascontiguousarray(t.cpu().numpy())
+    del t
+    torch.cuda.empty_cache()
+    assert fs.digest(memoryview(host).cast("B"), threads=16) == GOLD_BATCH["digest"]
