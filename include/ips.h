@@ -141,6 +141,10 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
  *               batch (default 131072)
  *  perm_wg      workgroup size of the block permutation: 128, 256 or 512
  *               threads (default 256)
+ *  k_root       maximum number of buckets of a root step (level 0; power of
+ *               two, 2..256; default k): fewer, larger buckets at the root
+ *               give larger blocks and fewer pointer operations there when
+ *               the next level still fits its buckets in the LDS tier
  *  profile_mask with IPS_FLAG_PROFILE: bit (1 << IPS_PH_x) selects the phases
  *               whose launches are timed (0 = all phases).  Every timed
  *               launch adds two event records to the stream.
@@ -156,7 +160,7 @@ typedef struct {
   uint32_t perm_groups;
   uint32_t profile_mask;
   uint32_t perm_wg;
-  uint32_t reserved;   /* must be 0 */
+  uint32_t k_root;
 } ips_params;
 
 typedef struct ips_ctx ips_ctx;
@@ -423,11 +427,12 @@ typedef struct {
   uint32_t piece_blocks;
   uint32_t perm_groups;
   uint32_t perm_wg;       /* workgroup size of the block permutation */
+  uint32_t k_root;        /* buckets of a root step at most */
 } ips_tune_entry;
 
 /* Parameters for one call from a tuning table: *out = *base (zeroed when
  * base is NULL), then every field of *out that is zero and tunable (k,
- * block_bytes, n0, lds_task_max, piece_blocks, perm_groups, perm_wg) takes the value
+ * block_bytes, n0, lds_task_max, piece_blocks, perm_groups, perm_wg, k_root) takes the value
  * of the first entry of table[0, count) that matches elem_type, algo,
  * batched and floor(log2 n) (n >= 1).  Fields the caller set are kept; flags,
  * seed and profile_mask are never changed.  Pass the same *out to the

@@ -60,7 +60,7 @@ class Params(ctypes.Structure):
                 ("lds_task_max", ctypes.c_uint32), ("piece_blocks", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("perm_groups", ctypes.c_uint32), ("profile_mask", ctypes.c_uint32),
-                ("perm_wg", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("perm_wg", ctypes.c_uint32), ("k_root", ctypes.c_uint32)]
 
 
 class RootInfo(ctypes.Structure):
@@ -82,10 +82,11 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("elem_type", ctypes.c_int32), ("algo", ctypes.c_int32), ("log2n_min", ctypes.c_uint32),
                 ("log2n_max", ctypes.c_uint32), ("batched", ctypes.c_uint32), ("k", ctypes.c_uint32),
                 ("block_bytes", ctypes.c_uint32), ("n0", ctypes.c_uint32), ("lds_task_max", ctypes.c_uint32),
-                ("piece_blocks", ctypes.c_uint32), ("perm_groups", ctypes.c_uint32), ("perm_wg", ctypes.c_uint32)]
+                ("piece_blocks", ctypes.c_uint32), ("perm_groups", ctypes.c_uint32), ("perm_wg", ctypes.c_uint32),
+                ("k_root", ctypes.c_uint32)]
 
 
-TUNE_FIELDS = ("k", "block_bytes", "n0", "lds_task_max", "piece_blocks", "perm_groups", "perm_wg")
+TUNE_FIELDS = ("k", "block_bytes", "n0", "lds_task_max", "piece_blocks", "perm_groups", "perm_wg", "k_root")
 # The table written by `python -m paper_2009_13569_amd.tune` (loaded by Sorter).
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -163,11 +164,11 @@ def lib() -> ctypes.CDLL:
 
 
 def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0,
-                perm_groups=0, profile_phases=None, perm_wg=0) -> Params:
+                perm_groups=0, profile_phases=None, perm_wg=0, k_root=0) -> Params:
     """profile_phases: names from PHASES to time with FLAG_PROFILE (None: all)."""
     p = Params()
     p.k, p.block_bytes, p.n0, p.lds_task_max, p.piece_blocks = k, block_bytes, n0, lds_task_max, piece_blocks
-    p.flags, p.seed, p.perm_groups, p.perm_wg = flags, seed, perm_groups, perm_wg
+    p.flags, p.seed, p.perm_groups, p.perm_wg, p.k_root = flags, seed, perm_groups, perm_wg, k_root
     p.profile_mask = 0 if profile_phases is None else sum(1 << PHASES.index(x) for x in profile_phases)
     return p
 

@@ -178,6 +178,7 @@ struct PlanCfg {
   uint64_t SB, SPB, PB, slot_max;
   uint32_t TB, WB, PWB, NBE, QCAP, CLNB;
   uint32_t D, DW, k, n0, cap, cmax, groups, b_req, gbuf, radix, tflags0, wg_target, perm_threads, buf_bytes;
+  uint32_t k_root;
 };
 
 // Arguments shared by the kernels of one batch.

@@ -40,6 +40,7 @@ struct Cfg {
   uint32_t D, DW;
   bool radix, gbuf;
   uint32_t k, n0, cap, cmax, flags;
+  uint32_t k_root;  // buckets of a root step at most (level 0; k for deeper levels)
   uint64_t seed;
   uint32_t b_req;   // requested block elements (0 = automatic)
   uint32_t groups;  // permutation groups per batch
@@ -116,7 +117,8 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
   c->perm_threads = p->perm_wg ? p->perm_wg : PERM_THREADS;
   c->buf_bytes = launchers_for(type)->buf_bytes;
   if (c->perm_threads != 128 && c->perm_threads != 256 && c->perm_threads != 512) return IPS_E_INVALID_ARG;
-  if (p->reserved) return IPS_E_INVALID_ARG;
+  c->k_root = p->k_root ? p->k_root : c->k;
+  if (c->k_root < 2 || c->k_root > MAX_K || (c->k_root & (c->k_root - 1))) return IPS_E_INVALID_ARG;
   c->seed = p->seed;
   c->b_req = 0;
   if (p->block_bytes) {
@@ -168,10 +170,11 @@ uint32_t paper_kprime(uint64_t n, uint32_t k, uint32_t n0) {
 // elements, so k' is the smallest power of two that makes the mean bucket at
 // most cap / 4 (a bucket then exceeds the tier only with negligible
 // probability), capped at k.
-uint32_t task_kprime(const Cfg& c, uint64_t n) {
-  if (c.n0) return paper_kprime(n, c.k, c.n0);
+uint32_t task_kprime(const Cfg& c, uint64_t n, uint32_t level) {
+  const uint32_t k = level ? c.k : c.k_root;
+  if (c.n0) return paper_kprime(n, k, c.n0);
   uint64_t r = 2;
-  while (r < c.k && r * (c.cap / 4) < n) r *= 2;
+  while (r < k && r * (c.cap / 4) < n) r *= 2;
   return (uint32_t)r;
 }
 
@@ -195,8 +198,8 @@ uint32_t max_nb(const Cfg& c) { return c.radix ? MAX_K : 2 * c.k; }
 // paper's rule does not, so it is bounded by k).
 uint32_t plan_nb(const Cfg& c, uint64_t n) {
   if (c.radix) return MAX_K;
-  if (c.n0) return 2 * c.k;
-  return 2 * task_kprime(c, n);
+  if (c.n0) return 2 * std::max(c.k, c.k_root);
+  return 2 * std::max(task_kprime(c, n, 0), task_kprime(c, n, 1));
 }
 
 struct Layout {
@@ -551,7 +554,7 @@ Need task_need(const Run& r, const HTask& t, uint64_t level_elems) {
   nd.slot = std::min<uint64_t>(nd.wg * r.L.slot_max,
                                std::max<uint64_t>(r.L.slot_max, t.n * r.c.D / 4 + nd.wg * 256));
   nd.spill = r.L.slot_max;
-  const uint32_t nbt = r.c.radix ? MAX_K : 2 * task_kprime(r.c, t.n);   // buckets at most
+  const uint32_t nbt = r.c.radix ? MAX_K : 2 * task_kprime(r.c, t.n, t.level);   // buckets at most
   const uint32_t bmin = block_elems(r.c, nbt);
   nd.pieces = 2ull * nbt + 3 + nd.wg + (t.n / bmin + 1) / r.c.cmax + 1;
   return nd;
@@ -572,7 +575,7 @@ int run_batch(Run& r, const std::vector<HTask>& bt, uint64_t level_elems, std::v
     p.tflags = bt[t].tflags | (c.radix ? TF_RADIX : 0u);
     p.shift = bt[t].shift;
     p.width = bt[t].width;
-    p.kp = task_kprime(c, bt[t].n);
+    p.kp = task_kprime(c, bt[t].n, bt[t].level);
   }
   PTask* d_tasks = wsp<PTask>(r, R_TASKS);
   StepRec* d_recs = wsp<StepRec>(r, R_RECS);
@@ -1071,7 +1074,7 @@ void plan_cfg(const Run& r, PlanCfg* pcp, ChildArgs* cap) {
   pc.SB = r.L.SB; pc.SPB = r.L.SPB; pc.PB = r.L.PB; pc.slot_max = r.L.slot_max;
   pc.TB = r.L.TB; pc.WB = r.L.WB; pc.PWB = r.L.PWB; pc.NBE = r.L.NBE; pc.QCAP = r.L.QCAP;
   pc.CLNB = r.L.NBE;
-  pc.D = c.D; pc.DW = c.DW; pc.k = c.k; pc.n0 = c.n0; pc.cap = c.cap; pc.cmax = c.cmax;
+  pc.D = c.D; pc.DW = c.DW; pc.k = c.k; pc.k_root = c.k_root; pc.n0 = c.n0; pc.cap = c.cap; pc.cmax = c.cmax;
   pc.groups = c.groups; pc.b_req = c.b_req; pc.gbuf = c.gbuf ? 1 : 0; pc.radix = c.radix ? 1 : 0;
   pc.tflags0 = 0; pc.wg_target = WG_TARGET; pc.perm_threads = c.perm_threads; pc.buf_bytes = c.buf_bytes;
   ChildArgs& ca = *cap;
@@ -1547,7 +1550,7 @@ int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_
       while (i + T < cur.size() && T < r.L.TB) {
         const HTask& t = cur[i + T];
         const uint32_t w = (uint32_t)std::min<uint64_t>(WG_TARGET, (t.n + S - 1) / S);
-        const uint32_t nbt = 2 * task_kprime(c, t.n) + 1;
+        const uint32_t nbt = 2 * task_kprime(c, t.n, t.level) + 1;
         if (T && (wsum + w > r.L.WB || nbsum + nbt > r.L.NBE)) break;
         wsum += w;
         nbsum += nbt;
@@ -1560,7 +1563,7 @@ int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_
         q.n = cur[i + t].n;
         q.level = cur[i + t].level;
         q.tflags = cur[i + t].tflags;
-        q.kp = task_kprime(c, q.n);
+        q.kp = task_kprime(c, q.n, q.level);
       }
       BatchArgs a = r.a;
       a.data = src;
@@ -2148,6 +2151,7 @@ int ips_tuned_params(const ips_tune_entry* table, uint32_t count, uint64_t n, in
     if (!p.piece_blocks) p.piece_blocks = e.piece_blocks;
     if (!p.perm_groups) p.perm_groups = e.perm_groups;
     if (!p.perm_wg) p.perm_wg = e.perm_wg;
+    if (!p.k_root) p.k_root = e.k_root;
     *out = p;
     return 1;
   }

@@ -1825,10 +1825,11 @@ __global__ void __launch_bounds__(256) k_children(BatchArgs a, ChildArgs c, uint
 // Buckets k' of a task (Section 4.2): the paper's adaptive rule when n0 is
 // given, otherwise the smallest power of two that makes the mean bucket at
 // most a quarter of the LDS-tier capacity.
-__device__ uint32_t dev_kprime(const PlanCfg& c, uint64_t n) {
+__device__ uint32_t dev_kprime(const PlanCfg& c, uint64_t n, uint32_t level) {
+  const uint32_t k = level ? c.k : c.k_root;
   if (c.n0) {
-    const uint64_t kn0 = (uint64_t)c.k * c.n0, kkn0 = kn0 * c.k;
-    uint64_t r = c.k;
+    const uint64_t kn0 = (uint64_t)k * c.n0, kkn0 = kn0 * k;
+    uint64_t r = k;
     if (n > kn0 && n < kkn0) {
       uint32_t q = 1;
       while (shl64(c.n0, 2 * q - 1) < n) ++q;
@@ -1838,10 +1839,10 @@ __device__ uint32_t dev_kprime(const PlanCfg& c, uint64_t n) {
       while (shl64(c.n0, q) < n) ++q;
       r = bit64(q);
     }
-    return (uint32_t)(r < 2 ? 2 : (r > c.k ? c.k : r));
+    return (uint32_t)(r < 2 ? 2 : (r > k ? k : r));
   }
   uint64_t r = 2;
-  while (r < c.k && r * (c.cap / 4) < n) r *= 2;
+  while (r < k && r * (c.cap / 4) < n) r *= 2;
   return (uint32_t)r;
 }
 
@@ -1919,7 +1920,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
     nslot = nw * c.slot_max;
     if (nslot > (s2 > c.slot_max ? s2 : c.slot_max)) nslot = s2 > c.slot_max ? s2 : c.slot_max;
     nspill = c.slot_max;
-    const uint32_t nbt = c.radix ? MAX_K : 2 * dev_kprime(c, q.n);   // buckets at most
+    const uint32_t nbt = c.radix ? MAX_K : 2 * dev_kprime(c, q.n, q.level);   // buckets at most
     const uint32_t bmin = dev_block_elems(c, nbt);
     npieces = 2ull * nbt + 3 + nw + (q.n / bmin + 1) / c.cmax + 1;
   }
@@ -1942,7 +1943,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_pop(BatchArgs a, PlanCfg 
     p.tflags = q.tflags | (c.radix ? TF_RADIX : 0u);
     p.shift = q.shift;
     p.width = q.width;
-    p.kp = c.radix ? 0u : dev_kprime(c, q.n);
+    p.kp = c.radix ? 0u : dev_kprime(c, q.n, q.level);
   }
   // statistics
   uint64_t tn = 0, mx = t < T ? q.n : 0;

@@ -350,6 +350,20 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   uint32_t* stage = reinterpret_cast<uint32_t*>(idxb + CAP);
   const uint32_t n = t.n, lane = tid & 63, wave = tid >> 6;
   const bool pf0 = pf && tid == 0;
+#ifdef IPS_LDS_STATS
+  // cycles of the task's phases seen by thread 0, added to control words
+  // 32.. (load, min/max, binning, bin sorts, re-binning, store, tasks)
+  uint64_t lt0 = __builtin_readcyclecounter();
+  auto LSTAT = [&](int i) {
+    if (tid == 0) {
+      const uint64_t t1 = __builtin_readcyclecounter();
+      atomicAdd(reinterpret_cast<unsigned long long*>(ctrl + 32) + i, (unsigned long long)(t1 - lt0));
+      lt0 = t1;
+    }
+  };
+#else
+  auto LSTAT = [](int) {};
+#endif
   if (n > CAP || n < 2) {
     if (tid == 0 && n > CAP) dev_error(ctrl, DE_LDST, ti, n);
     if (pf0) *s_t = lt[nxt];
@@ -517,10 +531,12 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
     mn = a2 < mn ? a2 : mn;
     mx = b2 > mx ? b2 : mx;
   }
+  LSTAT(0);
   if (lane == 0) { s_min[wave] = mn; s_max[wave] = mx; }
   if (pf0) *s_t = nt;
   for (uint32_t j = tid; j < MAXBINS; j += NT) s_cnt[j] = 0;
   __syncthreads();
+  LSTAT(1);
   mn = s_min[0];
   mx = s_max[0];
   for (uint32_t w = 1; w < NT / 64; ++w) {
@@ -556,8 +572,10 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
       }
     }
     __syncthreads();
+    LSTAT(2);
     // 4. Bins by size class.
     sort_bins(0, nbins, count_info(ush, mn));
+    LSTAT(3);
   }
 
   // 5. Re-binning rounds, one queued bin [o, o + s) at a time by the whole
@@ -639,6 +657,7 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   __syncthreads();
   if (s_fallback) block_network<Key, IDX>(keys, idxb, n);
   __syncthreads();
+  LSTAT(4);
 
   // 7. Store.
   if constexpr (IDX) {
@@ -667,6 +686,10 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
       st_elem<DW>(gd + (uint64_t)i * DW, w);
     }
   }
+  LSTAT(5);
+#ifdef IPS_LDS_STATS
+  if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(ctrl + 32) + 6, 1ull);
+#endif
 }
 
 // One workgroup per task of the list (cnt == nullptr: the grid is the

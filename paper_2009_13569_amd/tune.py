@@ -51,8 +51,9 @@ CANDIDATES = {
     "piece_blocks": [256, 512, 1024, 2048],
     "perm_groups": [32768, 65536, 131072, 262144],
     "perm_wg": [128, 256, 512],
+    "k_root": [64, 128],
 }
-RADIX_CANDIDATES = {f: v for f, v in CANDIDATES.items() if f not in ("k", "n0")}   # radix: 8-bit digits
+RADIX_CANDIDATES = {f: v for f, v in CANDIDATES.items() if f not in ("k", "n0", "k_root")}   # radix: 8-bit digits
 MAX_LOG2 = {"u32": 28, "u64": 28, "f64": 28, "pair": 27, "rec100": 24, "quartet": 27}
 CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
 NO_RADIX = ("rec100", "quartet")
