@@ -94,7 +94,13 @@ def test_fullsize_digest(sorter, name, algo):
     torch.cuda.empty_cache()
 
 
-def test_small_config_elementwise(sorter):
+@pytest.fixture(scope="module")
+def untuned():
+    """Without the tuning table: the configuration's parameters exactly."""
+    return ips.Sorter(0, tuning=None)
+
+
+def test_small_config_elementwise(untuned):
     """2^20 u64 Uniform keys with k = 256, 2 KiB blocks (buffer blocks in the
     workspace), n0 = 16 and the root's alpha = 4, element by element."""
     import synth
@@ -102,18 +108,18 @@ def test_small_config_elementwise(sorter):
     import torch
     p1 = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_LEVEL1_ONLY)
     t = torch.from_numpy(a).cuda()
-    sorter.sort_(t, params=p1)              # the root step alone: its parameters
+    untuned.sort_(t, params=p1)              # the root step alone: its parameters
     torch.cuda.synchronize()
-    ri = sorter.root_info()
+    ri = untuned.root_info()
     assert (ri.valid, ri.alpha, ri.k_prime, ri.m, ri.block_elems) == (1, 4, 256, 1024, 256)
     p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
     t = torch.from_numpy(a).cuda()
-    sorter.sort_(t, params=p)
+    untuned.sort_(t, params=p)
     torch.cuda.synchronize()
     assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))
 
 
-def test_small_config_insertion_base_case(sorter):
+def test_small_config_insertion_base_case(untuned):
     """The same configuration with the paper's base case: buckets of at most
     2 n0 = 32 elements, and every bucket of a task of at most k n0 = 4096
     elements, sorted by insertion sort; everything larger partitioned again
@@ -126,10 +132,10 @@ def test_small_config_insertion_base_case(sorter):
     a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
     t = torch.from_numpy(a).cuda()
     log("config 1 with insertion-sort base cases")
-    sorter.sort_(t, params=p)
+    untuned.sort_(t, params=p)
     torch.cuda.synchronize()
     assert_parity(t.cpu().numpy(), a, "u64", ref=oracle.sort(a, "u64"))
-    st = sorter.stats()
+    st = untuned.stats()
     assert st.levels >= 3, st.levels   # 2^20 -> 2^12 -> 16: three partitioning levels (k' adapts below)
     from gpu_util import generate
     for kind, dist, n in (("u32", "twodup", 300_001), ("pair", "rootdup", 100_003), ("rec100", "uniform", 20_011),
@@ -138,7 +144,7 @@ def test_small_config_insertion_base_case(sorter):
         log(f"insertion base case {kind} {dist} n={n}")
         q = ips.make_params(n0=16, flags=ips.FLAG_INSERTION_BASE | ips.FLAG_NO_SORTED_CHECK)
         t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
-        sorter.sort_(t, params=q, kind=kind)
+        untuned.sort_(t, params=q, kind=kind)
         torch.cuda.synchronize()
         assert_parity(t.cpu().numpy(), a, kind)
 

@@ -39,6 +39,15 @@ def sorter():
     return ips.Sorter(0)
 
 
+@pytest.fixture(scope="module")
+def untuned():
+    """A sorter without the tuning table: the root step runs exactly the
+    parameters the test gives (k = 256 unless set), as the oracle assumes."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ips.Sorter(0, tuning=None)
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_lds_tier(sorter, kind):
     cap = ips.LDS_CAP[kind]
@@ -205,7 +214,7 @@ LDS_CAP = ips.LDS_CAP
                                             ("pair", 100_003, False, 16), ("rec100", 30_011, False, 16),
                                             ("u64", 300_001, False, 0), ("rec100", 30_011, False, 0),
                                             ("quartet", 100_003, False, 16), ("quartet", 60_011, False, 0)])
-def test_level1_exact(sorter, kind, n, gbuf, n0):
+def test_level1_exact(untuned, kind, n, gbuf, n0):
     """The root step's sample, splitters, equality-bucket flag and bucket
     boundaries equal the oracle's, and every element lies in its bucket.
     n0 = 0 checks the default base-case size (a quarter of the LDS tier)."""
@@ -214,7 +223,7 @@ def test_level1_exact(sorter, kind, n, gbuf, n0):
         flags = ips.FLAG_LEVEL1_ONLY | (ips.FLAG_GLOBAL_BUFFERS if gbuf else 0)
         p = ips.make_params(block_bytes=2048 if gbuf else 0, flags=flags, seed=12345, n0=n0)
         log(f"level1 {kind} {dist} n={n} gbuf={gbuf} n0={n0}")
-        out, ri = _level1(sorter, a, kind, p)
+        out, ri = _level1(untuned, a, kind, p)
         if n0:
             st = oracle.sample_step(a, kind, seed=12345, n0=n0)
         else:
@@ -245,11 +254,11 @@ def test_level1_exact(sorter, kind, n, gbuf, n0):
 
 
 @pytest.mark.parametrize("kind", ["u32", "u64", "pair"])
-def test_level1_radix_exact(sorter, kind):
+def test_level1_radix_exact(untuned, kind):
     for dist in ("uniform", "rootdup", "exponential"):
         a = generate(kind, dist, 200_003, 5)
         log(f"level1 radix {kind} {dist}")
-        out, ri = _level1(sorter, a, kind, ips.make_params(flags=ips.FLAG_LEVEL1_ONLY), "radix")
+        out, ri = _level1(untuned, a, kind, ips.make_params(flags=ips.FLAG_LEVEL1_ONLY), "radix")
         d = oracle.radix_digit_info(a, kind)
         assert (ri.radix_shift, ri.radix_width) == (d["shift"], d["width"])
         h = oracle.radix_histogram(a, kind, d["shift"], d["width"])
