@@ -282,8 +282,8 @@ def main() -> int:
         "config": {"workload": f"{kind} {args.dist} n=2^{args.log2n}, IPS4o samplesort: at most "
                                f"{run_params['k']} buckets per step, buckets of at most {cap} keys sorted "
                                f"in the LDS tier (no n0 insertion-sort base case: k' is the smallest power "
-                               f"of two giving mean buckets of at most {cap // 4} keys), blocks sized for one "
-                               f"LDS buffer block per bucket",
+                               f"of two giving mean buckets of at most {cap // 4} keys), at least 16 samples per bucket "
+                               f"at every step, blocks sized for one LDS buffer block per bucket",
                    "n": n, "kind": kind, "algo": "samplesort", "dist": args.dist,
                    "params": run_params, "workspace_bytes": int(ws.numel())},
         "roofline": roofline,

@@ -110,6 +110,14 @@ typedef enum { IPS_SAMPLESORT = 0, IPS_RADIX = 1 } ips_algo;
                                           IPS_FLAG_HOST_PLAN, IPS_FLAG_LEVEL1_ONLY or
                                           IPS_FLAG_GLOBAL_BUFFERS; IPS_E_TOO_LARGE for
                                           n >= 2^31 - 2^16 elements */
+#define IPS_FLAG_PAPER_ROOT_ALPHA 0x400u /* the root step samples the paper's
+                                          alpha = max(1, floor(0.2 log2 n)) elements per
+                                          bucket (Section 6).  By default every step,
+                                          the root included, samples at least 16 per
+                                          bucket when 16 k' elements fit the 4096-key
+                                          sample: more even root buckets, so that no
+                                          level-1 bucket exceeds the LDS tier at
+                                          2^28 u64 (the sorted result is the same) */
 #define IPS_FLAG_INSERTION_BASE 0x200u /* IPS_SAMPLESORT with n0 > 0: the paper's base
                                           case (Section 4.2): a bucket of at most 2 n0
                                           elements, or any bucket of a task of at most

@@ -41,6 +41,7 @@ FLAG_GRAPH = 0x40
 FLAG_HOST_PLAN = 0x80
 FLAG_FUSED = 0x100
 FLAG_INSERTION_BASE = 0x200
+FLAG_PAPER_ROOT_ALPHA = 0x400
 MAX_LEVELS = 16
 PHASES = ["sorted_check", "minmax", "sample", "classify", "boundaries", "flags", "permute",
           "cleanup_a", "cleanup_b", "lds_sort", "reverse", "histogram", "fused"]

@@ -132,7 +132,7 @@ struct PTask {
   uint32_t pad1;
 };
 
-enum TaskFlags : uint32_t { TF_EQ_ON = 1u, TF_EQ_OFF = 2u, TF_RADIX = 4u };
+enum TaskFlags : uint32_t { TF_EQ_ON = 1u, TF_EQ_OFF = 2u, TF_RADIX = 4u, TF_ROOT_ALPHA = 8u };
 
 // A task of the LDS tier: sorted entirely inside one workgroup's LDS.
 struct LTask {

@@ -128,7 +128,7 @@ int make_cfg(uint64_t n, int type, int algo, const ips_params* p, Cfg* c) {
     c->b_req = paper_block(D);
   }
   if ((p->flags & IPS_FLAG_EQ_ON) && (p->flags & IPS_FLAG_EQ_OFF)) return IPS_E_INVALID_ARG;
-  if (p->flags & ~0x3FFu) return IPS_E_INVALID_ARG;
+  if (p->flags & ~0x7FFu) return IPS_E_INVALID_ARG;
   c->insertion = (p->flags & IPS_FLAG_INSERTION_BASE) != 0;
   if (c->insertion) {
     if (c->radix) return IPS_E_UNSUPPORTED;
@@ -964,6 +964,7 @@ bool make_root(const Cfg& c, uint64_t l, uint64_t n, uint64_t mn, uint64_t mx, H
   t->width = 0;
   if (c.flags & IPS_FLAG_EQ_ON) t->tflags |= TF_EQ_ON;
   if (c.flags & IPS_FLAG_EQ_OFF) t->tflags |= TF_EQ_OFF;
+  if (!(c.flags & IPS_FLAG_PAPER_ROOT_ALPHA)) t->tflags |= TF_ROOT_ALPHA;
   if (c.radix) {
     if (mn == mx) return false;
     const uint32_t h = 63u - (uint32_t)__builtin_clzll(mn ^ mx);
@@ -1533,6 +1534,7 @@ int oop_impl(ips_ctx* ctx, void* d, uint64_t n, int type, void* tmp, size_t tmp_
   std::vector<HTask> cur(1);
   cur[0].l = 0; cur[0].n = n; cur[0].level = 0; cur[0].shift = 0; cur[0].width = 0;
   cur[0].tflags = (c.flags & IPS_FLAG_EQ_ON) ? TF_EQ_ON : (c.flags & IPS_FLAG_EQ_OFF) ? TF_EQ_OFF : 0u;
+  if (!(c.flags & IPS_FLAG_PAPER_ROOT_ALPHA)) cur[0].tflags |= TF_ROOT_ALPHA;
   uint32_t level = 0;
   while (!cur.empty()) {
     const bool to_b = (level % 2) == 0;
@@ -1818,7 +1820,8 @@ bool lane_admit(SLane& L, ips_request& q, uint32_t id, std::vector<uint32_t>& ra
     radix_new.push_back(id);
   } else {
     CTask t;
-    t.l = l; t.n = q.n; t.level = 0; t.tflags = 0; t.shift = 0; t.width = 0;
+    t.l = l; t.n = q.n; t.level = 0; t.shift = 0; t.width = 0;
+    t.tflags = (L.r.c.flags & IPS_FLAG_PAPER_ROOT_ALPHA) ? 0u : TF_ROOT_ALPHA;
     L.roots_new.push_back(t);
   }
   return true;

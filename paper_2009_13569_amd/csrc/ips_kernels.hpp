@@ -268,11 +268,13 @@ k_sample(BatchArgs a, uint64_t seed) {
   const uint64_t n = tk.n, l = tk.l;
   StepRec* rec = a.recs + tix;
   const uint32_t kp = tk.kp;
-  // Oversampling: the paper's alpha at the root; below it at least
-  // DEEP_ALPHA (the sample of a small task costs next to nothing, and even
-  // bucket sizes keep its buckets inside the LDS tier's capacity).
+  // Oversampling: at least DEEP_ALPHA per bucket (the sample of a task
+  // costs next to nothing on the GPU, and even bucket sizes keep the next
+  // level's buckets inside the LDS tier's capacity); the paper's alpha at a
+  // root that asks for it.
   uint32_t alpha = step_alpha(n);
-  if (tk.level > 0 && alpha < DEEP_ALPHA && DEEP_ALPHA * kp <= MAX_SAMPLE) alpha = DEEP_ALPHA;
+  const bool deep = tk.level > 0 || (tk.tflags & TF_ROOT_ALPHA);
+  if (deep && alpha < DEEP_ALPHA && DEEP_ALPHA * kp <= MAX_SAMPLE) alpha = DEEP_ALPHA;
   const uint32_t m = alpha * kp;
   uint32_t P = 1;
   while (P < m) P <<= 1;

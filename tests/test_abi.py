@@ -50,7 +50,7 @@ def test_workspace_validation():
     assert _ws(1 << 20, 2, 0, ips.make_params(block_bytes=4096))[0] == -1
     assert _ws(1 << 20, 2, 0, ips.make_params(flags=ips.FLAG_EQ_ON | ips.FLAG_EQ_OFF))[0] == -1
     assert _ws(1 << 20, 2, 0, ips.make_params(lds_task_max=1 << 20))[0] == -1
-    assert _ws(1 << 20, 2, 0, ips.make_params(flags=1 << 10))[0] == -1
+    assert _ws(1 << 20, 2, 0, ips.make_params(flags=1 << 11))[0] == -1
     rc = ips.lib().ips_workspace_bytes(1 << 20, 2, 0, None, None)
     assert rc == -1
 
@@ -277,7 +277,7 @@ def test_fused_flag_validation():
         ips.workspace_bytes((1 << 31) - (1 << 16) + 1, "u32", "radix", ips.make_params(flags=F))
     assert e.value.code == -5
     with pytest.raises(ips.IpsError) as e:
-        ips.workspace_bytes(1000, "u64", "radix", ips.make_params(flags=0x400))
+        ips.workspace_bytes(1000, "u64", "radix", ips.make_params(flags=0x800))
     assert e.value.code == -1
 
 

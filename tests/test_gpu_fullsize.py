@@ -106,13 +106,14 @@ def test_small_config_elementwise(untuned):
     import synth
     a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
     import torch
-    p1 = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_LEVEL1_ONLY)
+    p1 = ips.make_params(k=256, block_bytes=2048, n0=16,
+                         flags=ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_LEVEL1_ONLY | ips.FLAG_PAPER_ROOT_ALPHA)
     t = torch.from_numpy(a).cuda()
     untuned.sort_(t, params=p1)              # the root step alone: its parameters
     torch.cuda.synchronize()
     ri = untuned.root_info()
     assert (ri.valid, ri.alpha, ri.k_prime, ri.m, ri.block_elems) == (1, 4, 256, 1024, 256)
-    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS)
+    p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_PAPER_ROOT_ALPHA)
     t = torch.from_numpy(a).cuda()
     untuned.sort_(t, params=p)
     torch.cuda.synchronize()
@@ -127,7 +128,7 @@ def test_small_config_insertion_base_case(untuned):
     for records and for inputs with many equal keys."""
     import synth
     import torch
-    flags = ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_INSERTION_BASE
+    flags = ips.FLAG_GLOBAL_BUFFERS | ips.FLAG_INSERTION_BASE | ips.FLAG_PAPER_ROOT_ALPHA
     p = ips.make_params(k=256, block_bytes=2048, n0=16, flags=flags)
     a = synth.generate("u64", "uniform", 1 << 20, synth.seed_for(1, 0))
     t = torch.from_numpy(a).cuda()

@@ -220,7 +220,7 @@ def test_level1_exact(untuned, kind, n, gbuf, n0):
     n0 = 0 checks the default base-case size (a quarter of the LDS tier)."""
     for dist in ("uniform", "rootdup"):
         a = generate(kind, dist, n, 3)
-        flags = ips.FLAG_LEVEL1_ONLY | (ips.FLAG_GLOBAL_BUFFERS if gbuf else 0)
+        flags = ips.FLAG_LEVEL1_ONLY | ips.FLAG_PAPER_ROOT_ALPHA | (ips.FLAG_GLOBAL_BUFFERS if gbuf else 0)
         p = ips.make_params(block_bytes=2048 if gbuf else 0, flags=flags, seed=12345, n0=n0)
         log(f"level1 {kind} {dist} n={n} gbuf={gbuf} n0={n0}")
         out, ri = _level1(untuned, a, kind, p)
