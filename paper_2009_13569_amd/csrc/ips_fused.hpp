@@ -472,7 +472,8 @@ __global__ void __launch_bounds__(FUSED_THREADS, 2) k_fused(BatchArgs a) {
   }
 #ifdef IPS_FUSED_STATS
   if (tid == 0) {
-    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + 32);
+    // root step at control words 32..47, deeper steps at 48..63
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + (tk.level ? 48 : 32));
     for (int i = 0; i < 8; ++i) atomicAdd(&c[i], (unsigned long long)fst[i]);
   }
 #endif

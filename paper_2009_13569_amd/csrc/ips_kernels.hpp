@@ -989,14 +989,17 @@ __device__ __forceinline__ void wait_regs(const uint32_t (&v)[PERM_RD]) {
 // wavefront together, then all block loads together, so that one iteration
 // costs about one atomic and one load latency whatever mix of states the
 // groups are in.
+// Elements of up to four dwords: seven wavefronts per SIMD (at most 72
+// VGPRs), so that as many block chains as possible are in flight.
 template <class T, uint32_t NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, (T::DW <= 4 ? 7 * 256 / NT : 1))
 k_permute(BatchArgs a) {
   using Key = typename T::Key;
   __shared__ Key s_tree[MAX_K];
   __shared__ Key s_spl[MAX_K];
   __shared__ uint32_t s_plb[MAX_NB];   // placement pieces of each bucket
   __shared__ uint32_t s_npl[MAX_NB];
+  __shared__ uint64_t s_full[MAX_NB];  // the workgroup's view of each bucket's full-piece mask
   if (a.devplan && blockIdx.x >= a.ctrl[CTRL_NPWG]) return;
   const uint32_t tix = a.perm_task[blockIdx.x];
   const PTask& tk = a.tasks[tix];
@@ -1014,6 +1017,7 @@ k_permute(BatchArgs a) {
     const uint32_t lo = a.b_plb[tk.bucket_base + j] - tk.piece_base;
     s_plb[j] = lo;
     s_npl[j] = a.b_ple[tk.bucket_base + j] - tk.piece_base - lo;
+    s_full[j] = a.b_full[tk.bucket_base + j];
   }
   __syncthreads();
   const uint32_t GL = tk.glanes;
@@ -1076,6 +1080,11 @@ k_permute(BatchArgs a) {
   for (int q = 0; q < PERM_RD; ++q) { dat[q] = 0; tmp[q] = 0; }
   uint32_t dest = 0, probe = 0, wpos = 0, spin = 0, fails = 0, cur_q = 0;
   bool use_mask = false;
+  // The first choice of a placement piece reads the workgroup's LDS copy of
+  // the full-piece mask when the task has few groups per piece: with many
+  // (a root step of the whole array) other workgroups fill pieces faster
+  // than a copy taken at the workgroup's start can follow.
+  const bool lds_mask = tk.ngrp <= 4u * np;
 
   auto store_block = [&](uint32_t* dst) {
 #pragma unroll
@@ -1112,18 +1121,28 @@ k_permute(BatchArgs a) {
         // one bit per chunk of cs consecutive pieces (cs = 1 for up to 64
         // pieces); a bit is set once every piece of its chunk is full.  The
         // first choice is a random piece of a random chunk not known to be
-        // full (mask read through the cache: it only gains bits, so a stale
-        // copy only costs a miss).  After a miss the mask is read
-        // coherently: with cs = 1 a random non-full piece is taken again;
-        // with cs > 1 the search moves on linearly from the missed piece,
-        // skipping full chunks, so it visits every piece with room.
+        // full (the mask only gains bits, so a stale copy only costs a
+        // miss).  With cs = 1 and few groups per piece that copy is the
+        // workgroup's own in LDS, which keeps the pointer update off a
+        // global load's latency; otherwise it is the mask read through the
+        // cache, which stays fresher.  After a miss the mask is read
+        // coherently (and merged into the LDS copy): with cs = 1 a random
+        // non-full piece is taken again; with cs > 1 the search moves on
+        // linearly from the missed piece, skipping full chunks, so it
+        // visits every piece with room.
         const uint32_t plb = s_plb[dest], npl = s_npl[dest];
         uint64_t* fm = a.b_full + bb + dest;
         const uint32_t cs = (npl + 63) >> 6;
         const uint32_t nch = cs ? (npl + cs - 1) / cs : 0;
         const uint64_t m = low_mask64(nch);
         if (npl) {
-          const uint64_t seen = use_mask ? at_load64(fm) : *fm;
+          uint64_t seen;
+          if (use_mask) {
+            seen = at_load64(fm);
+            if (cs == 1 && lds_mask) atomicOr((unsigned long long*)&s_full[dest], (unsigned long long)seen);
+          } else {
+            seen = (cs == 1 && lds_mask) ? s_full[dest] : *fm;
+          }
           const uint64_t fr = ~seen & m;
           if (cs == 1 || !use_mask) {
             uint32_t ch = probe % nch;
@@ -1161,6 +1180,7 @@ k_permute(BatchArgs a) {
             if (w + 1 == cap) {            // this placement filled the piece
               if (cs == 1) {
                 atomicOr((unsigned long long*)fm, bit64(q));
+                atomicOr((unsigned long long*)&s_full[dest], (unsigned long long)bit64(q));
               } else {
                 const uint32_t c0 = (q / cs) * cs, clen = min(cs, npl - c0);
                 if (atomicAdd(&a.p_fcnt[pb + plb + c0], 1u) + 1 == clen)
@@ -1168,7 +1188,10 @@ k_permute(BatchArgs a) {
               }
             }
           } else {
-            if (cs == 1) atomicOr((unsigned long long*)fm, bit64(q));
+            if (cs == 1) {
+              atomicOr((unsigned long long*)fm, bit64(q));
+              atomicOr((unsigned long long*)&s_full[dest], (unsigned long long)bit64(q));
+            }
             PSTAT(st_full);
           }
         }
@@ -1274,7 +1297,8 @@ k_permute(BatchArgs a) {
   }
 #ifdef IPS_PERM_STATS
   if (gl == 0) {
-    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + 32);
+    // root step at control words 32..49, deeper steps at 84..101
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.ctrl + (tk.level ? 84 : 32));
     atomicAdd(&c[0], (unsigned long long)st_claim_ok);
     atomicAdd(&c[1], (unsigned long long)st_claim_fail);
     atomicAdd(&c[2], (unsigned long long)st_swap);
