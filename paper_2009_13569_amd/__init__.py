@@ -29,7 +29,7 @@ STATUS = {0: "IPS_OK", -1: "IPS_E_INVALID_ARG", -2: "IPS_E_UNSUPPORTED", -3: "IP
 TYPES = {"u32": 1, "u64": 2, "f64": 3, "pair": 4, "rec100": 5, "quartet": 6}
 ELEM_BYTES = {"u32": 4, "u64": 8, "f64": 8, "pair": 16, "rec100": 100, "quartet": 32}
 # Largest task the LDS tier sorts by default (elements), per element kind.
-LDS_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
+LDS_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 8192, "rec100": 1024, "quartet": 2048}
 ALGOS = {"samplesort": 0, "radix": 1}
 FLAG_NO_SORTED_CHECK = 0x1
 FLAG_EQ_ON = 0x2

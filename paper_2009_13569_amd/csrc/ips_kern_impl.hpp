@@ -26,7 +26,7 @@ template <> struct LdsShape<TF64> {
   static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
 };
 template <> struct LdsShape<TPair> {
-  static constexpr uint32_t N0 = 256, E0 = 8, N1 = 1024, E1 = 4, N2 = 1024, E2 = 4, NET = 32;
+  static constexpr uint32_t N0 = 256, E0 = 8, N1 = 512, E1 = 8, N2 = 1024, E2 = 8, NET = 32;
 };
 template <> struct LdsShape<TRec100> {
   static constexpr uint32_t N0 = 256, E0 = 4, N1 = 256, E1 = 4, N2 = 256, E2 = 4, NET = 16;

@@ -24,7 +24,8 @@
 //      sub-bins) and a sub-bin of one value is final;
 //   6. only if a list overflows does the whole task fall back to a
 //      block-wide bitonic network in LDS;
-//   7. one coalesced store (records are gathered from their LDS copy).
+//   7. one coalesced store (records of up to four dwords are gathered from
+//      their input positions in HBM, wider ones from their LDS copy).
 #pragma once
 #include "ips_kernels.hpp"
 
@@ -313,9 +314,17 @@ struct LdsTier {
   static constexpr uint32_t MEAN = NET / 4;   // target keys per bin
   static constexpr uint32_t MAXBINS = (CAP / MEAN < 2048) ? CAP / MEAN : 2048;
   static constexpr bool IDX = !T::KEYS_ONLY;
-  // dynamic LDS: keys[CAP] | idx[CAP] (records) | stage[CAP * DW] (records)
+  // Records of up to four dwords (Pair) are not staged: the keys come from
+  // HBM like keys alone, (key, index) pairs are sorted, and the store
+  // gathers each record from its input position (every gather of the task
+  // returns before its first store), which leaves twice the capacity of a
+  // staged record in LDS.  Wider records are staged in LDS and gathered
+  // from there.
+  static constexpr bool GATHER = IDX && T::DW <= 4;
+  static constexpr bool STAGE = IDX && !GATHER;
+  // dynamic LDS: keys[CAP] | idx[CAP] (records) | stage[CAP * DW] (staged records)
   static constexpr size_t lds_bytes() {
-    return (size_t)CAP * sizeof(Key) + (IDX ? (size_t)CAP * 2 + (size_t)CAP * T::DW * 4 : 0);
+    return (size_t)CAP * sizeof(Key) + (IDX ? (size_t)CAP * 2 : 0) + (STAGE ? (size_t)CAP * T::DW * 4 : 0);
   }
 };
 
@@ -331,7 +340,7 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   using Img = decltype(bin_image(Key()));
   constexpr int DW = T::DW;
   constexpr uint32_t CAP = LT::CAP, MAXBINS = LT::MAXBINS;
-  constexpr bool IDX = LT::IDX;
+  constexpr bool IDX = LT::IDX, GATHER = LT::GATHER, STAGE = LT::STAGE;
   extern __shared__ __align__(16) uint8_t s_raw[];
   __shared__ uint32_t s_cnt[MAXBINS];
   __shared__ uint32_t s_off[MAXBINS + 1];
@@ -373,7 +382,7 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   LTask nt = t;
   if (pf0) nt = lt[nxt];
   if (tid == 0) { s_nmid = 0; s_mdone = 0; s_fat_head = 0; s_fat_tail = 0; s_fallback = 0; }
-  if constexpr (IDX) {   // records: staged in LDS, gathered at the store
+  if constexpr (STAGE) {   // wide records: staged in LDS, gathered at the store
     // SU dwords per lane are loaded before any is stored, so their loads overlap
     constexpr uint32_t SU = 8;
     const uint32_t tot = n * DW;
@@ -494,9 +503,9 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
     if (tid == 0) s_mdone = m1;
   };
 
-  // 1. Load keys into registers (records: from their LDS stage).
+  // 1. Load keys into registers (staged records: from their LDS stage).
   Key k[E];
-  if constexpr (IDX) {
+  if constexpr (STAGE) {
     __syncthreads();
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
@@ -512,8 +521,16 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
       const uint32_t i = e * NT + tid;
       if (i < n) {
         uint32_t w[DW];
-        ld_elem<DW>(gd + (uint64_t)i * DW, w);
-        k[e] = key_of<T>(w);
+        if constexpr (GATHER) {   // the key dwords only
+          static_assert(T::KDW == 2, "gathered records have two key dwords");
+          const uint2 v = *reinterpret_cast<const uint2*>(gd + (uint64_t)i * DW);
+          w[0] = v.x;
+          w[1] = v.y;
+          k[e] = T::key_w(w);
+        } else {
+          ld_elem<DW>(gd + (uint64_t)i * DW, w);
+          k[e] = key_of<T>(w);
+        }
       }
     }
   }
@@ -579,13 +596,15 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   }
 
   // 5. Re-binning rounds, one queued bin [o, o + s) at a time by the whole
-  // workgroup, with one key per thread at a time: the keys (and indices) are
-  // copied to the task's own range in HBM, which is free until the store,
-  // counted by sub-bin, and scattered back from the copy through per-sub-bin
-  // cursors.
+  // workgroup: the keys (and indices) are copied, counted by sub-bin, and
+  // scattered back from the copy through per-sub-bin cursors.  The copy is
+  // the task's own range in HBM, which is free until the store, one key per
+  // thread at a time; with gathered records that range still holds the
+  // input, so the copy is in registers (at most E keys per thread).
   constexpr uint32_t KW = (uint32_t)(sizeof(Key) / 4);        // key dwords
   constexpr uint32_t SW = KW + (IDX ? 1u : 0u);               // copy dwords per element
   static_assert(SW <= (uint32_t)DW, "the copy of an element fits the element");
+  constexpr uint32_t RE = GATHER ? E : 1;                     // register copy per thread
   for (uint32_t round = 0;; ++round) {
     const uint32_t head = s_fat_head, tail = s_fat_tail;
     if (head == tail || s_fallback) break;
@@ -597,16 +616,34 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
     }
     const uint32_t o = s_fat_o[head % FATCAP], s = s_fat_s[head % FATCAP];
     Img mn2 = ~(Img)0, mx2 = 0;
-    for (uint32_t i = tid; i < s; i += NT) {
-      const Key x = keys[o + i];
-      const Img b = bin_image(x);
-      mn2 = b < mn2 ? b : mn2;
-      mx2 = b > mx2 ? b : mx2;
-      uint32_t* dst = gd + (uint64_t)(o + i) * DW;
-      const uint32_t* xw = reinterpret_cast<const uint32_t*>(&x);
+    Key rx[RE];
+    uint32_t ri[RE];
+    if constexpr (GATHER) {
 #pragma unroll
-      for (uint32_t d = 0; d < KW; ++d) dst[d] = xw[d];
-      if constexpr (IDX) dst[KW] = idxb[o + i];
+      for (uint32_t e = 0; e < RE; ++e) {
+        const uint32_t i = e * NT + tid;
+        rx[e] = Key();
+        ri[e] = 0;
+        if (i < s) {
+          rx[e] = keys[o + i];
+          ri[e] = idxb[o + i];
+          const Img b = bin_image(rx[e]);
+          mn2 = b < mn2 ? b : mn2;
+          mx2 = b > mx2 ? b : mx2;
+        }
+      }
+    } else {
+      for (uint32_t i = tid; i < s; i += NT) {
+        const Key x = keys[o + i];
+        const Img b = bin_image(x);
+        mn2 = b < mn2 ? b : mn2;
+        mx2 = b > mx2 ? b : mx2;
+        uint32_t* dst = gd + (uint64_t)(o + i) * DW;
+        const uint32_t* xw = reinterpret_cast<const uint32_t*>(&x);
+#pragma unroll
+        for (uint32_t d = 0; d < KW; ++d) dst[d] = xw[d];
+        if constexpr (IDX) dst[KW] = idxb[o + i];
+      }
     }
     for (int sh = 32; sh > 0; sh >>= 1) {
       const Img a2 = shfl_xor_img(mn2, sh), b2 = shfl_xor_img(mx2, sh);
@@ -636,15 +673,26 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
     block_excl_scan<NT>(s_cnt, s_off, nsub, s_wsum);
     for (uint32_t j = tid; j < nsub; j += NT) s_cnt[j] = s_off[j];   // cursors
     __syncthreads();
-    for (uint32_t i = tid; i < s; i += NT) {
-      const uint32_t* src = gd + (uint64_t)(o + i) * DW;
-      Key x;
-      uint32_t* xw = reinterpret_cast<uint32_t*>(&x);
+    if constexpr (GATHER) {
 #pragma unroll
-      for (uint32_t d = 0; d < KW; ++d) xw[d] = src[d];
-      const uint32_t p = o + atomicAdd(&s_cnt[(uint32_t)((Img)(bin_image(x) - mn2) >> ush2)], 1u);
-      keys[p] = x;
-      if constexpr (IDX) idxb[p] = (uint16_t)src[KW];
+      for (uint32_t e = 0; e < RE; ++e) {
+        if (e * NT + tid < s) {
+          const uint32_t p = o + atomicAdd(&s_cnt[(uint32_t)((Img)(bin_image(rx[e]) - mn2) >> ush2)], 1u);
+          keys[p] = rx[e];
+          idxb[p] = (uint16_t)ri[e];
+        }
+      }
+    } else {
+      for (uint32_t i = tid; i < s; i += NT) {
+        const uint32_t* src = gd + (uint64_t)(o + i) * DW;
+        Key x;
+        uint32_t* xw = reinterpret_cast<uint32_t*>(&x);
+#pragma unroll
+        for (uint32_t d = 0; d < KW; ++d) xw[d] = src[d];
+        const uint32_t p = o + atomicAdd(&s_cnt[(uint32_t)((Img)(bin_image(x) - mn2) >> ush2)], 1u);
+        keys[p] = x;
+        if constexpr (IDX) idxb[p] = (uint16_t)src[KW];
+      }
     }
     __syncthreads();
     for (uint32_t j = tid; j < nsub; j += NT) s_cnt[j] = s_off[j + 1] - s_off[j];   // sizes
@@ -660,7 +708,30 @@ __device__ void lds_tier_task(const LTask t, uint32_t ti, uint32_t* data, uint32
   LSTAT(4);
 
   // 7. Store.
-  if constexpr (IDX) {
+  if constexpr (GATHER) {
+    // Each thread gathers the records of its output positions from their
+    // input positions in HBM; every gather of the workgroup has returned (an
+    // opaque use of each loaded register) before the barrier that precedes
+    // the first store.
+    uint32_t v[E][DW];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = e * NT + tid;
+#pragma unroll
+      for (int d = 0; d < DW; ++d) v[e][d] = 0;
+      if (i < n) ld_elem<DW>(gd + (uint64_t)idxb[i] * DW, v[e]);
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e)
+#pragma unroll
+      for (int d = 0; d < DW; ++d) asm volatile("" ::"v"(v[e][d]) : "memory");
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = e * NT + tid;
+      if (i < n) st_elem<DW>(gd + (uint64_t)i * DW, v[e]);
+    }
+  } else if constexpr (IDX) {
     constexpr uint32_t SU = 8;
     const uint32_t tot = n * DW;
     for (uint32_t x0 = tid; x0 < tot; x0 += NT * SU) {

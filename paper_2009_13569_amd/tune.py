@@ -55,7 +55,7 @@ CANDIDATES = {
 }
 RADIX_CANDIDATES = {f: v for f, v in CANDIDATES.items() if f not in ("k", "n0", "k_root")}   # radix: 8-bit digits
 MAX_LOG2 = {"u32": 28, "u64": 28, "f64": 28, "pair": 27, "rec100": 24, "quartet": 27}
-CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
+CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 8192, "rec100": 1024, "quartet": 2048}
 NO_RADIX = ("rec100", "quartet")
 
 

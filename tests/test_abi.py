@@ -57,7 +57,7 @@ def test_workspace_validation():
 
 # LDS-tier capacities (elements) of the element types: every queued
 # partitioning task holds more than this many elements.
-_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096, "rec100": 1024, "quartet": 2048}
+_CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 8192, "rec100": 1024, "quartet": 2048}
 
 
 def _ws_bound(n, kind, gbuf=False):

@@ -147,7 +147,7 @@ def test_lds_tier_sorted_reverse_repeated(sorter, kind):
     wavefront's keys wrong bins in about one run in ten for such inputs (u64,
     5000 and 5832 keys); the kernels now build those shifts from 32-bit
     operations."""
-    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 4096}[kind]
+    cap = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 8192}[kind]
     flags = ips.FLAG_NO_SORTED_CHECK
     for n in (5000, 5832, int(cap * 0.3) + 7, int(cap * 0.7) + 3):
         n = min(n, cap)
