@@ -989,10 +989,11 @@ __device__ __forceinline__ void wait_regs(const uint32_t (&v)[PERM_RD]) {
 // wavefront together, then all block loads together, so that one iteration
 // costs about one atomic and one load latency whatever mix of states the
 // groups are in.
-// Elements of up to four dwords: seven wavefronts per SIMD (at most 72
-// VGPRs), so that as many block chains as possible are in flight.
+// Elements of up to four dwords: at least seven wavefronts per SIMD (the
+// second bound; at most 72 VGPRs), so that as many block chains as
+// possible are in flight.
 template <class T, uint32_t NT>
-__global__ void __launch_bounds__(NT, (T::DW <= 4 ? 7 * 256 / NT : 1))
+__global__ void __launch_bounds__(NT, (T::DW <= 4 ? 7 : 1))
 k_permute(BatchArgs a) {
   using Key = typename T::Key;
   __shared__ Key s_tree[MAX_K];
