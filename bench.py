@@ -57,6 +57,8 @@ def main() -> int:
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="print the memory-system probes' bandwidths (include/ips_probe.h) as markdown")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
                     help="turn four rocprofv3 --pmc output folders into the traffic summary (markdown)")
     ap.add_argument("--kernel-stats-summary", metavar="CSV",
@@ -76,6 +78,8 @@ def main() -> int:
         return traffic_summary(*args.traffic_summary)
     if args.calib_copy:
         return calib_copy()
+    if args.ceilings:
+        return ceilings()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sort runs on a single "
               f"MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -362,6 +366,43 @@ def calib_copy() -> int:
     torch.cuda.synchronize()
     assert bool((dst == src).all())
     log(f"calibration copy: 3 x {CALIB_BYTES} bytes")
+    return 0
+
+
+def ceilings() -> int:
+    """What plain access patterns reach on this GPU (ips_probe_memory over
+    2 GiB buffers): streaming copy, read and write; blocks moved between
+    pseudo-random positions; the block permutation's chain (pointer atomic,
+    then the block's load and store) at several numbers of groups in flight."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    nbytes = 2 << 30
+    src = torch.arange(nbytes // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    table = torch.zeros(1 << 16, dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()
+    rows = []
+
+    def add(name, mode, moved, **kw):
+        ms = ips.probe_memory(mode, src, dst, reps=10, **kw)
+        gbs = moved / ms / 1e6
+        rows.append((name, round(ms, 4), round(gbs, 1), round(gbs / (HBM_PEAK_GBS), 3)))
+        log(f"{name}: {ms:.4f} ms, {gbs:.0f} GB/s")
+
+    add("copy (read + write)", "copy", 2 * nbytes)
+    add("read", "read", nbytes)
+    add("write", "write", nbytes)
+    for bb in (256, 512, 1024, 2048):
+        add(f"blocks of {bb} B between pseudo-random positions", "blocks", 2 * nbytes, block_bytes=bb)
+    for bb, g in ((512, 8192), (512, 16384), (512, 23552), (512, 32768), (1024, 23552)):
+        iters = nbytes // (g * bb)
+        add(f"chain: atomic, load, store of {bb} B blocks, {g} groups", "chain", 2 * g * bb * iters,
+            block_bytes=bb, table=table, groups=g)
+    print("| probe | ms per launch | GB/s | fraction of 8 TB/s |")
+    print("|---|---|---|---|")
+    for r in rows:
+        print(f"| {r[0]} | {r[1]} | {r[2]} | {r[3]} |")
     return 0
 
 

@@ -51,7 +51,7 @@ EXPORTS = ["ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_batch_workspace_bytes", "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace",
            "ips_get_root_info", "ips_get_stats", "ips_get_profile", "ips_last_hip_error",
            "ips_last_device_error", "ips_status_string", "ips_abi_version", "ips_tuned_params",
-           "ips_sort_keys_noalloc", "ips_oop_workspace_bytes", "ips_sort_oop"]
+           "ips_sort_keys_noalloc", "ips_oop_workspace_bytes", "ips_sort_oop", "ips_probe_memory"]
 SERVE_BATCH = 0
 SERVE_FIFO = 1
 
@@ -142,6 +142,8 @@ _lib.ips_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.ips_get_profile.argtypes = [_vp, ctypes.POINTER(Profile)]
 _lib.ips_last_hip_error.argtypes = [_vp]
 _lib.ips_last_device_error.argtypes = [_vp]
+_lib.ips_probe_memory.argtypes = [_i32, _vp, _vp, _u64, ctypes.c_uint32, _vp, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, _vp, ctypes.POINTER(ctypes.c_float)]
 _lib.ips_status_string.argtypes = [_i32]
 _lib.ips_status_string.restype = ctypes.c_char_p
 for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort_keys",
@@ -149,7 +151,7 @@ for _f in ("ips_ctx_create", "ips_ctx_destroy", "ips_workspace_bytes", "ips_sort
            "ips_sort_batch", "ips_serve_workspace_bytes", "ips_serve_trace", "ips_get_root_info",
            "ips_get_stats", "ips_get_profile", "ips_last_hip_error", "ips_last_device_error",
            "ips_abi_version", "ips_tuned_params", "ips_sort_keys_noalloc", "ips_oop_workspace_bytes",
-           "ips_sort_oop"):
+           "ips_sort_oop", "ips_probe_memory"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -162,6 +164,26 @@ class IpsError(RuntimeError):
 
 def lib() -> ctypes.CDLL:
     return _lib
+
+
+PROBES = {"copy": 0, "read": 1, "write": 2, "blocks": 3, "chain": 4}
+
+
+def probe_memory(mode: str, src, dst, block_bytes: int = 0, table=None, groups: int = 0, reps: int = 10,
+                 stream=None) -> float:
+    """ips_probe_memory on device tensors (src, dst of equal byte size; table:
+    a device int64 tensor for the chain probe): mean ms per launch."""
+    ms = ctypes.c_float(0.0)
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    rc = _lib.ips_probe_memory(PROBES[mode], src.data_ptr(), dst.data_ptr(), nbytes, block_bytes,
+                               table.data_ptr() if table is not None else None,
+                               table.numel() if table is not None else 0, groups, reps,
+                               stream.cuda_stream if stream is not None else None, ctypes.byref(ms))
+    if rc != 0:
+        raise IpsError(rc, "ips_probe_memory")
+    return ms.value
 
 
 def make_params(k=0, block_bytes=0, n0=0, lds_task_max=0, piece_blocks=0, flags=0, seed=0,

@@ -22,7 +22,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libips.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["ips_host.hip", "ips_serve.hip", "ips_kern_common.hip", "ips_kern_u32.hip", "ips_kern_u64.hip",
-           "ips_kern_f64.hip", "ips_kern_pair.hip", "ips_kern_rec100.hip", "ips_kern_quartet.hip"]
+           "ips_kern_f64.hip", "ips_kern_pair.hip", "ips_kern_rec100.hip", "ips_kern_quartet.hip",
+           "ips_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-include/ips.h declares, and rejects bad arguments before any HIP call."""
+the headers in include/ declare, and rejects bad arguments before any HIP call."""
 import ctypes
+import glob
 import os
 import re
 
@@ -12,9 +13,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "ips.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ips_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ips_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported():
@@ -290,3 +293,25 @@ def test_insertion_base_validation():
     with pytest.raises(ips.IpsError) as e:
         ips.workspace_bytes(1 << 20, "u64", "radix", ips.make_params(n0=16, flags=I))
     assert e.value.code == -2
+
+
+def test_probe_rejects_bad_arguments_before_any_hip_call():
+    f = ips.lib().ips_probe_memory
+    ms = ctypes.c_float(0.0)
+    a, b, t = 0x10000, 0x20000, 0x30000   # never dereferenced: every case fails validation
+    bad = [
+        (7, a, b, 1 << 20, 0, None, 0, 0, 1),          # mode
+        (0, None, b, 1 << 20, 0, None, 0, 0, 1),       # null src
+        (0, a, b, 1 << 20 | 8, 0, None, 0, 0, 1),      # bytes not a multiple of 16
+        (0, a + 8, b, 1 << 20, 0, None, 0, 0, 1),      # misaligned
+        (0, a, b, 1 << 20, 0, None, 0, 0, 0),          # reps
+        (3, a, b, 1 << 20, 384, None, 0, 0, 1),        # block size
+        (3, a, b, 3 << 20, 512, None, 0, 0, 1),        # block count not a power of two
+        (4, a, b, 1 << 20, 512, None, 4096, 64, 1),    # no table
+        (4, a, b, 1 << 20, 512, t, 3000, 64, 1),       # table size
+        (4, a, b, 1 << 20, 512, t, 4096, 0, 1),        # groups
+        (4, a, b, 1 << 20, 512, t, 4096, 4096, 1),     # fewer blocks than groups
+    ]
+    for mode, s, d, nbytes, bb, tab, tw, g, reps in bad:
+        assert f(mode, s, d, nbytes, bb, tab, tw, g, reps, None, ctypes.byref(ms)) == -1, (mode, nbytes, bb, tw, g)
+    assert f(0, a, b, 1 << 20, 0, None, 0, 0, 1, None, None) == -1   # null result
