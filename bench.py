@@ -57,6 +57,10 @@ def main() -> int:
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--phase-counters", choices=["perm", "fused", "lds"],
+                    help="with IPS_LIBRARY set to the matching counter build (python -m "
+                         "paper_2009_13569_amd.build --define IPS_PERM_STATS|IPS_FUSED_STATS|IPS_LDS_STATS "
+                         "--out ...): one u64 Uniform 2^28 sort's per-phase counters as markdown")
     ap.add_argument("--ceilings", action="store_true",
                     help="print the memory-system probes' bandwidths (include/ips_probe.h) as markdown")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
@@ -80,6 +84,8 @@ def main() -> int:
         return calib_copy()
     if args.ceilings:
         return ceilings()
+    if args.phase_counters:
+        return phase_counters(args.phase_counters)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sort runs on a single "
               f"MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -403,6 +409,62 @@ def ceilings() -> int:
     print("|---|---|---|---|")
     for r in rows:
         print(f"| {r[0]} | {r[1]} | {r[2]} | {r[3]} |")
+    return 0
+
+
+PHASE_COUNTERS = {
+    # kernel, algorithm, flags, {level label: first u64 slot of the control block}, counter names
+    "perm": ("block permutation (k_permute)", "samplesort", 0, {"root step": 16, "deeper steps": 42},
+             ["claims that took a block", "claims that found their piece empty", "swaps",
+              "blocks already in their bucket", "blocks placed in an empty slot", "placements that had to wait",
+              "placements into a full piece", "wait iterations", "loop iterations (wavefronts)"]),
+    "fused": ("fused radix step (k_fused)", "radix", 0x100, {"root step": 16, "deeper steps": 24},
+              ["cycles: classify", "cycles: reserve", "cycles: claims", "cycles: load", "cycles: waits",
+               "cycles: store", "tiles", "claims"]),
+    "lds": ("LDS tier (k_lds_tier)", "samplesort", 0, {"all steps": 16},
+            ["cycles: load", "cycles: min/max", "cycles: binning", "cycles: bin sorts", "cycles: re-binning",
+             "cycles: store", "tasks"]),
+}
+
+
+def phase_counters(which: str) -> int:
+    """Per-phase counters of one u64 Uniform 2^28 sort from a counter build
+    of the library (control words 32.. hold them; the control block is the
+    first bytes of the workspace and is cleared at the start of every call).
+    Cycle counters are thread 0's clock cycles per phase summed over the
+    workgroups; the fractions are of their sum."""
+    import torch
+
+    import paper_2009_13569_amd as ips
+    import synth
+    import synth.device as sd
+    name, algo, flags, levels, names = PHASE_COUNTERS[which]
+    lib = os.environ.get("IPS_LIBRARY", "")
+    sorter = ips.Sorter(0)
+    x = sd.generate("u64", "uniform", 1 << 28, synth.seed_for(2, 0), "cuda")
+    p = ips.make_params(flags=flags) if flags else None
+    for _ in range(2):
+        y = x.clone()
+        sorter.sort_(y, kind="u64", algo=algo, params=p)
+        torch.cuda.synchronize()
+    words = sorter.workspace(0)[:1024].view(torch.int64).cpu().tolist()
+    cols = {lab: words[o:o + len(names)] for lab, o in levels.items()}
+    if not any(any(v) for v in cols.values()):
+        log(f"no counters: IPS_LIBRARY ({lib or 'unset'}) is not a build with the {which} counters")
+        return 1
+    print(f"{name}, u64 Uniform 2^28 {algo}{' (fused)' if flags else ''}, library {os.path.basename(lib)}\n")
+    print("| counter | " + " | ".join(cols) + " |")
+    print("|---|" + "---|" * len(cols))
+    for i, nm in enumerate(names):
+        print(f"| {nm} | " + " | ".join(str(cols[c][i]) for c in cols) + " |")
+    cyc = [i for i, nm in enumerate(names) if nm.startswith("cycles")]
+    if cyc:
+        print()
+        print("| phase share of thread-0 cycles | " + " | ".join(cols) + " |")
+        print("|---|" + "---|" * len(cols))
+        for i in cyc:
+            print(f"| {names[i][8:]} | " + " | ".join(
+                f"{cols[c][i] / max(1, sum(cols[c][j] for j in cyc)):.3f}" for c in cols) + " |")
     return 0
 
 

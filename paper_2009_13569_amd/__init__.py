@@ -11,7 +11,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libips.so")
+# IPS_LIBRARY selects another build of the same sources (a counter build of
+# `python -m paper_2009_13569_amd.build --define ... --out ...`).
+LIB_PATH = os.environ.get("IPS_LIBRARY") or os.path.join(HERE, "libips.so")
 
 # PyTorch's HIP runtime is loaded first so that libips.so binds to the same
 # runtime (its dependency is recorded as plain libamdhip64.so).

@@ -29,9 +29,9 @@ FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17"
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-save-temps=obj", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, build_dir: str = BUILD, defines: tuple = ()) -> str:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-save-temps=obj", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -68,7 +68,7 @@ def check_device_asm(build_dir: str = BUILD) -> list[str]:
     return files
 
 
-def _hip_stub() -> str:
+def _hip_stub(build_dir: str = BUILD) -> str:
     """An empty shared object whose soname is plain `libamdhip64.so`.
 
     Linking against it records the HIP runtime dependency under that name,
@@ -76,7 +76,7 @@ def _hip_stub() -> str:
     bundled one) shares it with libips.so instead of loading a second
     runtime; elsewhere the name resolves to /opt/rocm/lib through the rpath.
     """
-    d = os.path.join(BUILD, "stub")
+    d = os.path.join(build_dir, "stub")
     os.makedirs(d, exist_ok=True)
     src = os.path.join(d, "stub.c")
     with open(src, "w") as f:
@@ -86,26 +86,45 @@ def _hip_stub() -> str:
     return d
 
 
-def build(verbose: bool = False) -> str:
-    """Compile all sources and link libips.so; always rebuilds."""
-    os.makedirs(BUILD, exist_ok=True)
+# Counter builds: the same sources with one of these defined add per-phase
+# counters to a kernel, written to the control block (see bench.py
+# --phase-counters); they are slower and never the library the package loads
+# by default.
+COUNTER_DEFINES = ("IPS_PERM_STATS", "IPS_FUSED_STATS", "IPS_LDS_STATS")
+
+
+def build(verbose: bool = False, defines: tuple = (), out: str | None = None) -> str:
+    """Compile all sources and link libips.so (or, with `defines`, a counter
+    build at `out`); always rebuilds."""
+    if defines and not out:
+        raise ValueError("a build with defines needs its own output path")
+    out = out or OUT
+    build_dir = BUILD if not defines else os.path.join(os.path.dirname(os.path.abspath(out)), "_build_" +
+                                                       "_".join(d.lower() for d in defines))
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    stub = _hip_stub()
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, tuple(defines)), SOURCES))
+    stub = _hip_stub(build_dir)
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", f"-L{stub}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    asm = check_device_asm(BUILD)
+    asm = check_device_asm(build_dir)
     if len(asm) != len(SOURCES):
         raise RuntimeError(f"expected {len(SOURCES)} device assembly files, found {len(asm)}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    import argparse
+    ap = argparse.ArgumentParser(description="build libips.so (or a counter build of it)")
+    ap.add_argument("--define", action="append", default=[], choices=COUNTER_DEFINES,
+                    help="a counter build: compile with this macro defined (needs --out)")
+    ap.add_argument("--out", default=None, help="output library path (default: the package's libips.so)")
+    a = ap.parse_args()
+    build(verbose=True, defines=tuple(a.define), out=a.out)
     sys.exit(0)
