@@ -9,8 +9,10 @@ For each element kind, algorithm and size class 2^c it sorts a Uniform
 array of 2^c elements (restored before every run, untimed) and times each
 run with HIP events on the sort's stream (median of `reps`).  Size classes
 beyond a kind's largest benchmark size (2^27 for Pair and Quartet, 2^24 for
-100-byte records) are skipped; radix is not tuned for the kinds it does not
-sort (records, Quartets).
+100-byte records) are skipped, and that size is a class of its own, so the
+table's last entry of a kind is measured at its benchmark size rather than
+carried over from a smaller class; radix is not tuned for the kinds it does
+not sort (records, Quartets).
 Starting from the library defaults it tunes one parameter at a time over a
 small candidate list, keeping a change only when it is at least 1% faster,
 for two rounds over the list (coordinate descent).  The paper tunes k, the
@@ -274,6 +276,8 @@ def main(argv=None) -> int:
             if algo == "radix" and kind in NO_RADIX:
                 continue
             ks = [c for c in classes if c <= MAX_LOG2[kind]]
+            if ks and MAX_LOG2[kind] > ks[-1] and MAX_LOG2[kind] <= classes[-1]:
+                ks.append(MAX_LOG2[kind])   # the kind's largest benchmark size is measured, not extrapolated
             for i, c in enumerate(ks):
                 cfg, ms, ms0 = tune_single(kind, algo, c, args.reps)
                 hi = ks[i + 1] - 1 if i + 1 < len(ks) else 40
