@@ -560,12 +560,14 @@ def result_summary(path: str) -> int:
         for c in d["cases"]:
             groups.setdefault((c["kind"], c["log2n"]), {}).setdefault(c["dist"], {})[c["algo"]] = c
         for (kind, lg), dists in groups.items():
+            fused = any("radix_fused" in a for a in dists.values())
             out += [f"## {kind}, n = 2^{lg}", "",
-                    "| generator | samplesort ms | Gelem/s | levels | IPS2Ra ms | Gelem/s | levels | "
-                    "sorted keys = oracle's |", "|---|---|---|---|---|---|---|---|"]
+                    "| generator | samplesort ms | Gelem/s | levels | IPS2Ra ms | Gelem/s | levels | " +
+                    ("IPS2Ra fused ms | Gelem/s | levels | " if fused else "") + "sorted keys = oracle's |",
+                    "|---|---|---|---|---|---|---|---|" + ("---|---|---|" if fused else "")]
             for dist, algos in dists.items():
                 cells, eq = [], []
-                for a in ("samplesort", "radix"):
+                for a in ("samplesort", "radix") + (("radix_fused",) if fused else ()):
                     c = algos.get(a)
                     cells += [str(c["ms"]), str(c["Gelems_per_s"]), str(c["levels"])] if c else ["-", "-", "-"]
                     if c:
@@ -774,8 +776,9 @@ def _golden_digests():
 
 
 def bench_sweep(args) -> int:
-    """Every generator at n = 2^28 for u64 and u32 keys (samplesort and
-    IPS2Ra), then the wider elements: f64 (Uniform, Exponential) and Pair
+    """Every generator at n = 2^28 for u64 and u32 keys (samplesort, IPS2Ra
+    and IPS2Ra with classification fused into the permutation), then the
+    wider elements: f64 (Uniform, Exponential) and Pair
     (Uniform, RootDup) at 2^27 with both algorithms, Quartets (Uniform) at
     2^27, 100-byte records (Uniform and RootDup keys) at 2^24.  Each case: one
     warmup and `steps` sorts of a pristine device copy (the copy untimed),
@@ -790,7 +793,8 @@ def bench_sweep(args) -> int:
 
     dev = torch.device("cuda:0")
     steps = max(1, min(args.steps, 5))
-    cases = [(k, d, 28, a) for k in ("u64", "u32") for d in SWEEP_DISTS for a in ("samplesort", "radix")]
+    cases = [(k, d, 28, a) for k in ("u64", "u32") for d in SWEEP_DISTS
+             for a in ("samplesort", "radix", "radix_fused")]
     cases += [(k, d, 27, a) for k, d in (("f64", "uniform"), ("f64", "exponential"), ("pair", "uniform"),
                                           ("pair", "rootdup")) for a in ("samplesort", "radix")]
     cases += [("quartet", "uniform", 27, "samplesort"),
@@ -810,13 +814,15 @@ def bench_sweep(args) -> int:
         if fp is None:
             fp = int(src.view(torch.int32).to(torch.int64).sum())
         work = torch.empty_like(src)
-        ws = sorter.workspace(ips.workspace_bytes(n, kind, algo, sorter.params_for(n, kind, algo, False)))
+        calg = "radix" if algo == "radix_fused" else algo
+        cp = ips.make_params(flags=ips.FLAG_FUSED) if algo == "radix_fused" else None
+        ws = sorter.workspace(ips.workspace_bytes(n, kind, calg, sorter.params_for(n, kind, calg, False, params=cp)))
         times = []
         for r in range(steps + 1):
             work.copy_(src)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            sorter.sort_(work, algo=algo, kind=kind, ws=ws)
+            sorter.sort_(work, algo=calg, kind=kind, ws=ws, params=cp)
             e1.record()
             torch.cuda.synchronize()
             if r:
