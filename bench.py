@@ -60,7 +60,7 @@ def main() -> int:
     ap.add_argument("--phase-counters", choices=["perm", "fused", "lds"],
                     help="with IPS_LIBRARY set to the matching counter build (python -m "
                          "paper_2009_13569_amd.build --define IPS_PERM_STATS|IPS_FUSED_STATS|IPS_LDS_STATS "
-                         "--out ...): one u64 Uniform 2^28 sort's per-phase counters as markdown")
+                         "--out ...): one u64 2^28 sort's per-phase counters (generator --dist) as markdown")
     ap.add_argument("--ceilings", action="store_true",
                     help="print the memory-system probes' bandwidths (include/ips_probe.h) as markdown")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
@@ -85,7 +85,7 @@ def main() -> int:
     if args.ceilings:
         return ceilings()
     if args.phase_counters:
-        return phase_counters(args.phase_counters)
+        return phase_counters(args.phase_counters, args.dist)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sort runs on a single "
               f"MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -427,8 +427,8 @@ PHASE_COUNTERS = {
 }
 
 
-def phase_counters(which: str) -> int:
-    """Per-phase counters of one u64 Uniform 2^28 sort from a counter build
+def phase_counters(which: str, dist: str = "uniform") -> int:
+    """Per-phase counters of one u64 2^28 sort (generator `dist`) from a counter build
     of the library (control words 32.. hold them; the control block is the
     first bytes of the workspace and is cleared at the start of every call).
     Cycle counters are thread 0's clock cycles per phase summed over the
@@ -441,7 +441,7 @@ def phase_counters(which: str) -> int:
     name, algo, flags, levels, names = PHASE_COUNTERS[which]
     lib = os.environ.get("IPS_LIBRARY", "")
     sorter = ips.Sorter(0)
-    x = sd.generate("u64", "uniform", 1 << 28, synth.seed_for(2, 0), "cuda")
+    x = sd.generate("u64", dist, 1 << 28, synth.seed_for(2, SWEEP_DISTS.index(dist)), "cuda")
     p = ips.make_params(flags=flags) if flags else None
     for _ in range(2):
         y = x.clone()
@@ -452,7 +452,7 @@ def phase_counters(which: str) -> int:
     if not any(any(v) for v in cols.values()):
         log(f"no counters: IPS_LIBRARY ({lib or 'unset'}) is not a build with the {which} counters")
         return 1
-    print(f"{name}, u64 Uniform 2^28 {algo}{' (fused)' if flags else ''}, library {os.path.basename(lib)}\n")
+    print(f"{name}, u64 {dist} 2^28 {algo}{' (fused)' if flags else ''}, library {os.path.basename(lib)}\n")
     print("| counter | " + " | ".join(cols) + " |")
     print("|---|" + "---|" * len(cols))
     for i, nm in enumerate(names):

@@ -136,8 +136,9 @@ __global__ void __launch_bounds__(MAX_K) k_fscan(BatchArgs a, uint32_t ntask) {
 }
 #endif  // IPS_COMMON_KERNELS
 
+// At least four wavefronts per SIMD (the second bound): two workgroups per CU.
 template <class T>
-__global__ void __launch_bounds__(FUSED_THREADS, 2) k_fused(BatchArgs a) {
+__global__ void __launch_bounds__(FUSED_THREADS, 4) k_fused(BatchArgs a) {
   constexpr int DW = T::DW;
   constexpr int EPT = FusedEpt<T>::value;   // elements per thread and tile
   constexpr uint32_t NT = FUSED_THREADS;
