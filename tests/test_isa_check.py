@@ -44,3 +44,11 @@ def test_last_build_has_no_hazard():
     if not files:
         pytest.skip("no device assembly kept by the last build")
     assert len(files) == len(b.SOURCES)
+
+
+def test_counter_build_needs_its_own_output():
+    """A build with counter macros never replaces the package's library."""
+    build = _build_mod()
+    with pytest.raises(ValueError):
+        build.build(defines=("IPS_PERM_STATS",))
+    assert set(build.COUNTER_DEFINES) == {"IPS_PERM_STATS", "IPS_FUSED_STATS", "IPS_LDS_STATS"}
