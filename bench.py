@@ -67,6 +67,8 @@ def main() -> int:
                     help="turn four rocprofv3 --pmc output folders into the traffic summary (markdown)")
     ap.add_argument("--kernel-stats-summary", metavar="CSV",
                     help="print a rocprofv3 kernel_stats.csv as a markdown table")
+    ap.add_argument("--trace-args", default="--steps 3 --warmup 1 --no-cpu --no-radix",
+                    help="with --kernel-stats-summary: the bench.py arguments of the traced run")
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
                     help="turn rocprofv3 --pmc output folders into a per-kernel counter table (markdown)")
     ap.add_argument("--summary", metavar="JSON",
@@ -75,7 +77,7 @@ def main() -> int:
     if args.summary:
         return result_summary(args.summary)
     if args.kernel_stats_summary:
-        return kernel_stats_summary(args.kernel_stats_summary)
+        return kernel_stats_summary(args.kernel_stats_summary, args.trace_args)
     if args.counter_summary:
         return counter_summary(args.counter_summary)
     if args.traffic_summary:
@@ -673,21 +675,25 @@ def counter_summary(folders: list) -> int:
     return 0
 
 
-def kernel_stats_summary(csv_path: str) -> int:
-    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+def kernel_stats_summary(csv_path: str, trace_args: str = "--steps 3 --warmup 1 --no-cpu --no-radix") -> int:
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)
+    of a traced run of this script with `trace_args`."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
-    print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort\n")
+    radix = "--no-radix" not in trace_args.split()
+    print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort" +
+          (", IPS2Ra and IPS2Ra fused\n" if radix else "\n"))
     folder = os.path.dirname(csv_path)
     prefix = os.path.basename(csv_path)[:-len("_kernel_stats.csv")]
+    extra = "" if trace_args == "--steps 3 --warmup 1 --no-cpu --no-radix" else f' --trace-args "{trace_args}"'
     print("Command (`cd /tmp`, `TMPDIR=/tmp`, R = repo root): `rocprofv3 --kernel-trace --stats --output-format csv "
-          f"-d {_from_root(folder)} -o {prefix} -- python3 $R/bench.py --steps 3 --warmup 1 --no-cpu --no-radix`; "
-          f"table from `python3 bench.py --kernel-stats-summary {csv_path}`.\n")
-    print("6 sorts (1 warmup, 3 timed, 2 timed per kernel for the per-level table) plus the bench's own "
-          "copies and checks; durations in microseconds.\n")
+          f"-d {_from_root(folder)} -o {prefix} -- python3 $R/bench.py {trace_args}`; "
+          f"table from `python3 bench.py --kernel-stats-summary {csv_path}{extra}`.\n")
+    print(("Per algorithm 6" if radix else "6") + " sorts (1 warmup, 3 timed, 2 timed per kernel for the per-level "
+          "table) plus the bench's own copies and checks; durations in microseconds.\n")
     print("| kernel | calls | total us | avg us | % |")
     print("|---|---|---|---|---|")
-    for r in rows[:16]:
+    for r in rows[:24 if radix else 16]:
         name = r["Name"].replace("|", "/")
         if len(name) > 70:
             name = name[:67] + "..."
