@@ -165,7 +165,7 @@ struct LaunchImpl {
   }
   static hipError_t minmax(const uint32_t* data, uint64_t n, uint32_t* ctrl, hipStream_t st) {
     if constexpr (T::RADIX_OK) {
-      uint32_t g = (uint32_t)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+      uint32_t g = (uint32_t)((n + 2047) / 2048 < 2048 ? (n + 2047) / 2048 : 2048);   // 2048 elements per round
       if (!g) g = 1;
       hipLaunchKernelGGL((k_minmax<T>), dim3(g), dim3(256), 0, st, data, n, ctrl);
       return hipGetLastError();

@@ -1629,18 +1629,20 @@ template <class T>
 __global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n, uint32_t* ctrl) {
   constexpr int DW = T::DW;
   constexpr int U = 8;   // loads in flight per lane
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  // A workgroup reads U * 256 consecutive elements per round (contiguous
+  // chunks, as a streaming copy does), then moves on by the grid's span.
+  const uint64_t stride = (uint64_t)gridDim.x * 256 * U;
   uint64_t mn = ~0ull, mx = 0;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += stride * U) {
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 * U + threadIdx.x; i0 < n; i0 += stride) {
     uint32_t w[U][DW];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint64_t i = i0 + (uint64_t)u * stride;
+      const uint64_t i = i0 + (uint64_t)u * 256;
       if (i < n) ld_elem<DW>(data + i * DW, w[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (i0 + (uint64_t)u * stride < n) {
+      if (i0 + (uint64_t)u * 256 < n) {
         const uint64_t k = T::rkey(key_of<T>(w[u]));
         mn = k < mn ? k : mn;
         mx = k > mx ? k : mx;
