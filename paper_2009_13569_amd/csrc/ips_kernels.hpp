@@ -1665,21 +1665,36 @@ __global__ void __launch_bounds__(256) k_minmax(const uint32_t* data, uint64_t n
 // Per-segment order check of a batched call (the sorted-input detection of
 // Section 6 applied to every segment): flags[2 seg] is set on a descent,
 // flags[2 seg + 1] on an ascent.  A chunk compares each element with its
-// predecessor unless the element starts the segment.
+// predecessor unless the element starts the segment, 2048 pairs per round;
+// it stops after the first round in which the workgroup has seen both a
+// descent and an ascent, since the segment can then be neither sorted nor
+// reverse sorted whatever the rest holds (random input stops after one
+// round, nearly sorted input after a few; only sorted runs read the whole
+// chunk).
 template <class T>
 __global__ void __launch_bounds__(256) k_seg_order(const SegItem* items, const uint32_t* data,
                                                    uint32_t* flags) {
   using Key = typename T::Key;
   constexpr int DW = T::DW;
+  constexpr uint32_t U = 8;
   const SegItem it = items[blockIdx.x];
   uint32_t desc = 0, asc = 0;
-  for (uint32_t q = threadIdx.x + (it.first ? 1u : 0u); q < it.n; q += 256) {
-    uint32_t w0[DW], w1[DW];
-    ld_elem<DW>(data + (it.l + q - 1) * DW, w0);
-    ld_elem<DW>(data + (it.l + q) * DW, w1);
-    const Key x = key_of<T>(w0), y = key_of<T>(w1);
-    desc |= kless(y, x) ? 1u : 0u;
-    asc |= kless(x, y) ? 1u : 0u;
+  const uint32_t q0 = it.first ? 1u : 0u;
+  for (uint32_t base = q0; base < it.n; base += 256 * U) {
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t q = base + u * 256 + threadIdx.x;
+      if (q < it.n) {
+        uint32_t w0[DW], w1[DW];
+        ld_elem<DW>(data + (it.l + q - 1) * DW, w0);
+        ld_elem<DW>(data + (it.l + q) * DW, w1);
+        const Key x = key_of<T>(w0), y = key_of<T>(w1);
+        desc |= kless(y, x) ? 1u : 0u;
+        asc |= kless(x, y) ? 1u : 0u;
+      }
+    }
+    // (both votes return the same value to every thread)
+    if (__syncthreads_or((int)desc) && __syncthreads_or((int)asc)) break;
   }
   if (__any(desc) && (threadIdx.x & 63) == 0) atomicOr(&flags[2 * it.seg], 1u);
   if (__any(asc) && (threadIdx.x & 63) == 0) atomicOr(&flags[2 * it.seg + 1], 1u);

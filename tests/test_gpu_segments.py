@@ -166,3 +166,29 @@ def test_segments_sorted_detection(sorter, kind):
         log(f"segments sorted detection {kind} flags={flags}")
         out = _run_segments(sorter, data, offs, sizes, kind, params=ips.make_params(flags=flags))
         _check(out, data, offs, sizes, kind)
+
+
+@pytest.mark.parametrize("kind", ["u64", "pair"])
+def test_segments_order_check_late_descent(sorter, kind):
+    """The per-segment order check stops a chunk early once it has seen a
+    descent and an ascent; a segment whose only descent (or ascent) lies far
+    into a later chunk must still be found unsorted and be sorted."""
+    n = 200_003
+    base = oracle.sort(generate(kind, "uniform", n, 91), kind)
+    parts = []
+    for pos in (n - 2, 65536 + 1000, 3 * 65536 + 7):      # one adjacent swap late in the segment
+        a = base.copy()
+        a[[pos, pos + 1]] = a[[pos + 1, pos]]
+        parts.append(a)
+    rev = base[::-1].copy()
+    rev[[n - 2, n - 1]] = rev[[n - 1, n - 2]]              # reverse sorted but for its last pair
+    parts.append(rev)
+    parts.append(base.copy())                               # sorted: stays as it is
+    sizes = [n] * len(parts)
+    offs, total = _layout(sizes, gap=5)
+    data = np.zeros((total,) + base.shape[1:], dtype=base.dtype)
+    for o, a in zip(offs, parts):
+        data[o:o + n] = a
+    log(f"segments late descent {kind}")
+    out = _run_segments(sorter, data, offs, sizes, kind)
+    _check(out, data, offs, sizes, kind)
