@@ -14,7 +14,10 @@ namespace ips {
 // LDS-tier shapes per type: (threads, keys per thread) of three variants of
 // increasing capacity (a task runs on the smallest variant that holds it),
 // and NET: bins hold about NET/4 keys and are sorted in registers up to
-// NET/2 keys.
+// NET/2 keys.  Keys with indices (Pair) take the smaller networks: with
+// NET = 32 their (key, index) networks spilled registers and the tier ran
+// a third slower (2.5 against 1.9 ms for 2^27 Pairs), while keys alone ran
+// it twice as long with NET = 16.
 template <class T> struct LdsShape;
 template <> struct LdsShape<TU32> {
   static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
@@ -26,7 +29,7 @@ template <> struct LdsShape<TF64> {
   static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
 };
 template <> struct LdsShape<TPair> {
-  static constexpr uint32_t N0 = 256, E0 = 8, N1 = 512, E1 = 8, N2 = 1024, E2 = 8, NET = 32;
+  static constexpr uint32_t N0 = 256, E0 = 8, N1 = 512, E1 = 8, N2 = 1024, E2 = 8, NET = 16;
 };
 template <> struct LdsShape<TRec100> {
   static constexpr uint32_t N0 = 256, E0 = 4, N1 = 256, E1 = 4, N2 = 256, E2 = 4, NET = 16;
