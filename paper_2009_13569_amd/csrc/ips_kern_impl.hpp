@@ -16,11 +16,12 @@ namespace ips {
 // and NET: bins hold about NET/4 keys and are sorted in registers up to
 // NET/2 keys.  Keys with indices (Pair) take the smaller networks: with
 // NET = 32 their (key, index) networks spilled registers and the tier ran
-// a third slower (2.5 against 1.9 ms for 2^27 Pairs), while keys alone ran
-// it twice as long with NET = 16.
+// a third slower (2.5 against 1.9 ms for 2^27 Pairs), while 8-byte keys
+// alone ran it twice as long with NET = 16; 4-byte keys fit networks of 32
+// keys per lane without spills (1.25 -> 1.22 ms for 2^28 u32).
 template <class T> struct LdsShape;
 template <> struct LdsShape<TU32> {
-  static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
+  static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 64;
 };
 template <> struct LdsShape<TU64> {
   static constexpr uint32_t N0 = 256, E0 = 16, N1 = 512, E1 = 16, N2 = 1024, E2 = 16, NET = 32;
