@@ -8,8 +8,8 @@ writes the tuning table (TUNING_PATH) that Sorter applies to every call.
 For each element kind, algorithm and size class 2^c it sorts a Uniform
 array of 2^c elements (restored before every run, untimed) and times each
 run with HIP events on the sort's stream (median of `reps`).  Size classes
-beyond a kind's largest benchmark size (2^27 for Pair and Quartet, 2^24 for
-100-byte records) are skipped, and that size is a class of its own, so the
+beyond a kind's largest benchmark size (2^27 for f64, Pair and Quartet, 2^24
+for 100-byte records) are skipped, and that size is a class of its own, so the
 table's last entry of a kind is measured at its benchmark size rather than
 carried over from a smaller class; radix is not tuned for the kinds it does
 not sort (records, Quartets).
@@ -56,7 +56,7 @@ CANDIDATES = {
     "k_root": [64, 128],
 }
 RADIX_CANDIDATES = {f: v for f, v in CANDIDATES.items() if f not in ("k", "n0", "k_root")}   # radix: 8-bit digits
-MAX_LOG2 = {"u32": 28, "u64": 28, "f64": 28, "pair": 27, "rec100": 24, "quartet": 27}
+MAX_LOG2 = {"u32": 28, "u64": 28, "f64": 27, "pair": 27, "rec100": 24, "quartet": 27}
 CAP = {"u32": 16384, "u64": 16384, "f64": 16384, "pair": 8192, "rec100": 1024, "quartet": 2048}
 NO_RADIX = ("rec100", "quartet")
 
