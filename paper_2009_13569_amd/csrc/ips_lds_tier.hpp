@@ -93,8 +93,8 @@ template <class Key, bool IDX>
 __device__ __forceinline__ void ce_up(Key& a, Key& b, uint32_t& ia, uint32_t& ib) {
   const bool sw = kless(b, a) || (IDX && keq(a, b) && ib < ia);
   const Key ta = a, tb = b;
-  a = sw ? tb : ta;
-  b = sw ? ta : tb;
+  a = ksel(sw, tb, ta);
+  b = ksel(sw, ta, tb);
   if (IDX) {
     const uint32_t ua = ia, ub = ib;
     ia = sw ? ub : ua;
@@ -178,7 +178,7 @@ __device__ void wave_reg_network(typename T::Key* keys, uint16_t* idx, uint32_t 
       for (uint32_t r = 0; r < R; ++r) {
         const uint32_t i = lane * R + r;
         const uint32_t pr = r ^ (m & (R - 1));            // partner's register
-        const Key own = (pr == 0) ? v[0] : v[R - 1];
+        const Key own = ksel(pr == 0, v[0], v[R - 1]);
         const uint32_t oix = (pr == 0) ? ix[0] : ix[R - 1];
         Key pv = own;
         uint32_t pix = oix;
@@ -190,7 +190,7 @@ __device__ void wave_reg_network(typename T::Key* keys, uint16_t* idx, uint32_t 
         const bool pless = kless(pv, v[r]) || (IDX && keq(pv, v[r]) && pix < ix[r]);
         const bool mless = kless(v[r], pv) || (IDX && keq(v[r], pv) && ix[r] < pix);
         const bool take = (i & J) == 0 ? pless : mless;
-        nv[r] = take ? pv : v[r];
+        nv[r] = ksel(take, pv, v[r]);
         nix[r] = take ? pix : ix[r];
       }
 #pragma unroll

@@ -43,6 +43,25 @@ __device__ __forceinline__ bool kless(const K192& x, const K192& y) {
 }
 __device__ __forceinline__ bool keq(const K192& x, const K192& y) { return x.a == y.a && x.b == y.b && x.c == y.c; }
 
+// c ? a : b, field by field for the composite keys (a select of whole
+// structures can be lowered through private memory).
+__device__ __forceinline__ uint32_t ksel(bool c, uint32_t a, uint32_t b) { return c ? a : b; }
+__device__ __forceinline__ uint64_t ksel(bool c, uint64_t a, uint64_t b) { return c ? a : b; }
+__device__ __forceinline__ K80 ksel(bool c, const K80& a, const K80& b) {
+  K80 r;
+  r.hi = c ? a.hi : b.hi;
+  r.lo = c ? a.lo : b.lo;
+  r.pad = 0;
+  return r;
+}
+__device__ __forceinline__ K192 ksel(bool c, const K192& x, const K192& y) {
+  K192 r;
+  r.a = c ? x.a : y.a;
+  r.b = c ? x.b : y.b;
+  r.c = c ? x.c : y.c;
+  return r;
+}
+
 constexpr uint32_t BUF_BYTES_DEFAULT = 128u * 1024u;
 
 __device__ __forceinline__ uint64_t f64_to_ord(uint64_t b) {
