@@ -833,7 +833,9 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
               uint32_t* pop) {
   using Key = typename T::Key;
   constexpr uint32_t NT = 256;
+  constexpr uint32_t LU = 8;
   constexpr int DW = T::DW;
+  static_assert(DW % 2 == 0 && (CAP * (sizeof(Key) + 2)) % 8 == 0, "records move as aligned 8-byte words");
   extern __shared__ __align__(16) uint8_t s_raw[];
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idx = reinterpret_cast<uint16_t*>(keys + CAP);
@@ -864,8 +866,25 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
     if (n > CAP) {
       if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
     } else if (n >= 2) {
-      uint32_t* gd = data + t.l * DW;
-      for (uint32_t x = tid; x < n * DW; x += NT) stage[x] = gd[x];
+      // Records move as 8-byte words (records are 8-byte aligned), LU of
+      // them in flight per thread before any reaches LDS: one load at a time
+      // per thread left the load phase waiting on HBM latency LU times over.
+      uint2* const g2 = reinterpret_cast<uint2*>(data + t.l * DW);
+      uint2* const s2 = reinterpret_cast<uint2*>(stage);
+      const uint32_t m = n * (DW / 2);
+      for (uint32_t x0 = 0; x0 < m; x0 += NT * LU) {
+        uint2 v[LU];
+#pragma unroll
+        for (uint32_t u = 0; u < LU; ++u) {
+          const uint32_t x = x0 + u * NT + tid;
+          if (x < m) v[u] = g2[x];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < LU; ++u) {
+          const uint32_t x = x0 + u * NT + tid;
+          if (x < m) s2[x] = v[u];
+        }
+      }
       __syncthreads();
       uint32_t P = 1;
       while (P < n) P <<= 1;
@@ -888,9 +907,21 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
           __syncthreads();
         }
       }
-      for (uint32_t x = tid; x < n * DW; x += NT) {
-        const uint32_t i = x / DW, d = x - i * DW;
-        gd[x] = stage[idx[i] * DW + d];
+      for (uint32_t x0 = 0; x0 < m; x0 += NT * LU) {
+        uint2 v[LU];
+#pragma unroll
+        for (uint32_t u = 0; u < LU; ++u) {
+          const uint32_t x = x0 + u * NT + tid;
+          if (x < m) {
+            const uint32_t i = x / (DW / 2), d = x - i * (DW / 2);
+            v[u] = s2[idx[i] * (DW / 2) + d];
+          }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < LU; ++u) {
+          const uint32_t x = x0 + u * NT + tid;
+          if (x < m) g2[x] = v[u];
+        }
       }
     }
     if (tid == 0 && seg_done) atomicAdd(&seg_done[t.req], (unsigned long long)t.n);   // serving
