@@ -52,6 +52,8 @@ def main() -> int:
                          "sweep: every generator at 2^28 for u64 and u32, and the wider elements "
                          "(f64 and Pair at 2^27, 100-byte records at 2^24); "
                          "oop: the out-of-place partitioning step (ablation) against the in-place one")
+    ap.add_argument("--only", default=None, metavar="KIND[-DIST],...",
+                    help="sweep: run only these cases (e.g. quartet, or u64-zipf,pair-rootdup)")
     ap.add_argument("--arrays", type=int, default=4096, help="batch: number of arrays")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget (GB)")
@@ -680,17 +682,27 @@ def kernel_stats_summary(csv_path: str, trace_args: str = "--steps 3 --warmup 1 
     of a traced run of this script with `trace_args`."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
-    radix = "--no-radix" not in trace_args.split()
-    print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort" +
-          (", IPS2Ra and IPS2Ra fused\n" if radix else "\n"))
+    targs = trace_args.split()
+    sweep = "--workload" in targs and targs[targs.index("--workload") + 1:][:1] == ["sweep"]
+    radix = "--no-radix" not in targs and not sweep
+    if sweep:
+        only = targs[targs.index("--only") + 1] if "--only" in targs[:-1] else "every case"
+        print(f"# Kernel time, generator sweep: {only}\n")
+    else:
+        print("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort" +
+              (", IPS2Ra and IPS2Ra fused\n" if radix else "\n"))
     folder = os.path.dirname(csv_path)
     prefix = os.path.basename(csv_path)[:-len("_kernel_stats.csv")]
     extra = "" if trace_args == "--steps 3 --warmup 1 --no-cpu --no-radix" else f' --trace-args "{trace_args}"'
     print("Command (`cd /tmp`, `TMPDIR=/tmp`, R = repo root): `rocprofv3 --kernel-trace --stats --output-format csv "
           f"-d {_from_root(folder)} -o {prefix} -- python3 $R/bench.py {trace_args}`; "
           f"table from `python3 bench.py --kernel-stats-summary {csv_path}{extra}`.\n")
-    print(("Per algorithm 6" if radix else "6") + " sorts (1 warmup, 3 timed, 2 timed per kernel for the per-level "
-          "table) plus the bench's own copies and checks; durations in microseconds.\n")
+    if sweep:
+        print("Per case 6 sorts (1 warmup, 5 timed, each of a fresh device copy of the input) plus the "
+              "sweep's own copies and checks; durations in microseconds.\n")
+    else:
+        print(("Per algorithm 6" if radix else "6") + " sorts (1 warmup, 3 timed, 2 timed per kernel for the "
+              "per-level table) plus the bench's own copies and checks; durations in microseconds.\n")
     print("| kernel | calls | total us | avg us | % |")
     print("|---|---|---|---|---|")
     for r in rows[:24 if radix else 16]:
@@ -805,6 +817,11 @@ def bench_sweep(args) -> int:
                                           ("pair", "rootdup")) for a in ("samplesort", "radix")]
     cases += [("quartet", "uniform", 27, "samplesort"),
               ("rec100", "uniform", 24, "samplesort"), ("rec100", "rootdup", 24, "samplesort")]
+    if args.only:
+        want = [w.strip() for w in args.only.split(",") if w.strip()]
+        cases = [c for c in cases if any(w in (c[0], f"{c[0]}-{c[1]}") for w in want)]
+        if not cases:
+            raise SystemExit(f"--only {args.only}: no sweep case matches")
     gold, fsmod = _golden_digests()
     sorter = ips.Sorter(0)
     rows = []
