@@ -823,23 +823,23 @@ k_lds_tier(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt,
 }
 
 // LDS tier of the Quartet, whose 192-bit keys the binning above has no
-// image for: the task's records are staged in LDS, (key, index) pairs
-// padded to a power of two are sorted by a bitonic network in LDS, and the
-// records are written back in key order from the stage.  Same calling
-// convention as k_lds_tier (a list, or claims from a device count).
+// image for: (key, index) pairs of the task, padded to a power of two, are
+// sorted by a bitonic network in LDS, and the records are gathered from the
+// task's region in key order into registers and stored back over it.  LDS
+// holds the pairs only (26 bytes per element), not the records, so that up
+// to seven 512-element tasks run on a CU at once.  Same calling convention
+// as k_lds_tier (a list, or claims from a device count).
 template <class T, uint32_t CAP>
 __global__ void __launch_bounds__(256)
 k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* cnt, uint32_t cnt_cap,
               uint32_t* pop) {
   using Key = typename T::Key;
   constexpr uint32_t NT = 256;
-  constexpr uint32_t LU = 8;
   constexpr int DW = T::DW;
-  static_assert(DW % 2 == 0 && (CAP * (sizeof(Key) + 2)) % 8 == 0, "records move as aligned 8-byte words");
+  static_assert(DW % 2 == 0 && CAP % NT == 0, "records move as aligned 8-byte words, CAP / NT per thread");
   extern __shared__ __align__(16) uint8_t s_raw[];
   Key* keys = reinterpret_cast<Key*>(s_raw);
   uint16_t* idx = reinterpret_cast<uint16_t*>(keys + CAP);
-  uint32_t* stage = reinterpret_cast<uint32_t*>(idx + CAP);
   __shared__ uint32_t s_next;
   __shared__ LTask s_t;
   uint32_t count;
@@ -866,31 +866,19 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
     if (n > CAP) {
       if (tid == 0) dev_error(ctrl, DE_LDST, ti, n);
     } else if (n >= 2) {
-      // Records move as 8-byte words (records are 8-byte aligned), LU of
-      // them in flight per thread before any reaches LDS: one load at a time
-      // per thread left the load phase waiting on HBM latency LU times over.
-      uint2* const g2 = reinterpret_cast<uint2*>(data + t.l * DW);
-      uint2* const s2 = reinterpret_cast<uint2*>(stage);
-      const uint32_t m = n * (DW / 2);
-      for (uint32_t x0 = 0; x0 < m; x0 += NT * LU) {
-        uint2 v[LU];
-#pragma unroll
-        for (uint32_t u = 0; u < LU; ++u) {
-          const uint32_t x = x0 + u * NT + tid;
-          if (x < m) v[u] = g2[x];
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < LU; ++u) {
-          const uint32_t x = x0 + u * NT + tid;
-          if (x < m) s2[x] = v[u];
-        }
-      }
-      __syncthreads();
+      // Keys come straight from the records (the task's region is read again
+      // for the gather below, from the caches); only (key, index) pairs live
+      // in LDS, so that more tasks fit on a CU at once.
+      const uint32_t* const gd = data + t.l * DW;
       uint32_t P = 1;
       while (P < n) P <<= 1;
-      for (uint32_t i = tid; i < P; i += NT) {
-        keys[i] = i < n ? T::key_w(stage + i * DW) : T::kmax();
-        idx[i] = (uint16_t)(i < n ? i : 0xFFFFu);
+#pragma unroll
+      for (uint32_t r = 0; r < CAP / NT; ++r) {
+        const uint32_t i = r * NT + tid;
+        if (i < P) {
+          keys[i] = i < n ? T::key_w(gd + (uint64_t)i * DW) : T::kmax();
+          idx[i] = (uint16_t)(i < n ? i : 0xFFFFu);
+        }
       }
       __syncthreads();
       for (uint32_t k = 2; k <= P; k <<= 1) {
@@ -907,21 +895,32 @@ k_lds_bitonic(const LTask* lt, uint32_t* data, uint32_t* ctrl, const uint32_t* c
           __syncthreads();
         }
       }
-      for (uint32_t x0 = 0; x0 < m; x0 += NT * LU) {
-        uint2 v[LU];
+      // Gather: every record of the task is read into registers in key order,
+      // each value used before the barrier (so every load has returned), and
+      // only then are the records stored over the task's region.
+      // Each thread moves 8-byte words x = u * NT + tid of the output, word
+      // x % (DW / 2) of the record that sorts to position x / (DW / 2).
+      constexpr uint32_t RW = CAP / NT * (DW / 2);
+      const uint32_t m = n * (DW / 2);
+      const uint2* const src = reinterpret_cast<const uint2*>(gd);
+      uint2 v[RW];
 #pragma unroll
-        for (uint32_t u = 0; u < LU; ++u) {
-          const uint32_t x = x0 + u * NT + tid;
-          if (x < m) {
-            const uint32_t i = x / (DW / 2), d = x - i * (DW / 2);
-            v[u] = s2[idx[i] * (DW / 2) + d];
-          }
+      for (uint32_t u = 0; u < RW; ++u) {
+        const uint32_t x = u * NT + tid;
+        if (x < m) {
+          const uint32_t i = x / (DW / 2), w = x - i * (DW / 2);
+          v[u] = src[(uint64_t)idx[i] * (DW / 2) + w];
         }
+      }
 #pragma unroll
-        for (uint32_t u = 0; u < LU; ++u) {
-          const uint32_t x = x0 + u * NT + tid;
-          if (x < m) g2[x] = v[u];
-        }
+      for (uint32_t u = 0; u < RW; ++u)
+        if (u * NT + tid < m) asm volatile("" ::"v"(v[u].x), "v"(v[u].y));
+      __syncthreads();
+      uint2* const g2 = reinterpret_cast<uint2*>(data + t.l * DW);
+#pragma unroll
+      for (uint32_t u = 0; u < RW; ++u) {
+        const uint32_t x = u * NT + tid;
+        if (x < m) g2[x] = v[u];
       }
     }
     if (tid == 0 && seg_done) atomicAdd(&seg_done[t.req], (unsigned long long)t.n);   // serving
@@ -966,7 +965,7 @@ k_insertion(const LTask* lt, uint32_t nt, uint32_t* data, uint32_t* ctrl, const 
 
 template <class T, uint32_t CAP>
 constexpr size_t lds_bitonic_bytes() {
-  return (size_t)CAP * sizeof(typename T::Key) + (size_t)CAP * 2 + (size_t)CAP * T::DW * 4;
+  return (size_t)CAP * sizeof(typename T::Key) + (size_t)CAP * 2;
 }
 
 }  // namespace ips
