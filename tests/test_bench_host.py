@@ -37,3 +37,36 @@ def test_gpu_count_above_one_is_refused(capsys):
     finally:
         sys.argv = old
     assert "one GPU" in capsys.readouterr().err
+
+
+def _stats_csv(path):
+    with open(path, "w") as f:
+        f.write("Name,Calls,TotalDurationNs,AverageNs,Percentage\n")
+        f.write('"void ips::k_lds_bitonic<ips::TQuartet, 512u>(x)",6,6000000,1000000,60.0\n')
+        f.write('"void ips::k_permute<ips::TQuartet, 256u>(x)",6,4000000,666666.7,40.0\n')
+
+
+def test_kernel_stats_summary_names_the_traced_command(tmp_path, capsys):
+    csv_path = str(tmp_path / "kq_kernel_stats.csv")
+    _stats_csv(csv_path)
+    assert bench.kernel_stats_summary(csv_path, "--workload sweep --only quartet") == 0
+    out = capsys.readouterr().out
+    assert out.startswith("# Kernel time, generator sweep: quartet\n")
+    assert "-o kq -- python3 $R/bench.py --workload sweep --only quartet`" in out
+    assert f'--kernel-stats-summary {csv_path} --trace-args "--workload sweep --only quartet"' in out
+    assert "| 6 | 6000.0 | 1000.0 | 60.00 |" in out
+    assert bench.kernel_stats_summary(csv_path) == 0
+    out = capsys.readouterr().out
+    assert out.startswith("# Kernel time, u64 Uniform n=2^28, IPS4o samplesort\n")
+    assert "--trace-args" not in out
+
+
+def test_committed_kernel_time_profiles_name_their_commands():
+    for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if not name.startswith("kernel_time_"):
+            continue
+        txt = open(os.path.join(ROOT, "profiles", name)).read()
+        traced = txt.split("-- python3 $R/bench.py ", 1)[1].split("`", 1)[0]
+        table = txt.split("table from `python3 bench.py --kernel-stats-summary ", 1)[1].split("`", 1)[0]
+        if traced != "--steps 3 --warmup 1 --no-cpu --no-radix":
+            assert table.endswith(f'--trace-args "{traced}"'), name
